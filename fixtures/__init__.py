@@ -290,8 +290,10 @@ def custom(nx, ny, L, counts, seed, r_scale=1.0, ocean=None, G=5.0e3, dt=30.0,
            r_med=1500.0, sigma=0.5, lo=500.0, hi=4000.0) -> Workload:
     """A small seeded workload of any shape (tests)."""
     counts = np.broadcast_to(np.asarray(counts, np.int32), (nx * ny,)).copy()
+    # wavelengths of at least two cells, as in the benchmark fields (4-32 cells)
+    kmax = max(1.5, min(nx, ny) / 2.0)
     ocean = ocean if ocean is not None else random_modes(np.random.Generator(np.random.PCG64(seed)),
-                                                         4, nx * L, ny * L)
+                                                         4, nx * L, ny * L, kmin=1.0, kmax=kmax)
     return _assemble("custom", nx, ny, L, dt, 10, counts, seed, r_scale, ocean, G,
                      r_med=r_med, sigma=sigma, lo=lo, hi=hi)
 

@@ -1,0 +1,172 @@
+/*
+ * spdem: superparameterised sea-ice floe DEM on one MI355X (gfx950).
+ *
+ * Method: Deng, Stechmann & Chen, "Particle-continuum multiscale modeling of
+ * sea ice floes".  Every coarse grid cell runs its own doubly periodic DEM of
+ * rigid disk floes (Sec. 3.1); one fine step integrates the DEM system of
+ * Sec. 2.1 (ocean drag and drag torque, Hooke normal and Coulomb-capped
+ * tangential contact forces and their spin torques); the per-cell statistics
+ * of the floes (Sec. 2.3, Sec. 3.2) drive one Lax-Friedrichs step of the
+ * moment equations for mass density, momentum and spin angular momentum, with
+ * the Oseen treatment of the momentum advection (Sec. 3.2).
+ *
+ * Conventions shared by every call:
+ *   - cells are numbered c = iy * nx + ix; floes are stored sorted by cell;
+ *   - positions are cell-local, as unsigned 32-bit fractions of the cell side:
+ *     x = cell_lx * xi / 2^32 (periodic wrap is the natural 2^32 wrap);
+ *   - velocities u, v (m/s), spin omega (1/s), angle theta (rad), radius r (m)
+ *     and thickness h (m) are float32; mass m = rho_ice h pi r^2, I = m r^2;
+ *   - the ocean current is prescribed (Sec. 2.1):
+ *     u_o(X, Y) = (u0, v0) + sum_m (au_m, av_m) sin(kx_m X + ky_m Y + phase_m)
+ *     at global X = (ix + xi / 2^32) cell_lx, with curl dv_o/dX - du_o/dY;
+ *   - all calls are asynchronous on the context's stream except those marked
+ *     "synchronises"; no call throws; errors are returned as sp_status and the
+ *     message of the last failure is kept per context (sp_last_error);
+ *   - faults detected on the device (coincident centres, non-finite state,
+ *     CFL > 1, contact-list overflow) are latched in a device flag and
+ *     returned by the next synchronising call;
+ *   - a context is thread-compatible, not thread-safe.
+ */
+#ifndef SPDEM_H
+#define SPDEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sp_ctx sp_ctx;
+
+typedef enum {
+    SP_OK = 0,
+    SP_EINVAL = -1,     /* bad argument: size, range, null pointer, r_max >= L/4 */
+    SP_ENOMEM = -2,     /* device allocation failed */
+    SP_EDEVICE = -3,    /* HIP runtime error */
+    SP_ECFL = -4,       /* continuum CFL number exceeded 1 (Sec. 3.2) */
+    SP_EOVERLAP = -5,   /* two floe centres coincide: contact normal undefined */
+    SP_ENAN = -6,       /* non-finite floe state */
+    SP_ESTATE = -7,     /* call out of order (e.g. step before set_floes) */
+    SP_ECAPACITY = -8   /* a cell exceeds the per-cell floe or contact capacity */
+} sp_status;
+
+/* sp_params.flags */
+#define SP_OCEAN_OFF 1u       /* no drag, no drag torque */
+#define SP_FORWARD_EULER 2u   /* positions advance with the old velocities */
+#define SP_NO_CONTINUUM 4u    /* skip the coarse Lax-Friedrichs update */
+
+/* sp_params.schedule: how a cell's contact candidates are enumerated.
+ * Every schedule yields the same contact set and, because each floe sums its
+ * contacts in ascending partner index, the same floe state bit for bit. */
+#define SP_SCHED_AUTO 0       /* binned where the cell allows >= 3 bins per side */
+#define SP_SCHED_ALLPAIRS 1   /* every floe against every floe of its cell */
+#define SP_SCHED_BINNED 2     /* square sub-bins of side >= 2 r_max, 3x3 sweep */
+
+/* sp_read_moments(which) */
+#define SP_MOMENTS_DEM 0        /* [ncells][SP_NMOM] statistics of the current floe state */
+#define SP_MOMENTS_CONTINUUM 1  /* [ncells][4] continuum state Q = (rho, P_x, P_y, P_w) */
+
+/* DEM statistics per cell, in this order (FP64 sums over the cell's floes):
+ * n, M = sum m, P_x = sum m u, P_y = sum m v, L = sum I omega, U_x = sum u,
+ * U_y = sum v, S_vx, S_vy = sum of ocean drag forces, S_w = sum of drag
+ * torques, A_ice = sum pi r^2.  The continuum coefficients are U/n and the
+ * sources S/A (A = cell area); Q^0 = (M, P_x, P_y, L) / A of the initial state
+ * (Algorithm 1 initialises the coarse model from DEM data). */
+#define SP_NMOM 11
+
+#define SP_MAX_MODES 16        /* ocean Fourier modes */
+#define SP_MAX_CELL_FLOES 1024 /* floes per cell (LDS-resident cell) */
+#define SP_CONTACT_CAP 16      /* contacts per floe per step */
+
+typedef struct {
+    int32_t nx, ny;           /* coarse grid = one DEM per cell (Sec. 3.1) */
+    double cell_lx, cell_ly;  /* cell size (m); also the coarse spacing dX, dY */
+    double rho_ice;           /* ice density (kg/m^3) */
+    double rho_ocean;         /* ocean density (kg/m^3) */
+    double cd;                /* ocean drag coefficient d_o */
+    double E;                 /* normal stiffness per unit chord length (N/m^2) */
+    double G;                 /* tangential viscous coefficient per unit chord (N s/m^2) */
+    double mu;                /* Coulomb friction coefficient */
+    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER | SP_NO_CONTINUUM */
+    int32_t schedule;         /* SP_SCHED_* */
+} sp_params;
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t the
+ * caller owns (e.g. torch.cuda.current_stream().cuda_stream) or NULL, in which
+ * case the context creates its own default-priority stream.
+ * Errors: SP_EINVAL (null out, nx/ny < 1, non-positive sizes or constants),
+ * SP_EDEVICE. */
+sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out);
+
+/* Release every device buffer the context owns.  NULL is ignored. */
+void sp_destroy(sp_ctx* ctx);
+
+/* Message of the last failing call on this context (never NULL). */
+const char* sp_last_error(const sp_ctx* ctx);
+
+/* Prescribed ocean current (Sec. 2.1).  Host arrays of nmodes doubles, copied.
+ * 0 <= nmodes <= SP_MAX_MODES.  May be called before or after sp_set_floes.
+ * Errors: SP_EINVAL. */
+sp_status sp_set_ocean(sp_ctx* ctx, double u0, double v0, int32_t nmodes, const double* kx,
+                       const double* ky, const double* au, const double* av, const double* phase);
+
+/* Floe state from host arrays (copied).  counts[ncells] floes per cell,
+ * sum(counts) = n; per-floe arrays of length n sorted by cell.  omega and theta
+ * may be NULL (zero).  Resets the continuum to the statistics of this state.
+ * Errors: SP_EINVAL (sizes, r <= 0, h <= 0, r_max >= min(cell_lx, cell_ly)/4),
+ * SP_ECAPACITY (a cell above SP_MAX_CELL_FLOES), SP_ENOMEM, SP_EDEVICE. */
+sp_status sp_set_floes(sp_ctx* ctx, int64_t n, const int32_t* counts, const uint32_t* xi,
+                       const uint32_t* yi, const float* u, const float* v, const float* omega,
+                       const float* theta, const float* r, const float* h);
+
+/* The same from device buffers (e.g. torch tensors), copied on the stream;
+ * counts stays a host array.  Synchronises (radius validation). */
+sp_status sp_set_floes_device(sp_ctx* ctx, int64_t n, const int32_t* counts, const void* xi,
+                              const void* yi, const void* u, const void* v, const void* omega,
+                              const void* theta, const void* r, const void* h);
+
+/* Advance nsteps fine steps of size dt (s): each step is one DEM step of every
+ * cell fused with the statistics of the pre-step state, then (unless
+ * SP_NO_CONTINUUM) one Lax-Friedrichs step of the continuum driven by those
+ * statistics (coarse step = fine step, N0 = N1 = 1 in Algorithm 1).
+ * Asynchronous.  Errors: SP_EINVAL (dt <= 0, nsteps < 0), SP_ESTATE. */
+sp_status sp_step(sp_ctx* ctx, double dt, int64_t nsteps);
+
+/* Block until the stream is idle; returns the first latched device fault. */
+sp_status sp_synchronize(sp_ctx* ctx);
+
+/* Copy moments to a caller-owned host array: [ncells][SP_NMOM] for
+ * SP_MOMENTS_DEM (statistics of the current state, drag at the current
+ * state) or [ncells][4] for SP_MOMENTS_CONTINUUM.  Synchronises. */
+sp_status sp_read_moments(sp_ctx* ctx, int32_t which, double* out);
+
+/* Copy the floe state to caller-owned host arrays of length n (any may be NULL).
+ * Synchronises. */
+sp_status sp_read_floes(sp_ctx* ctx, uint32_t* xi, uint32_t* yi, float* u, float* v,
+                        float* omega, float* theta, float* r);
+
+/* Contact pairs of the current state as global floe indices l < j, sorted by
+ * (l, j); writes min(count, cap) pairs and sets *count.  Debug/test call: the
+ * decision is the one the step kernels take.  Synchronises. */
+sp_status sp_read_pairs(sp_ctx* ctx, int64_t cap, int32_t* l, int32_t* j, int64_t* count);
+
+/* Counters since the last sp_set_floes: contacts summed over steps and floe
+ * pairs (each pair counted once), steps taken, and the largest continuum CFL
+ * number seen.  Synchronises. */
+sp_status sp_get_stats(sp_ctx* ctx, int64_t* contacts, int64_t* steps, double* max_cfl);
+
+/* Run nsteps steps like sp_step, with HIP events recorded on the context's
+ * stream around every kernel, and return the mean duration (ms) of the DEM
+ * cell kernel and of the continuum kernel (0 if skipped).  For measurement and
+ * schedule tuning; the state advances exactly as with sp_step.  Synchronises. */
+sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_ms, double* lf_ms);
+
+/* Schedule actually used for the current floes (after SP_SCHED_AUTO), and the
+ * sub-bins per side it uses (1 for all-pairs). */
+sp_status sp_get_schedule(sp_ctx* ctx, int32_t* schedule, int32_t* bins_x, int32_t* bins_y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPDEM_H */

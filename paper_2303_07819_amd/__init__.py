@@ -1,0 +1,211 @@
+"""spdem: superparameterised sea-ice floe DEM on MI355X.
+
+Thin Python binding over the C ABI of ``libspdem.so`` (declared in
+``include/spdem.h``): argument marshalling only, every step of the path runs in
+the HIP kernels.  There is no CPU fallback: importing the binding without the
+built library raises.
+
+Method: Deng, Stechmann & Chen, "Particle-continuum multiscale modeling of sea
+ice floes" (one doubly periodic disk-floe DEM per coarse cell, Sec. 3.1; DEM of
+Sec. 2.1; moment equations of Sec. 2.3 advanced by Lax-Friedrichs, Sec. 3.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspdem.so")
+
+SP_OCEAN_OFF = 1
+SP_FORWARD_EULER = 2
+SP_NO_CONTINUUM = 4
+SCHED_AUTO, SCHED_ALLPAIRS, SCHED_BINNED = 0, 1, 2
+MOMENTS_DEM, MOMENTS_CONTINUUM = 0, 1
+NMOM = 11
+STATUS = {0: "SP_OK", -1: "SP_EINVAL", -2: "SP_ENOMEM", -3: "SP_EDEVICE", -4: "SP_ECFL",
+          -5: "SP_EOVERLAP", -6: "SP_ENAN", -7: "SP_ESTATE", -8: "SP_ECAPACITY"}
+
+EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_floes",
+            "sp_set_floes_device", "sp_step", "sp_synchronize", "sp_read_moments", "sp_read_floes",
+            "sp_read_pairs", "sp_get_stats", "sp_get_schedule", "sp_profile_steps"]
+
+
+class SpdemError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("cell_lx", ctypes.c_double), ("cell_ly", ctypes.c_double),
+                ("rho_ice", ctypes.c_double), ("rho_ocean", ctypes.c_double),
+                ("cd", ctypes.c_double), ("E", ctypes.c_double), ("G", ctypes.c_double),
+                ("mu", ctypes.c_double), ("flags", ctypes.c_uint32), ("schedule", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspdem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2303_07819_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.sp_create.argtypes = [ctypes.POINTER(_Params), P, ctypes.POINTER(P)]
+    lib.sp_destroy.argtypes = [P]
+    lib.sp_destroy.restype = None
+    lib.sp_last_error.argtypes = [P]
+    lib.sp_last_error.restype = ctypes.c_char_p
+    lib.sp_set_ocean.argtypes = [P, D, D, I32, P, P, P, P, P]
+    lib.sp_set_floes.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
+    lib.sp_set_floes_device.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
+    lib.sp_step.argtypes = [P, D, I64]
+    lib.sp_synchronize.argtypes = [P]
+    lib.sp_read_moments.argtypes = [P, I32, P]
+    lib.sp_read_floes.argtypes = [P, P, P, P, P, P, P, P]
+    lib.sp_read_pairs.argtypes = [P, I64, P, P, ctypes.POINTER(I64)]
+    lib.sp_get_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(D)]
+    lib.sp_profile_steps.argtypes = [P, D, I64, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    for name in EXPORTED:
+        fn = getattr(lib, name)
+        if name not in ("sp_destroy", "sp_last_error"):
+            fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(int(a.data_ptr()))    # torch tensor on the device
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dt)
+
+
+class Sim:
+    """One superparameterised DEM (one context of the C library)."""
+
+    def __init__(self, nx, ny, cell_lx, cell_ly, rho_ice, rho_ocean, cd, E, G, mu,
+                 flags: int = 0, schedule: int = SCHED_AUTO, stream=None):
+        self._lib = load_library()
+        self.nx, self.ny = int(nx), int(ny)
+        self.ncells = self.nx * self.ny
+        self.n = 0
+        prm = _Params(self.nx, self.ny, cell_lx, cell_ly, rho_ice, rho_ocean, cd, E, G, mu,
+                      flags, schedule)
+        h = ctypes.c_void_p()
+        st = self._lib.sp_create(ctypes.byref(prm), None if stream is None else ctypes.c_void_p(stream),
+                                 ctypes.byref(h))
+        if st != 0:
+            raise SpdemError(st, "sp_create failed")
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, flags: int = 0, schedule: int = SCHED_AUTO, stream=None) -> "Sim":
+        """Context for a workload object (grid, constants, ocean and floes)."""
+        s = cls(w.nx, w.ny, w.Lx, w.Ly, w.rho_ice, w.rho_ocean, w.cd, w.E, w.G, w.mu,
+                flags, schedule, stream)
+        oc = w.ocean
+        s.set_ocean(oc.u0, oc.v0, oc.kx, oc.ky, oc.au, oc.av, oc.phase)
+        s.set_floes(w.counts, w.xi, w.yi, w.u, w.v, w.omega, w.theta, w.r, w.h)
+        return s
+
+    def _check(self, st):
+        if st != 0:
+            raise SpdemError(st, self._lib.sp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ ABI
+    def set_ocean(self, u0, v0, kx, ky, au, av, phase):
+        arrs = [_c(a, np.float64) for a in (kx, ky, au, av, phase)]
+        self._check(self._lib.sp_set_ocean(self._h, float(u0), float(v0), int(arrs[0].size),
+                                           *[_p(a) for a in arrs]))
+
+    def set_floes(self, counts, xi, yi, u, v, omega, theta, r, h):
+        counts = _c(counts, np.int32)
+        arrs = [_c(xi, np.uint32), _c(yi, np.uint32)] + [_c(a, np.float32) for a in (u, v, omega, theta, r, h)]
+        self.n = int(arrs[0].size)
+        self._check(self._lib.sp_set_floes(self._h, self.n, _p(counts), *[_p(a) for a in arrs]))
+
+    def set_floes_device(self, counts, xi, yi, u, v, omega, theta, r, h):
+        """Device tensors (torch, contiguous, 4-byte elements) are copied on the stream."""
+        counts = _c(counts, np.int32)
+        self.n = int(xi.numel())
+        self._check(self._lib.sp_set_floes_device(self._h, self.n, _p(counts),
+                                                  *[_p(a) for a in (xi, yi, u, v, omega, theta, r, h)]))
+
+    def step(self, dt: float, nsteps: int = 1):
+        self._check(self._lib.sp_step(self._h, float(dt), int(nsteps)))
+
+    def synchronize(self):
+        self._check(self._lib.sp_synchronize(self._h))
+
+    def read_moments(self, which: int = MOMENTS_DEM) -> np.ndarray:
+        k = NMOM if which == MOMENTS_DEM else 4
+        out = np.zeros((self.ncells, k), np.float64)
+        self._check(self._lib.sp_read_moments(self._h, int(which), _p(out)))
+        return out
+
+    def read_floes(self) -> dict:
+        n = self.n
+        out = dict(xi=np.zeros(n, np.uint32), yi=np.zeros(n, np.uint32), u=np.zeros(n, np.float32),
+                   v=np.zeros(n, np.float32), omega=np.zeros(n, np.float32),
+                   theta=np.zeros(n, np.float32), r=np.zeros(n, np.float32))
+        self._check(self._lib.sp_read_floes(self._h, *[_p(out[k]) for k in
+                                                       ("xi", "yi", "u", "v", "omega", "theta", "r")]))
+        return out
+
+    def read_pairs(self) -> np.ndarray:
+        cnt = ctypes.c_int64(0)
+        self._check(self._lib.sp_read_pairs(self._h, 0, None, None, ctypes.byref(cnt)))
+        cap = int(cnt.value)
+        l = np.zeros(max(cap, 1), np.int32)
+        j = np.zeros(max(cap, 1), np.int32)
+        self._check(self._lib.sp_read_pairs(self._h, cap, _p(l), _p(j), ctypes.byref(cnt)))
+        return np.stack([l[:cap], j[:cap]], axis=1)
+
+    def stats(self) -> dict:
+        c, s, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        self._check(self._lib.sp_get_stats(self._h, ctypes.byref(c), ctypes.byref(s), ctypes.byref(m)))
+        return dict(contacts=int(c.value), steps=int(s.value), max_cfl=float(m.value))
+
+    def profile_steps(self, dt: float, nsteps: int):
+        """Advance like step() and return the mean (dem_ms, lf_ms) kernel durations."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.sp_profile_steps(self._h, float(dt), int(nsteps), ctypes.byref(a),
+                                               ctypes.byref(b)))
+        return float(a.value), float(b.value)
+
+    def schedule(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.sp_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return int(a.value), int(b.value), int(c.value)

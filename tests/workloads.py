@@ -1,0 +1,28 @@
+"""Contact-heavy test workloads (seeded) shared by the CPU and GPU tests."""
+import numpy as np
+
+import fixtures
+
+
+def dense_workload(seed=11, nx=3, ny=2, n=256, vel=0.2):
+    """Benchmark-style cells with random initial velocities and spins, so that
+    many contacts form within a few steps."""
+    w = fixtures.custom(nx, ny, 25e3, n, seed=seed, r_scale=fixtures.radius_scale(n, 25e3 ** 2))
+    rng = np.random.default_rng(seed)
+    w.u[:] = rng.normal(0, vel, w.nfloes)
+    w.v[:] = rng.normal(0, vel, w.nfloes)
+    w.omega[:] = rng.normal(0, 1e-4, w.nfloes)
+    w.theta[:] = rng.uniform(0, 6.28, w.nfloes)
+    return w
+
+
+def ragged_workload(seed=5):
+    """Empty, single-floe, partial-wave and multi-floe-per-lane cells."""
+    rng = np.random.default_rng(seed)
+    nx, ny = 5, 3
+    counts = rng.integers(0, 700, nx * ny)
+    counts[0], counts[1], counts[2], counts[3] = 0, 1, 64, 257
+    w = fixtures.custom(nx, ny, 25e3, counts, seed=seed, r_scale=fixtures.radius_scale(700, 25e3 ** 2))
+    w.u[:] = rng.normal(0, 0.2, w.nfloes)
+    w.v[:] = rng.normal(0, 0.2, w.nfloes)
+    return w
