@@ -47,7 +47,7 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMomStride = 12;          // doubles per cell in the statistics buffer
+constexpr int kMomStride = 16;          // doubles per cell in the statistics buffer (128 B)
 constexpr int kListCap = SP_CONTACT_CAP;
 constexpr int kMaxBinsSide = 32;
 constexpr double kPi = 3.14159265358979323846;
@@ -60,7 +60,7 @@ constexpr uint32_t kErrNaN = 2u;
 constexpr uint32_t kErrCFL = 4u;
 constexpr uint32_t kErrCapacity = 8u;
 
-enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE };
+enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE, M_UBAR, M_VBAR };
 
 struct Modes {
     float kxL[SP_MAX_MODES];  // kx * Lx: phase per cell fraction
@@ -180,16 +180,97 @@ __device__ void block_exclusive_scan(const int* cnt, int* start, int nb, int* ws
     __syncthreads();
 }
 
+// sin and cos of a moderate FP32 argument: Cody-Waite reduction by pi/2 and
+// Taylor polynomials on [-pi/4, pi/4] (truncation below 2e-9).
+__device__ __forceinline__ void sincos_small(float x, float& s, float& c)
+{
+    const float k = rintf(x * 0.63661977236758134f);
+    float r = fmaf(-k, 1.57079637050628662109375f, x);
+    r = fmaf(k, 4.37113900018624283e-8f, r);
+    const float r2 = r * r;
+    float sp = fmaf(r2, 2.7557319224e-6f, -1.9841269841e-4f);
+    sp = fmaf(r2, sp, 8.3333333333e-3f);
+    sp = fmaf(r2, sp, -1.6666666667e-1f);
+    const float sr = fmaf(r * r2, sp, r);
+    float cp = fmaf(r2, -2.7557319224e-7f, 2.4801587302e-5f);
+    cp = fmaf(r2, cp, -1.3888888889e-3f);
+    cp = fmaf(r2, cp, 4.1666666667e-2f);
+    cp = fmaf(r2, cp, -0.5f);
+    const float cr = fmaf(r2, cp, 1.0f);
+    const int q = (int)k;
+    const float s1 = (q & 1) ? cr : sr;
+    const float c1 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s1 : s1;
+    c = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// Sum over a row of 16 lanes with DPP row shifts (deterministic order); the
+// row total lands in the row's last lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row_sum(double x)
+{
+    x += dpp_shr<0x111>(x);   // row_shr:1
+    x += dpp_shr<0x112>(x);   // row_shr:2
+    x += dpp_shr<0x114>(x);   // row_shr:4
+    x += dpp_shr<0x118>(x);   // row_shr:8
+    return x;
+}
+
 // ------------------------------------------------------------ cell kernel
-// SCHED: 1 all pairs, 2 binned.  STEP: false = statistics of the current
-// state only (no contacts, no update).
+// Statistics reduced by every step.  n, M and A_ice depend only on the radii
+// and thicknesses; the statistics kernel writes them when the floes are set.
+constexpr int kDyn = 8;
+__device__ __forceinline__ int dyn_slot(int k)
+{
+    return k < 3 ? M_PX + k : M_UX + (k - 3);   // Px Py L | Ux Uy Svx Svy Sw
+}
+
+// Append partner index `who` to the contact list of floe `to`.
+__device__ __forceinline__ void list_append(uint16_t* lst, int* cnt, int to, int who)
+{
+    const int slot = atomicAdd(&cnt[to], 1);
+    if (slot < kListCap) lst[(size_t)to * kListCap + slot] = (uint16_t)who;
+}
+
+// Screen the candidates q in [q0, q1) of the sorted copy against floe o; the
+// next candidate is loaded while the current one is screened.
+__device__ __forceinline__ void sweep(const uint4* S, int q0, int q1, uint32_t xl, uint32_t yl,
+                                     float rl, int o, uint16_t* lst, int* cnt, const StepArgs& a)
+{
+    if (q0 >= q1) return;
+    uint4 pj = S[q0];
+    for (int q = q0; q < q1; ++q) {
+        const uint4 nxt = S[min(q + 1, q1 - 1)];
+        float diff, R2;
+        screen((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a.qx, a.qy, diff, R2);
+        if (diff < kGuard * R2) {
+            const int o2 = (int)(pj.w & 0xffffu);
+            list_append(lst, cnt, o, o2);
+            list_append(lst, cnt, o2, o);
+        }
+        pj = nxt;
+    }
+}
+
+// SCHED: 1 all pairs, 2 binned half shell.  STEP: false = statistics of the
+// current state only (no contacts, no update, all 11 statistics).
 template <int SCHED, bool STEP>
 __global__ __launch_bounds__(kBlock) void dem_cell_kernel(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kBlock / 64][SP_NMOM];
+    __shared__ double red11[SP_NMOM][kBlock / 16];
     __shared__ int wsum[kBlock / 64];
     __shared__ unsigned long long csum[kBlock / 64];
+
+    __shared__ float4 mode_k[SP_MAX_MODES];   // kx Lx, ky Ly, au, av
+    __shared__ float4 mode_c[SP_MAX_MODES];   // curl coefficient, sin and cos of the centre phase, -
 
     const int c = blockIdx.x;
     const int tid = threadIdx.x;
@@ -197,11 +278,19 @@ __global__ __launch_bounds__(kBlock) void dem_cell_kernel(StepArgs a)
     const int n = a.cell_start[c + 1] - s;
     const int cap = a.cap;
 
+    if (tid < a.nmodes) {
+        const float2 sc = a.phase[(size_t)c * a.nmodes + tid];
+        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
+        mode_c[tid] = make_float4(a.modes.cz[tid], sc.x, sc.y, 0.0f);
+    }
+    if (!STEP) __syncthreads();
+
     uint4* P = reinterpret_cast<uint4*>(smem);                // xi, yi, r bits, -
     float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, -
-    uint4* S = reinterpret_cast<uint4*>(V + cap);             // binned copy: xi, yi, r bits, index
+    uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy: xi, yi, r bits, index | bin << 16
     uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));  // [cap][kListCap]
-    int* binof = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
+    int* cnt = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
+    int* binof = cnt + cap;
     int* rank = binof + (SCHED == 2 ? cap : 0);
     int* bcnt = rank + (SCHED == 2 ? cap : 0);
     int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
@@ -210,15 +299,16 @@ __global__ __launch_bounds__(kBlock) void dem_cell_kernel(StepArgs a)
         for (int i = tid; i < n; i += kBlock) {
             P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), 0u);
             V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], 0.0f);
+            cnt[i] = 0;
         }
         if (SCHED == 2) {
             const int nb = a.nbx * a.nby;
             for (int b = tid; b < nb; b += kBlock) bcnt[b] = 0;
             __syncthreads();
             for (int i = tid; i < n; i += kBlock) {
-                int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
-                int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
-                int b = by * a.nbx + bx;
+                const int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
+                const int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
+                const int b = by * a.nbx + bx;
                 binof[i] = b;
                 rank[i] = atomicAdd(&bcnt[b], 1);
             }
@@ -226,8 +316,71 @@ __global__ __launch_bounds__(kBlock) void dem_cell_kernel(StepArgs a)
             block_exclusive_scan(bcnt, bstart, nb, wsum);
             for (int i = tid; i < n; i += kBlock) {
                 uint4 p = P[i];
-                p.w = (uint32_t)i;
+                p.w = (uint32_t)i | ((uint32_t)binof[i] << 16);
                 S[bstart[binof[i]] + rank[i]] = p;
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 1: contact candidates -> per-floe lists
+        if (SCHED == 1) {
+            // every floe against every floe (itself included, skipped later);
+            // the list comes out in ascending partner order
+            for (int l = tid; l < n; l += kBlock) {
+                const uint4 pl = P[l];
+                const float rl = __uint_as_float(pl.z);
+                uint16_t* my = lst + (size_t)l * kListCap;
+                int k = 0;
+                for (int j = 0; j < n; ++j) {
+                    const uint4 pj = P[j];
+                    float diff, R2;
+                    screen((int)(pj.x - pl.x), (int)(pj.y - pl.y), rl, __uint_as_float(pj.z), a.qx,
+                           a.qy, diff, R2);
+                    if (diff < kGuard * R2) {
+                        if (k < kListCap) my[k] = (uint16_t)j;
+                        ++k;
+                    }
+                }
+                cnt[l] = k;
+            }
+        } else {
+            // half shell over the bin-sorted copy: lanes take consecutive sorted
+            // floes (neighbouring lanes share their neighbourhood); each pair is
+            // screened once, from the bin whose offset to the other is in
+            // {own bin (later sorted index), E, NW, N, NE}, and appended to both lists
+            for (int t = tid; t < n; t += kBlock) {
+                const uint4 own = S[t];
+                const int o = (int)(own.w & 0xffffu);
+                const int b = (int)(own.w >> 16);
+                const int bx = b % a.nbx, by = b / a.nbx;
+                const float rl = __uint_as_float(own.z);
+                if (a.nbx >= 3 && bx + 1 < a.nbx) {
+                    // own-bin tail and the east bin are contiguous
+                    sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
+                } else {
+                    sweep(S, t + 1, bstart[b + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    if (a.nbx >= 3) {
+                        const int be = by * a.nbx;   // east neighbour across the seam
+                        sweep(S, bstart[be], bstart[be + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    }
+                }
+                if (a.nby >= 3) {
+                    const int row = (by + 1 == a.nby ? 0 : by + 1) * a.nbx;
+                    if (a.nbx < 3) {
+                        sweep(S, bstart[row], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                    } else if (bx == 0) {
+                        sweep(S, bstart[row], bstart[row + 2], own.x, own.y, rl, o, lst, cnt, a);
+                        sweep(S, bstart[row + a.nbx - 1], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    } else if (bx == a.nbx - 1) {
+                        sweep(S, bstart[row + a.nbx - 2], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                        sweep(S, bstart[row], bstart[row + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    } else {
+                        sweep(S, bstart[row + bx - 1], bstart[row + bx + 2], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -239,208 +392,209 @@ __global__ __launch_bounds__(kBlock) void dem_cell_kernel(StepArgs a)
     unsigned long long ncontact = 0;
 
     for (int l = tid; l < n; l += kBlock) {
-        const uint32_t xl = a.xi[s + l], yl = a.yi[s + l];
-        const float rl = a.r[s + l], hl = a.h[s + l];
-        const float ul = a.u[s + l], vl = a.v[s + l], wl = a.w[s + l];
+        uint32_t xl, yl;
+        float rl, ul, vl, wl;
+        if (STEP) {
+            const uint4 pl = P[l];
+            const float4 vv = V[l];
+            xl = pl.x;
+            yl = pl.y;
+            rl = __uint_as_float(pl.z);
+            ul = vv.x;
+            vl = vv.y;
+            wl = vv.z;
+        } else {
+            xl = a.xi[s + l];
+            yl = a.yi[s + l];
+            rl = a.r[s + l];
+            ul = a.u[s + l];
+            vl = a.v[s + l];
+            wl = a.w[s + l];
+        }
 
         // ---- ocean current and curl at the floe centre (angle addition around
         // the cell centre keeps the FP32 arguments below (|kx| Lx + |ky| Ly) / 2),
         // then drag and drag torque in FP64
+        const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
         double fdx = 0.0, fdy = 0.0, tdr = 0.0;
         if (!(a.flags & SP_OCEAN_OFF)) {
             const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
             const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
             float uo = a.u0, vo = a.v0, zeta = 0.0f;
-            const float2* cs = a.phase + (size_t)c * a.nmodes;
+#pragma unroll 2
             for (int m = 0; m < a.nmodes; ++m) {
-                const float dth = a.modes.kxL[m] * fx + a.modes.kyL[m] * fy;
+                const float4 mk = mode_k[m];
+                const float4 mc = mode_c[m];
+                const float dth = mk.x * fx + mk.y * fy;
                 float sd, cd;
-                sincosf(dth, &sd, &cd);
-                const float2 sc = cs[m];                   // (sin, cos) of the centre phase
-                const float sn = sc.x * cd + sc.y * sd;
-                const float cn = sc.y * cd - sc.x * sd;
-                uo += a.modes.au[m] * sn;
-                vo += a.modes.av[m] * sn;
-                zeta += a.modes.cz[m] * cn;
+                sincos_small(dth, sd, cd);
+                const float sn = mc.y * cd + mc.z * sd;    // sin and cos of the full phase
+                const float cn = mc.z * cd - mc.y * sd;
+                uo += mk.z * sn;
+                vo += mk.w * sn;
+                zeta += mc.x * cn;
             }
-            const double du = (double)uo - (double)ul, dv = (double)vo - (double)vl;
+            const double du = (double)uo - uld, dv = (double)vo - vld;
             const double sp = sqrt(du * du + dv * dv);
-            const double rd = (double)rl;
-            const double alpha = a.cdrho * kPi * rd * rd;
+            const double alpha = a.cdrho * kPi * rld * rld;
             fdx = alpha * du * sp;
             fdy = alpha * dv * sp;
-            const double dW = 0.5 * (double)zeta - (double)wl;
-            const double r2 = rd * rd;
-            const double beta = a.cdrho * kPi * r2 * r2 * rd;
+            const double dW = 0.5 * (double)zeta - wld;
+            const double r2 = rld * rld;
+            const double beta = a.cdrho * kPi * r2 * r2 * rld;
             tdr = beta * dW * fabs(dW);
+        }
+        const double hld = (double)a.h[s + l];
+        const double md = a.rho_ice_d * hld * kPi * rld * rld;
+
+        if (STEP) {
+            uint16_t* my = lst + (size_t)l * kListCap;
+            int k = cnt[l];
+            if (k > kListCap) {
+                atomicOr(a.err, kErrCapacity);
+                k = kListCap;
+            }
+            if (SCHED == 2) {
+                // ascending partner order: insertion sort of the short list
+                for (int i = 1; i < k; ++i) {
+                    const uint16_t key = my[i];
+                    int j = i - 1;
+                    while (j >= 0 && my[j] > key) {
+                        my[j + 1] = my[j];
+                        --j;
+                    }
+                    my[j + 1] = key;
+                }
+            }
+
+            // ---- phase 2: contact forces and torques in ascending partner order (FP64)
+            double Fx = fdx, Fy = fdy, T = tdr;
+            for (int q = 0; q < k; ++q) {
+                const int j = my[q];
+                if (j == l) continue;
+                const uint4 pj = P[j];
+                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
+                const float rj = __uint_as_float(pj.z);
+                if (!decide(dxi, dyi, rl, rj, a)) continue;
+                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
+                const double d2 = dx * dx + dy * dy;
+                if (!(d2 > 0.0)) {
+                    atomicOr(a.err, kErrOverlap);
+                    continue;
+                }
+                const double rjd = (double)rj;
+                const double d = sqrt(d2);
+                const double inv_d = 1.0 / d;
+                const double nx = dx * inv_d, ny = dy * inv_d;
+                const double tx = -ny, ty = nx;
+                const double R = rld + rjd;
+                const double delta = d - R;
+                const double dr = fabs(rld - rjd);
+                double cc;
+                if (d <= dr) {
+                    cc = 2.0 * fmin(rld, rjd);
+                } else {
+                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
+                    cc = sqrt(fmax(p, 0.0)) * inv_d;
+                }
+                const double Fn = cc * a.Ed * delta;
+                const float4 vj = V[j];
+                const double wjd = (double)vj.z;
+                // spin sum in a fixed operand order (lower floe index first) so that
+                // the pair forces are exactly antisymmetric
+                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
+                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
+                const double capf = a.mud * fabs(Fn);
+                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+                Fx += Fn * nx + Ft * tx;
+                Fy += Fn * ny + Ft * ty;
+                T += rld * Ft;
+                ncontact += (l < j) ? 1ull : 0ull;
+            }
+
+            // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
+            // FP32 / fixed-point storage
+            const double inv_m = 1.0 / md;
+            const double dt = a.dtd;
+            const double und = uld + dt * (Fx * inv_m);
+            const double vnd = vld + dt * (Fy * inv_m);
+            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
+            const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
+            const int sx = __double2int_rn(dt * ux * a.inv_qxd);
+            const int sy = __double2int_rn(dt * vx * a.inv_qyd);
+            const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
+            a.xi[s + l] = xl + (uint32_t)sx;
+            a.yi[s + l] = yl + (uint32_t)sy;
+            a.u[s + l] = un;
+            a.v[s + l] = vn;
+            a.w[s + l] = wn;
+            a.th[s + l] = (float)((double)a.th[s + l] + dt * wx);
+            if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
+        } else {
+            acc[M_N] += 1.0;
+            acc[M_MASS] += md;
+            acc[M_AICE] += kPi * rld * rld;
         }
 
         // ---- cell statistics of the pre-step state (FP64)
-        {
-            const double rd = (double)rl;
-            const double md = a.rho_ice_d * (double)hl * kPi * rd * rd;
-            acc[M_N] += 1.0;
-            acc[M_MASS] += md;
-            acc[M_PX] += md * (double)ul;
-            acc[M_PY] += md * (double)vl;
-            acc[M_L] += md * rd * rd * (double)wl;
-            acc[M_UX] += (double)ul;
-            acc[M_UY] += (double)vl;
-            acc[M_SVX] += fdx;
-            acc[M_SVY] += fdy;
-            acc[M_SW] += tdr;
-            acc[M_AICE] += kPi * rd * rd;
-        }
-        if (!STEP) continue;
-
-        // ---- phase 1: candidates -> per-floe list (includes the floe itself)
-        uint16_t* my = lst + (size_t)l * kListCap;
-        int k = 0;
-        if (SCHED == 1) {
-            for (int j = 0; j < n; ++j) {
-                const uint4 pj = P[j];
-                float diff, R2;
-                screen((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a.qx, a.qy,
-                       diff, R2);
-                if (diff < kGuard * R2) {
-                    if (k < kListCap) my[k] = (uint16_t)j;
-                    ++k;
-                }
-            }
-        } else {
-            const int bx = (int)__umulhi(xl, (uint32_t)a.nbx);
-            const int by = (int)__umulhi(yl, (uint32_t)a.nby);
-            const int ox0 = a.nbx >= 3 ? -1 : 0, ox1 = a.nbx >= 3 ? 1 : 0;
-            const int oy0 = a.nby >= 3 ? -1 : 0, oy1 = a.nby >= 3 ? 1 : 0;
-            for (int oy = oy0; oy <= oy1; ++oy) {
-                int yy = by + oy;
-                yy += yy < 0 ? a.nby : 0;
-                yy -= yy >= a.nby ? a.nby : 0;
-                for (int ox = ox0; ox <= ox1; ++ox) {
-                    int xx = bx + ox;
-                    xx += xx < 0 ? a.nbx : 0;
-                    xx -= xx >= a.nbx ? a.nbx : 0;
-                    const int b = yy * a.nbx + xx;
-                    const int e = bstart[b + 1];
-                    for (int q = bstart[b]; q < e; ++q) {
-                        const uint4 pj = S[q];
-                        float diff, R2;
-                        screen((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z),
-                               a.qx, a.qy, diff, R2);
-                        if (diff < kGuard * R2) {
-                            if (k < kListCap) my[k] = (uint16_t)pj.w;
-                            ++k;
-                        }
-                    }
-                }
-            }
-        }
-        if (k > kListCap) {
-            atomicOr(a.err, kErrCapacity);
-            k = kListCap;
-        }
-        if (SCHED == 2) {
-            // ascending partner order: insertion sort of the short list
-            for (int i = 1; i < k; ++i) {
-                uint16_t key = my[i];
-                int j = i - 1;
-                while (j >= 0 && my[j] > key) {
-                    my[j + 1] = my[j];
-                    --j;
-                }
-                my[j + 1] = key;
-            }
-        }
-
-        // ---- phase 2: contact forces and torques in ascending partner order (FP64)
-        double Fx = fdx, Fy = fdy, T = tdr;
-        const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
-        for (int q = 0; q < k; ++q) {
-            const int j = my[q];
-            if (j == l) continue;
-            const uint4 pj = P[j];
-            const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
-            const float rj = __uint_as_float(pj.z);
-            if (!decide(dxi, dyi, rl, rj, a)) continue;
-            const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
-            const double d2 = dx * dx + dy * dy;
-            if (!(d2 > 0.0)) {
-                atomicOr(a.err, kErrOverlap);
-                continue;
-            }
-            const double rjd = (double)rj;
-            const double d = sqrt(d2);
-            const double inv_d = 1.0 / d;
-            const double nx = dx * inv_d, ny = dy * inv_d;
-            const double tx = -ny, ty = nx;
-            const double R = rld + rjd;
-            const double delta = d - R;
-            const double dr = fabs(rld - rjd);
-            double cc;
-            if (d <= dr) {
-                cc = 2.0 * fmin(rld, rjd);
-            } else {
-                const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
-                cc = sqrt(fmax(p, 0.0)) * inv_d;
-            }
-            const double Fn = cc * a.Ed * delta;
-            const float4 vj = V[j];
-            const double wjd = (double)vj.z;
-            // spin sum in a fixed operand order (lower floe index first) so that the
-            // pair forces are exactly antisymmetric
-            const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
-            const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
-            const double capf = a.mud * fabs(Fn);
-            const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
-            Fx += Fn * nx + Ft * tx;
-            Fy += Fn * ny + Ft * ty;
-            T += rld * Ft;
-            ncontact += (l < j) ? 1ull : 0ull;
-        }
-
-        // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
-        // FP32 / fixed-point storage
-        const double m = a.rho_ice_d * (double)hl * kPi * rld * rld;
-        const double I = m * rld * rld;
-        const double dt = a.dtd;
-        const double und = uld + dt * (Fx / m);
-        const double vnd = vld + dt * (Fy / m);
-        const double wnd = wld + dt * (T / I);
-        const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
-        const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
-        const int sx = __double2int_rn(dt * ux * a.inv_qxd);
-        const int sy = __double2int_rn(dt * vx * a.inv_qyd);
-        const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
-        a.xi[s + l] = xl + (uint32_t)sx;
-        a.yi[s + l] = yl + (uint32_t)sy;
-        a.u[s + l] = un;
-        a.v[s + l] = vn;
-        a.w[s + l] = wn;
-        a.th[s + l] = (float)((double)a.th[s + l] + dt * wx);
-        if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
+        acc[M_PX] += md * uld;
+        acc[M_PY] += md * vld;
+        acc[M_L] += md * rld * rld * wld;
+        acc[M_UX] += uld;
+        acc[M_UY] += vld;
+        acc[M_SVX] += fdx;
+        acc[M_SVY] += fdy;
+        acc[M_SW] += tdr;
     }
 
-    // ---- block reduction of the statistics (fixed tree: deterministic)
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int k = 0; k < SP_NMOM; ++k) {
-        double x = wave_sum(acc[k]);
-        if (lane == 0) red[wave][k] = x;
-    }
+    const int lane = tid & 63;
     if (STEP) {
+        // ---- block reduction of the 8 step statistics through LDS: lane
+        // partials -> 16 segment sums per quantity -> DPP row sum (fixed order)
         unsigned long long cs = wave_sum_u64(ncontact);
-        if (lane == 0) csum[wave] = cs;
-    }
-    __syncthreads();
-    if (tid < SP_NMOM) {
-        double x = red[0][tid];
+        if (lane == 0) csum[tid >> 6] = cs;
+        __syncthreads();   // every lane is done with the cell's LDS data
+        double* red = reinterpret_cast<double*>(smem);     // [kDyn][kBlock]
 #pragma unroll
-        for (int q = 1; q < kBlock / 64; ++q) x += red[q][tid];
-        a.mom[(size_t)c * kMomStride + tid] = x;
-    }
-    if (STEP && tid == 0) {
-        unsigned long long cs = csum[0] + csum[1] + csum[2] + csum[3];
-        if (cs) atomicAdd(a.contacts, cs);
+        for (int k = 0; k < kDyn; ++k) red[k * kBlock + tid] = acc[dyn_slot(k)];
+        __syncthreads();
+        if (tid < kDyn * 16) {
+            const int k = tid >> 4, seg = tid & 15;
+            const double* src = red + k * kBlock + seg * 16;
+            double x = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x += src[i];
+            x = row_sum(x);
+            if (seg == 15) {
+                const int slot = dyn_slot(k);
+                a.mom[(size_t)c * kMomStride + slot] = x;
+                if (slot == M_UX || slot == M_UY)   // continuum coefficient <v> = U / n
+                    a.mom[(size_t)c * kMomStride + (slot == M_UX ? M_UBAR : M_VBAR)] =
+                        n > 0 ? x / (double)n : 0.0;
+            }
+        }
+        if (tid == 0) {
+            const unsigned long long t = csum[0] + csum[1] + csum[2] + csum[3];
+            if (t) atomicAdd(a.contacts, t);
+        }
+    } else {
+        // ---- all 11 statistics: DPP row sums, then 16 row partials per quantity
+        const int rowid = tid >> 4;
+#pragma unroll
+        for (int k = 0; k < SP_NMOM; ++k) {
+            const double x = row_sum(acc[k]);
+            if ((lane & 15) == 15) red11[k][rowid] = x;
+        }
+        __syncthreads();
+        if (tid < SP_NMOM) {
+            double x = red11[tid][0];
+#pragma unroll
+            for (int q = 1; q < kBlock / 16; ++q) x += red11[tid][q];
+            a.mom[(size_t)c * kMomStride + tid] = x;
+            if (tid == M_UX || tid == M_UY)
+                a.mom[(size_t)c * kMomStride + (tid == M_UX ? M_UBAR : M_VBAR)] = n > 0 ? x / (double)n : 0.0;
+        }
     }
 }
 
@@ -457,11 +611,10 @@ struct LfArgs {
 
 __device__ __forceinline__ double ubar(const double* mom, int c, int f)
 {
-    const double n = mom[(size_t)c * kMomStride + M_N];
-    return n > 0.0 ? mom[(size_t)c * kMomStride + f] / n : 0.0;
+    return mom[(size_t)c * kMomStride + (f == M_UX ? M_UBAR : M_VBAR)];
 }
 
-__global__ __launch_bounds__(256) void lf_kernel(LfArgs a)
+__global__ __launch_bounds__(64) void lf_kernel(LfArgs a)
 {
     const int nc = a.nx * a.ny;
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
@@ -496,17 +649,13 @@ __global__ __launch_bounds__(256) void lf_kernel(LfArgs a)
             a.Qn[(size_t)f * nc + C] = q;
         }
     }
-    // block max of the CFL number, one atomic per block
-    __shared__ double bm[4];
+    // wavefront max of the CFL number, one atomic per wavefront
     double x = cfl;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-    if ((threadIdx.x & 63) == 0) bm[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double mx = fmax(fmax(bm[0], bm[1]), fmax(bm[2], bm[3]));
-        atomicMax(a.max_cfl_bits, (unsigned long long)__double_as_longlong(mx));
-        if (mx > 1.0) atomicOr(a.err, kErrCFL);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(a.max_cfl_bits, (unsigned long long)__double_as_longlong(x));
+        if (x > 1.0) atomicOr(a.err, kErrCFL);
     }
 }
 
@@ -641,8 +790,9 @@ void free_all(sp_ctx* c)
 
 size_t lds_bytes(int sched, int cap, int nb)
 {
-    size_t b = (size_t)cap * (16 + 16 + 2 * kListCap);
+    size_t b = (size_t)cap * (16 + 16 + 2 * kListCap + 4);
     if (sched == SP_SCHED_BINNED) b += (size_t)cap * (16 + 4 + 4) + (size_t)(2 * nb + 1) * 4;
+    b = std::max(b, (size_t)kDyn * kBlock * sizeof(double));   // reduction buffer
     return (b + 15) & ~(size_t)15;
 }
 
@@ -993,7 +1143,7 @@ static sp_status sp_step_lf(sp_ctx* c, double dt)
     la.inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
     la.Q = c->Q[c->qcur];
     la.Qn = c->Q[c->qcur ^ 1];
-    hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, la);
+    hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, la);
     HIP_TRY(c, hipGetLastError());
     c->qcur ^= 1;
     return SP_OK;
