@@ -155,11 +155,38 @@ sp_status sp_read_pairs(sp_ctx* ctx, int64_t cap, int32_t* l, int32_t* j, int64_
  * number seen.  Synchronises. */
 sp_status sp_get_stats(sp_ctx* ctx, int64_t* contacts, int64_t* steps, double* max_cfl);
 
-/* Run nsteps steps like sp_step, with HIP events recorded on the context's
- * stream around every kernel, and return the mean duration (ms) of the DEM
- * cell kernel and of the continuum kernel (0 if skipped).  For measurement and
- * schedule tuning; the state advances exactly as with sp_step.  Synchronises. */
+/* Run nsteps steps like sp_step (without graph replay), with HIP events
+ * recorded on the context's stream around every step's DEM launches, and
+ * return their mean duration (ms) in *dem_ms; *lf_ms is 0 because the
+ * continuum update runs inside those launches.  The state advances exactly as
+ * with sp_step.  Synchronises. */
 sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_ms, double* lf_ms);
+
+/* Batching of cells with uneven floe counts.  Cells are grouped by count into
+ * SP_NUM_BUCKETS buckets (<= 64, <= 128, <= 256, <= 512, <= 1024 floes); each
+ * bucket is one launch per step over its cells, costliest first, with W
+ * wavefronts per cell (W = 1, 2, 4 or 8: one wavefront per small cell up to a
+ * tile of 8 wavefronts per large cell) and either grid-ordered or persistent
+ * workgroups that pull cells from a work counter.  Every choice gives the same
+ * floe state bit for bit; cell statistics agree to FP64 rounding (the
+ * reduction tree follows W).
+ * sp_get_batching: cells[b], waves[b], persistent[b] for each bucket (any may be NULL).
+ * sp_set_batching: choose waves[b] and persistent[b] (0/1) for every bucket.
+ * Errors: SP_EINVAL. */
+#define SP_NUM_BUCKETS 5
+sp_status sp_get_batching(sp_ctx* ctx, int32_t* cells, int32_t* waves, int32_t* persistent);
+sp_status sp_set_batching(sp_ctx* ctx, const int32_t* waves, const int32_t* persistent);
+
+/* Time every (waves, persistent) variant of every non-empty bucket on a scratch
+ * copy of the floe state (reps timed repetitions of two steps each, minimum
+ * kept) and keep the fastest.  The simulation state is not advanced.  *best_ms
+ * (may be NULL) receives the summed best step time of the buckets.
+ * Synchronises.  Errors: SP_EINVAL, SP_ESTATE, SP_ENOMEM, SP_EDEVICE. */
+sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
+
+/* sp_step replays runs of `chunk` steps as one captured HIP graph (default 16;
+ * 0 disables capture; must be even).  Results are identical either way. */
+sp_status sp_set_graph_chunk(sp_ctx* ctx, int32_t chunk);
 
 /* Schedule actually used for the current floes (after SP_SCHED_AUTO), and the
  * sub-bins per side it uses (1 for all-pairs). */

@@ -30,7 +30,9 @@ STATUS = {0: "SP_OK", -1: "SP_EINVAL", -2: "SP_ENOMEM", -3: "SP_EDEVICE", -4: "S
 
 EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_floes",
             "sp_set_floes_device", "sp_step", "sp_synchronize", "sp_read_moments", "sp_read_floes",
-            "sp_read_pairs", "sp_get_stats", "sp_get_schedule", "sp_profile_steps"]
+            "sp_read_pairs", "sp_get_stats", "sp_get_schedule", "sp_profile_steps",
+            "sp_get_batching", "sp_set_batching", "sp_autotune", "sp_set_graph_chunk"]
+NUM_BUCKETS = 5
 
 
 class SpdemError(RuntimeError):
@@ -74,6 +76,10 @@ def load_library(path: str = LIB_PATH):
     lib.sp_read_pairs.argtypes = [P, I64, P, P, ctypes.POINTER(I64)]
     lib.sp_get_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(D)]
     lib.sp_profile_steps.argtypes = [P, D, I64, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.sp_get_batching.argtypes = [P, P, P, P]
+    lib.sp_set_batching.argtypes = [P, P, P]
+    lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
+    lib.sp_set_graph_chunk.argtypes = [P, I32]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
     for name in EXPORTED:
         fn = getattr(lib, name)
@@ -204,6 +210,27 @@ class Sim:
         self._check(self._lib.sp_profile_steps(self._h, float(dt), int(nsteps), ctypes.byref(a),
                                                ctypes.byref(b)))
         return float(a.value), float(b.value)
+
+    def batching(self):
+        """(cells, waves, persistent) per count bucket."""
+        c = np.zeros(NUM_BUCKETS, np.int32)
+        w = np.zeros(NUM_BUCKETS, np.int32)
+        q = np.zeros(NUM_BUCKETS, np.int32)
+        self._check(self._lib.sp_get_batching(self._h, _p(c), _p(w), _p(q)))
+        return c, w, q
+
+    def set_batching(self, waves, persistent):
+        w = _c(waves, np.int32)
+        q = _c(persistent, np.int32)
+        self._check(self._lib.sp_set_batching(self._h, _p(w), _p(q)))
+
+    def autotune(self, dt: float, reps: int = 3) -> float:
+        best = ctypes.c_double()
+        self._check(self._lib.sp_autotune(self._h, float(dt), int(reps), ctypes.byref(best)))
+        return float(best.value)
+
+    def set_graph_chunk(self, chunk: int):
+        self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))
 
     def schedule(self):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -1,0 +1,750 @@
+// Device code of spdem: the fused DEM cell step, the cell statistics, the
+// Lax-Friedrichs continuum update and the contact-pair export.
+//
+// Method: Deng, Stechmann & Chen, "Particle-continuum multiscale modeling of
+// sea ice floes".  One doubly periodic DEM per coarse cell (Sec. 3.1); the DEM
+// system and contact law of Sec. 2.1; cell statistics feeding the moment
+// equations of Sec. 2.3; Lax-Friedrichs with the Oseen momentum advection
+// (Sec. 3.2).
+//
+// Work decomposition: a "group" of W wavefronts owns one cell for one step.
+// A workgroup holds max(1, 4 / W) groups (256 threads, or 512 for W = 8), so
+// small cells run a wavefront each and large cells a tile of up to 8
+// wavefronts.  Cells reach groups either in grid order from a cost-sorted cell
+// list, or through a per-launch work counter (persistent workgroups).
+//
+// Per cell and step the group:
+//   1. stages positions, radii, velocities and spins in LDS; binned schedule:
+//      counting sort into sub-bins of side >= 2 r_max;
+//   2. screens contact candidates in FP32 (all pairs, or a half shell over the
+//      bin-sorted copy) and appends each candidate pair to both floes' LDS
+//      contact lists; pairs within a 2^-19 relative guard band of touching are
+//      decided later by the FP64 expression (dx dx + dy dy) < R R without
+//      contraction, so the contact set is the one that expression defines;
+//   3. per floe: ocean current and curl (angle addition around the cell centre,
+//      Taylor sincos), FP64 drag and drag torque, contacts in ascending partner
+//      index (FP64), semi-implicit update, FP32 / fixed-point store;
+//   4. reduces the FP64 statistics of the pre-step state (LDS + DPP, fixed
+//      order, deterministic);
+//   5. (optionally) advances the continuum of its cell by one LF step from the
+//      previous time level's statistics (the continuum update of step k is
+//      fused into the DEM launch of step k + 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spdem.h"
+
+namespace spdem {
+
+constexpr int kMomStride = 16;          // doubles per cell in the statistics buffers (128 B)
+constexpr int kListCap = SP_CONTACT_CAP;
+constexpr int kMaxBinsSide = 32;
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kGuard = 1.0f / 524288.0f;  // 2^-19
+constexpr int kDyn = 8;                 // statistics reduced by every step
+
+// device fault bits
+constexpr uint32_t kErrOverlap = 1u;
+constexpr uint32_t kErrNaN = 2u;
+constexpr uint32_t kErrCFL = 4u;
+constexpr uint32_t kErrCapacity = 8u;
+
+enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE, M_UBAR, M_VBAR };
+
+struct Modes {
+    float kxL[SP_MAX_MODES];  // kx * Lx: phase per cell fraction
+    float kyL[SP_MAX_MODES];
+    float au[SP_MAX_MODES];
+    float av[SP_MAX_MODES];
+    float cz[SP_MAX_MODES];   // curl coefficient av kx - au ky
+};
+
+struct StepArgs {
+    // floe state, SoA sorted by cell
+    uint32_t* xi;
+    uint32_t* yi;
+    float* u;
+    float* v;
+    float* w;
+    float* th;
+    const float* r;
+    const float* h;
+    const int32_t* cell_start;
+    const float2* phase;       // [ncells][nmodes]: (sin, cos) of the phase at the cell centre
+    double* mom;               // statistics written by this step [ncells][kMomStride]
+    uint32_t* err;
+    unsigned long long* contacts;
+    // work list
+    const int4* work;          // (cell, first floe, floe count, -) of this launch, costliest first
+    int32_t ncl;
+    int32_t* queue;            // persistent workgroups: this step's work counter (null: grid order)
+    int32_t* queue_reset;      // the other counter, zeroed for the step after this one
+    int32_t group_bytes;       // LDS bytes per group
+    int32_t cap;               // LDS floe capacity per group
+    // fused continuum update of the previous time level
+    int32_t lf;
+    const double* mom_prev;
+    const double* Qp;          // [4][ncells]
+    double* Qn;
+    unsigned long long* max_cfl_bits;
+    int32_t nx, ny;
+    double dX, dY, inv_area;
+    // geometry and constants
+    int32_t ncells;
+    int32_t nmodes;
+    int32_t nbx, nby;          // sub-bins per side (1: all pairs along that axis)
+    uint32_t flags;
+    float qx, qy;              // Lx 2^-32, Ly 2^-32
+    double qxd, qyd;
+    double inv_qxd, inv_qyd;
+    double dtd;
+    double Ed, Gd, mud;
+    double cdrho;              // Cd rho_o
+    double rho_ice_d;
+    float u0, v0;
+    Modes modes;
+};
+
+// ----------------------------------------------------------------- helpers
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// FP64 contact predicate: (dx*dx + dy*dy) < R*R without contraction.
+__device__ __noinline__ bool exact_contact(int dxi, int dyi, float rl, float rj, double qxd,
+                                           double qyd)
+{
+#pragma clang fp contract(off)
+    double dx = (double)dxi * qxd;
+    double dy = (double)dyi * qyd;
+    double R = (double)rl + (double)rj;
+    double d2 = dx * dx + dy * dy;
+    return d2 < R * R;
+}
+
+// FP32 screen value d^2 - R^2 and R^2.
+__device__ __forceinline__ void screen(int dxi, int dyi, float rl, float rj, float qx, float qy,
+                                       float& diff, float& R2)
+{
+    float dx = (float)dxi * qx;
+    float dy = (float)dyi * qy;
+    float R = rl + rj;
+    R2 = R * R;
+    diff = (dx * dx + dy * dy) - R2;
+}
+
+// Final contact decision for a listed candidate.
+__device__ __forceinline__ bool decide(int dxi, int dyi, float rl, float rj, const StepArgs& a)
+{
+    float diff, R2;
+    screen(dxi, dyi, rl, rj, a.qx, a.qy, diff, R2);
+    if (fabsf(diff) <= kGuard * R2) return exact_contact(dxi, dyi, rl, rj, a.qxd, a.qyd);
+    return diff < 0.0f;
+}
+
+// sin and cos of a moderate FP32 argument: Cody-Waite reduction by pi/2 and
+// Taylor polynomials on [-pi/4, pi/4] (truncation below 2e-9).
+__device__ __forceinline__ void sincos_small(float x, float& s, float& c)
+{
+    const float k = rintf(x * 0.63661977236758134f);
+    float r = fmaf(-k, 1.57079637050628662109375f, x);
+    r = fmaf(k, 4.37113900018624283e-8f, r);
+    const float r2 = r * r;
+    float sp = fmaf(r2, 2.7557319224e-6f, -1.9841269841e-4f);
+    sp = fmaf(r2, sp, 8.3333333333e-3f);
+    sp = fmaf(r2, sp, -1.6666666667e-1f);
+    const float sr = fmaf(r * r2, sp, r);
+    float cp = fmaf(r2, -2.7557319224e-7f, 2.4801587302e-5f);
+    cp = fmaf(r2, cp, -1.3888888889e-3f);
+    cp = fmaf(r2, cp, 4.1666666667e-2f);
+    cp = fmaf(r2, cp, -0.5f);
+    const float cr = fmaf(r2, cp, 1.0f);
+    const int q = (int)k;
+    const float s1 = (q & 1) ? cr : sr;
+    const float c1 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s1 : s1;
+    c = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// Sum over a row of 16 lanes with DPP row shifts (deterministic order); the
+// row total lands in the row's last lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row_sum(double x)
+{
+    x += dpp_shr<0x111>(x);   // row_shr:1
+    x += dpp_shr<0x112>(x);   // row_shr:2
+    x += dpp_shr<0x114>(x);   // row_shr:4
+    x += dpp_shr<0x118>(x);   // row_shr:8
+    return x;
+}
+
+// Exclusive scan of cnt[0..nb) into start[0..nb] by the G threads of a group
+// (thread gt of group g); nb <= 16 G.  Every thread of the workgroup calls it.
+template <int G>
+__device__ void group_exclusive_scan(const int* cnt, int* start, int nb, int gt, int* wsum)
+{
+    constexpr int W = G / 64;
+    const int lane = gt & 63, wave = gt >> 6;
+    const int ch = (nb + G - 1) / G;
+    const int b0 = gt * ch;
+    int tot = 0;
+    for (int k = 0; k < ch; ++k) tot += (b0 + k < nb) ? cnt[b0 + k] : 0;
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - tot;
+#pragma unroll
+    for (int k = 0; k < W; ++k) run += (k < wave) ? wsum[k] : 0;
+    for (int k = 0; k < ch; ++k) {
+        if (b0 + k < nb) start[b0 + k] = run;
+        run += (b0 + k < nb) ? cnt[b0 + k] : 0;
+    }
+    if (gt == G - 1) start[nb] = run;
+    __syncthreads();
+}
+
+// Statistics reduced by every step.  n, M and A_ice depend only on the radii
+// and thicknesses; the statistics kernel writes them when the floes are set.
+__device__ __forceinline__ int dyn_slot(int k)
+{
+    return k < 3 ? M_PX + k : M_UX + (k - 3);   // Px Py L | Ux Uy Svx Svy Sw
+}
+
+// Append partner index `who` to the contact list of floe `to`.
+__device__ __forceinline__ void list_append(uint16_t* lst, int* cnt, int to, int who)
+{
+    const int slot = atomicAdd(&cnt[to], 1);
+    if (slot < kListCap) lst[(size_t)to * kListCap + slot] = (uint16_t)who;
+}
+
+// Screen the candidates q in [q0, q1) of the sorted copy against floe o; the
+// next candidate is loaded while the current one is screened.
+__device__ __forceinline__ void sweep(const uint4* S, int q0, int q1, uint32_t xl, uint32_t yl,
+                                     float rl, int o, uint16_t* lst, int* cnt, const StepArgs& a)
+{
+    if (q0 >= q1) return;
+    uint4 pj = S[q0];
+    for (int q = q0; q < q1; ++q) {
+        const uint4 nxt = S[min(q + 1, q1 - 1)];
+        float diff, R2;
+        screen((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a.qx, a.qy, diff, R2);
+        if (diff < kGuard * R2) {
+            const int o2 = (int)(pj.w & 0xffffu);
+            list_append(lst, cnt, o, o2);
+            list_append(lst, cnt, o2, o);
+        }
+        pj = nxt;
+    }
+}
+
+// ---------------------------------------------------------- continuum step
+// One Lax-Friedrichs step of eq. pde for cell C (Sec. 3.2): mass and spin
+// angular momentum in conservative form with flux <v> q, momentum with the
+// Oseen approximation <v>.grad<rho v>, drag sources S / A; periodic grid.
+__device__ __forceinline__ void lf_cell(int C, const double* mom, const double* Q, double* Qn,
+                                        int nx, int ny, double dT, double dX, double dY,
+                                        double inv_area, unsigned long long* max_cfl_bits,
+                                        uint32_t* err)
+{
+    const int nc = nx * ny;
+    const int ix = C % nx, iy = C / nx;
+    const int E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
+    const int W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
+    const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
+    const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
+    const double uE = mom[(size_t)E * kMomStride + M_UBAR], uW = mom[(size_t)W * kMomStride + M_UBAR];
+    const double vN = mom[(size_t)N * kMomStride + M_VBAR], vS = mom[(size_t)S * kMomStride + M_VBAR];
+    const double uC = mom[(size_t)C * kMomStride + M_UBAR], vC = mom[(size_t)C * kMomStride + M_VBAR];
+    const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
+    const double* sC = mom + (size_t)C * kMomStride;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
+        const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
+        const double avg = 0.25 * (qE + qW + qN + qS);
+        double q;
+        if (f == 0) {
+            q = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS);
+        } else if (f == 3) {
+            q = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS) + dT * sC[M_SW] * inv_area;
+        } else {
+            q = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY)) +
+                dT * sC[f == 1 ? M_SVX : M_SVY] * inv_area;
+        }
+        Qn[(size_t)f * nc + C] = q;
+    }
+    const double cfl = fabs(uC) * dT / dX + fabs(vC) * dT / dY;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(cfl);
+    if (bits > *max_cfl_bits) atomicMax(max_cfl_bits, bits);
+    if (cfl > 1.0) atomicOr(err, kErrCFL);
+}
+
+// ------------------------------------------------------------- DEM step
+// SCHED: 1 all pairs, 2 binned half shell.  W: wavefronts per cell.
+// QUEUE: workgroups fetch cells from a work counter until the list is empty.
+template <int SCHED, int W, bool QUEUE>
+__global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArgs a)
+{
+    constexpr int G = 64 * W;                  // threads per group
+    constexpr int BT = G >= 256 ? G : 256;     // largest workgroup
+    constexpr int GPB = BT / G;                // largest number of groups (cells) per workgroup
+    const int gpb = blockDim.x / G;            // groups in this launch (LDS may allow fewer)
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float4 mode_k[SP_MAX_MODES];            // kx Lx, ky Ly, au, av
+    __shared__ float4 mode_c[GPB][SP_MAX_MODES];       // curl coefficient, sin, cos of centre phase
+    __shared__ int wsum[GPB][W];
+    __shared__ unsigned long long csum[BT / 64];
+    __shared__ int qbase;
+
+    const int tid = threadIdx.x;
+    const int g = tid / G, gt = tid % G;
+    unsigned char* gsm = smem + (size_t)g * a.group_bytes;
+    const int cap = a.cap;
+
+    if (tid < a.nmodes)
+        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
+    if (QUEUE && blockIdx.x == 0 && tid == 0) *a.queue_reset = 0;
+
+    uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, -
+    float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, -
+    uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy: xi, yi, r bits, index | bin << 16
+    uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));  // [cap][kListCap]
+    int* cnt = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
+    int* binof = cnt + cap;
+    int* rank = binof + (SCHED == 2 ? cap : 0);
+    int* bcnt = rank + (SCHED == 2 ? cap : 0);
+    int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
+    double* red = reinterpret_cast<double*>(gsm);             // [kDyn][G], after the floes are done
+
+    for (int iter = 0;; ++iter) {
+        int base;
+        if (QUEUE) {
+            __syncthreads();
+            if (tid == 0) qbase = atomicAdd(a.queue, gpb);
+            __syncthreads();
+            base = qbase;
+            if (base >= a.ncl) break;
+        } else {
+            base = blockIdx.x * gpb;
+        }
+        const int item = base + g;
+        const bool valid = item < a.ncl;
+        const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
+        const int c = wk.x, s = wk.y, n = wk.z;
+
+        if (valid && gt < a.nmodes) {
+            const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
+            mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
+        }
+        for (int i = gt; i < n; i += G) {
+            P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), 0u);
+            V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], 0.0f);
+            cnt[i] = 0;
+        }
+        if (SCHED == 2) {
+            const int nb = a.nbx * a.nby;
+            for (int b = gt; b < nb; b += G) bcnt[b] = 0;
+            __syncthreads();
+            for (int i = gt; i < n; i += G) {
+                const int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
+                const int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
+                const int b = by * a.nbx + bx;
+                binof[i] = b;
+                rank[i] = atomicAdd(&bcnt[b], 1);
+            }
+            __syncthreads();
+            group_exclusive_scan<G>(bcnt, bstart, nb, gt, wsum[g]);
+            for (int i = gt; i < n; i += G) {
+                uint4 p = P[i];
+                p.w = (uint32_t)i | ((uint32_t)binof[i] << 16);
+                S[bstart[binof[i]] + rank[i]] = p;
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 1: contact candidates -> per-floe lists
+        if (SCHED == 1) {
+            // every floe against every floe (itself included, skipped later);
+            // the list comes out in ascending partner order
+            for (int l = gt; l < n; l += G) {
+                const uint4 pl = P[l];
+                const float rl = __uint_as_float(pl.z);
+                uint16_t* my = lst + (size_t)l * kListCap;
+                int k = 0;
+                for (int j = 0; j < n; ++j) {
+                    const uint4 pj = P[j];
+                    float diff, R2;
+                    screen((int)(pj.x - pl.x), (int)(pj.y - pl.y), rl, __uint_as_float(pj.z), a.qx,
+                           a.qy, diff, R2);
+                    if (diff < kGuard * R2) {
+                        if (k < kListCap) my[k] = (uint16_t)j;
+                        ++k;
+                    }
+                }
+                cnt[l] = k;
+            }
+        } else {
+            // half shell over the bin-sorted copy: lanes take consecutive sorted
+            // floes (neighbouring lanes share their neighbourhood); each pair is
+            // screened once, from the bin whose offset to the other is in
+            // {own bin (later sorted index), E, NW, N, NE}, and appended to both lists
+            for (int t = gt; t < n; t += G) {
+                const uint4 own = S[t];
+                const int o = (int)(own.w & 0xffffu);
+                const int b = (int)(own.w >> 16);
+                const int bx = b % a.nbx, by = b / a.nbx;
+                const float rl = __uint_as_float(own.z);
+                if (a.nbx >= 3 && bx + 1 < a.nbx) {
+                    // own-bin tail and the east bin are contiguous
+                    sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
+                } else {
+                    sweep(S, t + 1, bstart[b + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    if (a.nbx >= 3) {
+                        const int be = by * a.nbx;   // east neighbour across the seam
+                        sweep(S, bstart[be], bstart[be + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    }
+                }
+                if (a.nby >= 3) {
+                    const int row = (by + 1 == a.nby ? 0 : by + 1) * a.nbx;
+                    if (a.nbx < 3) {
+                        sweep(S, bstart[row], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                    } else if (bx == 0) {
+                        sweep(S, bstart[row], bstart[row + 2], own.x, own.y, rl, o, lst, cnt, a);
+                        sweep(S, bstart[row + a.nbx - 1], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    } else if (bx == a.nbx - 1) {
+                        sweep(S, bstart[row + a.nbx - 2], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                        sweep(S, bstart[row], bstart[row + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    } else {
+                        sweep(S, bstart[row + bx - 1], bstart[row + bx + 2], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        double acc[kDyn];
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
+        unsigned long long ncontact = 0;
+
+        for (int l = gt; l < n; l += G) {
+            const uint4 pl = P[l];
+            const float4 vv = V[l];
+            const uint32_t xl = pl.x, yl = pl.y;
+            const float rl = __uint_as_float(pl.z);
+            const float ul = vv.x, vl = vv.y, wl = vv.z;
+
+            // ---- ocean current and curl at the floe centre (angle addition around
+            // the cell centre keeps the FP32 arguments below (|kx| Lx + |ky| Ly) / 2),
+            // then drag and drag torque in FP64
+            const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
+            double fdx = 0.0, fdy = 0.0, tdr = 0.0;
+            if (!(a.flags & SP_OCEAN_OFF)) {
+                const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
+                const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
+                float uo = a.u0, vo = a.v0, zeta = 0.0f;
+#pragma unroll 2
+                for (int m = 0; m < a.nmodes; ++m) {
+                    const float4 mk = mode_k[m];
+                    const float4 mc = mode_c[g][m];
+                    const float dth = mk.x * fx + mk.y * fy;
+                    float sd, cd;
+                    sincos_small(dth, sd, cd);
+                    const float sn = mc.y * cd + mc.z * sd;    // sin and cos of the full phase
+                    const float cn = mc.z * cd - mc.y * sd;
+                    uo += mk.z * sn;
+                    vo += mk.w * sn;
+                    zeta += mc.x * cn;
+                }
+                const double du = (double)uo - uld, dv = (double)vo - vld;
+                const double sp = sqrt(du * du + dv * dv);
+                const double alpha = a.cdrho * kPi * rld * rld;
+                fdx = alpha * du * sp;
+                fdy = alpha * dv * sp;
+                const double dW = 0.5 * (double)zeta - wld;
+                const double r2 = rld * rld;
+                const double beta = a.cdrho * kPi * r2 * r2 * rld;
+                tdr = beta * dW * fabs(dW);
+            }
+            const double md = a.rho_ice_d * (double)a.h[s + l] * kPi * rld * rld;
+
+            uint16_t* my = lst + (size_t)l * kListCap;
+            int k = cnt[l];
+            if (k > kListCap) {
+                atomicOr(a.err, kErrCapacity);
+                k = kListCap;
+            }
+            if (SCHED == 2) {
+                // ascending partner order: insertion sort of the short list
+                for (int i = 1; i < k; ++i) {
+                    const uint16_t key = my[i];
+                    int j = i - 1;
+                    while (j >= 0 && my[j] > key) {
+                        my[j + 1] = my[j];
+                        --j;
+                    }
+                    my[j + 1] = key;
+                }
+            }
+
+            // ---- contact forces and torques in ascending partner order (FP64)
+            double Fx = fdx, Fy = fdy, T = tdr;
+            for (int q = 0; q < k; ++q) {
+                const int j = my[q];
+                if (j == l) continue;
+                const uint4 pj = P[j];
+                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
+                const float rj = __uint_as_float(pj.z);
+                if (!decide(dxi, dyi, rl, rj, a)) continue;
+                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
+                const double d2 = dx * dx + dy * dy;
+                if (!(d2 > 0.0)) {
+                    atomicOr(a.err, kErrOverlap);
+                    continue;
+                }
+                const double rjd = (double)rj;
+                const double d = sqrt(d2);
+                const double inv_d = 1.0 / d;
+                const double nx = dx * inv_d, ny = dy * inv_d;
+                const double tx = -ny, ty = nx;
+                const double R = rld + rjd;
+                const double delta = d - R;
+                const double dr = fabs(rld - rjd);
+                double cc;
+                if (d <= dr) {
+                    cc = 2.0 * fmin(rld, rjd);
+                } else {
+                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
+                    cc = sqrt(fmax(p, 0.0)) * inv_d;
+                }
+                const double Fn = cc * a.Ed * delta;
+                const float4 vj = V[j];
+                const double wjd = (double)vj.z;
+                // spin sum in a fixed operand order (lower floe index first) so that
+                // the pair forces are exactly antisymmetric
+                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
+                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
+                const double capf = a.mud * fabs(Fn);
+                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+                Fx += Fn * nx + Ft * tx;
+                Fy += Fn * ny + Ft * ty;
+                T += rld * Ft;
+                ncontact += (l < j) ? 1ull : 0ull;
+            }
+
+            // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
+            // FP32 / fixed-point storage
+            const double inv_m = 1.0 / md;
+            const double dt = a.dtd;
+            const double und = uld + dt * (Fx * inv_m);
+            const double vnd = vld + dt * (Fy * inv_m);
+            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
+            const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
+            const int sx = __double2int_rn(dt * ux * a.inv_qxd);
+            const int sy = __double2int_rn(dt * vx * a.inv_qyd);
+            const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
+            a.xi[s + l] = xl + (uint32_t)sx;
+            a.yi[s + l] = yl + (uint32_t)sy;
+            a.u[s + l] = un;
+            a.v[s + l] = vn;
+            a.w[s + l] = wn;
+            a.th[s + l] = (float)((double)a.th[s + l] + dt * wx);
+            if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
+
+            // ---- statistics of the pre-step state (FP64)
+            acc[0] += md * uld;
+            acc[1] += md * vld;
+            acc[2] += md * rld * rld * wld;
+            acc[3] += uld;
+            acc[4] += vld;
+            acc[5] += fdx;
+            acc[6] += fdy;
+            acc[7] += tdr;
+        }
+
+        // ---- group reduction through LDS: lane partials -> 16 segment sums per
+        // quantity -> DPP row sum (fixed order, deterministic)
+        const unsigned long long cs = wave_sum_u64(ncontact);
+        if ((tid & 63) == 0) csum[tid >> 6] = cs;
+        __syncthreads();   // every lane is done with the cell's LDS data
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) red[k * G + gt] = acc[k];
+        __syncthreads();
+        constexpr int SEG = G / 16;                 // values per segment
+        for (int kq = gt >> 4; kq < kDyn; kq += G / 16) {
+            const int seg = gt & 15;
+            const double* src = red + kq * G + seg * SEG;
+            double x = 0.0;
+#pragma unroll
+            for (int i = 0; i < SEG; ++i) x += src[i];
+            x = row_sum(x);
+            if (seg == 15 && valid) {
+                const int slot = dyn_slot(kq);
+                a.mom[(size_t)c * kMomStride + slot] = x;
+                if (slot == M_UX || slot == M_UY)   // continuum coefficient <v> = U / n
+                    a.mom[(size_t)c * kMomStride + (slot == M_UX ? M_UBAR : M_VBAR)] =
+                        n > 0 ? x / (double)n : 0.0;
+            }
+        }
+        if (tid == 0) {
+            unsigned long long t = 0;
+            for (int q = 0; q < (int)(blockDim.x / 64); ++q) t += csum[q];
+            if (t) atomicAdd(a.contacts, t);
+        }
+        // continuum update of the previous level for this cell; it reads only
+        // buffers this launch does not write, so it runs last, where its memory
+        // latency overlaps other workgroups' work
+        if (valid && a.lf && gt == G - 1)
+            lf_cell(c, a.mom_prev, a.Qp, a.Qn, a.nx, a.ny, a.dtd, a.dX, a.dY, a.inv_area,
+                    a.max_cfl_bits, a.err);
+        if (!QUEUE) break;
+    }
+}
+
+// ------------------------------------------------------- cell statistics
+// All 11 statistics of the current state, one 256-thread workgroup per cell.
+__global__ __launch_bounds__(256) void stats_kernel(StepArgs a)
+{
+    __shared__ double red11[SP_NMOM][16];
+    __shared__ float4 mode_k[SP_MAX_MODES];
+    __shared__ float4 mode_c[SP_MAX_MODES];
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int s = a.cell_start[c];
+    const int n = a.cell_start[c + 1] - s;
+    if (tid < a.nmodes) {
+        const float2 sc = a.phase[(size_t)c * a.nmodes + tid];
+        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
+        mode_c[tid] = make_float4(a.modes.cz[tid], sc.x, sc.y, 0.0f);
+    }
+    __syncthreads();
+    double acc[SP_NMOM];
+#pragma unroll
+    for (int k = 0; k < SP_NMOM; ++k) acc[k] = 0.0;
+    for (int l = tid; l < n; l += 256) {
+        const uint32_t xl = a.xi[s + l], yl = a.yi[s + l];
+        const double rld = a.r[s + l], uld = a.u[s + l], vld = a.v[s + l], wld = a.w[s + l];
+        double fdx = 0.0, fdy = 0.0, tdr = 0.0;
+        if (!(a.flags & SP_OCEAN_OFF)) {
+            const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
+            const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
+            float uo = a.u0, vo = a.v0, zeta = 0.0f;
+            for (int m = 0; m < a.nmodes; ++m) {
+                const float4 mk = mode_k[m];
+                const float4 mc = mode_c[m];
+                float sd, cd;
+                sincos_small(mk.x * fx + mk.y * fy, sd, cd);
+                const float sn = mc.y * cd + mc.z * sd;
+                const float cn = mc.z * cd - mc.y * sd;
+                uo += mk.z * sn;
+                vo += mk.w * sn;
+                zeta += mc.x * cn;
+            }
+            const double du = (double)uo - uld, dv = (double)vo - vld;
+            const double sp = sqrt(du * du + dv * dv);
+            const double alpha = a.cdrho * kPi * rld * rld;
+            fdx = alpha * du * sp;
+            fdy = alpha * dv * sp;
+            const double dW = 0.5 * (double)zeta - wld;
+            const double r2 = rld * rld;
+            tdr = a.cdrho * kPi * r2 * r2 * rld * dW * fabs(dW);
+        }
+        const double md = a.rho_ice_d * (double)a.h[s + l] * kPi * rld * rld;
+        acc[M_N] += 1.0;
+        acc[M_MASS] += md;
+        acc[M_PX] += md * uld;
+        acc[M_PY] += md * vld;
+        acc[M_L] += md * rld * rld * wld;
+        acc[M_UX] += uld;
+        acc[M_UY] += vld;
+        acc[M_SVX] += fdx;
+        acc[M_SVY] += fdy;
+        acc[M_SW] += tdr;
+        acc[M_AICE] += kPi * rld * rld;
+    }
+    const int lane = tid & 63, rowid = tid >> 4;
+#pragma unroll
+    for (int k = 0; k < SP_NMOM; ++k) {
+        const double x = row_sum(acc[k]);
+        if ((lane & 15) == 15) red11[k][rowid] = x;
+    }
+    __syncthreads();
+    if (tid < SP_NMOM) {
+        double x = red11[tid][0];
+#pragma unroll
+        for (int q = 1; q < 16; ++q) x += red11[tid][q];
+        a.mom[(size_t)c * kMomStride + tid] = x;
+        if (tid == M_UX || tid == M_UY)
+            a.mom[(size_t)c * kMomStride + (tid == M_UX ? M_UBAR : M_VBAR)] = n > 0 ? x / (double)n : 0.0;
+    }
+}
+
+// ------------------------------------------------ standalone continuum step
+__global__ __launch_bounds__(64) void lf_kernel(const double* mom, const double* Q, double* Qn, int nx,
+                                                int ny, double dT, double dX, double dY,
+                                                double inv_area, unsigned long long* max_cfl_bits,
+                                                uint32_t* err)
+{
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C < nx * ny) lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
+}
+
+__global__ void q_from_moments_kernel(const double* mom, double* Q, int nc, double inv_area)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double* s = mom + (size_t)c * kMomStride;
+    Q[c] = s[M_MASS] * inv_area;
+    Q[(size_t)nc + c] = s[M_PX] * inv_area;
+    Q[(size_t)2 * nc + c] = s[M_PY] * inv_area;
+    Q[(size_t)3 * nc + c] = s[M_L] * inv_area;
+}
+
+// ------------------------------------------------------- pair export (debug)
+__global__ __launch_bounds__(256) void pairs_kernel(StepArgs a, int32_t* pl, int32_t* pj,
+                                                    unsigned long long* count, long long cap)
+{
+    const int c = blockIdx.x;
+    const int s = a.cell_start[c];
+    const int n = a.cell_start[c + 1] - s;
+    for (int l = threadIdx.x; l < n; l += 256) {
+        const uint32_t xl = a.xi[s + l], yl = a.yi[s + l];
+        const float rl = a.r[s + l];
+        for (int j = l + 1; j < n; ++j) {
+            const int dxi = (int)(a.xi[s + j] - xl), dyi = (int)(a.yi[s + j] - yl);
+            float diff, R2;
+            screen(dxi, dyi, rl, a.r[s + j], a.qx, a.qy, diff, R2);
+            if (!(diff < kGuard * R2)) continue;
+            if (!decide(dxi, dyi, rl, a.r[s + j], a)) continue;
+            const unsigned long long k = atomicAdd(count, 1ull);
+            if ((long long)k < cap) {
+                pl[k] = s + l;
+                pj[k] = s + j;
+            }
+        }
+    }
+}
+
+}  // namespace spdem

@@ -1,0 +1,121 @@
+"""Batched uneven cells: count buckets, wavefront / tile groups, persistent
+workgroups, the autotuner and graph replay (needs an MI355X).
+
+Every batching choice must give the same floe state bit for bit (each floe's
+arithmetic does not depend on how cells are grouped) and statistics equal to
+FP64 rounding; the uneven workload must match the oracle like the plain one.
+"""
+import numpy as np
+import pytest
+
+import fixtures
+import oracle
+from metrics import rel_err
+from workloads import uneven_workload
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2303_07819_amd")
+
+TOL = 1e-5
+TOL_CONTACT = 5e-5      # dense cells form contacts within 10 steps (see test_storage_floor.py)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def run(w, nsteps, waves=None, persistent=None, chunk=None, autotune=False):
+    s = sp.Sim.from_workload(w)
+    if chunk is not None:
+        s.set_graph_chunk(chunk)
+    if waves is not None:
+        s.set_batching(waves, persistent)
+    if autotune:
+        s.autotune(w.dt, 2)
+    s.step(w.dt, nsteps)
+    out = (s.read_floes(), s.read_moments(sp.MOMENTS_DEM), s.read_moments(sp.MOMENTS_CONTINUUM),
+           s.batching())
+    s.close()
+    return out
+
+
+def test_uneven_buckets_cover_all_cells():
+    w = uneven_workload()
+    with sp.Sim.from_workload(w) as s:
+        cells, waves, q = s.batching()
+    edges = [-1, 64, 128, 256, 512, 1024]
+    for b in range(5):
+        expect = np.sum((w.counts > edges[b]) & (w.counts <= edges[b + 1]))
+        assert cells[b] == expect, (b, cells[b], expect)
+    assert cells.sum() == w.ncells
+    assert list(waves) == [1, 2, 4, 4, 8] and not q.any()
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_uneven_parity(nsteps):
+    w = uneven_workload()
+    _say(f"uneven {w.ncells} cells, {w.nfloes} floes, counts {w.counts.min()}..{w.counts.max()}")
+    st, Q, mom, _ = oracle.run_plain(w, nsteps)
+    f, gm, gq, _ = run(w, nsteps)
+    em, eq = rel_err(gm, mom).max(), rel_err(gq, Q).max()
+    _say(f"  max rel err moments {em:.2e} continuum {eq:.2e}")
+    assert np.array_equal(gm[:, 0], mom[:, 0])
+    tol = TOL if nsteps == 1 else TOL_CONTACT
+    assert em <= tol and eq <= tol
+
+
+def test_every_batching_gives_the_same_floes():
+    w = uneven_workload(seed=8)
+    rng = np.random.default_rng(0)
+    w.u[:] = rng.normal(0, 0.2, w.nfloes)        # contacts within the run
+    w.v[:] = rng.normal(0, 0.2, w.nfloes)
+    ref = run(w, 6, chunk=0)
+    for waves in (1, 2, 4, 8):
+        for persistent in (0, 1):
+            got = run(w, 6, waves=[waves] * 5, persistent=[persistent] * 5, chunk=0)
+            _say(f"waves {waves} persistent {persistent}")
+            for k in ref[0]:
+                assert np.array_equal(ref[0][k], got[0][k]), (waves, persistent, k)
+            np.testing.assert_allclose(got[1], ref[1], rtol=1e-12, atol=1e-300)
+            np.testing.assert_allclose(got[2], ref[2], rtol=1e-12, atol=1e-300)
+
+
+def test_graph_replay_equals_eager():
+    w = uneven_workload(seed=4)
+    eager = run(w, 37, chunk=0)
+    graph = run(w, 37, chunk=8)
+    for k in eager[0]:
+        assert np.array_equal(eager[0][k], graph[0][k]), k
+    assert np.array_equal(eager[1], graph[1])
+    assert np.array_equal(eager[2], graph[2])
+
+
+def test_autotune_does_not_advance_the_state():
+    w = uneven_workload(seed=5)
+    plain = run(w, 4, chunk=0)
+    tuned = run(w, 4, chunk=0, autotune=True)
+    _say(f"autotuned waves {tuned[3][1].tolist()} persistent {tuned[3][2].tolist()}")
+    for k in plain[0]:
+        assert np.array_equal(plain[0][k], tuned[0][k]), k
+    np.testing.assert_allclose(tuned[2], plain[2], rtol=1e-12, atol=1e-300)
+
+
+def test_full_size_uneven128_sampled_cells():
+    """The 128x128 uneven workload (~4 M floes) in the benchmark launch
+    configuration; sampled cells, including the fullest, against the oracle."""
+    w = fixtures.make_config(2)
+    nsteps = 10
+    rng = np.random.default_rng(2)
+    sample = np.unique(np.concatenate([rng.choice(w.ncells, 6, replace=False),
+                                       [int(np.argmax(w.counts)), int(np.argmin(w.counts))]]))
+    _say(f"uneven128: {w.nfloes} floes, max/cell {w.counts.max()}, sample {sample.tolist()}")
+    with sp.Sim.from_workload(w) as s:
+        s.step(w.dt, nsteps)
+        gm = s.read_moments(sp.MOMENTS_DEM)
+    m = oracle.Model(w)
+    st = oracle.State.from_workload(w)
+    oracle.dem_steps(m, st, w.dt, nsteps, cells=sample)
+    ref = oracle.moments(m, st)[sample]
+    e = rel_err(gm[sample], ref)
+    _say(f"  max rel err {e.max():.2e}")
+    assert e.max() <= TOL_CONTACT

@@ -13,7 +13,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import rel_err
-from workloads import dense_workload, ragged_workload
+from workloads import dense_workload, ragged_workload, uneven_workload
 
 
 def run_stored(w, nsteps):
@@ -30,9 +30,10 @@ def run_stored(w, nsteps):
     return Q, oracle.moments(m, st)
 
 
-@pytest.mark.parametrize("name", ["small", "dense", "ragged"])
+@pytest.mark.parametrize("name", ["small", "dense", "ragged", "uneven"])
 def test_storage_floor(name):
-    w = {"small": lambda: fixtures.make_config(0), "dense": dense_workload, "ragged": ragged_workload}[name]()
+    w = {"small": lambda: fixtures.make_config(0), "dense": dense_workload, "ragged": ragged_workload,
+         "uneven": uneven_workload}[name]()
     _, Q, mom, _ = oracle.run_plain(w, 10)
     Qs, moms = run_stored(w, 10)
     floor = max(rel_err(moms, mom).max(), rel_err(Qs, Q).max())

@@ -26,3 +26,16 @@ def ragged_workload(seed=5):
     w.u[:] = rng.normal(0, 0.2, w.nfloes)
     w.v[:] = rng.normal(0, 0.2, w.nfloes)
     return w
+
+
+def uneven_workload(seed=3, nx=12, ny=8):
+    """Poisson counts from a marginal-ice-zone concentration field (0-~700 per
+    cell), at rest, radii scaled to area fraction 0.40 at 512 floes."""
+    rng = np.random.default_rng(seed)
+    c = fixtures.miz_concentration(rng, nx, ny, smooth_cells=2.0)
+    counts = rng.poisson(512 * c).reshape(-1).astype(np.int32)
+    counts[0] = 0
+    counts[1] = 1
+    counts[2] = 700
+    return fixtures.custom(nx, ny, 25e3, counts, seed=seed, r_scale=fixtures.radius_scale(512, 25e3 ** 2),
+                           G=3.5e3)
