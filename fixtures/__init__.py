@@ -307,3 +307,21 @@ def from_arrays(nx, ny, L, counts, xi, yi, r, h, u=None, v=None, omega=None, the
                     np.asarray(xi, np.uint32).copy(), np.asarray(yi, np.uint32).copy(),
                     f(u), f(v), f(omega), f(theta), f(r), f(h), ocean if ocean is not None else Ocean(),
                     G=G)
+
+
+# ------------------------------------------------------------- closure network
+MLP_SIZES = [45, 128, 128, 128, 4]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial closure-network parameters (flat FP32 vector, layout
+    W1 [128x45], b1, W2 [128x128], b2, W3 [128x128], b3, W4 [4x128], b4):
+    Kaiming-uniform weights with bound sqrt(6 / fan_in), zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l in range(1, 5):
+        fan_in = MLP_SIZES[l - 1]
+        bound = math.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-bound, bound, (MLP_SIZES[l], fan_in)).reshape(-1))
+        parts.append(np.zeros(MLP_SIZES[l]))
+    return np.concatenate(parts).astype(np.float32)

@@ -188,6 +188,57 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * 0 disables capture; must be even).  Results are identical either way. */
 sp_status sp_set_graph_chunk(sp_ctx* ctx, int32_t chunk);
 
+/* ------------------------------------------------------------------------
+ * Learned closure.  The paper closes the momentum equation's stress term
+ * only through the fine-scale DEM (Sec. 2.3); this network maps a cell's
+ * coarse neighbourhood to its moment tendencies so that cells away from the
+ * marginal ice zone can skip the DEM.  Architecture: 45 -> 128 -> 128 -> 128
+ * -> 4, GELU (erf form), bfloat16 weights and activations, FP32 accumulation
+ * on MFMA, FP32 master weights, Adam (beta = 0.9, 0.999, eps = 1e-8), mean
+ * squared error on normalised targets.  Parameters are one flat FP32 vector of
+ * SP_MLP_NPARAMS entries: W1 [128 x 45], b1, W2 [128 x 128], b2, W3, b3,
+ * W4 [4 x 128], b4 (row-major, W[o][i] multiplies input i into output o).
+ * Inputs per cell (SP_MLP_IN): the continuum state (rho, P_x, P_y, P_w) of the
+ * 3 x 3 neighbourhood row by row from the south-west (36), the ocean current
+ * and curl at the cell centre (3), and the cell's static floe descriptors n,
+ * A_ice / A, mean r, mean r^2, mean h, sum m r^2 / sum m (6).  Outputs
+ * (SP_MLP_OUT): d(rho, P_x, P_y, P_w)/dt.  Inputs and outputs are normalised
+ * per column by the stored means and standard deviations.
+ * All data pointers of the sp_mlp_* calls are device pointers except where
+ * marked host.  The object runs on its own stream (or the one given). */
+#define SP_MLP_NPARAMS 39428
+#define SP_MLP_IN 45
+#define SP_MLP_OUT 4
+typedef struct sp_mlp sp_mlp;
+sp_status sp_mlp_create(void* stream, sp_mlp** out);
+void sp_mlp_destroy(sp_mlp* net);
+const char* sp_mlp_last_error(const sp_mlp* net);
+/* host params[SP_MLP_NPARAMS]; set also resets the Adam state */
+sp_status sp_mlp_set_params(sp_mlp* net, const float* params);
+sp_status sp_mlp_get_params(sp_mlp* net, float* params);
+/* host arrays: x_mean, x_std [SP_MLP_IN], y_mean, y_std [SP_MLP_OUT]; a zero
+ * x_std drops that input */
+sp_status sp_mlp_set_norm(sp_mlp* net, const float* x_mean, const float* x_std, const float* y_mean,
+                          const float* y_std);
+sp_status sp_mlp_get_norm(sp_mlp* net, float* x_mean, float* x_inv_std, float* y_mean, float* y_std);
+/* per-column mean and standard deviation of a device data set X [n][45], T [n][4] */
+sp_status sp_mlp_fit_norm(sp_mlp* net, const float* X, const float* T, int64_t n);
+/* y [M][4] = network(x [M][45]), de-normalised */
+sp_status sp_mlp_forward(sp_mlp* net, const float* x, int64_t M, float* y);
+/* gradient of the loss over B samples into host grad[SP_MLP_NPARAMS]; *loss (host) */
+sp_status sp_mlp_gradient(sp_mlp* net, const float* X, const float* T, int32_t B, float* grad, float* loss);
+/* one Adam step on the B rows of X, T listed in rows (device, may be NULL = first B) */
+sp_status sp_mlp_train_step(sp_mlp* net, const float* X, const float* T, const int32_t* rows, int32_t B,
+                            float lr, float* loss);
+/* floor(n / batch) Adam steps over X, T in the order of perm (device [n]); *mean_loss (host) */
+sp_status sp_mlp_train_epoch(sp_mlp* net, const float* X, const float* T, const int32_t* perm, int64_t n,
+                             int32_t batch, float lr, float* mean_loss);
+/* closure inputs of every cell of the current state into x [ncells][45] (device) */
+sp_status sp_closure_features(sp_ctx* ctx, float* x);
+/* one training sample per cell: inputs at the current level into x, one step
+ * of size dt, tendencies (Q_new - Q_old) / dt into t [ncells][4] (device) */
+sp_status sp_closure_sample(sp_ctx* ctx, double dt, float* x, float* t);
+
 /* Schedule actually used for the current floes (after SP_SCHED_AUTO), and the
  * sub-bins per side it uses (1 for all-pairs). */
 sp_status sp_get_schedule(sp_ctx* ctx, int32_t* schedule, int32_t* bins_x, int32_t* bins_y);

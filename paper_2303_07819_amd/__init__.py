@@ -31,8 +31,12 @@ STATUS = {0: "SP_OK", -1: "SP_EINVAL", -2: "SP_ENOMEM", -3: "SP_EDEVICE", -4: "S
 EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_floes",
             "sp_set_floes_device", "sp_step", "sp_synchronize", "sp_read_moments", "sp_read_floes",
             "sp_read_pairs", "sp_get_stats", "sp_get_schedule", "sp_profile_steps",
-            "sp_get_batching", "sp_set_batching", "sp_autotune", "sp_set_graph_chunk"]
+            "sp_get_batching", "sp_set_batching", "sp_autotune", "sp_set_graph_chunk",
+            "sp_mlp_create", "sp_mlp_destroy", "sp_mlp_last_error", "sp_mlp_set_params", "sp_mlp_get_params",
+            "sp_mlp_set_norm", "sp_mlp_get_norm", "sp_mlp_fit_norm", "sp_mlp_forward", "sp_mlp_gradient",
+            "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample"]
 NUM_BUCKETS = 5
+MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
 
 class SpdemError(RuntimeError):
@@ -80,11 +84,28 @@ def load_library(path: str = LIB_PATH):
     lib.sp_set_batching.argtypes = [P, P, P]
     lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
     lib.sp_set_graph_chunk.argtypes = [P, I32]
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.sp_mlp_create.argtypes = [P, ctypes.POINTER(P)]
+    lib.sp_mlp_destroy.argtypes = [P]
+    lib.sp_mlp_last_error.argtypes = [P]
+    lib.sp_mlp_set_params.argtypes = [P, P]
+    lib.sp_mlp_get_params.argtypes = [P, P]
+    lib.sp_mlp_set_norm.argtypes = [P, P, P, P, P]
+    lib.sp_mlp_get_norm.argtypes = [P, P, P, P, P]
+    lib.sp_mlp_fit_norm.argtypes = [P, P, P, I64]
+    lib.sp_mlp_forward.argtypes = [P, P, I64, P]
+    lib.sp_mlp_gradient.argtypes = [P, P, P, I32, P, F]
+    lib.sp_mlp_train_step.argtypes = [P, P, P, P, I32, ctypes.c_float, F]
+    lib.sp_mlp_train_epoch.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, F]
+    lib.sp_closure_features.argtypes = [P, P]
+    lib.sp_closure_sample.argtypes = [P, D, P, P]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("sp_destroy", "sp_last_error"):
+        if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error"):
             fn.restype = ctypes.c_int
+    lib.sp_mlp_destroy.restype = None
+    lib.sp_mlp_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -232,7 +253,93 @@ class Sim:
     def set_graph_chunk(self, chunk: int):
         self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))
 
+    def closure_features(self, x):
+        """Closure inputs of every cell into the device tensor x [ncells, 45] (float32)."""
+        self._check(self._lib.sp_closure_features(self._h, _p(x)))
+
+    def closure_sample(self, dt: float, x, t):
+        """Inputs at the current level into x [ncells, 45], one step, tendencies into t [ncells, 4]."""
+        self._check(self._lib.sp_closure_sample(self._h, float(dt), _p(x), _p(t)))
+
     def schedule(self):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(self._lib.sp_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return int(a.value), int(b.value), int(c.value)
+
+
+class MLP:
+    """The closure network (one sp_mlp object).  Data arguments are device
+    tensors (torch, float32 / int32, contiguous); parameters cross as host arrays."""
+
+    def __init__(self, stream=None):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        st = self._lib.sp_mlp_create(None if stream is None else ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise SpdemError(st, "sp_mlp_create failed")
+        self._h = h
+
+    def _check(self, st):
+        if st != 0:
+            raise SpdemError(st, self._lib.sp_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sp_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_params(self, theta):
+        th = _c(theta, np.float32)
+        assert th.size == MLP_NPARAMS
+        self._check(self._lib.sp_mlp_set_params(self._h, _p(th)))
+
+    def get_params(self) -> np.ndarray:
+        th = np.zeros(MLP_NPARAMS, np.float32)
+        self._check(self._lib.sp_mlp_get_params(self._h, _p(th)))
+        return th
+
+    def set_norm(self, x_mean, x_std, y_mean, y_std):
+        a = [_c(v, np.float32) for v in (x_mean, x_std, y_mean, y_std)]
+        self._check(self._lib.sp_mlp_set_norm(self._h, *[_p(v) for v in a]))
+
+    def get_norm(self):
+        out = [np.zeros(MLP_IN, np.float32), np.zeros(MLP_IN, np.float32), np.zeros(MLP_OUT, np.float32),
+               np.zeros(MLP_OUT, np.float32)]
+        self._check(self._lib.sp_mlp_get_norm(self._h, *[_p(v) for v in out]))
+        return out   # x_mean, x_inv_std, y_mean, y_std
+
+    def fit_norm(self, X, T):
+        self._check(self._lib.sp_mlp_fit_norm(self._h, _p(X), _p(T), int(X.shape[0])))
+
+    def forward(self, x, y):
+        self._check(self._lib.sp_mlp_forward(self._h, _p(x), int(x.shape[0]), _p(y)))
+
+    def gradient(self, X, T):
+        g = np.zeros(MLP_NPARAMS, np.float32)
+        loss = ctypes.c_float()
+        self._check(self._lib.sp_mlp_gradient(self._h, _p(X), _p(T), int(X.shape[0]), _p(g), ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, X, T, rows, batch: int, lr: float = 1e-3) -> float:
+        loss = ctypes.c_float()
+        self._check(self._lib.sp_mlp_train_step(self._h, _p(X), _p(T), _p(rows), int(batch), float(lr),
+                                                ctypes.byref(loss)))
+        return float(loss.value)
+
+    def train_epoch(self, X, T, perm, batch: int, lr: float = 1e-3) -> float:
+        loss = ctypes.c_float()
+        self._check(self._lib.sp_mlp_train_epoch(self._h, _p(X), _p(T), _p(perm), int(perm.shape[0]), int(batch),
+                                                 float(lr), ctypes.byref(loss)))
+        return float(loss.value)

@@ -1,0 +1,598 @@
+// Host side of the learned closure (included at the end of spdem.hip, where
+// sp_ctx and its helpers are visible): the network object (parameters, Adam
+// state, normalisation, workspaces), inference, gradients and training, the
+// per-cell feature gather and the (feature, tendency) sampler.
+#pragma once
+
+#include "mlp_kernels.h"
+
+namespace spdem {
+
+// Static descriptors of each cell's floes: n, A_ice / A, mean r, mean r^2,
+// mean h, sum m r^2 / sum m (one workgroup per cell, fixed-order FP64 sums).
+__global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cell_start, const float* r,
+                                                          const float* h, double inv_area, float* desc)
+{
+    __shared__ double part[7][256];
+    const int c = blockIdx.x;
+    const int s = cell_start[c], n = cell_start[c + 1] - s;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int l = threadIdx.x; l < n; l += 256) {
+        const double rl = r[s + l], hl = h[s + l];
+        const double m = hl * rl * rl;   // proportional to the mass (rho_ice pi cancels in the ratio)
+        acc[0] += 1.0;
+        acc[1] += kPi * rl * rl;
+        acc[2] += rl;
+        acc[3] += rl * rl;
+        acc[4] += hl;
+        acc[5] += m * rl * rl;
+        acc[6] += m;
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) part[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nn = part[0][0];
+        float* d = desc + (size_t)c * 6;
+        d[0] = (float)nn;
+        d[1] = (float)(part[1][0] * inv_area);
+        d[2] = nn > 0 ? (float)(part[2][0] / nn) : 0.0f;
+        d[3] = nn > 0 ? (float)(part[3][0] / nn) : 0.0f;
+        d[4] = nn > 0 ? (float)(part[4][0] / nn) : 0.0f;
+        d[5] = part[6][0] > 0 ? (float)(part[5][0] / part[6][0]) : 0.0f;
+    }
+}
+
+// The 45 closure inputs of every cell: the continuum state (rho, P_x, P_y, P_w)
+// on the 3 x 3 neighbourhood (row by row from the south-west, periodic), the
+// ocean current and curl at the cell centre, and the six static descriptors.
+__global__ void features_kernel(const double* Q, int nx, int ny, const float2* phase, int nmodes, Modes modes,
+                                float u0, float v0, const float* desc, float* x)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = nx * ny;
+    if (c >= nc) return;
+    const int ix = c % nx, iy = c / nx;
+    float* o = x + (size_t)c * spmlp::kIn;
+    int k = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = (iy + dy + ny) % ny;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int nb = yy * nx + (ix + dx + nx) % nx;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) o[k++] = (float)Q[(size_t)f * nc + nb];
+        }
+    }
+    float uo = u0, vo = v0, zeta = 0.0f;
+    for (int m = 0; m < nmodes; ++m) {
+        const float2 sc = phase[(size_t)c * nmodes + m];
+        uo += modes.au[m] * sc.x;
+        vo += modes.av[m] * sc.x;
+        zeta += modes.cz[m] * sc.y;
+    }
+    o[36] = uo;
+    o[37] = vo;
+    o[38] = zeta;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o[39 + q] = desc[(size_t)c * 6 + q];
+}
+
+// Tendency (Q_now - Q_prev) / dt per cell, [nc][4] FP32.
+__global__ void tendency_kernel(const double* Qnow, const double* Qprev, int nc, double inv_dt, float* t)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        t[(size_t)c * 4 + f] = (float)((Qnow[(size_t)f * nc + c] - Qprev[(size_t)f * nc + c]) * inv_dt);
+}
+
+// Per-column mean and standard deviation of X [n][cols] (FP64, fixed order).
+__global__ __launch_bounds__(256) void column_stats_kernel(const float* X, long n, int cols, float* mean,
+                                                           float* inv_std, float* stdv)
+{
+    __shared__ double part[256];
+    __shared__ double mu;
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (long i = threadIdx.x; i < n; i += 256) s += (double)X[i * cols + col];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mu = n > 0 ? part[0] / (double)n : 0.0;
+    __syncthreads();
+    double q = 0.0;
+    for (long i = threadIdx.x; i < n; i += 256) {
+        const double e = (double)X[i * cols + col] - mu;
+        q += e * e;
+    }
+    part[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sd = n > 1 ? sqrt(part[0] / (double)n) : 0.0;
+        mean[col] = (float)mu;
+        // a constant column carries no information: it is zeroed (inputs) or left unscaled (outputs)
+        const bool flat = !(sd > 1e-12 * (fabs(mu) + 1e-30));
+        if (inv_std) inv_std[col] = flat ? 0.0f : (float)(1.0 / sd);
+        if (stdv) stdv[col] = flat ? 1.0f : (float)sd;
+    }
+}
+
+}  // namespace spdem
+
+struct sp_mlp {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    float* theta = nullptr;      // FP32 master parameters
+    uint16_t* theta_h = nullptr; // bfloat16 copy read by the matrix products
+    float* m = nullptr;          // Adam moments
+    float* v = nullptr;
+    float* grad = nullptr;
+    int64_t adam_t = 0;
+    // normalisation: x_n = (x - x_mean) x_inv_std; y = y_n y_std + y_mean
+    float* norm = nullptr;       // [x_mean 45 | x_inv_std 45 | y_mean 4 | y_inv_std 4 | y_std 4]
+    // workspace for `rows` samples
+    int64_t rows = 0;
+    uint16_t* a0 = nullptr;
+    float* z[3] = {nullptr, nullptr, nullptr};
+    uint16_t* a[3] = {nullptr, nullptr, nullptr};
+    float* y = nullptr;
+    float* dF = nullptr;
+    uint16_t* dH = nullptr;
+    float* dzF[2] = {nullptr, nullptr};
+    uint16_t* dzH[2] = {nullptr, nullptr};
+    float* sq = nullptr;
+    float* loss_d = nullptr;
+};
+
+namespace {
+
+using namespace spmlp;
+
+sp_status mfail(sp_mlp* m, sp_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (m) m->err = buf;
+    return st;
+}
+
+#define MLP_HIP(mm, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            (void)hipGetLastError();                                                          \
+            return mfail((mm), SP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));           \
+        }                                                                                     \
+    } while (0)
+
+template <class T>
+sp_status malloc_m(sp_mlp* mm, T** p, size_t count)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(1, count) * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return mfail(mm, SP_ENOMEM, "hipMalloc(%zu): %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    return SP_OK;
+}
+
+sp_status ensure_rows(sp_mlp* mm, int64_t rows)
+{
+    if (rows <= mm->rows) return SP_OK;
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    const size_t R = (size_t)rows;
+    sp_status st = SP_OK;
+    if (!st) st = malloc_m(mm, &mm->a0, R * kIn);
+    for (int l = 0; l < 3 && !st; ++l) {
+        st = malloc_m(mm, &mm->z[l], R * kHid);
+        if (!st) st = malloc_m(mm, &mm->a[l], R * kHid);
+    }
+    if (!st) st = malloc_m(mm, &mm->y, R * kOut);
+    if (!st) st = malloc_m(mm, &mm->dF, R * kOut);
+    if (!st) st = malloc_m(mm, &mm->dH, R * kOut);
+    for (int q = 0; q < 2 && !st; ++q) {
+        st = malloc_m(mm, &mm->dzF[q], R * kHid);
+        if (!st) st = malloc_m(mm, &mm->dzH[q], R * kHid);
+    }
+    if (!st) st = malloc_m(mm, &mm->sq, R * kOut);
+    if (st) return st;
+    mm->rows = rows;
+    return SP_OK;
+}
+
+sp_status gemm(sp_mlp* mm, GemmArgs g)
+{
+    if (g.M <= 0 || g.N <= 0) return SP_OK;
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, mm->stream, g);
+    MLP_HIP(mm, hipGetLastError());
+    return SP_OK;
+}
+
+GemmArgs gemm_args(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn, int M, int N,
+                   int K, int mode)
+{
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.A = A;
+    g.sam = sam;
+    g.sak = sak;
+    g.B = B;
+    g.sbk = sbk;
+    g.sbn = sbn;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.mode = mode;
+    return g;
+}
+
+// Forward pass of `B` rows (gathered by `rows` if not null).  keep: store the
+// pre-activations for the backward pass; out_raw: de-normalised output there
+// instead of the normalised output in mm->y.
+sp_status mlp_forward(sp_mlp* mm, const float* X, const int32_t* rows, int B, bool keep, float* out_raw)
+{
+    const float* xm = mm->norm;
+    const float* xis = mm->norm + kIn;
+    const float* ym = mm->norm + 2 * kIn;
+    const float* ys = mm->norm + 2 * kIn + 2 * kOut;
+    const long tot = (long)B * kIn;
+    hipLaunchKernelGGL(normalize_input_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, mm->stream, X,
+                       rows, (long)B, xm, xis, mm->a0);
+    MLP_HIP(mm, hipGetLastError());
+    const uint16_t* Wh[4] = {mm->theta_h + kOffW1, mm->theta_h + kOffW2, mm->theta_h + kOffW3,
+                             mm->theta_h + kOffW4};
+    const float* bias[4] = {mm->theta + kOffB1, mm->theta + kOffB2, mm->theta + kOffB3, mm->theta + kOffB4};
+    const uint16_t* in = mm->a0;
+    int K = kIn;
+    for (int l = 0; l < 3; ++l) {
+        GemmArgs g = gemm_args(in, K, 1, Wh[l], 1, K, B, kHid, K, EPI_HIDDEN);
+        g.bias = bias[l];
+        g.outF = keep ? mm->z[l] : nullptr;
+        g.ldf = kHid;
+        g.outH = mm->a[l];
+        g.ldh = kHid;
+        SP_TRY(gemm(mm, g));
+        in = mm->a[l];
+        K = kHid;
+    }
+    GemmArgs g = gemm_args(in, kHid, 1, Wh[3], 1, kHid, B, kOut, kHid, EPI_AFFINE);
+    g.bias = bias[3];
+    if (out_raw) {
+        g.scale = ys;
+        g.shift = ym;
+        g.outF = out_raw;
+    } else {
+        g.outF = mm->y;
+    }
+    g.ldf = kOut;
+    return gemm(mm, g);
+}
+
+// Backward pass of the mean squared error on normalised targets into mm->grad;
+// the loss into mm->loss_d.
+sp_status mlp_backward(sp_mlp* mm, const float* T, const int32_t* rows, int B)
+{
+    const float* tm = mm->norm + 2 * kIn;
+    const float* tis = mm->norm + 2 * kIn + kOut;
+    hipLaunchKernelGGL(mse_grad_kernel, dim3((B * kOut + 255) / 256), dim3(256), 0, mm->stream, mm->y, T, rows, B,
+                       tm, tis, mm->dF, mm->dH, mm->sq);
+    MLP_HIP(mm, hipGetLastError());
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, mm->stream, mm->sq, B * kOut, mm->loss_d);
+    MLP_HIP(mm, hipGetLastError());
+    const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+    const int offB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
+    const int nin[4] = {kIn, kHid, kHid, kHid};
+    const int nout[4] = {kHid, kHid, kHid, kOut};
+    const uint16_t* acts[4] = {mm->a0, mm->a[0], mm->a[1], mm->a[2]};
+    const float* dF = mm->dF;
+    const uint16_t* dH = mm->dH;
+    for (int l = 3; l >= 0; --l) {
+        // dW_l = d^T a_{l-1}   [nout x nin], reduction over the batch
+        GemmArgs gw = gemm_args(dH, 1, nout[l], acts[l], nin[l], 1, nout[l], nin[l], B, EPI_STORE);
+        gw.outF = mm->grad + offW[l];
+        gw.ldf = nin[l];
+        SP_TRY(gemm(mm, gw));
+        hipLaunchKernelGGL(colsum_kernel, dim3(nout[l]), dim3(256), 0, mm->stream, dF, B, nout[l],
+                           mm->grad + offB[l]);
+        MLP_HIP(mm, hipGetLastError());
+        if (l == 0) break;
+        // d_{l-1} = (d W_l) * gelu'(z_{l-1})
+        const int q = l & 1;
+        GemmArgs gd = gemm_args(dH, nout[l], 1, mm->theta_h + offW[l], nin[l], 1, B, nin[l], nout[l],
+                                EPI_GELU_BACK);
+        gd.zsaved = mm->z[l - 1];
+        gd.ldz = kHid;
+        gd.outF = mm->dzF[q];
+        gd.ldf = kHid;
+        gd.outH = mm->dzH[q];
+        gd.ldh = kHid;
+        SP_TRY(gemm(mm, gd));
+        dF = mm->dzF[q];
+        dH = mm->dzH[q];
+    }
+    return SP_OK;
+}
+
+sp_status mlp_adam(sp_mlp* mm, float lr)
+{
+    mm->adam_t++;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)mm->adam_t));
+    const float c2 = (float)(1.0 - pow(b2, (double)mm->adam_t));
+    hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, mm->m, mm->v,
+                       mm->grad, kNParams, lr, (float)b1, (float)b2, 1e-8f, c1, c2, mm->theta_h);
+    MLP_HIP(mm, hipGetLastError());
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sp_status sp_mlp_create(void* stream, sp_mlp** out)
+{
+    if (!out) return SP_EINVAL;
+    *out = nullptr;
+    sp_mlp* mm = new sp_mlp();
+    if (stream) {
+        mm->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&mm->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete mm;
+            return SP_EDEVICE;
+        }
+        mm->own_stream = true;
+    }
+    sp_status st = SP_OK;
+    if (!st) st = malloc_m(mm, &mm->theta, kNParams);
+    if (!st) st = malloc_m(mm, &mm->theta_h, kNParams);
+    if (!st) st = malloc_m(mm, &mm->m, kNParams);
+    if (!st) st = malloc_m(mm, &mm->v, kNParams);
+    if (!st) st = malloc_m(mm, &mm->grad, kNParams);
+    if (!st) st = malloc_m(mm, &mm->norm, 2 * kIn + 3 * kOut);
+    if (!st) st = malloc_m(mm, &mm->loss_d, 1);
+    if (!st) {
+        std::vector<float> nrm(2 * kIn + 3 * kOut, 0.0f);
+        for (int i = 0; i < kIn; ++i) nrm[kIn + i] = 1.0f;
+        for (int i = 0; i < kOut; ++i) nrm[2 * kIn + kOut + i] = nrm[2 * kIn + 2 * kOut + i] = 1.0f;
+        if (hipMemcpy(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice) != hipSuccess) st = SP_EDEVICE;
+        if (!st && hipMemset(mm->theta, 0, kNParams * 4) != hipSuccess) st = SP_EDEVICE;
+        if (!st && hipMemset(mm->theta_h, 0, kNParams * 2) != hipSuccess) st = SP_EDEVICE;
+        if (!st && hipMemset(mm->m, 0, kNParams * 4) != hipSuccess) st = SP_EDEVICE;
+        if (!st && hipMemset(mm->v, 0, kNParams * 4) != hipSuccess) st = SP_EDEVICE;
+    }
+    if (st) {
+        sp_mlp_destroy(mm);
+        return st;
+    }
+    *out = mm;
+    return SP_OK;
+}
+
+void sp_mlp_destroy(sp_mlp* mm)
+{
+    if (!mm) return;
+    if (mm->stream) (void)hipStreamSynchronize(mm->stream);
+    void* ps[] = {mm->theta, mm->theta_h, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->a0, mm->z[0], mm->z[1],
+                  mm->z[2], mm->a[0], mm->a[1], mm->a[2], mm->y, mm->dF, mm->dH, mm->dzF[0], mm->dzF[1],
+                  mm->dzH[0], mm->dzH[1], mm->sq};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    if (mm->own_stream && mm->stream) (void)hipStreamDestroy(mm->stream);
+    delete mm;
+}
+
+const char* sp_mlp_last_error(const sp_mlp* mm) { return mm ? mm->err.c_str() : "null network"; }
+
+sp_status sp_mlp_set_params(sp_mlp* mm, const float* params)
+{
+    if (!mm || !params) return mm ? mfail(mm, SP_EINVAL, "null parameters") : SP_EINVAL;
+    for (int i = 0; i < kNParams; ++i)
+        if (!std::isfinite(params[i])) return mfail(mm, SP_EINVAL, "non-finite parameter %d", i);
+    MLP_HIP(mm, hipMemcpyAsync(mm->theta, params, kNParams * 4, hipMemcpyHostToDevice, mm->stream));
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, kNParams,
+                       mm->theta_h);
+    MLP_HIP(mm, hipGetLastError());
+    MLP_HIP(mm, hipMemsetAsync(mm->m, 0, kNParams * 4, mm->stream));
+    MLP_HIP(mm, hipMemsetAsync(mm->v, 0, kNParams * 4, mm->stream));
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    mm->adam_t = 0;
+    return SP_OK;
+}
+
+sp_status sp_mlp_get_params(sp_mlp* mm, float* params)
+{
+    if (!mm || !params) return mm ? mfail(mm, SP_EINVAL, "null output") : SP_EINVAL;
+    MLP_HIP(mm, hipMemcpyAsync(params, mm->theta, kNParams * 4, hipMemcpyDeviceToHost, mm->stream));
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    return SP_OK;
+}
+
+sp_status sp_mlp_set_norm(sp_mlp* mm, const float* x_mean, const float* x_std, const float* y_mean,
+                          const float* y_std)
+{
+    if (!mm || !x_mean || !x_std || !y_mean || !y_std) return mm ? mfail(mm, SP_EINVAL, "null arrays") : SP_EINVAL;
+    std::vector<float> nrm(2 * kIn + 3 * kOut);
+    for (int i = 0; i < kIn; ++i) {
+        nrm[i] = x_mean[i];
+        nrm[kIn + i] = x_std[i] > 0.0f ? 1.0f / x_std[i] : 0.0f;
+    }
+    for (int i = 0; i < kOut; ++i) {
+        if (!(y_std[i] > 0.0f)) return mfail(mm, SP_EINVAL, "output scale %d not positive", i);
+        nrm[2 * kIn + i] = y_mean[i];
+        nrm[2 * kIn + kOut + i] = 1.0f / y_std[i];
+        nrm[2 * kIn + 2 * kOut + i] = y_std[i];
+    }
+    MLP_HIP(mm, hipMemcpyAsync(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice, mm->stream));
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    return SP_OK;
+}
+
+sp_status sp_mlp_get_norm(sp_mlp* mm, float* x_mean, float* x_inv_std, float* y_mean, float* y_std)
+{
+    if (!mm) return SP_EINVAL;
+    std::vector<float> nrm(2 * kIn + 3 * kOut);
+    MLP_HIP(mm, hipMemcpyAsync(nrm.data(), mm->norm, nrm.size() * 4, hipMemcpyDeviceToHost, mm->stream));
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    for (int i = 0; i < kIn; ++i) {
+        if (x_mean) x_mean[i] = nrm[i];
+        if (x_inv_std) x_inv_std[i] = nrm[kIn + i];
+    }
+    for (int i = 0; i < kOut; ++i) {
+        if (y_mean) y_mean[i] = nrm[2 * kIn + i];
+        if (y_std) y_std[i] = nrm[2 * kIn + 2 * kOut + i];
+    }
+    return SP_OK;
+}
+
+sp_status sp_mlp_fit_norm(sp_mlp* mm, const float* X, const float* T, int64_t n)
+{
+    if (!mm || !X || !T || n < 2) return mm ? mfail(mm, SP_EINVAL, "need device data and n >= 2") : SP_EINVAL;
+    hipLaunchKernelGGL(column_stats_kernel, dim3(kIn), dim3(256), 0, mm->stream, X, (long)n, kIn, mm->norm,
+                       mm->norm + kIn, (float*)nullptr);
+    MLP_HIP(mm, hipGetLastError());
+    hipLaunchKernelGGL(column_stats_kernel, dim3(kOut), dim3(256), 0, mm->stream, T, (long)n, kOut,
+                       mm->norm + 2 * kIn, mm->norm + 2 * kIn + kOut, mm->norm + 2 * kIn + 2 * kOut);
+    MLP_HIP(mm, hipGetLastError());
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    // outputs with no spread keep unit scale (inv_std = 1 / 1)
+    std::vector<float> nrm(2 * kIn + 3 * kOut);
+    MLP_HIP(mm, hipMemcpy(nrm.data(), mm->norm, nrm.size() * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < kOut; ++i)
+        if (nrm[2 * kIn + kOut + i] == 0.0f) nrm[2 * kIn + kOut + i] = 1.0f;
+    MLP_HIP(mm, hipMemcpy(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice));
+    return SP_OK;
+}
+
+sp_status sp_mlp_forward(sp_mlp* mm, const float* x, int64_t M, float* y)
+{
+    if (!mm || (M > 0 && (!x || !y)) || M < 0 || M > INT32_MAX / kHid)
+        return mm ? mfail(mm, SP_EINVAL, "bad forward arguments") : SP_EINVAL;
+    if (M == 0) return SP_OK;
+    SP_TRY(ensure_rows(mm, M));
+    return mlp_forward(mm, x, nullptr, (int)M, false, y);
+}
+
+sp_status sp_mlp_gradient(sp_mlp* mm, const float* X, const float* T, int32_t B, float* grad_host, float* loss)
+{
+    if (!mm || !X || !T || B < 1 || !grad_host) return mm ? mfail(mm, SP_EINVAL, "bad gradient arguments") : SP_EINVAL;
+    SP_TRY(ensure_rows(mm, B));
+    SP_TRY(mlp_forward(mm, X, nullptr, B, true, nullptr));
+    SP_TRY(mlp_backward(mm, T, nullptr, B));
+    MLP_HIP(mm, hipMemcpyAsync(grad_host, mm->grad, kNParams * 4, hipMemcpyDeviceToHost, mm->stream));
+    float ls = 0.0f;
+    MLP_HIP(mm, hipMemcpyAsync(&ls, mm->loss_d, 4, hipMemcpyDeviceToHost, mm->stream));
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    if (loss) *loss = ls / (float)(B * kOut);
+    return SP_OK;
+}
+
+sp_status sp_mlp_train_step(sp_mlp* mm, const float* X, const float* T, const int32_t* rows, int32_t B, float lr,
+                            float* loss)
+{
+    if (!mm || !X || !T || B < 1 || !(lr > 0)) return mm ? mfail(mm, SP_EINVAL, "bad training arguments") : SP_EINVAL;
+    SP_TRY(ensure_rows(mm, B));
+    SP_TRY(mlp_forward(mm, X, rows, B, true, nullptr));
+    SP_TRY(mlp_backward(mm, T, rows, B));
+    SP_TRY(mlp_adam(mm, lr));
+    if (loss) {
+        float ls = 0.0f;
+        MLP_HIP(mm, hipMemcpyAsync(&ls, mm->loss_d, 4, hipMemcpyDeviceToHost, mm->stream));
+        MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+        *loss = ls / (float)(B * kOut);
+    }
+    return SP_OK;
+}
+
+sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const int32_t* perm, int64_t n,
+                             int32_t batch, float lr, float* mean_loss)
+{
+    if (!mm || !X || !T || !perm || n < 1 || batch < 1 || !(lr > 0))
+        return mm ? mfail(mm, SP_EINVAL, "bad epoch arguments") : SP_EINVAL;
+    SP_TRY(ensure_rows(mm, batch));
+    const int64_t nb = n / batch;   // full batches only
+    std::vector<float> losses;
+    float* lbuf = nullptr;
+    SP_TRY(malloc_m(mm, &lbuf, (size_t)std::max<int64_t>(nb, 1)));
+    sp_status st = SP_OK;
+    for (int64_t b = 0; b < nb && !st; ++b) {
+        st = mlp_forward(mm, X, perm + b * batch, batch, true, nullptr);
+        if (!st) st = mlp_backward(mm, T, perm + b * batch, batch);
+        if (!st) st = mlp_adam(mm, lr);
+        if (!st && hipMemcpyAsync(lbuf + b, mm->loss_d, 4, hipMemcpyDeviceToDevice, mm->stream) != hipSuccess)
+            st = SP_EDEVICE;
+    }
+    if (!st && mean_loss) {
+        losses.resize((size_t)std::max<int64_t>(nb, 1));
+        if (hipMemcpyAsync(losses.data(), lbuf, losses.size() * 4, hipMemcpyDeviceToHost, mm->stream) != hipSuccess ||
+            hipStreamSynchronize(mm->stream) != hipSuccess)
+            st = SP_EDEVICE;
+        double s = 0.0;
+        for (int64_t b = 0; b < nb; ++b) s += losses[b];
+        *mean_loss = nb > 0 ? (float)(s / (double)nb / (double)(batch * kOut)) : 0.0f;
+    }
+    (void)hipStreamSynchronize(mm->stream);
+    (void)hipFree(lbuf);
+    if (st == SP_EDEVICE) return mfail(mm, st, "epoch copy failed");
+    return st;
+}
+
+// ------------------------------------------------- closure <-> simulation
+sp_status sp_closure_features(sp_ctx* c, float* x)
+{
+    if (!c || !x) return c ? fail(c, SP_EINVAL, "null features buffer") : SP_EINVAL;
+    if (!c->have_floes) return fail(c, SP_ESTATE, "no floes");
+    SP_TRY(flush_lf(c));
+    SP_TRY(upload_phase(c));
+    if (!c->desc) {
+        SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
+        hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, c->cell_start, c->r, c->h,
+                           1.0 / (c->p.cell_lx * c->p.cell_ly), c->desc);
+        HIP_TRY(c, hipGetLastError());
+    }
+    const StepArgs a = make_args(c, 0.0);
+    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
+                       c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, x);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
+sp_status sp_closure_sample(sp_ctx* c, double dt, float* x, float* t)
+{
+    if (!c || !x || !t) return c ? fail(c, SP_EINVAL, "null sample buffers") : SP_EINVAL;
+    if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "sampling needs the continuum update");
+    SP_TRY(sp_closure_features(c, x));
+    if (!c->qprev) SP_TRY(dalloc(c, &c->qprev, (size_t)c->ncells * 4));
+    HIP_TRY(c, hipMemcpyAsync(c->qprev, c->Q[c->kstep & 1], (size_t)c->ncells * 4 * 8, hipMemcpyDeviceToDevice,
+                              c->stream));
+    SP_TRY(sp_step(c, dt, 1));
+    SP_TRY(flush_lf(c));
+    hipLaunchKernelGGL(tendency_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, c->Q[c->kstep & 1],
+                       c->qprev, c->ncells, 1.0 / dt, t);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
+}  // extern "C"

@@ -89,6 +89,8 @@ struct sp_ctx {
     uint32_t* err_d = nullptr;
     unsigned long long* contacts_d = nullptr;
     unsigned long long* cfl_bits_d = nullptr;
+    float* desc = nullptr;                  // closure descriptors [ncells][6] (lazy)
+    double* qprev = nullptr;                // continuum snapshot for tendencies
 
     // time stepping
     int64_t kstep = 0;          // DEM steps since the floes were set
@@ -163,7 +165,7 @@ void free_all(sp_ctx* c)
     drop_graph(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d};
+                  c->cfl_bits_d, c->desc, c->qprev};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -180,6 +182,8 @@ void free_all(sp_ctx* c)
     c->Q[0] = c->Q[1] = nullptr;
     c->err_d = nullptr;
     c->contacts_d = c->cfl_bits_d = nullptr;
+    c->desc = nullptr;
+    c->qprev = nullptr;
 }
 
 // LDS bytes of one group (one cell) for a schedule, capacity and W.
@@ -629,6 +633,8 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     c->have_floes = false;
+    if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
+    c->desc = nullptr;
     const size_t N = (size_t)n;
     SP_TRY(dalloc(c, &c->xi, N));
     SP_TRY(dalloc(c, &c->yi, N));
@@ -1048,3 +1054,5 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
 }
 
 }  // extern "C"
+
+#include "closure_host.h"

@@ -1,0 +1,183 @@
+"""Closure network on the GPU (bfloat16 MFMA, FP32 accumulation) against the
+FP64 reference of oracle/mlp.py, and the per-cell feature / tendency gather
+against the oracle (needs an MI355X)."""
+import math
+
+import numpy as np
+import pytest
+
+import fixtures
+import oracle
+from metrics import rel_err
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2303_07819_amd")
+torch = pytest.importorskip("torch")
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cosine(a, b):
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def make_net(seed=1):
+    rng = np.random.default_rng(seed)
+    th = fixtures.mlp_init(seed)
+    th = th + rng.normal(0, 0.02, th.size).astype(np.float32)   # nonzero biases
+    net = sp.MLP()
+    net.set_params(th)
+    net.set_norm(np.zeros(45), np.ones(45), np.zeros(4), np.ones(4))
+    return net, th.astype(np.float64)
+
+
+@pytest.mark.parametrize("M", [1, 63, 300, 4096])
+def test_forward_matches_reference(M):
+    net, th = make_net(1)
+    x = np.random.default_rng(M).normal(0, 1, (M, 45)).astype(np.float32)
+    y = torch.zeros((M, 4), device="cuda")
+    net.forward(dev(x), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    ref16 = omlp.forward(th, x.astype(np.float64), bf16_mode=True)
+    ref64 = omlp.forward(th, x.astype(np.float64))
+    e16, e64 = rel_l2(got, ref16), rel_l2(got, ref64)
+    _say(f"M={M}: rel L2 vs bf16 reference {e16:.2e}, vs FP64 {e64:.2e}")
+    # bfloat16 reference: only FP32-vs-FP64 accumulation differs (an activation
+    # occasionally rounds to the neighbouring bfloat16); FP64: the bfloat16 storage itself
+    assert e16 <= 5e-4
+    assert e64 <= 2e-2
+    net.close()
+
+
+def test_normalisation_is_applied():
+    net, th = make_net(2)
+    rng = np.random.default_rng(0)
+    xm, xs = rng.normal(0, 3, 45), rng.uniform(0.5, 4, 45)
+    ym, ys = rng.normal(0, 2, 4), rng.uniform(0.1, 3, 4)
+    xs[7] = 0.0                                  # a dropped input
+    net.set_norm(xm, xs, ym, ys)
+    x = rng.normal(0, 1, (100, 45)) * xs + xm
+    y = torch.zeros((100, 4), device="cuda")
+    net.forward(dev(x), y)
+    xn = np.where(xs > 0, (x - xm) / np.where(xs > 0, xs, 1), 0.0)
+    ref = omlp.forward(th, xn, bf16_mode=True) * ys + ym
+    e = rel_l2(y.cpu().numpy(), ref)
+    _say(f"normalised forward rel L2 {e:.2e}")
+    assert e <= 2e-3
+    net.close()
+
+
+def test_gradient_matches_reference():
+    net, th = make_net(3)
+    rng = np.random.default_rng(1)
+    B = 512
+    x = rng.normal(0, 1, (B, 45)).astype(np.float32)
+    t = rng.normal(0, 1, (B, 4)).astype(np.float32)
+    g, loss = net.gradient(dev(x), dev(t))
+    ref16 = omlp.grad(th, x.astype(np.float64), t.astype(np.float64), bf16_mode=True)
+    ref64 = omlp.grad(th, x.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(omlp.loss(th, x.astype(np.float64), t.astype(np.float64), True), rel=1e-3)
+    o = 0
+    for name, shp in omlp.SHAPES:
+        k = int(np.prod(shp))
+        a, b16, b64 = g[o:o + k].astype(np.float64), ref16[o:o + k], ref64[o:o + k]
+        _say(f"{name}: rel L2 vs bf16 ref {rel_l2(a, b16):.2e}, cos vs FP64 {cosine(a, b64):.5f}, "
+             f"rel L2 vs FP64 {rel_l2(a, b64):.2e}")
+        assert rel_l2(a, b16) <= 2e-3 and cosine(a, b16) >= 0.99999
+        assert cosine(a, b64) >= 0.99 and rel_l2(a, b64) <= 5e-2
+        o += k
+    net.close()
+
+
+def test_adam_step_matches_closed_form():
+    net, th = make_net(4)
+    rng = np.random.default_rng(2)
+    B = 256
+    x = dev(rng.normal(0, 1, (B, 45)))
+    t = dev(rng.normal(0, 1, (B, 4)))
+    g, _ = net.gradient(x, t)
+    rows = dev(np.arange(B), torch.int32)
+    net.train_step(x, t, rows, B, lr=1e-3)
+    new = net.get_params().astype(np.float64)
+    th32 = th.astype(np.float32).astype(np.float64)
+    ref, _, _ = omlp.adam(th32, np.zeros_like(th32), np.zeros_like(th32), g.astype(np.float64), 1, lr=1e-3)
+    np.testing.assert_allclose(new, ref, rtol=0, atol=2e-7)
+    net.close()
+
+
+def test_training_reduces_loss_on_a_smooth_target():
+    net, _ = make_net(5)
+    rng = np.random.default_rng(3)
+    n = 8192
+    x = rng.normal(0, 1, (n, 45)).astype(np.float32)
+    t = np.stack([np.sin(x[:, 0]) + 0.5 * x[:, 1], x[:, 2] * x[:, 3], np.tanh(x[:, 4]), x[:, 5] ** 2],
+                 axis=1).astype(np.float32)
+    X, T = dev(x), dev(t)
+    net.fit_norm(X, T)
+    losses = []
+    for ep in range(6):
+        perm = dev(np.random.default_rng(ep).permutation(n), torch.int32)
+        losses.append(net.train_epoch(X, T, perm, 512, lr=2e-3))
+    _say("epoch losses", [f"{l:.4f}" for l in losses])
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
+
+
+def _descriptors(w):
+    st = w.start
+    out = np.zeros((w.ncells, 6))
+    for c in range(w.ncells):
+        r = w.r[st[c]:st[c + 1]].astype(np.float64)
+        h = w.h[st[c]:st[c + 1]].astype(np.float64)
+        n = r.size
+        if n:
+            out[c] = [n, np.sum(np.pi * r * r) / (w.Lx * w.Ly), r.mean(), (r * r).mean(), h.mean(),
+                      np.sum(h * r ** 4) / np.sum(h * r ** 2)]
+    return out
+
+
+def test_features_and_tendencies_match_oracle():
+    w = fixtures.custom(6, 5, 25e3, 40, seed=21, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    w.counts[3] = 0
+    w = fixtures.custom(6, 5, 25e3, w.counts, seed=21, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    nsteps = 3
+    _, Q0, _, _ = oracle.run_plain(w, nsteps)
+    _, Q1, _, _ = oracle.run_plain(w, nsteps + 1)
+    m = oracle.Model(w)
+    with sp.Sim.from_workload(w) as s:
+        s.step(w.dt, nsteps)
+        x = torch.zeros((w.ncells, 45), device="cuda")
+        t = torch.zeros((w.ncells, 4), device="cuda")
+        s.closure_sample(w.dt, x, t)
+        torch.cuda.synchronize()
+        xs, ts = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    ref = np.zeros((w.ncells, 45))
+    for c in range(w.ncells):
+        ix, iy = c % w.nx, c // w.nx
+        k = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb = ((iy + dy) % w.ny) * w.nx + (ix + dx) % w.nx
+                ref[c, k:k + 4] = Q0[nb]
+                k += 4
+        ref[c, 36:39] = oracle.ocean_at(m, (ix + 0.5) * w.Lx, (iy + 0.5) * w.Ly)
+    ref[:, 39:] = _descriptors(w)
+    e = rel_err(xs, ref)
+    _say(f"features max rel err {e.max():.2e}")
+    assert e.max() <= 1e-5
+    tend = (Q1 - Q0) / w.dt
+    et = np.abs(ts - tend) / np.maximum(np.abs(tend), 1e-2 * np.sqrt(np.mean(tend ** 2, axis=0)))
+    _say(f"tendency max rel err {et.max():.2e}")
+    assert et.max() <= 1e-3
