@@ -239,6 +239,54 @@ sp_status sp_closure_features(sp_ctx* ctx, float* x);
  * of size dt, tendencies (Q_new - Q_old) / dt into t [ncells][4] (device) */
 sp_status sp_closure_sample(sp_ctx* ctx, double dt, float* x, float* t);
 
+/* ------------------------------------------------------------------------
+ * Coarse-to-fine re-synchronisation (Sec. 3.3, the nudging of the fine state
+ * towards the coarse one, with all its sub-steps taken at once).
+ * Moves the floes of each listed cell to host targets[i] = (rho, P_x, P_y,
+ * P_w) per unit area: every radius is multiplied by s = sqrt(rho A / M) (the
+ * increment proportional to the radius that gives the cell mass rho A), then
+ * every floe of the cell gets the velocity shift (A P - sum m v) / M and the
+ * spin shift (A P_w - sum I w) / sum I, with M and I of the rescaled floes
+ * (FP64 sums, results stored FP32).  A radius may not exceed the contact
+ * search radius fixed when the floes were set (the largest radius then): a
+ * cell whose scale would pass it is scaled only up to it, keeps less mass
+ * than its target, and is counted in *clamped (host, may be NULL).
+ * cells (host, ncl distinct indices) and targets (host, [ncl][4]) are read
+ * only during the call.  Errors: SP_EINVAL (index out of range or repeated,
+ * rho <= 0 or non-finite target for a cell with floes, nonzero target for
+ * an empty cell; nothing is changed then), SP_ESTATE (no floes), SP_ENOMEM,
+ * SP_EDEVICE.  Synchronises. */
+sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const double* targets,
+                          int32_t* clamped);
+
+/* ------------------------------------------------------------------------
+ * DEM + closure hybrid.  closure_cells (host, [ncells], copied) flags the
+ * cells whose continuum state advances by the network's tendency instead of
+ * by their DEM: Q += dt T(features) with the features of sp_closure_features.
+ * All other cells run the DEM step and the continuum update of Sec. 3.2, which
+ * takes <v> = (P_x, P_y) / rho as the coefficient of a neighbouring closure
+ * cell.  Every check_every steps the next check_cells closure cells (round
+ * robin) are re-synchronised to their continuum state (as sp_resync_cells);
+ * their DEM statistics then give the plain method's tendency, and a cell whose
+ * network tendency differs from it by more than tol (|T_dem| + 0.1 sd) in any
+ * component (sd: the network's output scale) runs the DEM for the next
+ * fallback_steps steps.  A null closure_cells removes the hybrid.  The network
+ * must stay alive and unchanged while the hybrid is set; it runs on the
+ * simulation's stream.  Setting new floes removes the hybrid.
+ * Errors: SP_EINVAL, SP_ESTATE (no floes, or SP_NO_CONTINUUM), SP_ENOMEM,
+ * SP_EDEVICE.  Synchronises. */
+sp_status sp_hybrid_set(sp_ctx* ctx, sp_mlp* net, const uint8_t* closure_cells, int32_t check_every,
+                        int32_t check_cells, double tol, int32_t fallback_steps);
+/* nsteps hybrid steps of size dt (asynchronous except at checks and mode
+ * changes).  Floe statistics of closure cells are not advanced.
+ * Errors: SP_EINVAL, SP_ESTATE (no hybrid), SP_EDEVICE. */
+sp_status sp_step_hybrid(sp_ctx* ctx, double dt, int64_t nsteps);
+/* current DEM-mode and closure-mode cell counts, checks made, fallbacks
+ * triggered, checked cells whose re-synchronisation was clamped (host, any may
+ * be NULL).  Errors: SP_ESTATE (no hybrid). */
+sp_status sp_hybrid_stats(sp_ctx* ctx, int32_t* dem_cells, int32_t* closure_cells, int64_t* checks,
+                          int64_t* fallbacks, int64_t* clamped);
+
 /* Schedule actually used for the current floes (after SP_SCHED_AUTO), and the
  * sub-bins per side it uses (1 for all-pairs). */
 sp_status sp_get_schedule(sp_ctx* ctx, int32_t* schedule, int32_t* bins_x, int32_t* bins_y);

@@ -34,7 +34,8 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_get_batching", "sp_set_batching", "sp_autotune", "sp_set_graph_chunk",
             "sp_mlp_create", "sp_mlp_destroy", "sp_mlp_last_error", "sp_mlp_set_params", "sp_mlp_get_params",
             "sp_mlp_set_norm", "sp_mlp_get_norm", "sp_mlp_fit_norm", "sp_mlp_forward", "sp_mlp_gradient",
-            "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample"]
+            "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample",
+            "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -100,6 +101,11 @@ def load_library(path: str = LIB_PATH):
     lib.sp_closure_features.argtypes = [P, P]
     lib.sp_closure_sample.argtypes = [P, D, P, P]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.sp_resync_cells.argtypes = [P, I32, P, P, ctypes.POINTER(I32)]
+    lib.sp_hybrid_set.argtypes = [P, P, P, I32, I32, D, I32]
+    lib.sp_step_hybrid.argtypes = [P, D, I64]
+    lib.sp_hybrid_stats.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64),
+                                    ctypes.POINTER(I64), ctypes.POINTER(I64)]
     for name in EXPORTED:
         fn = getattr(lib, name)
         if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error"):
@@ -260,6 +266,39 @@ class Sim:
     def closure_sample(self, dt: float, x, t):
         """Inputs at the current level into x [ncells, 45], one step, tendencies into t [ncells, 4]."""
         self._check(self._lib.sp_closure_sample(self._h, float(dt), _p(x), _p(t)))
+
+    def resync_cells(self, cells, targets) -> int:
+        """Move the floes of the listed cells to targets [ncl, 4] = (rho, P_x, P_y, P_w);
+        returns the number of cells whose radius scale was clamped."""
+        cl = _c(cells, np.int32)
+        tg = _c(targets, np.float64).reshape(-1, 4)
+        assert tg.shape[0] == cl.size
+        n = ctypes.c_int32()
+        self._check(self._lib.sp_resync_cells(self._h, int(cl.size), _p(cl), _p(tg), ctypes.byref(n)))
+        return int(n.value)
+
+    def hybrid_set(self, net, closure_cells, check_every: int = 50, check_cells: int = 64, tol: float = 0.2,
+                   fallback_steps: int = 100):
+        """Flag closure cells (bool array [ncells]) for the network `net` (an MLP); None removes the hybrid."""
+        if closure_cells is None:
+            self._check(self._lib.sp_hybrid_set(self._h, None, None, 1, 0, 1.0, 1))
+            self._net = None
+            return
+        m = _c(np.asarray(closure_cells).astype(np.uint8), np.uint8)
+        self._check(self._lib.sp_hybrid_set(self._h, net._h, _p(m), int(check_every), int(check_cells), float(tol),
+                                            int(fallback_steps)))
+        self._net = net   # the network must outlive the hybrid
+
+    def step_hybrid(self, dt: float, nsteps: int = 1):
+        self._check(self._lib.sp_step_hybrid(self._h, float(dt), int(nsteps)))
+
+    def hybrid_stats(self) -> dict:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        c, d, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.sp_hybrid_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                              ctypes.byref(d), ctypes.byref(e)))
+        return {"dem_cells": int(a.value), "closure_cells": int(b.value), "checks": int(c.value),
+                "fallbacks": int(d.value), "clamped": int(e.value)}
 
     def schedule(self):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

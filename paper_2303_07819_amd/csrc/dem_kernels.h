@@ -624,13 +624,14 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 }
 
 // ------------------------------------------------------- cell statistics
-// All 11 statistics of the current state, one 256-thread workgroup per cell.
-__global__ __launch_bounds__(256) void stats_kernel(StepArgs a)
+// All 11 statistics of the current state, one 256-thread workgroup per cell
+// (cell blockIdx.x, or cells[blockIdx.x] with a cell list).
+__global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* cells)
 {
     __shared__ double red11[SP_NMOM][16];
     __shared__ float4 mode_k[SP_MAX_MODES];
     __shared__ float4 mode_c[SP_MAX_MODES];
-    const int c = blockIdx.x;
+    const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
     const int s = a.cell_start[c];
     const int n = a.cell_start[c + 1] - s;

@@ -76,7 +76,10 @@ struct sp_ctx {
     int32_t sched = SP_SCHED_ALLPAIRS;
     bool have_floes = false;
     std::vector<int32_t> start_h;
+    std::vector<int32_t> counts_h;
     Bucket bk[kNumBuckets];
+    float r_bin = 0.0f;         // largest radius the sub-bins are sized for
+    struct HybridState* hyb = nullptr;
 
     // device buffers
     uint32_t *xi = nullptr, *yi = nullptr;
@@ -105,6 +108,8 @@ struct sp_ctx {
     hipGraphExec_t gexec = nullptr;
     double graph_dt = 0.0;
 };
+
+void hybrid_free(sp_ctx* c);   // hybrid_host.h
 
 namespace {
 
@@ -163,6 +168,7 @@ void drop_graph(sp_ctx* c)
 void free_all(sp_ctx* c)
 {
     drop_graph(c);
+    hybrid_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
                   c->cfl_bits_d, c->desc, c->qprev};
@@ -420,19 +426,22 @@ sp_status prepare_buckets(sp_ctx* c)
     return SP_OK;
 }
 
-sp_status build_buckets(sp_ctx* c, const int32_t* counts)
+// Count buckets over the cells with include[cell] != 0 (all cells if null).
+sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const uint8_t* include)
 {
-    for (int q = 0; q < kNumBuckets; ++q) c->bk[q].cells_h.clear();
-    std::vector<int32_t> order(c->ncells);
-    std::iota(order.begin(), order.end(), 0);
+    for (int q = 0; q < kNumBuckets; ++q) bk[q].cells_h.clear();
+    std::vector<int32_t> order;
+    order.reserve(c->ncells);
+    for (int32_t cell = 0; cell < c->ncells; ++cell)
+        if (!include || include[cell]) order.push_back(cell);
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return counts[x] > counts[y]; });
     for (int32_t cell : order) {
         int q = 0;
         while (counts[cell] > kBucketHi[q]) ++q;
-        c->bk[q].cells_h.push_back(cell);
+        bk[q].cells_h.push_back(cell);
     }
     for (int q = 0; q < kNumBuckets; ++q) {
-        Bucket& b = c->bk[q];
+        Bucket& b = bk[q];
         int mx = 0;
         for (int32_t cell : b.cells_h) mx = std::max(mx, counts[cell]);
         b.cap = std::max(16, (mx + 15) / 16 * 16);
@@ -452,12 +461,14 @@ sp_status build_buckets(sp_ctx* c, const int32_t* counts)
     return SP_OK;
 }
 
+sp_status build_buckets(sp_ctx* c, const int32_t* counts) { return build_buckets_into(c, c->bk, counts, nullptr); }
+
 sp_status reset_continuum(sp_ctx* c)
 {
     StepArgs a = make_args(c, 0.0);
     a.mom = c->momb[0];
     if (c->ncells > 0) {
-        hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
         HIP_TRY(c, hipGetLastError());
         // the static statistics (n, M, A_ice) must be present at both levels
         HIP_TRY(c, hipMemcpyAsync(c->momb[1], c->momb[0], (size_t)c->ncells * kMomStride * 8,
@@ -632,6 +643,7 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
 
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
+    hybrid_free(c);   // its cell lists follow the floes
     c->have_floes = false;
     if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
     c->desc = nullptr;
@@ -674,6 +686,8 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
 
     c->start_h.assign((size_t)c->ncells + 1, 0);
     for (int i = 0; i < c->ncells; ++i) c->start_h[i + 1] = c->start_h[i] + counts[i];
+    c->counts_h.assign(counts, counts + c->ncells);
+    c->r_bin = rmax;
     HIP_TRY(c, hipMemcpyAsync(c->cell_start, c->start_h.data(), ((size_t)c->ncells + 1) * 4,
                               hipMemcpyHostToDevice, c->stream));
     // sub-bins of side >= 2 r_max
@@ -799,7 +813,7 @@ sp_status sp_read_moments(sp_ctx* c, int32_t which, double* out)
         StepArgs a = make_args(c, 0.0);
         a.mom = c->mom2;
         if (nc > 0) {
-            hipLaunchKernelGGL(stats_kernel, dim3(nc), dim3(256), 0, c->stream, a);
+            hipLaunchKernelGGL(stats_kernel, dim3(nc), dim3(256), 0, c->stream, a, nullptr);
             HIP_TRY(c, hipGetLastError());
         }
         std::vector<double> buf((size_t)nc * kMomStride);
@@ -1056,3 +1070,4 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
 }  // extern "C"
 
 #include "closure_host.h"
+#include "hybrid_host.h"

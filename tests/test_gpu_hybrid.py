@@ -1,0 +1,332 @@
+"""Coarse-to-fine re-synchronisation and the DEM + closure hybrid step on the
+GPU against compositions of the FP64 oracle (needs an MI355X).
+
+Bars: re-synchronised floes within 1e-5 of the oracle's re-synchronisation;
+after it, the cell's P and P_w on their targets up to the FP32 storage of the
+velocities; a hybrid with no closure cell identical to the plain step; a
+hybrid with closure cells within 1e-5 of the oracle composition (DEM cells:
+oracle DEM + LF with the closure cells' <v> = P / rho; closure cells:
+Q + dt T with T from the bfloat16 reference network)."""
+import numpy as np
+import pytest
+
+import fixtures
+import oracle
+from metrics import rel_err
+from oracle import mlp as omlp
+from workloads import dense_workload
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2303_07819_amd")
+torch = pytest.importorskip("torch")
+
+TOL = 1e-5
+TOL_CONTACT = 5e-5   # per-floe state through contacts (the bar of the plain parity tests)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------- re-synchronisation
+def _targets(w, m, cells, factors):
+    mom = oracle.moments(m, oracle.State.from_workload(w))
+    Q = oracle.q_from_moments(m, mom)
+    t = np.zeros((len(cells), 4))
+    for i, c in enumerate(cells):
+        rho = Q[c, 0]
+        t[i] = [rho * factors[0], Q[c, 1] + factors[1] * rho, Q[c, 2] + factors[2] * rho,
+                Q[c, 3] + factors[3] * rho]
+    return t
+
+
+# (rho factor, added <v> in m/s, added <v_y>, added P_w / rho in m^2/s); none asks a
+# radius above the largest one, so nothing is clamped
+@pytest.mark.parametrize("factors", [(0.97, 0.01, -0.005, 20.0), (0.999, 0.0, 0.0, 0.0),
+                                     (0.5, -0.05, 0.03, -50.0)])
+def test_resync_matches_oracle(factors):
+    w = dense_workload(seed=31)
+    m = oracle.Model(w)
+    cells = [0, 2, 5]
+    tg = _targets(w, m, cells, factors)
+    _say(f"resync factors={factors} cells={cells}")
+    with sp.Sim.from_workload(w) as s:
+        clamped = s.resync_cells(cells, tg)
+        f = s.read_floes()
+        gm = s.read_moments(sp.MOMENTS_DEM)
+    assert clamped == 0
+    ost = oracle.State.from_workload(w)
+    for i, c in enumerate(cells):
+        oracle.resync_cell(m, ost, c, tg[i])
+    touched = np.zeros(w.nfloes, bool)
+    for c in cells:
+        touched[w.start[c]:w.start[c + 1]] = True
+    # cells not listed are untouched, bit for bit
+    for k, a in (("u", w.u), ("v", w.v), ("omega", w.omega), ("r", w.r)):
+        assert np.array_equal(f[k][~touched], a[~touched])
+    assert np.array_equal(f["xi"], w.xi) and np.array_equal(f["yi"], w.yi)
+    er = np.abs(f["r"][touched] - ost.r[touched]) / ost.r[touched]
+    _say(f"  radius max rel err {er.max():.2e}")
+    assert er.max() <= 2.0 ** -23
+    for k, ref in (("u", ost.u), ("v", ost.v), ("omega", ost.w)):
+        e = rel_err(f[k][touched][:, None], ref[touched][:, None])
+        _say(f"  {k} max rel err {e.max():.2e}")
+        assert e.max() <= TOL
+    # the cell moments land on the targets (up to the FP32 storage of u, v, w, r)
+    A = w.Lx * w.Ly
+    st = w.start
+    for i, c in enumerate(cells):
+        sl = slice(st[c], st[c + 1])
+        mass = 920.0 * w.h[sl].astype(np.float64) * np.pi * ost.r[sl] ** 2
+        fl_p = 2.0 ** -22 * np.sum(mass * np.abs(ost.u[sl])) / A + 1e-12 * abs(tg[i, 1])
+        fl_l = 2.0 ** -22 * np.sum(mass * ost.r[sl] ** 2 * np.abs(ost.w[sl])) / A + 1e-12 * abs(tg[i, 3])
+        assert abs(gm[c, 1] / A - tg[i, 0]) <= 2.0 ** -21 * tg[i, 0]
+        assert abs(gm[c, 2] / A - tg[i, 1]) <= 2 * fl_p + 1e-9 * tg[i, 0]
+        assert abs(gm[c, 4] / A - tg[i, 3]) <= 2 * fl_l + 1e-12 * tg[i, 0]
+
+
+def test_resync_clamps_at_the_search_radius():
+    w = dense_workload(seed=32)
+    m = oracle.Model(w)
+    rmax = float(w.r.max())
+    tg = _targets(w, m, [1, 3], (4.0, 0.02, 0.0, 0.0))
+    with sp.Sim.from_workload(w) as s:
+        clamped = s.resync_cells([1, 3], tg)
+        f = s.read_floes()
+        gm = s.read_moments(sp.MOMENTS_DEM)
+    assert clamped == 2
+    assert f["r"].max() <= rmax
+    A = w.Lx * w.Ly
+    for i, c in enumerate([1, 3]):
+        sl = slice(w.start[c], w.start[c + 1])
+        assert np.isclose(f["r"][sl].max(), rmax, rtol=2.0 ** -23)
+        assert gm[c, 1] / A < tg[i, 0]
+        mass = 920.0 * w.h[sl].astype(np.float64) * np.pi * f["r"][sl].astype(np.float64) ** 2
+        fl_p = 2.0 ** -22 * np.sum(mass * np.abs(f["u"][sl])) / A
+        assert abs(gm[c, 2] / A - tg[i, 1]) <= 2 * fl_p + 1e-9 * tg[i, 0]
+
+
+def test_resync_rejects_bad_targets():
+    w = fixtures.custom(3, 2, 25e3, [10, 0, 10, 10, 10, 10], seed=33, r_scale=0.3)
+    with sp.Sim.from_workload(w) as s:
+        before = s.read_floes()
+        good = np.array([[0.3, 0.0, 0.0, 0.0]])
+        for cells, tg in (([6], good), ([-1], good), ([0, 0], np.repeat(good, 2, 0)),
+                          ([0], np.array([[0.0, 0, 0, 0]])), ([0], np.array([[np.nan, 0, 0, 0]])),
+                          ([1], good)):
+            with pytest.raises(sp.SpdemError) as ei:
+                s.resync_cells(cells, tg)
+            assert ei.value.status == -1
+        assert s.resync_cells([1], np.zeros((1, 4))) == 0   # an empty cell with a zero target
+        after = s.read_floes()
+    for k in before:
+        assert np.array_equal(before[k], after[k])
+
+
+# ------------------------------------------------------------------ hybrid
+def _net(seed, x_mean, x_std, y_mean, y_std, zero=False):
+    th = np.zeros(omlp.NPARAMS, np.float32) if zero else fixtures.mlp_init(seed)
+    if not zero:
+        th = th + np.random.default_rng(seed).normal(0, 0.02, th.size).astype(np.float32)
+    net = sp.MLP()
+    net.set_params(th)
+    net.set_norm(x_mean, x_std, y_mean, y_std)
+    return net, th.astype(np.float64)
+
+
+def _descriptors(w):
+    out = np.zeros((w.ncells, 6))
+    for c in range(w.ncells):
+        r = w.r[w.start[c]:w.start[c + 1]].astype(np.float64)
+        h = w.h[w.start[c]:w.start[c + 1]].astype(np.float64)
+        if r.size:
+            out[c] = [r.size, np.sum(np.pi * r * r) / (w.Lx * w.Ly), r.mean(), (r * r).mean(), h.mean(),
+                      np.sum(h * r ** 4) / np.sum(h * r ** 2)]
+    return out
+
+
+def _features(w, m, Q, cells, desc):
+    x = np.zeros((len(cells), 45))
+    for i, c in enumerate(cells):
+        ix, iy = c % w.nx, c // w.nx
+        k = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb = ((iy + dy) % w.ny) * w.nx + (ix + dx) % w.nx
+                x[i, k:k + 4] = Q[nb]
+                k += 4
+        x[i, 36:39] = oracle.ocean_at(m, (ix + 0.5) * w.Lx, (iy + 0.5) * w.Ly)
+        x[i, 39:] = desc[c]
+    return x
+
+
+def _net_reference(th, x, x_mean, x_std, y_mean, y_std):
+    """The network's output as the configuration stores it: inputs normalised
+    in FP32 and rounded to bfloat16, products on bfloat16 operands."""
+    x32 = x.astype(np.float32)
+    inv = np.where(x_std > 0, np.float32(1.0) / np.maximum(x_std, np.float32(1e-30)), np.float32(0.0))
+    xn = omlp.bf16((x32 - x_mean) * inv.astype(np.float32))
+    y = omlp.forward(th, xn, bf16_mode=True)
+    return y * y_std.astype(np.float64) + y_mean.astype(np.float64)
+
+
+def _oracle_hybrid(w, closure, th, norm, nsteps):
+    m = oracle.Model(w)
+    st = oracle.State.from_workload(w)
+    Q = oracle.q_from_moments(m, oracle.moments(m, st))
+    dem_cells = np.flatnonzero(~closure).astype(np.int32)
+    clos_cells = np.flatnonzero(closure)
+    desc = _descriptors(w)
+    for _ in range(nsteps):
+        T = _net_reference(th, _features(w, m, Q, clos_cells, desc), *norm)
+        mom_dem, _ = oracle.dem_steps(m, st, w.dt, 1, cells=dem_cells, record=True)
+        mom = np.zeros((w.ncells, oracle.NMOM))
+        mom[dem_cells] = mom_dem[0]
+        for c in clos_cells:   # <v> = P / rho enters the neighbours' update
+            mom[c, 0] = 1.0
+            mom[c, 5] = Q[c, 1] / Q[c, 0]
+            mom[c, 6] = Q[c, 2] / Q[c, 0]
+        Qn, _ = oracle.lf_step(m, Q, mom, w.dt)
+        for i, c in enumerate(clos_cells):
+            Qn[c] = Q[c] + w.dt * T[i]
+        Q = Qn
+    return st, Q
+
+
+def _norm_for(w):
+    """Input scaling from the initial features; an output scale giving
+    dt |T| ~ 1e-4 of the continuum state."""
+    m = oracle.Model(w)
+    st = oracle.State.from_workload(w)
+    Q = oracle.q_from_moments(m, oracle.moments(m, st))
+    x = _features(w, m, Q, range(w.ncells), _descriptors(w))
+    x_mean = x.mean(0).astype(np.float32)
+    x_std = x.std(0).astype(np.float32)
+    x_std[x_std < 1e-6 * (np.abs(x_mean) + 1e-30)] = 0.0
+    q_rms = np.sqrt(np.mean(Q ** 2, axis=0)) + 1e-30
+    y_std = (1e-4 * q_rms / w.dt).astype(np.float32)
+    y_mean = np.zeros(4, np.float32)
+    return x_mean, x_std, y_mean, y_std
+
+
+def test_hybrid_without_closure_cells_is_the_plain_step():
+    w = dense_workload(seed=41)
+    norm = _norm_for(w)
+    net, _ = _net(3, *norm)
+    with sp.Sim.from_workload(w) as a, sp.Sim.from_workload(w) as b:
+        a.step(w.dt, 6)
+        b.hybrid_set(net, np.zeros(w.ncells, bool), check_every=2, check_cells=4)
+        b.step_hybrid(w.dt, 6)
+        fa, fb = a.read_floes(), b.read_floes()
+        qa, qb = a.read_moments(sp.MOMENTS_CONTINUUM), b.read_moments(sp.MOMENTS_CONTINUUM)
+        hs = b.hybrid_stats()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    # the same continuum arithmetic, in a kernel of its own instead of fused
+    _say(f"continuum bitwise equal: {np.array_equal(qa, qb)}")
+    assert rel_err(qb, qa).max() <= 1e-13
+    assert hs["dem_cells"] == w.ncells and hs["closure_cells"] == 0 and hs["checks"] == 0
+    net.close()
+
+
+def test_hybrid_constant_tendency_closure():
+    """All cells on a network whose output is its output offset: Q advances by
+    dt y_mean exactly, the floes do not move."""
+    w = fixtures.custom(4, 3, 25e3, 30, seed=42, r_scale=0.3)
+    c = np.array([1e-3, -2e-4, 3e-4, 5e-2], np.float32)
+    net, _ = _net(0, np.zeros(45, np.float32), np.ones(45, np.float32), c, np.ones(4, np.float32), zero=True)
+    m = oracle.Model(w)
+    Q = oracle.q_from_moments(m, oracle.moments(m, oracle.State.from_workload(w)))
+    with sp.Sim.from_workload(w) as s:
+        s.hybrid_set(net, np.ones(w.ncells, bool), check_every=1000)
+        s.step_hybrid(w.dt, 5)
+        q = s.read_moments(sp.MOMENTS_CONTINUUM)
+        f = s.read_floes()
+        hs = s.hybrid_stats()
+    for _ in range(5):
+        Q = Q + w.dt * c.astype(np.float64)
+    e = rel_err(q, Q)
+    _say(f"constant tendency max rel err {e.max():.2e}")
+    assert e.max() <= 1e-12
+    assert np.array_equal(f["u"], w.u) and np.array_equal(f["xi"], w.xi)
+    assert hs == {"dem_cells": 0, "closure_cells": w.ncells, "checks": 0, "fallbacks": 0, "clamped": 0}
+    net.close()
+
+
+@pytest.mark.parametrize("nsteps", [1, 6])
+def test_hybrid_mixed_matches_oracle(nsteps):
+    w = fixtures.custom(6, 5, 25e3, 40, seed=43, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    rng = np.random.default_rng(43)
+    w.u[:] = rng.normal(0, 0.1, w.nfloes)
+    w.v[:] = rng.normal(0, 0.1, w.nfloes)
+    closure = np.array([(c % w.nx + c // w.nx) % 3 == 0 for c in range(w.ncells)])
+    norm = _norm_for(w)
+    net, th = _net(5, *norm)
+    _say(f"hybrid mixed: {closure.sum()} closure cells of {w.ncells}, {nsteps} steps")
+    st, Q = _oracle_hybrid(w, closure, th, norm, nsteps)
+    with sp.Sim.from_workload(w) as s:
+        s.hybrid_set(net, closure, check_every=1000)
+        s.step_hybrid(w.dt, nsteps)
+        q = s.read_moments(sp.MOMENTS_CONTINUUM)
+        f = s.read_floes()
+    e = rel_err(q, Q)
+    _say(f"  continuum max rel err {e.max():.2e} (closure cells {e[closure].max():.2e}, "
+         f"DEM cells {e[~closure].max():.2e})")
+    assert e.max() <= TOL, np.unravel_index(e.argmax(), e.shape)
+    dem = np.zeros(w.nfloes, bool)
+    for c in np.flatnonzero(~closure):
+        dem[w.start[c]:w.start[c + 1]] = True
+    # closure cells' floes are not stepped
+    for k, a in (("u", w.u), ("xi", w.xi), ("omega", w.omega)):
+        assert np.array_equal(f[k][~dem], a[~dem])
+    ou = rel_err(f["u"][dem][:, None], st.u[dem][:, None])
+    _say(f"  DEM-cell floe velocity max rel err {ou.max():.2e}")
+    assert ou.max() <= TOL_CONTACT
+    net.close()
+
+
+def test_hybrid_checks_and_fallback():
+    w = fixtures.custom(6, 4, 25e3, 40, seed=44, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    closure = np.zeros(w.ncells, bool)
+    closure[::2] = True
+    norm = list(_norm_for(w))
+    nclos = int(closure.sum())
+    # a tolerance nothing violates: checks run, no fallback
+    net, _ = _net(6, *norm)
+    with sp.Sim.from_workload(w) as s:
+        s.hybrid_set(net, closure, check_every=3, check_cells=5, tol=1e30, fallback_steps=4)
+        s.step_hybrid(w.dt, 9)
+        hs = s.hybrid_stats()
+        assert hs["checks"] == 15 and hs["fallbacks"] == 0 and hs["closure_cells"] == nclos
+        # re-synchronised cells carry their continuum state
+        q = s.read_moments(sp.MOMENTS_CONTINUUM)
+        gm = s.read_moments(sp.MOMENTS_DEM)
+        f = s.read_floes()
+    A = w.Lx * w.Ly
+    order = np.flatnonzero(closure)
+    last = [order[(10 + i) % nclos] for i in range(5)]   # cells of the third check (cursor 10)
+    rmax = float(w.r.max())
+    for c in last:
+        on_target = abs(gm[c, 1] / A - q[c, 0]) <= 2.0 ** -20 * q[c, 0]
+        clamped = np.isclose(f["r"][w.start[c]:w.start[c + 1]].max(), rmax, rtol=2.0 ** -23)
+        assert on_target or (clamped and gm[c, 1] / A < q[c, 0])
+    net.close()
+    # an output far off the DEM tendency: every checked cell falls back, then returns
+    # (an offset of a tenth of the state per step; the floes start at rest, so
+    # the momentum tendencies of the network are ~0 while the DEM's drag is not)
+    norm[2] = (1e3 * norm[3]).astype(np.float32)
+    net, _ = _net(6, *norm)
+    base = w.ncells - nclos
+    with sp.Sim.from_workload(w) as s:
+        s.hybrid_set(net, closure, check_every=3, check_cells=5, tol=0.5, fallback_steps=4)
+        s.step_hybrid(w.dt, 3)   # check at step 3: five cells fall back for steps 4-7
+        hs = s.hybrid_stats()
+        assert hs["fallbacks"] == 5 and hs["dem_cells"] == base + 5, hs
+        s.step_hybrid(w.dt, 3)   # check at step 6: five more
+        hs = s.hybrid_stats()
+        assert hs["fallbacks"] == 10 and hs["dem_cells"] == base + 10, hs
+        s.step_hybrid(w.dt, 1)   # step 7: the first windows end
+        hs = s.hybrid_stats()
+        assert hs["fallbacks"] == 10 and hs["dem_cells"] == base + 5, hs
+        s.hybrid_set(None, None)
+    net.close()
