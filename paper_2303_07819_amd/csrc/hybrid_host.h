@@ -546,6 +546,10 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     HybridState* h = c->hyb;
     SP_TRY(upload_phase(c));
     SP_TRY(flush_lf(c));
+    if (nsteps == 0) return SP_OK;
+    // plain steps may have run since the last hybrid one
+    SP_TRY(zero_queues(c, h->bk));
+    c->plain_queues_stale = true;
     const StepArgs base = make_args(c, dt);
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
     for (int64_t it = 0; it < nsteps; ++it) {

@@ -80,6 +80,7 @@ struct sp_ctx {
     Bucket bk[kNumBuckets];
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
     struct HybridState* hyb = nullptr;
+    bool plain_queues_stale = false;   // hybrid steps ran since the last plain launch
 
     // device buffers
     uint32_t *xi = nullptr, *yi = nullptr;
@@ -461,6 +462,15 @@ sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const
     return SP_OK;
 }
 
+// Zero both work counters of every bucket: needed when the buckets did not
+// run the step before the next one (their in-kernel reset then did not happen).
+sp_status zero_queues(sp_ctx* c, Bucket* bk)
+{
+    for (int q = 0; q < kNumBuckets; ++q)
+        if (bk[q].q_d) HIP_TRY(c, hipMemsetAsync(bk[q].q_d, 0, 2 * sizeof(int32_t), c->stream));
+    return SP_OK;
+}
+
 sp_status build_buckets(sp_ctx* c, const int32_t* counts) { return build_buckets_into(c, c->bk, counts, nullptr); }
 
 sp_status reset_continuum(sp_ctx* c)
@@ -744,6 +754,10 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
         return fail(c, SP_EINVAL, "dt must be positive and nsteps non-negative");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));   // pending update of another dt
+    if (c->plain_queues_stale) {
+        SP_TRY(zero_queues(c, c->bk));
+        c->plain_queues_stale = false;
+    }
     const bool cont = !(c->p.flags & SP_NO_CONTINUUM);
     const StepArgs base = make_args(c, dt);
     int64_t left = nsteps;
@@ -774,6 +788,10 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
     if (!(dt > 0.0) || nsteps < 1) return fail(c, SP_EINVAL, "dt must be positive and nsteps >= 1");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));
+    if (c->plain_queues_stale) {
+        SP_TRY(zero_queues(c, c->bk));
+        c->plain_queues_stale = false;
+    }
     std::vector<hipEvent_t> ev((size_t)nsteps * 2);
     for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
     const StepArgs base = make_args(c, dt);
@@ -1063,6 +1081,8 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     cleanup();
     if (st) return st == SP_EDEVICE ? fail(c, st, "autotune timing failed") : st;
     SP_TRY(prepare_buckets(c));
+    c->plain_queues_stale = true;   // a bucket may have changed to persistent workgroups
+    drop_graph(c);
     if (best_ms) *best_ms = total;
     return SP_OK;
 }
