@@ -235,9 +235,27 @@ sp_status sp_mlp_train_epoch(sp_mlp* net, const float* X, const float* T, const 
                              int32_t batch, float lr, float* mean_loss);
 /* closure inputs of every cell of the current state into x [ncells][45] (device) */
 sp_status sp_closure_features(sp_ctx* ctx, float* x);
-/* one training sample per cell: inputs at the current level into x, one step
- * of size dt, tendencies (Q_new - Q_old) / dt into t [ncells][4] (device) */
-sp_status sp_closure_sample(sp_ctx* ctx, double dt, float* x, float* t);
+/* Tendency targets of sp_closure_sample.  SP_TEND_FULL: (Q_new - Q_old) / dt,
+ * with the features of Q_old.  SP_TEND_RESIDUAL: the part of the update the
+ * coarse state does not determine, with the features of the transported state
+ * Q* (below): (Q_new - relax(Q*)) / dt.  Q* is the continuum update of Sec. 3.2
+ * without sources and with every coefficient <v> taken as (P_x, P_y) / rho of
+ * the continuum state itself (0 where rho <= 1 kg/m^2, nearly open water);
+ * relax moves each cell of Q* by mean-field drag: its ice, moving with
+ * P* / rho* and spinning at P_w* / (rho* r2m), relaxes over dt towards the
+ * ocean current and half-curl at the cell centre by the closed form
+ * w / (1 + k |w| dt) of one floe's quadratic drag (Sec. 2.1), with
+ * k = C_d rho_o sum pi r^2 / sum m for the velocity and
+ * C_d rho_o sum pi r^5 / sum m r^2 for the spin, r2m = sum m r^2 / sum m,
+ * sums over the cell's floes.  The hybrid uses networks trained on
+ * SP_TEND_RESIDUAL. */
+#define SP_TEND_FULL 0
+#define SP_TEND_RESIDUAL 1
+/* one training sample per cell: inputs of `mode` into x [ncells][45], one
+ * step of size dt, tendencies of `mode` into t [ncells][4] (device).
+ * Errors: SP_EINVAL (null buffer, dt <= 0, unknown mode), SP_ESTATE,
+ * SP_EDEVICE. */
+sp_status sp_closure_sample(sp_ctx* ctx, double dt, int32_t mode, float* x, float* t);
 
 /* ------------------------------------------------------------------------
  * Coarse-to-fine re-synchronisation (Sec. 3.3, the nudging of the fine state
@@ -261,16 +279,19 @@ sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const 
 
 /* ------------------------------------------------------------------------
  * DEM + closure hybrid.  closure_cells (host, [ncells], copied) flags the
- * cells whose continuum state advances by the network's tendency instead of
- * by their DEM: Q += dt T(features) with the features of sp_closure_features.
- * All other cells run the DEM step and the continuum update of Sec. 3.2, which
- * takes <v> = (P_x, P_y) / rho as the coefficient of a neighbouring closure
- * cell.  Every check_every steps the next check_cells closure cells (round
- * robin) are re-synchronised to their continuum state (as sp_resync_cells);
- * their DEM statistics then give the plain method's tendency, and a cell whose
- * network tendency differs from it by more than tol (|T_dem| + 0.1 sd) in any
- * component (sd: the network's output scale) runs the DEM for the next
- * fallback_steps steps.  A null closure_cells removes the hybrid.  The network
+ * cells whose continuum state advances without their DEM (a flag on a cell
+ * without floes is ignored: its plain update needs no DEM work):
+ * Q <- relax(Q*) + dt T(features of Q*), with Q*, relax and the features of
+ * SP_TEND_RESIDUAL and T the output of a network trained on its targets.  All other cells run the DEM step and the continuum update of
+ * Sec. 3.2, which takes <v> = (P_x, P_y) / rho as the coefficient of a
+ * neighbouring closure cell.  Every check_every steps the next check_cells
+ * closure cells (round robin) are re-synchronised to their continuum state
+ * (as sp_resync_cells); their DEM statistics then give the plain method's
+ * residual tendency T_dem, and a cell whose network output differs from it by
+ * more than tol (|T_dem| + 0.1 sd) in any component (sd: the network's output
+ * scale) runs the DEM for the next fallback_steps steps.  A checked cell whose
+ * continuum mass is more than 4 times above or below its floes' mass, or not
+ * positive, falls back without being re-synchronised.  A null closure_cells removes the hybrid.  The network
  * must stay alive and unchanged while the hybrid is set; it runs on the
  * simulation's stream.  Setting new floes removes the hybrid.
  * Errors: SP_EINVAL, SP_ESTATE (no floes, or SP_NO_CONTINUUM), SP_ENOMEM,

@@ -25,6 +25,7 @@ SP_NO_CONTINUUM = 4
 SCHED_AUTO, SCHED_ALLPAIRS, SCHED_BINNED = 0, 1, 2
 MOMENTS_DEM, MOMENTS_CONTINUUM = 0, 1
 NMOM = 11
+TEND_FULL, TEND_RESIDUAL = 0, 1
 STATUS = {0: "SP_OK", -1: "SP_EINVAL", -2: "SP_ENOMEM", -3: "SP_EDEVICE", -4: "SP_ECFL",
           -5: "SP_EOVERLAP", -6: "SP_ENAN", -7: "SP_ESTATE", -8: "SP_ECAPACITY"}
 
@@ -99,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.sp_mlp_train_step.argtypes = [P, P, P, P, I32, ctypes.c_float, F]
     lib.sp_mlp_train_epoch.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, F]
     lib.sp_closure_features.argtypes = [P, P]
-    lib.sp_closure_sample.argtypes = [P, D, P, P]
+    lib.sp_closure_sample.argtypes = [P, D, I32, P, P]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sp_resync_cells.argtypes = [P, I32, P, P, ctypes.POINTER(I32)]
     lib.sp_hybrid_set.argtypes = [P, P, P, I32, I32, D, I32]
@@ -263,9 +264,11 @@ class Sim:
         """Closure inputs of every cell into the device tensor x [ncells, 45] (float32)."""
         self._check(self._lib.sp_closure_features(self._h, _p(x)))
 
-    def closure_sample(self, dt: float, x, t):
-        """Inputs at the current level into x [ncells, 45], one step, tendencies into t [ncells, 4]."""
-        self._check(self._lib.sp_closure_sample(self._h, float(dt), _p(x), _p(t)))
+    def closure_sample(self, dt: float, x, t, mode: int = None):
+        """Inputs at the current level into x [ncells, 45], one step, tendencies
+        (TEND_FULL or TEND_RESIDUAL, default full) into t [ncells, 4]."""
+        mode = TEND_FULL if mode is None else mode
+        self._check(self._lib.sp_closure_sample(self._h, float(dt), int(mode), _p(x), _p(t)))
 
     def resync_cells(self, cells, targets) -> int:
         """Move the floes of the listed cells to targets [ncl, 4] = (rho, P_x, P_y, P_w);

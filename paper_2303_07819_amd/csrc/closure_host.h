@@ -9,17 +9,23 @@
 namespace spdem {
 
 // Static descriptors of each cell's floes: n, A_ice / A, mean r, mean r^2,
-// mean h, sum m r^2 / sum m (one workgroup per cell, fixed-order FP64 sums).
-__global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cell_start, const float* r,
-                                                          const float* h, double inv_area, float* desc)
+// mean h, sum m r^2 / sum m; and the cell's mean-field drag coefficients
+// mf = (kappa_v, kappa_w, r2m, 0): kappa_v = C_d rho_o sum pi r^2 / sum m,
+// kappa_w = C_d rho_o sum pi r^5 / sum m (the drag and drag-torque laws of
+// Sec. 2.1 summed over the cell per unit mass), r2m = sum m r^2 / sum m.
+// One workgroup per cell (blockIdx.x, or cells[blockIdx.x] with a list),
+// fixed-order FP64 sums.
+__global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cells, const int32_t* cell_start,
+                                                          const float* r, const float* h, double inv_area,
+                                                          double cdrho_over_rho_ice, float* desc, double* mf)
 {
-    __shared__ double part[7][256];
-    const int c = blockIdx.x;
+    __shared__ double part[8][256];
+    const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
     const int s = cell_start[c], n = cell_start[c + 1] - s;
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int l = threadIdx.x; l < n; l += 256) {
         const double rl = r[s + l], hl = h[s + l];
-        const double m = hl * rl * rl;   // proportional to the mass (rho_ice pi cancels in the ratio)
+        const double m = hl * rl * rl;   // proportional to the mass (rho_ice pi cancels in the ratios)
         acc[0] += 1.0;
         acc[1] += kPi * rl * rl;
         acc[2] += rl;
@@ -27,25 +33,32 @@ __global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cell_st
         acc[4] += hl;
         acc[5] += m * rl * rl;
         acc[6] += m;
+        acc[7] += rl * rl * rl * rl * rl;
     }
 #pragma unroll
-    for (int k = 0; k < 7; ++k) part[k][threadIdx.x] = acc[k];
+    for (int k = 0; k < 8; ++k) part[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
 #pragma unroll
-            for (int k = 0; k < 7; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + w];
+            for (int k = 0; k < 8; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double nn = part[0][0];
+        const double nn = part[0][0], hm = part[6][0];
         float* d = desc + (size_t)c * 6;
         d[0] = (float)nn;
         d[1] = (float)(part[1][0] * inv_area);
         d[2] = nn > 0 ? (float)(part[2][0] / nn) : 0.0f;
         d[3] = nn > 0 ? (float)(part[3][0] / nn) : 0.0f;
         d[4] = nn > 0 ? (float)(part[4][0] / nn) : 0.0f;
-        d[5] = part[6][0] > 0 ? (float)(part[5][0] / part[6][0]) : 0.0f;
+        d[5] = hm > 0 ? (float)(part[5][0] / hm) : 0.0f;
+        double* q = mf + (size_t)c * 4;
+        // sum m = rho_ice pi sum h r^2
+        q[0] = hm > 0 ? cdrho_over_rho_ice * part[3][0] / hm : 0.0;
+        q[1] = hm > 0 ? cdrho_over_rho_ice * part[7][0] / hm : 0.0;
+        q[2] = hm > 0 ? part[5][0] / hm : 0.0;
+        q[3] = 0.0;
     }
 }
 
@@ -83,14 +96,119 @@ __global__ void features_kernel(const double* Q, int nx, int ny, const float2* p
     for (int q = 0; q < 6; ++q) o[39 + q] = desc[(size_t)c * 6 + q];
 }
 
-// Tendency (Q_now - Q_prev) / dt per cell, [nc][4] FP32.
-__global__ void tendency_kernel(const double* Qnow, const double* Qprev, int nc, double inv_dt, float* t)
+// Density below which a cell's continuum state gives no velocity: P / rho is
+// meaningless in (nearly) open water, where the floes' number average it
+// stands for has no floes behind it (1 kg/m^2 ~ 1 mm of ice spread over the cell).
+constexpr double kRhoCoefMin = 1.0;
+
+__device__ __forceinline__ double coarse_velocity(const double* Q, int nc, int X, int f)
+{
+    return Q[X] > kRhoCoefMin ? Q[(size_t)f * nc + X] / Q[X] : 0.0;
+}
+
+// The continuum update of a cell that the coarse state determines by itself
+// (the base of the closure) has two parts, applied in this order.
+//
+// Transport (transport_cell): the Lax-Friedrichs step of lf_cell with every
+// coefficient <v> taken as coarse_velocity (P_x, P_y) / rho of the continuum
+// state, without sources.
+//
+// Mean-field drag (relax_cell), local to the cell and applied to its
+// transported state (rho*, P*, P_w*): the cell's ice moving with P* / rho* and
+// spinning at P_w* / (rho* r2m) relaxes towards the ocean current and
+// half-curl at the cell centre over the step as one floe does under the drag
+// laws of Sec. 2.1 (dw/dt = -k |w| w has w(t) = w0 / (1 + k |w0| t), with
+// k = kappa_v for the velocity and kappa_w / r2m for the spin).  To first
+// order in dT the sources are dT rho kappa_v |du| du and dT rho kappa_w |dW| dW.
+//
+// Local physics acts on the transported state, not the old one, because the
+// averaging of the Lax-Friedrichs step maps a checkerboard pattern q to -q: a
+// source that damps the old value would push the new one further out (growth
+// by 1 + f / (1 + f) per step, f = k |w| dT), where damping the new value
+// shrinks it by 1 / (1 + f).  The learned residual is likewise a function of
+// the transported state.
+__device__ __forceinline__ void transport_cell(int C, const double* Q, int nx, int ny, double dT, double dX,
+                                               double dY, double out[4])
+{
+    const int nc = nx * ny;
+    const int ix = C % nx, iy = C / nx;
+    const int E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
+    const int W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
+    const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
+    const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
+    const double uE = coarse_velocity(Q, nc, E, 1), uW = coarse_velocity(Q, nc, W, 1);
+    const double vN = coarse_velocity(Q, nc, N, 2), vS = coarse_velocity(Q, nc, S, 2);
+    const double uC = coarse_velocity(Q, nc, C, 1), vC = coarse_velocity(Q, nc, C, 2);
+    const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
+        const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
+        const double avg = 0.25 * (qE + qW + qN + qS);
+        if (f == 0 || f == 3)
+            out[f] = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS);
+        else
+            out[f] = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY));
+    }
+}
+
+// Transported state of every cell: Qs [4][nc].
+__global__ void transport_kernel(const double* Q, double* Qs, int nx, int ny, double dT, double dX, double dY)
+{
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = nx * ny;
+    if (C >= nc) return;
+    double o[4];
+    transport_cell(C, Q, nx, ny, dT, dX, dY, o);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) Qs[(size_t)f * nc + C] = o[f];
+}
+
+__device__ __forceinline__ void relax_cell(int C, const double* Qs, int nc, const double* mf, const float2* phase,
+                                           int nmodes, const Modes& modes, float u0, float v0, double dT,
+                                           double out[4])
+{
+#pragma unroll
+    for (int f = 0; f < 4; ++f) out[f] = Qs[(size_t)f * nc + C];
+    double uo = u0, vo = v0, zeta = 0.0;
+    for (int m = 0; m < nmodes; ++m) {
+        const float2 sc = phase[(size_t)C * nmodes + m];
+        uo += (double)modes.au[m] * (double)sc.x;
+        vo += (double)modes.av[m] * (double)sc.x;
+        zeta += (double)modes.cz[m] * (double)sc.y;
+    }
+    const double* k = mf + (size_t)C * 4;
+    const bool moving = out[0] > kRhoCoefMin;
+    const double rho = out[0] > 0.0 ? out[0] : 0.0;
+    const double us = moving ? out[1] / out[0] : 0.0, vs = moving ? out[2] / out[0] : 0.0;
+    const double om = (moving && k[2] > 0.0) ? out[3] / (out[0] * k[2]) : 0.0;
+    const double du = uo - us, dv = vo - vs;
+    const double fv = dT * k[0] * sqrt(du * du + dv * dv);
+    const double dW = 0.5 * zeta - om;
+    const double fw = k[2] > 0.0 ? dT * k[1] / k[2] * fabs(dW) : 0.0;
+    out[1] += rho * du * fv / (1.0 + fv);
+    out[2] += rho * dv * fv / (1.0 + fv);
+    out[3] += rho * k[2] * dW * fw / (1.0 + fw);
+}
+
+// Tendency per cell, [nc][4] FP32: (Q_now - ref) / dt with ref = Qref (the
+// old state), or with `residual` ref = relax_cell of Qref (the transported old
+// state): the part of the update the coarse state does not determine.
+__global__ void tendency_kernel(const double* Qnow, const double* Qref, const double* mf, const float2* phase,
+                                int nmodes, Modes modes, float u0, float v0, int nc, double dt, int residual,
+                                float* t)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
+    double ref[4];
+    if (residual) {
+        relax_cell(c, Qref, nc, mf, phase, nmodes, modes, u0, v0, dt, ref);
+    } else {
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-        t[(size_t)c * 4 + f] = (float)((Qnow[(size_t)f * nc + c] - Qprev[(size_t)f * nc + c]) * inv_dt);
+        for (int f = 0; f < 4; ++f) ref[f] = Qref[(size_t)f * nc + c];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) t[(size_t)c * 4 + f] = (float)((Qnow[(size_t)f * nc + c] - ref[f]) / dt);
 }
 
 // Per-column mean and standard deviation of X [n][cols] (FP64, fixed order).
@@ -560,18 +678,35 @@ sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const i
 }
 
 // ------------------------------------------------- closure <-> simulation
+}  // extern "C"
+
+namespace {
+
+// Descriptors and mean-field coefficients of every cell, computed once per
+// floe set (cells re-synchronised later refresh their own).
+sp_status ensure_cell_data(sp_ctx* c)
+{
+    if (c->desc && c->mf) return SP_OK;
+    SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
+    SP_TRY(dalloc(c, &c->mf, (size_t)c->ncells * 4));
+    hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, nullptr, c->cell_start, c->r,
+                       c->h, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.cd * c->p.rho_ocean / c->p.rho_ice, c->desc,
+                       c->mf);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sp_status sp_closure_features(sp_ctx* c, float* x)
 {
     if (!c || !x) return c ? fail(c, SP_EINVAL, "null features buffer") : SP_EINVAL;
     if (!c->have_floes) return fail(c, SP_ESTATE, "no floes");
     SP_TRY(flush_lf(c));
     SP_TRY(upload_phase(c));
-    if (!c->desc) {
-        SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
-        hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, c->cell_start, c->r, c->h,
-                           1.0 / (c->p.cell_lx * c->p.cell_ly), c->desc);
-        HIP_TRY(c, hipGetLastError());
-    }
+    SP_TRY(ensure_cell_data(c));
     const StepArgs a = make_args(c, 0.0);
     hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
                        c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, x);
@@ -579,18 +714,34 @@ sp_status sp_closure_features(sp_ctx* c, float* x)
     return SP_OK;
 }
 
-sp_status sp_closure_sample(sp_ctx* c, double dt, float* x, float* t)
+sp_status sp_closure_sample(sp_ctx* c, double dt, int32_t mode, float* x, float* t)
 {
     if (!c || !x || !t) return c ? fail(c, SP_EINVAL, "null sample buffers") : SP_EINVAL;
+    if (mode != SP_TEND_FULL && mode != SP_TEND_RESIDUAL) return fail(c, SP_EINVAL, "unknown tendency mode %d", mode);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SP_EINVAL, "dt must be positive");
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "sampling needs the continuum update");
-    SP_TRY(sp_closure_features(c, x));
+    if (!c->have_floes) return fail(c, SP_ESTATE, "no floes");
+    SP_TRY(flush_lf(c));
+    SP_TRY(upload_phase(c));
+    SP_TRY(ensure_cell_data(c));
     if (!c->qprev) SP_TRY(dalloc(c, &c->qprev, (size_t)c->ncells * 4));
-    HIP_TRY(c, hipMemcpyAsync(c->qprev, c->Q[c->kstep & 1], (size_t)c->ncells * 4 * 8, hipMemcpyDeviceToDevice,
-                              c->stream));
+    const double* Q = c->Q[c->kstep & 1];
+    if (mode == SP_TEND_RESIDUAL) {
+        hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, Q, c->qprev,
+                           c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+        HIP_TRY(c, hipGetLastError());
+    } else {
+        HIP_TRY(c, hipMemcpyAsync(c->qprev, Q, (size_t)c->ncells * 4 * 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+    const StepArgs a = make_args(c, dt);
+    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->qprev, c->p.nx,
+                       c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, x);
+    HIP_TRY(c, hipGetLastError());
     SP_TRY(sp_step(c, dt, 1));
     SP_TRY(flush_lf(c));
     hipLaunchKernelGGL(tendency_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, c->Q[c->kstep & 1],
-                       c->qprev, c->ncells, 1.0 / dt, t);
+                       c->qprev, c->mf, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->ncells, dt,
+                       mode == SP_TEND_RESIDUAL ? 1 : 0, t);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }

@@ -8,13 +8,17 @@
 // A dP / M and the same spin shift A dP_w / sum I, which puts P and P_w exactly
 // on their targets.
 //
-// Hybrid step: cells flagged as closure cells skip the DEM and advance their
-// continuum state by the network's tendency, Q += dt T(features).  The other
+// Hybrid step: cells flagged as closure cells skip the DEM.  Their continuum
+// state takes the part of the update the coarse state determines by itself
+// (transport_cell, the Lax-Friedrichs step with <v> = P / rho, then
+// relax_cell, mean-field drag) plus the network's residual tendency for the
+// features of the transported state Q*: Q <- relax(Q*) + dt T(features(Q*)).
+// The other
 // cells run the DEM step and the Lax-Friedrichs update, which reads the
 // coefficient <v> = P / rho of neighbouring closure cells.  Every check_every
 // steps a rotating sample of closure cells is re-synchronised to its continuum
-// state; its DEM statistics give the tendency the plain method would apply
-// there, and a cell whose network tendency misses it by more than the
+// state; its DEM statistics give the residual tendency the plain method would
+// apply there, and a cell whose network output misses it by more than the
 // tolerance runs the DEM for the next fallback_steps steps.
 #pragma once
 
@@ -26,12 +30,16 @@ enum { RS_OK = 0, RS_CLAMPED = 1, RS_INVALID = 2 };
 // null, from the continuum state Q [4][nc].  The radius scale is limited so
 // that no radius exceeds r_lim (the contact-search bin radius); such a cell
 // reports RS_CLAMPED and keeps a smaller mass than its target.  A target that
-// cannot be met (rho <= 0 or not finite for a cell with floes, or anything
-// nonzero for an empty cell) leaves the cell unchanged and reports RS_INVALID.
+// cannot be met (rho <= 0 or not finite for a cell with floes, anything
+// nonzero for an empty cell, or, with max_ratio > 0, a mass more than
+// max_ratio times above or below the floes' mass, a mean speed |P| / rho above
+// max_speed or a mean spin above max_spin) leaves the cell unchanged and
+// reports RS_INVALID.
 __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
                                                      const float* h, float* u, float* v, float* w,
                                                      const double* targets, const double* Q, int nc,
-                                                     double rho_ice, double area, float r_lim, int32_t* status)
+                                                     double rho_ice, double area, float r_lim, double max_ratio,
+                                                     double max_speed, double max_spin, int32_t* status)
 {
     __shared__ double part[5][256];
     __shared__ double tot[5];
@@ -54,25 +62,40 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         if (tid == 0) status[blockIdx.x] = RS_INVALID;
         return;
     }
-    // mass and largest radius of the cell
-    double m0 = 0.0;
+    // mass, inertia and largest radius of the cell
+    double m0 = 0.0, i0 = 0.0;
     float r0 = 0.0f;
     for (int l = tid; l < n; l += 256) {
         const double rl = r[s + l];
-        m0 += rho_ice * (double)h[s + l] * kPi * rl * rl;
+        const double m = rho_ice * (double)h[s + l] * kPi * rl * rl;
+        m0 += m;
+        i0 += m * rl * rl;
         r0 = fmaxf(r0, r[s + l]);
     }
     part[0][tid] = m0;
+    part[1][tid] = i0;
     rpart[tid] = r0;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (tid < k) {
             part[0][tid] += part[0][tid + k];
+            part[1][tid] += part[1][tid + k];
             rpart[tid] = fmaxf(rpart[tid], rpart[tid + k]);
         }
         __syncthreads();
     }
-    double sc = sqrt(tg[0] * area / part[0][0]);
+    const double ratio = tg[0] * area / part[0][0];
+    if (max_ratio > 0.0) {
+        // inertia scales with the fourth power of the radius scale
+        const double spin = fabs(tg[3]) * area / (part[1][0] * ratio * ratio);
+        const double speed = sqrt(tg[1] * tg[1] + tg[2] * tg[2]) / tg[0];
+        if (ratio > max_ratio || ratio * max_ratio < 1.0 || speed > max_speed || spin > max_spin) {
+            if (tid == 0) status[blockIdx.x] = RS_INVALID;
+            return;
+        }
+    }
+    __syncthreads();
+    double sc = sqrt(ratio);
     const double lim = (double)r_lim / (double)rpart[0];
     const bool clamped = sc > lim;
     if (clamped) sc = lim;
@@ -112,47 +135,6 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     if (tid == 0) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
 }
 
-// Descriptors of the listed cells (definition of descriptors_kernel).
-__global__ __launch_bounds__(256) void descriptors_list_kernel(const int32_t* cells, const int32_t* cell_start,
-                                                               const float* r, const float* h, double inv_area,
-                                                               float* desc)
-{
-    __shared__ double part[7][256];
-    const int c = cells[blockIdx.x];
-    const int s = cell_start[c], n = cell_start[c + 1] - s;
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int l = threadIdx.x; l < n; l += 256) {
-        const double rl = r[s + l], hl = h[s + l];
-        const double m = hl * rl * rl;
-        acc[0] += 1.0;
-        acc[1] += kPi * rl * rl;
-        acc[2] += rl;
-        acc[3] += rl * rl;
-        acc[4] += hl;
-        acc[5] += m * rl * rl;
-        acc[6] += m;
-    }
-#pragma unroll
-    for (int k = 0; k < 7; ++k) part[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int wv = 128; wv > 0; wv >>= 1) {
-        if ((int)threadIdx.x < wv)
-#pragma unroll
-            for (int k = 0; k < 7; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + wv];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double nn = part[0][0];
-        float* d = desc + (size_t)c * 6;
-        d[0] = (float)nn;
-        d[1] = (float)(part[1][0] * inv_area);
-        d[2] = nn > 0 ? (float)(part[2][0] / nn) : 0.0f;
-        d[3] = nn > 0 ? (float)(part[3][0] / nn) : 0.0f;
-        d[4] = nn > 0 ? (float)(part[4][0] / nn) : 0.0f;
-        d[5] = part[6][0] > 0 ? (float)(part[5][0] / part[6][0]) : 0.0f;
-    }
-}
-
 // Features (layout of features_kernel) of the listed cells into consecutive rows.
 __global__ void features_list_kernel(const int32_t* cells, int ncl, const double* Q, int nx, int ny,
                                      const float2* phase, int nmodes, Modes modes, float u0, float v0,
@@ -187,41 +169,46 @@ __global__ void features_list_kernel(const int32_t* cells, int ncl, const double
     for (int q = 0; q < 6; ++q) o[39 + q] = desc[(size_t)c * 6 + q];
 }
 
-// Continuum coefficient <v> = P / rho of the listed (closure) cells.
+// Continuum coefficient <v> = P / rho (coarse_velocity) of the listed closure cells.
 __global__ void closure_coeff_kernel(const int32_t* cells, int ncl, const double* Q, int nc, double* mom)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncl) return;
     const int c = cells[i];
-    const double rho = Q[c];
-    mom[(size_t)c * kMomStride + M_UBAR] = rho > 0.0 ? Q[(size_t)nc + c] / rho : 0.0;
-    mom[(size_t)c * kMomStride + M_VBAR] = rho > 0.0 ? Q[(size_t)2 * nc + c] / rho : 0.0;
+    mom[(size_t)c * kMomStride + M_UBAR] = coarse_velocity(Q, nc, c, 1);
+    mom[(size_t)c * kMomStride + M_VBAR] = coarse_velocity(Q, nc, c, 2);
 }
 
-// Continuum step of the hybrid: closure cells Q + dT T, the others LF.
-__global__ void hybrid_continuum_kernel(const double* mom, const double* Q, double* Qn, const int32_t* row,
-                                        const float* T, int nx, int ny, double dT, double dX, double dY,
-                                        double inv_area, unsigned long long* max_cfl_bits, uint32_t* err)
+// Continuum step of the hybrid: closure cells relax_cell(Qs) + dT T (Qs: the
+// transported state, T: the network's residual tendency for its features), the
+// others the LF step of their statistics.
+__global__ void hybrid_continuum_kernel(const double* mom, const double* Q, const double* Qs, double* Qn,
+                                        const int32_t* row, const float* T, const double* mf, const float2* phase,
+                                        int nmodes, Modes modes, float u0, float v0, int nx, int ny, double dT,
+                                        double dX, double dY, double inv_area, unsigned long long* max_cfl_bits,
+                                        uint32_t* err)
 {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     const int nc = nx * ny;
     if (C >= nc) return;
     const int q = row[C];
     if (q >= 0) {
+        double b[4];
+        relax_cell(C, Qs, nc, mf, phase, nmodes, modes, u0, v0, dT, b);
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
-            Qn[(size_t)f * nc + C] = Q[(size_t)f * nc + C] + dT * (double)T[(size_t)q * 4 + f];
+        for (int f = 0; f < 4; ++f) Qn[(size_t)f * nc + C] = b[f] + dT * (double)T[(size_t)q * 4 + f];
     } else {
         lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
     }
 }
 
-// Plain-method tendency (LF(Q) - Q) / dT of the listed cells: their own
-// coefficients and sources from the statistics `fresh`, the neighbours'
-// coefficients from `mom`.
+// Plain-method residual tendency (LF(Q) - relax_cell(Qs)) / dT of the listed
+// cells: their own coefficients and sources from the statistics `fresh`, the
+// neighbours' coefficients from `mom`; Qs is the transported state.
 __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const double* fresh, const double* mom,
-                                      const double* Q, int nx, int ny, double dT, double dX, double dY,
-                                      double inv_area, float* T)
+                                      const double* Q, const double* Qs, const double* mf, const float2* phase,
+                                      int nmodes, Modes modes, float u0, float v0, int nx, int ny, double dT,
+                                      double dX, double dY, double inv_area, float* T)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncl) return;
@@ -239,8 +226,9 @@ __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const doubl
     const double vN = N == C ? vC : mom[(size_t)N * kMomStride + M_VBAR];
     const double vS = S == C ? vC : mom[(size_t)S * kMomStride + M_VBAR];
     const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
+    double base[4];
+    relax_cell(C, Qs, nc, mf, phase, nmodes, modes, u0, v0, dT, base);
     for (int f = 0; f < 4; ++f) {
-        const double qC = Q[(size_t)f * nc + C];
         const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
         const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
         const double avg = 0.25 * (qE + qW + qN + qS);
@@ -252,7 +240,7 @@ __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const doubl
             qn = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY)) +
                  dT * sC[f == 1 ? M_SVX : M_SVY] * inv_area;
         }
-        T[(size_t)i * 4 + f] = (float)((qn - qC) / dT);
+        T[(size_t)i * 4 + f] = (float)((qn - base[f]) / dT);
     }
 }
 
@@ -278,10 +266,19 @@ struct HybridState {
     float* Tk = nullptr;
     float* Tdem = nullptr;
     double* fresh = nullptr;              // statistics of re-synchronised cells [ncells][kMomStride]
+    double* Qs = nullptr;                 // transported continuum state [4][ncells]
     int ndem = 0;
 };
 
 namespace {
+
+// Limits of the state a check re-synchronises a cell to: beyond them the
+// closure has failed there and the cell falls back with its floes as they are.
+// The speed and spin limits keep the floes inside the range where the explicit
+// quadratic drag is stable (k |du| dt < 2 with k = C_d rho_o / (rho_ice h)).
+constexpr double kCheckMassRatio = 4.0;   // mass change factor
+constexpr double kCheckMaxSpeed = 2.0;    // m/s
+constexpr double kCheckMaxSpin = 1e-2;    // 1/s
 
 void hybrid_free_buffers(HybridState* h)
 {
@@ -291,22 +288,12 @@ void hybrid_free_buffers(HybridState* h)
         b.work_d = nullptr;
         b.q_d = nullptr;
     }
-    void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->rs_d, h->Xk, h->Tk, h->Tdem, h->fresh};
+    void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->rs_d, h->Xk, h->Tk, h->Tdem, h->fresh, h->Qs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     h->clos_d = h->row_d = h->chk_d = h->rs_d = nullptr;
     h->X = h->T = h->Xk = h->Tk = h->Tdem = nullptr;
-    h->fresh = nullptr;
-}
-
-sp_status ensure_desc(sp_ctx* c)
-{
-    if (c->desc) return SP_OK;
-    SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
-    hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, c->cell_start, c->r, c->h,
-                       1.0 / (c->p.cell_lx * c->p.cell_ly), c->desc);
-    HIP_TRY(c, hipGetLastError());
-    return SP_OK;
+    h->fresh = h->Qs = nullptr;
 }
 
 // Rebuild the DEM buckets and the closure list from the current modes.
@@ -357,16 +344,19 @@ sp_status net_forward_on(sp_ctx* c, sp_mlp* net, const float* x, int rows, float
 
 // Re-synchronise the listed cells (device list); per-cell status into status_d;
 // descriptors refreshed if they exist.
-sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* targets_d, int32_t* status_d)
+sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* targets_d, bool guarded,
+                      int32_t* status_d)
 {
     if (ncl <= 0) return SP_OK;
     hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
                        c->v, c->w, targets_d, c->Q[c->kstep & 1], c->ncells, c->p.rho_ice,
-                       c->p.cell_lx * c->p.cell_ly, c->r_bin, status_d);
+                       c->p.cell_lx * c->p.cell_ly, c->r_bin, guarded ? kCheckMassRatio : 0.0, kCheckMaxSpeed,
+                       kCheckMaxSpin, status_d);
     HIP_TRY(c, hipGetLastError());
-    if (c->desc) {
-        hipLaunchKernelGGL(descriptors_list_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r,
-                           c->h, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->desc);
+    if (c->desc && c->mf) {
+        hipLaunchKernelGGL(descriptors_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h,
+                           1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.cd * c->p.rho_ocean / c->p.rho_ice, c->desc,
+                           c->mf);
         HIP_TRY(c, hipGetLastError());
     }
     return SP_OK;
@@ -383,8 +373,9 @@ sp_status hybrid_check(sp_ctx* c, double dt)
     for (int i = 0; i < nk; ++i) pick[i] = h->clos_h[(size_t)((h->cursor + i) % nclos)];
     h->cursor = (h->cursor + nk) % nclos;
     HIP_TRY(c, hipMemcpyAsync(h->chk_d, pick.data(), (size_t)nk * 4, hipMemcpyHostToDevice, c->stream));
-    // 1. the sampled cells' floes to their continuum state
-    SP_TRY(resync_list(c, h->chk_d, nk, nullptr, h->rs_d));
+    // 1. the sampled cells' floes to their continuum state, unless it asks for a
+    //    mass change beyond kCheckMassRatio: the closure has then failed there
+    SP_TRY(resync_list(c, h->chk_d, nk, nullptr, true, h->rs_d));
     // 2. their statistics and the plain method's tendency; the neighbours'
     //    coefficients are those of the step just taken
     StepArgs a = make_args(c, dt);
@@ -393,14 +384,16 @@ sp_status hybrid_check(sp_ctx* c, double dt)
     HIP_TRY(c, hipGetLastError());
     const int64_t k = c->kstep - 1;
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
+    hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
+                       h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+    HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(check_tendency_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, h->fresh,
-                       c->momb[k & 1], c->Q[c->kstep & 1], c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
-                       inv_area, h->Tdem);
+                       c->momb[k & 1], c->Q[c->kstep & 1], h->Qs, c->mf, c->phase, c->nmodes, a.modes, a.u0, a.v0,
+                       c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly, inv_area, h->Tdem);
     HIP_TRY(c, hipGetLastError());
     // 3. the network's tendency for the same cells
-    hipLaunchKernelGGL(features_list_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk,
-                       c->Q[c->kstep & 1], c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc,
-                       h->Xk);
+    hipLaunchKernelGGL(features_list_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, h->Qs,
+                       c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, h->Xk);
     HIP_TRY(c, hipGetLastError());
     SP_TRY(net_forward_on(c, h->net, h->Xk, nk, h->Tk));
     std::vector<float> tm((size_t)nk * 4), td((size_t)nk * 4), ys(4);
@@ -478,7 +471,7 @@ sp_status sp_resync_cells(sp_ctx* c, int32_t ncl, const int32_t* cells, const do
     if (!st && (hipMemcpyAsync(cd, cells, (size_t)ncl * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
                 hipMemcpyAsync(td, targets, (size_t)ncl * 4 * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess))
         st = fail(c, SP_EDEVICE, "target upload failed");
-    if (!st) st = resync_list(c, cd, ncl, td, sd);
+    if (!st) st = resync_list(c, cd, ncl, td, false, sd);
     if (!st && hipMemcpyAsync(rs.data(), sd, (size_t)ncl * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         st = fail(c, SP_EDEVICE, "status download failed");
     if (hipStreamSynchronize(c->stream) != hipSuccess && !st) st = fail(c, SP_EDEVICE, "synchronisation failed");
@@ -514,6 +507,8 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     c->hyb = h;
     h->net = net;
     h->closure.assign(closure_cells, closure_cells + c->ncells);
+    for (int i = 0; i < c->ncells; ++i)   // a cell without floes has no DEM work: the plain update is exact
+        if (c->counts_h[i] == 0) h->closure[i] = 0;
     h->fallback_left.assign(c->ncells, 0);
     h->check_every = check_every;
     h->check_cells = check_cells;
@@ -531,8 +526,9 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     SP_TRY(dalloc(c, &h->Tk, nk * spmlp::kOut));
     SP_TRY(dalloc(c, &h->Tdem, nk * spmlp::kOut));
     SP_TRY(dalloc(c, &h->fresh, (size_t)c->ncells * kMomStride));
+    SP_TRY(dalloc(c, &h->Qs, (size_t)c->ncells * 4));
     SP_TRY(upload_phase(c));
-    SP_TRY(ensure_desc(c));
+    SP_TRY(ensure_cell_data(c));
     drop_graph(c);
     return hybrid_rebuild(c);
 }
@@ -556,10 +552,14 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
         const int64_t k = c->kstep;
         const int nclos = (int)h->clos_h.size();
         if (nclos > 0) {
-            // closure tendencies and coefficients from the level-k state
+            // transported level-k state, closure tendencies for its features,
+            // closure-cell coefficients of the level-k state
+            hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
+                               h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+            HIP_TRY(c, hipGetLastError());
             hipLaunchKernelGGL(features_list_kernel, dim3((nclos + 127) / 128), dim3(128), 0, c->stream, h->clos_d,
-                               nclos, c->Q[k & 1], c->p.nx, c->p.ny, c->phase, c->nmodes, base.modes, base.u0,
-                               base.v0, c->desc, h->X);
+                               nclos, h->Qs, c->p.nx, c->p.ny, c->phase, c->nmodes, base.modes, base.u0, base.v0,
+                               c->desc, h->X);
             HIP_TRY(c, hipGetLastError());
             SP_TRY(net_forward_on(c, h->net, h->X, nclos, h->T));
             hipLaunchKernelGGL(closure_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream, h->clos_d,
@@ -569,8 +569,9 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
         // DEM step of the other cells (statistics of level k)
         for (auto& b : h->bk) SP_TRY(launch_bucket(c, b, base, k, false));
         hipLaunchKernelGGL(hybrid_continuum_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream,
-                           c->momb[k & 1], c->Q[k & 1], c->Q[(k + 1) & 1], h->row_d, h->T, c->p.nx, c->p.ny, dt,
-                           c->p.cell_lx, c->p.cell_ly, inv_area, c->cfl_bits_d, c->err_d);
+                           c->momb[k & 1], c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->mf, c->phase,
+                           c->nmodes, base.modes, base.u0, base.v0, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
+                           inv_area, c->cfl_bits_d, c->err_d);
         HIP_TRY(c, hipGetLastError());
         c->kstep++;
         c->steps++;

@@ -94,6 +94,7 @@ struct sp_ctx {
     unsigned long long* contacts_d = nullptr;
     unsigned long long* cfl_bits_d = nullptr;
     float* desc = nullptr;                  // closure descriptors [ncells][6] (lazy)
+    double* mf = nullptr;                   // mean-field drag coefficients [ncells][4] (with desc)
     double* qprev = nullptr;                // continuum snapshot for tendencies
 
     // time stepping
@@ -172,7 +173,7 @@ void free_all(sp_ctx* c)
     hybrid_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d, c->desc, c->qprev};
+                  c->cfl_bits_d, c->desc, c->mf, c->qprev};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -190,6 +191,7 @@ void free_all(sp_ctx* c)
     c->err_d = nullptr;
     c->contacts_d = c->cfl_bits_d = nullptr;
     c->desc = nullptr;
+    c->mf = nullptr;
     c->qprev = nullptr;
 }
 
@@ -656,7 +658,9 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     hybrid_free(c);   // its cell lists follow the floes
     c->have_floes = false;
     if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
+    if (c->mf) (void)hipFree(c->mf);
     c->desc = nullptr;
+    c->mf = nullptr;
     const size_t N = (size_t)n;
     SP_TRY(dalloc(c, &c->xi, N));
     SP_TRY(dalloc(c, &c->yi, N));

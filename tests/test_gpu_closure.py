@@ -9,6 +9,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import rel_err
+from closure_ref import base_update, transport
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
@@ -181,3 +182,42 @@ def test_features_and_tendencies_match_oracle():
     et = np.abs(ts - tend) / np.maximum(np.abs(tend), 1e-2 * np.sqrt(np.mean(tend ** 2, axis=0)))
     _say(f"tendency max rel err {et.max():.2e}")
     assert et.max() <= 1e-3
+
+
+def test_residual_tendencies_match_oracle():
+    """Residual samples: the features of the transported state Q* and the
+    targets (Q_new - relax(Q*)) / dt of closure_ref.py."""
+    w = fixtures.custom(5, 4, 25e3, 40, seed=22, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    rng = np.random.default_rng(22)
+    w.u[:] = rng.normal(0, 0.1, w.nfloes)
+    w.v[:] = rng.normal(0, 0.1, w.nfloes)
+    nsteps = 2
+    _, Q0, _, _ = oracle.run_plain(w, nsteps)
+    _, Q1, _, _ = oracle.run_plain(w, nsteps + 1)
+    m = oracle.Model(w)
+    Qb = base_update(w, m, Q0, w.dt)
+    ref = (Q1 - Qb) / w.dt
+    Qs = transport(m, Q0, w.dt)
+    with sp.Sim.from_workload(w) as s:
+        s.step(w.dt, nsteps)
+        x = torch.zeros((w.ncells, 45), device="cuda")
+        t = torch.zeros((w.ncells, 4), device="cuda")
+        s.closure_sample(w.dt, x, t, mode=sp.TEND_RESIDUAL)
+        torch.cuda.synchronize()
+        xs, ts = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    xref = np.zeros((w.ncells, 36))
+    for c in range(w.ncells):
+        ix, iy = c % w.nx, c // w.nx
+        k = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb = ((iy + dy) % w.ny) * w.nx + (ix + dx) % w.nx
+                xref[c, k:k + 4] = Qs[nb]
+                k += 4
+    ex = rel_err(xs[:, :36], xref)
+    _say(f"transported-state features max rel err {ex.max():.2e}")
+    assert ex.max() <= 1e-5
+    # the residual is the small part of the update: measure against its own scale
+    e = np.abs(ts - ref) / np.maximum(np.abs(ref), 1e-2 * np.sqrt(np.mean(ref ** 2, axis=0)))
+    _say(f"residual tendency max rel err {e.max():.2e}")
+    assert e.max() <= 1e-3
