@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-hybrid", action="store_true",
+                    help="skip training the closure and the DEM + closure run on the 512 x 512 grid")
+    ap.add_argument("--hybrid-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -121,10 +124,41 @@ def main():
         "contacts_per_floe_step": contacts_per_floe_step,
         "wall_s_timed": wall,
     }
+    if not args.no_hybrid:
+        out["hybrid"] = hybrid_leg(args, stream)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def hybrid_leg(args, stream):
+    """Plain DEM vs DEM + closure on the 512 x 512 grid (33.6M floes): the
+    closure is trained here, on the GPU, from the method's own runs."""
+    import time as _t
+    import torch
+    import fixtures
+    from paper_2303_07819_amd import closure as cl
+
+    def log(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    t0 = _t.perf_counter()
+    X, T = cl.training_set(stream=stream.cuda_stream, log=log)
+    t1 = _t.perf_counter()
+    net, hist = cl.train(X, T, stream=stream.cuda_stream, log=log)
+    del X, T
+    torch.cuda.empty_cache()
+    w = fixtures.make_config("hybrid512")
+    log(f"hybrid512: {w.nfloes} floes in {w.ncells} cells")
+    res = cl.hybrid_experiment(w, net, args.hybrid_steps, stream, log=log)
+    net.close()
+    res["training"] = {"samples": hist["samples"], "epochs": len(hist["train"]), "adam_steps": hist["steps"],
+                       "seconds": hist["seconds"], "sampling_seconds": t1 - t0,
+                       "final_train_loss": hist["train"][-1], "held_out_loss": hist["val"][-1]}
+    res["workload"] = "hybrid512"
+    res["metric"] = "floe-steps/s, plain DEM vs DEM + closure, relative L2 moment error vs full DEM"
+    return res
 
 
 if __name__ == "__main__":

@@ -27,6 +27,10 @@ the paper is nondimensional and gives no SI values):
 ``closure256`` 256x256 cells, plain64-style fields (closure inference grid)
 ``hybrid512``  512x512 cells, Poisson(256 c) floes/cell, dt 30 s
 =============  =====================================================================
+
+Every 25 km-cell workload draws its 8 ocean modes as integer wave-vectors
+2 <= |(p, q)| <= 16 on its own periodic domain (100-800 km wavelengths on the
+64 x 64 grid, proportionally longer on the larger grids).
 """
 from __future__ import annotations
 

@@ -198,12 +198,25 @@ sp_status sp_set_graph_chunk(sp_ctx* ctx, int32_t chunk);
  * squared error on normalised targets.  Parameters are one flat FP32 vector of
  * SP_MLP_NPARAMS entries: W1 [128 x 45], b1, W2 [128 x 128], b2, W3, b3,
  * W4 [4 x 128], b4 (row-major, W[o][i] multiplies input i into output o).
- * Inputs per cell (SP_MLP_IN): the continuum state (rho, P_x, P_y, P_w) of the
+ * Inputs per cell (SP_MLP_IN): a continuum state (rho, P_x, P_y, P_w) on the
  * 3 x 3 neighbourhood row by row from the south-west (36), the ocean current
- * and curl at the cell centre (3), and the cell's static floe descriptors n,
- * A_ice / A, mean r, mean r^2, mean h, sum m r^2 / sum m (6).  Outputs
- * (SP_MLP_OUT): d(rho, P_x, P_y, P_w)/dt.  Inputs and outputs are normalised
+ * and curl at the cell centre (3), the cell's A_ice / A, mean h and
+ * r2m = sum m r^2 / sum m (3), and the relative velocity and spin of its
+ * reduced DEM (below) at the current time (3).  Outputs (SP_MLP_OUT): moment
+ * tendencies d(rho, P_x, P_y, P_w)/dt.  Inputs and outputs are normalised
  * per column by the stored means and standard deviations.
+ *
+ * Reduced DEM of a cell: its floes seen as one body under the drag laws of
+ * Sec. 2.1.  Taken from the floes at time t0 (mean velocity U = sum v / n,
+ * mean spin W = L / (M r2m)), its velocity and spin relative to the ocean
+ * current u_o and half-curl at the cell centre relax in the closed form of a
+ * single floe's quadratic drag, du(t) = du(t0) / (1 + k_v |du(t0)| (t - t0)),
+ * dW(t) = dW(t0) / (1 + (k_w / r2m) |dW(t0)| (t - t0)), with the cell's
+ * k_v = C_d rho_o sum pi r^2 / sum m and k_w = C_d rho_o sum pi r^5 / sum m.
+ * Its statistics are the coefficient <v> = u_o - du and the sources per unit
+ * area rho_f k_v |du| du and rho_f k_w |dW| dW, rho_f = sum m / A.  Every
+ * cell's reduced DEM is taken from its floes when they are set, when the
+ * ocean is set, and when the cell is re-synchronised.
  * All data pointers of the sp_mlp_* calls are device pointers except where
  * marked host.  The object runs on its own stream (or the one given). */
 #define SP_MLP_NPARAMS 39428
@@ -233,22 +246,14 @@ sp_status sp_mlp_train_step(sp_mlp* net, const float* X, const float* T, const i
 /* floor(n / batch) Adam steps over X, T in the order of perm (device [n]); *mean_loss (host) */
 sp_status sp_mlp_train_epoch(sp_mlp* net, const float* X, const float* T, const int32_t* perm, int64_t n,
                              int32_t batch, float lr, float* mean_loss);
-/* closure inputs of every cell of the current state into x [ncells][45] (device) */
+/* closure inputs of every cell of the current state Q into x [ncells][45] (device) */
 sp_status sp_closure_features(sp_ctx* ctx, float* x);
-/* Tendency targets of sp_closure_sample.  SP_TEND_FULL: (Q_new - Q_old) / dt,
- * with the features of Q_old.  SP_TEND_RESIDUAL: the part of the update the
- * coarse state does not determine, with the features of the transported state
- * Q* (below): (Q_new - relax(Q*)) / dt.  Q* is the continuum update of Sec. 3.2
- * without sources and with every coefficient <v> taken as (P_x, P_y) / rho of
- * the continuum state itself (0 where rho <= 1 kg/m^2, nearly open water);
- * relax moves each cell of Q* by mean-field drag: its ice, moving with
- * P* / rho* and spinning at P_w* / (rho* r2m), relaxes over dt towards the
- * ocean current and half-curl at the cell centre by the closed form
- * w / (1 + k |w| dt) of one floe's quadratic drag (Sec. 2.1), with
- * k = C_d rho_o sum pi r^2 / sum m for the velocity and
- * C_d rho_o sum pi r^5 / sum m r^2 for the spin, r2m = sum m r^2 / sum m,
- * sums over the cell's floes.  The hybrid uses networks trained on
- * SP_TEND_RESIDUAL. */
+/* Samples of sp_closure_sample.  SP_TEND_FULL: features of the current state
+ * Q, targets (Q_new - Q) / dt.  SP_TEND_RESIDUAL: the part of the update the
+ * reduced DEMs do not give, the training target of the hybrid's network:
+ * features of the base-updated state Q_b, targets (Q_new - Q_b) / dt, where
+ * Q_b is the continuum update of Sec. 3.2 with the statistics of every cell
+ * taken from its reduced DEM. */
 #define SP_TEND_FULL 0
 #define SP_TEND_RESIDUAL 1
 /* one training sample per cell: inputs of `mode` into x [ncells][45], one
@@ -273,7 +278,8 @@ sp_status sp_closure_sample(sp_ctx* ctx, double dt, int32_t mode, float* x, floa
  * only during the call.  Errors: SP_EINVAL (index out of range or repeated,
  * rho <= 0 or non-finite target for a cell with floes, nonzero target for
  * an empty cell; nothing is changed then), SP_ESTATE (no floes), SP_ENOMEM,
- * SP_EDEVICE.  Synchronises. */
+ * SP_EDEVICE.  The cells' reduced DEMs restart from the re-synchronised
+ * floes.  Synchronises. */
 sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const double* targets,
                           int32_t* clamped);
 
@@ -281,32 +287,38 @@ sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const 
  * DEM + closure hybrid.  closure_cells (host, [ncells], copied) flags the
  * cells whose continuum state advances without their DEM (a flag on a cell
  * without floes is ignored: its plain update needs no DEM work):
- * Q <- relax(Q*) + dt T(features of Q*), with Q*, relax and the features of
- * SP_TEND_RESIDUAL and T the output of a network trained on its targets.  All other cells run the DEM step and the continuum update of
- * Sec. 3.2, which takes <v> = (P_x, P_y) / rho as the coefficient of a
- * neighbouring closure cell.  Every check_every steps the next check_cells
- * closure cells (round robin) are re-synchronised to their continuum state
- * (as sp_resync_cells); their DEM statistics then give the plain method's
- * residual tendency T_dem, and a cell whose network output differs from it by
- * more than tol (|T_dem| + 0.1 sd) in any component (sd: the network's output
- * scale) runs the DEM for the next fallback_steps steps.  A checked cell whose
- * continuum mass is more than 4 times above or below its floes' mass, or not
- * positive, falls back without being re-synchronised.  A null closure_cells removes the hybrid.  The network
- * must stay alive and unchanged while the hybrid is set; it runs on the
- * simulation's stream.  Setting new floes removes the hybrid.
+ * Q <- Q_b + dt T(features of Q_b), with Q_b and the features of
+ * SP_TEND_RESIDUAL and T the output of a network trained on its targets.  All
+ * other cells run the DEM step and the continuum update of Sec. 3.2, which
+ * takes the reduced DEM's <v> as the coefficient of a neighbouring closure
+ * cell.  A closure cell's floes stay frozen.  Every check_every steps the next
+ * check_cells closure cells (round robin) are checked: their floes catch up
+ * with the DEM steps they missed (the cells' DEMs do not interact, so these
+ * are the plain method's floes), their statistics give the plain method's
+ * residual tendency T_dem, and a cell whose closure residual T (T = 0 once
+ * its reduced DEM is older than net_window) misses it so much that
+ * check_every dt |T - T_dem| exceeds tol (|Q_cell| + 0.01 mean |Q| of the
+ * sample) in any component runs the DEM for the next fallback_steps steps,
+ * after which its reduced DEM restarts from its floes.  Every checked cell's
+ * reduced DEM restarts from its caught-up floes.  With net_window > 0 the
+ * network's term is applied to a closure cell only during the first
+ * net_window seconds of its reduced DEM (the relaxation transient the network
+ * is trained on); later the reduced DEM alone carries the cell.  A null
+ * closure_cells removes the hybrid.  The network must stay alive and
+ * unchanged while the hybrid is set; it runs on the simulation's stream.
+ * Setting new floes removes the hybrid.
  * Errors: SP_EINVAL, SP_ESTATE (no floes, or SP_NO_CONTINUUM), SP_ENOMEM,
  * SP_EDEVICE.  Synchronises. */
 sp_status sp_hybrid_set(sp_ctx* ctx, sp_mlp* net, const uint8_t* closure_cells, int32_t check_every,
-                        int32_t check_cells, double tol, int32_t fallback_steps);
+                        int32_t check_cells, double tol, int32_t fallback_steps, double net_window);
 /* nsteps hybrid steps of size dt (asynchronous except at checks and mode
- * changes).  Floe statistics of closure cells are not advanced.
+ * changes).
  * Errors: SP_EINVAL, SP_ESTATE (no hybrid), SP_EDEVICE. */
 sp_status sp_step_hybrid(sp_ctx* ctx, double dt, int64_t nsteps);
 /* current DEM-mode and closure-mode cell counts, checks made, fallbacks
- * triggered, checked cells whose re-synchronisation was clamped (host, any may
- * be NULL).  Errors: SP_ESTATE (no hybrid). */
+ * triggered (host, any may be NULL).  Errors: SP_ESTATE (no hybrid). */
 sp_status sp_hybrid_stats(sp_ctx* ctx, int32_t* dem_cells, int32_t* closure_cells, int64_t* checks,
-                          int64_t* fallbacks, int64_t* clamped);
+                          int64_t* fallbacks);
 
 /* Schedule actually used for the current floes (after SP_SCHED_AUTO), and the
  * sub-bins per side it uses (1 for all-pairs). */

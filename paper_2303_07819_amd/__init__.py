@@ -103,10 +103,10 @@ def load_library(path: str = LIB_PATH):
     lib.sp_closure_sample.argtypes = [P, D, I32, P, P]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sp_resync_cells.argtypes = [P, I32, P, P, ctypes.POINTER(I32)]
-    lib.sp_hybrid_set.argtypes = [P, P, P, I32, I32, D, I32]
+    lib.sp_hybrid_set.argtypes = [P, P, P, I32, I32, D, I32, D]
     lib.sp_step_hybrid.argtypes = [P, D, I64]
     lib.sp_hybrid_stats.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64),
-                                    ctypes.POINTER(I64), ctypes.POINTER(I64)]
+                                    ctypes.POINTER(I64)]
     for name in EXPORTED:
         fn = getattr(lib, name)
         if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error"):
@@ -280,16 +280,16 @@ class Sim:
         self._check(self._lib.sp_resync_cells(self._h, int(cl.size), _p(cl), _p(tg), ctypes.byref(n)))
         return int(n.value)
 
-    def hybrid_set(self, net, closure_cells, check_every: int = 50, check_cells: int = 64, tol: float = 0.2,
-                   fallback_steps: int = 100):
+    def hybrid_set(self, net, closure_cells, check_every: int = 250, check_cells: int = 256, tol: float = 0.02,
+                   fallback_steps: int = 100, net_window: float = 0.0):
         """Flag closure cells (bool array [ncells]) for the network `net` (an MLP); None removes the hybrid."""
         if closure_cells is None:
-            self._check(self._lib.sp_hybrid_set(self._h, None, None, 1, 0, 1.0, 1))
+            self._check(self._lib.sp_hybrid_set(self._h, None, None, 1, 0, 1.0, 1, 0.0))
             self._net = None
             return
         m = _c(np.asarray(closure_cells).astype(np.uint8), np.uint8)
         self._check(self._lib.sp_hybrid_set(self._h, net._h, _p(m), int(check_every), int(check_cells), float(tol),
-                                            int(fallback_steps)))
+                                            int(fallback_steps), float(net_window)))
         self._net = net   # the network must outlive the hybrid
 
     def step_hybrid(self, dt: float, nsteps: int = 1):
@@ -297,11 +297,11 @@ class Sim:
 
     def hybrid_stats(self) -> dict:
         a, b = ctypes.c_int32(), ctypes.c_int32()
-        c, d, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        c, d = ctypes.c_int64(), ctypes.c_int64()
         self._check(self._lib.sp_hybrid_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                              ctypes.byref(d), ctypes.byref(e)))
+                                              ctypes.byref(d)))
         return {"dem_cells": int(a.value), "closure_cells": int(b.value), "checks": int(c.value),
-                "fallbacks": int(d.value), "clamped": int(e.value)}
+                "fallbacks": int(d.value)}
 
     def schedule(self):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -2,13 +2,13 @@
 the GPU, and the DEM + closure hybrid measured against full DEM.
 
 Everything here drives the C library (``Sim`` and ``MLP``); the arithmetic runs
-in its kernels.  The network maps a cell's features (the continuum state of
-its 3 x 3 neighbourhood, the ocean current and curl at its centre and six
-static floe descriptors) to the residual tendency of its continuum state: the
-part of (Q_new - Q_old) / dt that the coarse state does not determine by itself
-(the drag sources and the difference between the number-averaged velocity of
-the floes and P / rho).  The hybrid advances closure cells by the
-Lax-Friedrichs step with <v> = P / rho plus dt times that residual.
+in its kernels.  A closure cell replaces its DEM by a reduced DEM (the cell's
+floes as one body relaxing towards the ocean under the drag laws, in closed
+form) whose statistics drive the continuum update as the DEM's would, and the
+network adds the residual: the part of the plain method's update the reduced
+DEMs miss (the spread of floe thicknesses and velocities, contacts), as a
+function of the base-updated continuum state around the cell, the ocean, three
+static floe descriptors and the reduced DEM's relative velocity and spin.
 
 Training runs are synthetic: grids of 25 km cells with a marginal-ice-zone
 concentration field, Poisson floe counts and seeded Fourier-mode currents, so
@@ -26,31 +26,40 @@ from . import MLP, Sim, TEND_RESIDUAL, MOMENTS_CONTINUUM
 MIZ_LO, MIZ_HI = 0.15, 0.8   # marginal ice zone: the DEM runs where lo <= c <= hi
 
 
-def training_workload(seed: int, n: int = 64, nmax: int = 256):
-    """A 64 x 64 grid of 25 km cells, Poisson(nmax c) floes per cell with a
+def training_workload(seed: int, n: int = 64, nmax: int = 256, domain_cells: int = 512):
+    """A 64 x 64 window of 25 km cells drawn from the recipe of a
+    domain_cells x domain_cells grid: Poisson(nmax c) floes per cell with a
     marginal-ice-zone concentration c, radii scaled to area fraction 0.40 at
-    nmax, 8 Fourier modes of 100-800 km at 0.15 m/s rms, dt 30 s."""
+    nmax, 8 Fourier modes 2 <= |(p, q)| <= 16 on the whole domain, evaluated at
+    the window's place in it; dt 30 s.  The window's continuum grid is
+    periodic; its cells' DEMs are independent as in any grid."""
     import fixtures
     rng = np.random.Generator(np.random.PCG64(seed))
     L = 25e3
-    oc = fixtures.random_modes(rng, 8, n * L, n * L)
-    c = fixtures.miz_concentration(rng, n, n)
+    D = domain_cells * L
+    oc = fixtures.random_modes(rng, 8, D, D)
+    c_all = fixtures.miz_concentration(rng, domain_cells, domain_cells)
+    ox, oy = (int(v) for v in rng.integers(0, domain_cells - n + 1, 2))
+    c = c_all[oy:oy + n, ox:ox + n].copy()
+    # the window's origin moves to (0, 0): shift every mode's phase
+    oc.phase = oc.phase + oc.kx * ox * L + oc.ky * oy * L
     counts = rng.poisson(nmax * c).astype(np.int32).reshape(-1)
     s = fixtures.radius_scale(nmax, L * L)
     xi, yi, r, h = fixtures.place_floes(counts, L, L, seed, s)
     z = np.zeros(xi.size, np.float32)
-    return fixtures.Workload(f"train{seed}", n, n, L, L, 30.0, 2048, counts, xi, yi, z.copy(), z.copy(),
+    return fixtures.Workload(f"window{seed}", n, n, L, L, 30.0, 2048, counts, xi, yi, z.copy(), z.copy(),
                              z.copy(), z.copy(), r, h, oc, G=5.0e3, conc=c)
 
 
-def sample_schedule(first: int = 32, every: int = 20, count: int = 128):
-    """Steps at which samples are taken: the first `first` steps one by one
-    (the floes spin up from rest within a few tens of steps), then every
-    `every`-th step, `count` in all."""
-    steps = list(range(min(first, count)))
-    while len(steps) < count:
-        steps.append(steps[-1] + every)
-    return steps
+NET_WINDOW_STEPS = 400   # the network acts during the first 400 steps of a reduced DEM
+
+
+def sample_schedule(window: int = NET_WINDOW_STEPS, first: int = 24, count: int = 64):
+    """Steps at which samples are taken, all inside the network's window: the
+    first `first` steps one by one (the floes spin up from rest within a few
+    tens of steps), the rest spread evenly up to the window's end."""
+    rest = np.linspace(first, window - 1, count - first)
+    return sorted(set(range(first)) | set(int(round(v)) for v in rest))
 
 
 def generate_samples(workloads, schedule=None, stream=None, log=None):
@@ -80,10 +89,17 @@ def generate_samples(workloads, schedule=None, stream=None, log=None):
 
 
 def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0, holdout: float = 0.05,
-          stream=None, log=None):
+          stencil_noise: float = 0.5, use_stencil: bool = True, stream=None, log=None):
     """Adam on the bfloat16 network from Kaiming-uniform initial weights;
-    normalisation from the training rows.  Returns (net, history) with the
-    mean training loss per epoch and the held-out loss (normalised MSE)."""
+    normalisation from the training rows.  Every epoch sees the continuum
+    stencil inputs (the first 36 features) with Gaussian noise of
+    stencil_noise times each column's spread added: in the plain method a
+    cell's residual comes from its own floes, and a network that leans on the
+    continuum state it also drives feeds its own errors back (rollouts then
+    diverge although one-step errors are small).  Returns (net, history) with
+    the mean training loss per epoch and the held-out loss (normalised MSE,
+    clean inputs).  With use_stencil False the stencil inputs are dropped
+    (zero input scale)."""
     import torch
     import fixtures
     n = X.shape[0]
@@ -97,11 +113,23 @@ def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int
     Xtr = X[tr.to("cuda")].contiguous()
     Ttr = T[tr.to("cuda")].contiguous()
     net.fit_norm(Xtr, Ttr)
+    if not use_stencil:
+        xm, xinv, ym, ys = net.get_norm()
+        xs = np.where(xinv > 0, 1.0 / np.where(xinv > 0, xinv, 1.0), 0.0).astype(np.float32)
+        xs[:36] = 0.0
+        net.set_norm(xm, xs, ym, ys)
     hist = {"train": [], "val": [], "seconds": 0.0}
+    sd = Xtr[:, :36].std(dim=0, keepdim=True)
+    gd = torch.Generator(device="cuda").manual_seed(seed + 1)
     t0 = time.perf_counter()
     for ep in range(epochs):
         perm = torch.randperm(Xtr.shape[0], generator=g).to("cuda", torch.int32)
-        hist["train"].append(net.train_epoch(Xtr, Ttr, perm, batch, lr))
+        Xe = Xtr
+        if stencil_noise > 0:
+            Xe = Xtr.clone()
+            Xe[:, :36] += stencil_noise * sd * torch.randn(Xe.shape[0], 36, device="cuda", generator=gd)
+        hist["train"].append(net.train_epoch(Xe, Ttr, perm, batch, lr))
+        del Xe
         hist["val"].append(validation_loss(net, X, T, val))
         if log:
             log(f"epoch {ep + 1}: train {hist['train'][-1]:.4f} held-out {hist['val'][-1]:.4f}")
@@ -157,52 +185,84 @@ def timed_run(sim, dt, nsteps, hybrid: bool, stream):
     return e0.elapsed_time(e1) / 1e3
 
 
-def hybrid_experiment(w, net, nsteps: int, stream, check_every=50, check_cells=256, tol=1.0,
-                      fallback_steps=100, log=None, baseline_net=None):
-    """Full DEM and the hybrid from the same initial state, nsteps each.
-    Returns a dict of throughputs and errors (relative L2 per component and the
-    95th percentile per-cell relative error, both against full DEM)."""
-    dem = miz_mask(w)
-    out = {"cells": w.ncells, "floes": w.nfloes, "steps": nsteps, "dem_cells": int(dem.sum()),
-           "floes_in_dem_cells": int(w.counts[dem].sum())}
+def training_set(seeds=range(8), stream=None, log=None):
+    """Samples of eight 64 x 64 windows (about 2.1M cell-steps)."""
+    ws = [training_workload(230307900 + k) for k in seeds]
+    return generate_samples(ws, stream=stream, log=log)
+
+
+def _evolve(w, stream, nsteps, marks, net=None, dem=None, window=0.0, check=(250, 0, 0.02, 100), timed=False):
+    """Run full DEM (net None) or the hybrid for nsteps; continuum states at
+    the marks (and the seconds of the whole run when timed, without reads)."""
+    out = {}
     with Sim.from_workload(w, stream=stream.cuda_stream) as s:
-        s.step(w.dt, 4)                        # warm-up (graph capture), then a fresh start
-        s.set_floes(w.counts, w.xi, w.yi, w.u, w.v, w.omega, w.theta, w.r, w.h)
-        sec = timed_run(s, w.dt, nsteps, False, stream)
-        Qf = s.read_moments(MOMENTS_CONTINUUM)
-    out["full_dem_floe_steps_per_s"] = w.nfloes * nsteps / sec
-    out["full_dem_ms_per_step"] = 1e3 * sec / nsteps
-    if log:
-        log(f"full DEM: {1e3 * sec / nsteps:.3f} ms/step")
-
-    def run_h(model):
-        with Sim.from_workload(w, stream=stream.cuda_stream) as s:
-            s.hybrid_set(model, ~dem, check_every, check_cells, tol, fallback_steps)
-            s.step_hybrid(w.dt, 2)             # warm-up of the network's workspace
-            s.set_floes(w.counts, w.xi, w.yi, w.u, w.v, w.omega, w.theta, w.r, w.h)
-            s.hybrid_set(model, ~dem, check_every, check_cells, tol, fallback_steps)
-            sec = timed_run(s, w.dt, nsteps, True, stream)
-            Q = s.read_moments(MOMENTS_CONTINUUM)
-            return sec, Q, s.hybrid_stats()
-
-    sec, Qh, hs = run_h(net)
-    e = rel_l2(Qh, Qf)
-    scale = np.sqrt(np.mean(Qf * Qf, axis=0))
-    cell = np.abs(Qh - Qf) / np.maximum(np.abs(Qf), 1e-3 * scale)
-    out.update({"hybrid_floe_steps_per_s": w.nfloes * nsteps / sec, "hybrid_ms_per_step": 1e3 * sec / nsteps,
-                "speedup": out["full_dem_ms_per_step"] / (1e3 * sec / nsteps),
-                "rel_l2": dict(zip(["rho", "Px", "Py", "Pw"], map(float, e))),
-                "p95_cell_rel_err": dict(zip(["rho", "Px", "Py", "Pw"], map(float, np.percentile(cell, 95, axis=0)))),
-                "checks": hs["checks"], "fallbacks": hs["fallbacks"], "clamped": hs["clamped"]})
-    if log:
-        log(f"hybrid: {1e3 * sec / nsteps:.3f} ms/step, rel L2 {e}, fallbacks {hs['fallbacks']}/{hs['checks']}")
-    if baseline_net is not None:
-        _, Qb, _ = run_h(baseline_net)
-        eb = rel_l2(Qb, Qf)
-        out["no_network_rel_l2"] = dict(zip(["rho", "Px", "Py", "Pw"], map(float, eb)))
-        if log:
-            log(f"without the network (coarse-only update in closure cells): rel L2 {eb}")
+        if net is not None:
+            s.hybrid_set(net, ~dem, check[0], check[1], check[2], check[3], window)
+        if timed:
+            out["seconds"] = timed_run(s, w.dt, nsteps, net is not None, stream)
+            out[nsteps] = s.read_moments(MOMENTS_CONTINUUM)
+            if net is not None:
+                out["stats"] = s.hybrid_stats()
+            return out
+        at = 0
+        for mk in marks:
+            if net is not None:
+                s.step_hybrid(w.dt, mk - at)
+            else:
+                s.step(w.dt, mk - at)
+            at = mk
+            out[mk] = s.read_moments(MOMENTS_CONTINUUM)
     return out
+
+
+def hybrid_experiment(w, net, nsteps: int, stream, marks=(10, 100, 400), window_steps: int = NET_WINDOW_STEPS,
+                      check=(250, 256, 0.02, 100), log=None):
+    """Full DEM, the hybrid with the network and the hybrid without it (the
+    reduced DEMs alone), all from the same initial state.  Throughputs of
+    nsteps-step runs, relative L2 errors against full DEM per component at
+    nsteps and at the marks (short horizons), 95th-percentile per-cell errors."""
+    import torch
+    dem = miz_mask(w)
+    names = ["rho", "Px", "Py", "Pw"]
+    res = {"cells": w.ncells, "floes": w.nfloes, "steps": nsteps, "dem_cells": int(dem.sum()),
+           "floes_in_dem_cells": int(w.counts[dem].sum()), "net_window_steps": window_steps}
+    window = window_steps * w.dt
+    zero = zero_network(stream.cuda_stream)
+    # warm-up: kernels loaded, graph captured, network workspace sized
+    _evolve(w, stream, 20, (20,))
+    _evolve(w, stream, 20, (20,), net, dem, window)
+    full = _evolve(w, stream, nsteps, (), timed=True)
+    hyb = _evolve(w, stream, nsteps, (), net, dem, window, check, timed=True)
+    base = _evolve(w, stream, nsteps, (), zero, dem, window, check, timed=True)
+    Qf = full[nsteps]
+
+    def errs(Q, ref):
+        cell = np.abs(Q - ref) / np.maximum(np.abs(ref), 1e-3 * np.sqrt(np.mean(ref * ref, axis=0)))
+        return (dict(zip(names, map(float, rel_l2(Q, ref)))),
+                dict(zip(names, map(float, np.percentile(cell, 95, axis=0)))))
+
+    res["full_dem_ms_per_step"] = 1e3 * full["seconds"] / nsteps
+    res["full_dem_floe_steps_per_s"] = w.nfloes * nsteps / full["seconds"]
+    res["hybrid_ms_per_step"] = 1e3 * hyb["seconds"] / nsteps
+    res["hybrid_floe_steps_per_s"] = w.nfloes * nsteps / hyb["seconds"]
+    res["speedup"] = full["seconds"] / hyb["seconds"]
+    res["no_network_ms_per_step"] = 1e3 * base["seconds"] / nsteps
+    res["rel_l2"], res["p95_cell_rel_err"] = errs(hyb[nsteps], Qf)
+    res["no_network_rel_l2"], res["no_network_p95_cell_rel_err"] = errs(base[nsteps], Qf)
+    res["checks"], res["fallbacks"] = hyb["stats"]["checks"], hyb["stats"]["fallbacks"]
+    # short horizons (no checks, so that only the network differs)
+    fm = _evolve(w, stream, max(marks), marks)
+    hm = _evolve(w, stream, max(marks), marks, net, dem, window)
+    bm = _evolve(w, stream, max(marks), marks, zero, dem, window)
+    res["short_horizon_rel_l2"] = {str(mk): {"network": errs(hm[mk], fm[mk])[0],
+                                             "no_network": errs(bm[mk], fm[mk])[0]} for mk in marks}
+    zero.close()
+    if log:
+        log(f"full DEM {res['full_dem_ms_per_step']:.3f} ms/step, hybrid {res['hybrid_ms_per_step']:.3f} ms/step "
+            f"(x{res['speedup']:.2f}); rel L2 at {nsteps}: {res['rel_l2']}, without network "
+            f"{res['no_network_rel_l2']}; short horizons {res['short_horizon_rel_l2']}")
+    torch.cuda.synchronize()
+    return res
 
 
 def zero_network(stream=None):

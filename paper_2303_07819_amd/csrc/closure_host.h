@@ -8,16 +8,39 @@
 
 namespace spdem {
 
-// Static descriptors of each cell's floes: n, A_ice / A, mean r, mean r^2,
-// mean h, sum m r^2 / sum m; and the cell's mean-field drag coefficients
-// mf = (kappa_v, kappa_w, r2m, 0): kappa_v = C_d rho_o sum pi r^2 / sum m,
-// kappa_w = C_d rho_o sum pi r^5 / sum m (the drag and drag-torque laws of
-// Sec. 2.1 summed over the cell per unit mass), r2m = sum m r^2 / sum m.
-// One workgroup per cell (blockIdx.x, or cells[blockIdx.x] with a list),
+// ---------------------------------------------------------------------------
+// The closure replaces a cell's DEM by a reduced one plus a learned residual.
+//
+// Reduced DEM.  Without contacts every floe relaxes towards the ocean under
+// the quadratic drag laws of Sec. 2.1, dw/dt = -k |w| w for its velocity
+// relative to the current (k = C_d rho_o / (rho_ice h)) and likewise for its
+// spin relative to the half-curl; that equation has the closed form
+// w(t) = w0 / (1 + k |w0| t).  The reduced DEM of a cell is one such body with
+// the cell's summed drag: its relative velocity and spin at the time t0 they
+// were last taken from the cell's floes, red = (du0_x, du0_y, dW0, t0), relax
+// in closed form with the cell's mean-field rates
+//     kappa_v = C_d rho_o sum pi r^2 / sum m,   kappa_w / r2m,
+//     kappa_w = C_d rho_o sum pi r^5 / sum m,   r2m = sum m r^2 / sum m,
+// and give the statistics the continuum update consumes: the coefficient
+// <v> = u_o - du and the sources per unit area S_v / A = rho_f kappa_v |du| du,
+// S_w / A = rho_f kappa_w |dW| dW, rho_f = sum m / A (u_o, curl at the cell
+// centre).  As in the plain method, these do not depend on the continuum state.
+//
+// Base update (base_cell): the Lax-Friedrichs step of lf_cell with every cell's
+// statistics taken from its reduced DEM.  The network adds the rest of the
+// plain method's update (the residual), as a function of the features of the
+// base-updated state; the residual then acts on the new state, so that a
+// relaxation it has learned damps the checkerboard mode the averaging of the
+// Lax-Friedrichs step maps to its negative instead of amplifying it.
+// ---------------------------------------------------------------------------
+
+// Static data of each cell's floes: desc = (A_ice / A, mean h, r2m, n, mean r,
+// mean r^2) as float, mf = (kappa_v, kappa_w, r2m, rho_f) as double.  One
+// workgroup per cell (blockIdx.x, or cells[blockIdx.x] with a list),
 // fixed-order FP64 sums.
 __global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cells, const int32_t* cell_start,
                                                           const float* r, const float* h, double inv_area,
-                                                          double cdrho_over_rho_ice, float* desc, double* mf)
+                                                          double rho_ice, double cdrho, float* desc, double* mf)
 {
     __shared__ double part[8][256];
     const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
@@ -25,15 +48,14 @@ __global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cells, 
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int l = threadIdx.x; l < n; l += 256) {
         const double rl = r[s + l], hl = h[s + l];
-        const double m = hl * rl * rl;   // proportional to the mass (rho_ice pi cancels in the ratios)
+        const double m = hl * rl * rl;   // the mass over rho_ice pi
         acc[0] += 1.0;
-        acc[1] += kPi * rl * rl;
+        acc[1] += rl * rl;
         acc[2] += rl;
-        acc[3] += rl * rl;
-        acc[4] += hl;
-        acc[5] += m * rl * rl;
-        acc[6] += m;
-        acc[7] += rl * rl * rl * rl * rl;
+        acc[3] += hl;
+        acc[4] += m * rl * rl;
+        acc[5] += m;
+        acc[6] += rl * rl * rl * rl * rl;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) part[k][threadIdx.x] = acc[k];
@@ -45,34 +67,172 @@ __global__ __launch_bounds__(256) void descriptors_kernel(const int32_t* cells, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double nn = part[0][0], hm = part[6][0];
+        const double nn = part[0][0], hm = part[5][0];
+        const double r2m = hm > 0 ? part[4][0] / hm : 0.0;
         float* d = desc + (size_t)c * 6;
-        d[0] = (float)nn;
-        d[1] = (float)(part[1][0] * inv_area);
-        d[2] = nn > 0 ? (float)(part[2][0] / nn) : 0.0f;
-        d[3] = nn > 0 ? (float)(part[3][0] / nn) : 0.0f;
-        d[4] = nn > 0 ? (float)(part[4][0] / nn) : 0.0f;
-        d[5] = hm > 0 ? (float)(part[5][0] / hm) : 0.0f;
+        d[0] = (float)(kPi * part[1][0] * inv_area);
+        d[1] = nn > 0 ? (float)(part[3][0] / nn) : 0.0f;
+        d[2] = (float)r2m;
+        d[3] = (float)nn;
+        d[4] = nn > 0 ? (float)(part[2][0] / nn) : 0.0f;
+        d[5] = nn > 0 ? (float)(part[1][0] / nn) : 0.0f;
         double* q = mf + (size_t)c * 4;
         // sum m = rho_ice pi sum h r^2
-        q[0] = hm > 0 ? cdrho_over_rho_ice * part[3][0] / hm : 0.0;
-        q[1] = hm > 0 ? cdrho_over_rho_ice * part[7][0] / hm : 0.0;
-        q[2] = hm > 0 ? part[5][0] / hm : 0.0;
-        q[3] = 0.0;
+        q[0] = hm > 0 ? cdrho * part[1][0] / (rho_ice * hm) : 0.0;
+        q[1] = hm > 0 ? cdrho * part[6][0] / (rho_ice * hm) : 0.0;
+        q[2] = r2m;
+        q[3] = rho_ice * kPi * hm * inv_area;
     }
 }
 
-// The 45 closure inputs of every cell: the continuum state (rho, P_x, P_y, P_w)
-// on the 3 x 3 neighbourhood (row by row from the south-west, periodic), the
-// ocean current and curl at the cell centre, and the six static descriptors.
-__global__ void features_kernel(const double* Q, int nx, int ny, const float2* phase, int nmodes, Modes modes,
-                                float u0, float v0, const float* desc, float* x)
+struct CellOcean {
+    double u, v, zeta;
+};
+
+// Ocean current and curl at the centre of cell C (from its phase table).
+__device__ __forceinline__ CellOcean ocean_centre(int C, const float2* phase, int nmodes, const Modes& modes,
+                                                  float u0, float v0)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nc = nx * ny;
-    if (c >= nc) return;
+    CellOcean o{(double)u0, (double)v0, 0.0};
+    for (int m = 0; m < nmodes; ++m) {
+        const float2 sc = phase[(size_t)C * nmodes + m];
+        o.u += (double)modes.au[m] * (double)sc.x;
+        o.v += (double)modes.av[m] * (double)sc.x;
+        o.zeta += (double)modes.cz[m] * (double)sc.y;
+    }
+    return o;
+}
+
+// Relative velocity and spin of cell C's reduced DEM at time t.
+__device__ __forceinline__ void reduced_rel(int C, const double* red, const double* mf, double t, double& dux,
+                                            double& duy, double& dw)
+{
+    const double* q = red + (size_t)C * 4;
+    const double* k = mf + (size_t)C * 4;
+    const double tr = t > q[3] ? t - q[3] : 0.0;
+    const double fu = 1.0 / (1.0 + k[0] * sqrt(q[0] * q[0] + q[1] * q[1]) * tr);
+    dux = q[0] * fu;
+    duy = q[1] * fu;
+    const double kw = k[2] > 0.0 ? k[1] / k[2] : 0.0;
+    dw = q[2] / (1.0 + kw * fabs(q[2]) * tr);
+}
+
+// Statistics of cell C's reduced DEM at time t: coefficient (u, v), sources
+// per unit area (s_x, s_y, s_w).
+__device__ __forceinline__ void reduced_stats(int C, const double* red, const double* mf, const float2* phase,
+                                              int nmodes, const Modes& modes, float u0, float v0, double t,
+                                              double out[5])
+{
+    const CellOcean o = ocean_centre(C, phase, nmodes, modes, u0, v0);
+    double dux, duy, dw;
+    reduced_rel(C, red, mf, t, dux, duy, dw);
+    const double* k = mf + (size_t)C * 4;
+    const double sp = sqrt(dux * dux + duy * duy);
+    out[0] = o.u - dux;
+    out[1] = o.v - duy;
+    out[2] = k[3] * k[0] * sp * dux;
+    out[3] = k[3] * k[0] * sp * duy;
+    out[4] = k[3] * k[1] * fabs(dw) * dw;
+}
+
+struct ClosureArgs {
+    const double* red;
+    const double* mf;
+    const float2* phase;
+    int nmodes;
+    Modes modes;
+    float u0, v0;
+    int nx, ny;
+    double dX, dY;
+    double t;       // time of the pre-step state
+};
+
+// The base update of cell C (lf_cell with the reduced DEM statistics of every cell).
+__device__ __forceinline__ void base_cell(int C, const double* Q, const ClosureArgs& a, double dT, double out[4])
+{
+    const int nx = a.nx, ny = a.ny, nc = nx * ny;
+    const int ix = C % nx, iy = C / nx;
+    const int E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
+    const int W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
+    const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
+    const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
+    double sC[5], sE[5], sW[5], sN[5], sS[5];
+    reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sC);
+    reduced_stats(E, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sE);
+    reduced_stats(W, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sW);
+    reduced_stats(N, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sN);
+    reduced_stats(S, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sS);
+    const double cx = dT / (2.0 * a.dX), cy = dT / (2.0 * a.dY);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
+        const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
+        const double avg = 0.25 * (qE + qW + qN + qS);
+        if (f == 0 || f == 3)
+            out[f] = avg - cx * (sE[0] * qE - sW[0] * qW) - cy * (sN[1] * qN - sS[1] * qS) + (f == 3 ? dT * sC[4] : 0.0);
+        else
+            out[f] = avg - dT * (sC[0] * (qE - qW) / (2.0 * a.dX) + sC[1] * (qN - qS) / (2.0 * a.dY)) +
+                     dT * sC[f == 1 ? 2 : 3];
+    }
+}
+
+// Base-updated state of every cell: Qb [4][nc].
+__global__ void base_kernel(const double* Q, double* Qb, ClosureArgs a, double dT)
+{
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = a.nx * a.ny;
+    if (C >= nc) return;
+    double o[4];
+    base_cell(C, Q, a, dT, o);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) Qb[(size_t)f * nc + C] = o[f];
+}
+
+// Reduced DEM of the listed cells (all cells with a null list) taken from
+// their floes' statistics `mom` at time t: velocity U / n, spin L / (M r2m).
+// Cells whose status entry is RS_INVALID (when a status array is given) keep
+// their reduced DEM.
+__global__ void reduced_init_kernel(const int32_t* cells, int ncl, const int32_t* status, const double* mom,
+                                    ClosureArgs a, double* red)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    if (status && status[i] == 2) return;
+    const int C = cells ? cells[i] : i;
+    const double* s = mom + (size_t)C * kMomStride;
+    const double n = s[M_N], M = s[M_MASS], r2m = a.mf[(size_t)C * 4 + 2];
+    const double U = n > 0.0 ? s[M_UX] / n : 0.0, V = n > 0.0 ? s[M_UY] / n : 0.0;
+    const double Om = (M > 0.0 && r2m > 0.0) ? s[M_L] / (M * r2m) : 0.0;
+    const CellOcean o = ocean_centre(C, a.phase, a.nmodes, a.modes, a.u0, a.v0);
+    double* q = red + (size_t)C * 4;
+    q[0] = o.u - U;
+    q[1] = o.v - V;
+    q[2] = 0.5 * o.zeta - Om;
+    q[3] = a.t;
+}
+
+// Coefficient <v> of the listed (closure) cells' reduced DEM at time t, into
+// the statistics rows their neighbours' update reads.
+__global__ void reduced_coeff_kernel(const int32_t* cells, int ncl, ClosureArgs a, double* mom)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const int c = cells[i];
+    double st[5];
+    reduced_stats(c, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, st);
+    mom[(size_t)c * kMomStride + M_UBAR] = st[0];
+    mom[(size_t)c * kMomStride + M_VBAR] = st[1];
+}
+
+// The 45 closure inputs of cell C into o: the continuum state Q (rho, P_x, P_y,
+// P_w) on the 3 x 3 neighbourhood (row by row from the south-west, periodic),
+// the ocean current and curl at the cell centre, A_ice / A, mean h, r2m, and
+// the reduced DEM's relative velocity and spin at time t.
+__device__ __forceinline__ void cell_features(int c, const double* Q, const ClosureArgs& a, const float* desc,
+                                              float* o)
+{
+    const int nx = a.nx, ny = a.ny, nc = nx * ny;
     const int ix = c % nx, iy = c / nx;
-    float* o = x + (size_t)c * spmlp::kIn;
     int k = 0;
     for (int dy = -1; dy <= 1; ++dy) {
         const int yy = (iy + dy + ny) % ny;
@@ -82,133 +242,38 @@ __global__ void features_kernel(const double* Q, int nx, int ny, const float2* p
             for (int f = 0; f < 4; ++f) o[k++] = (float)Q[(size_t)f * nc + nb];
         }
     }
-    float uo = u0, vo = v0, zeta = 0.0f;
-    for (int m = 0; m < nmodes; ++m) {
-        const float2 sc = phase[(size_t)c * nmodes + m];
-        uo += modes.au[m] * sc.x;
-        vo += modes.av[m] * sc.x;
-        zeta += modes.cz[m] * sc.y;
-    }
-    o[36] = uo;
-    o[37] = vo;
-    o[38] = zeta;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) o[39 + q] = desc[(size_t)c * 6 + q];
+    const CellOcean oc = ocean_centre(c, a.phase, a.nmodes, a.modes, a.u0, a.v0);
+    o[36] = (float)oc.u;
+    o[37] = (float)oc.v;
+    o[38] = (float)oc.zeta;
+    o[39] = desc[(size_t)c * 6 + 0];
+    o[40] = desc[(size_t)c * 6 + 1];
+    o[41] = desc[(size_t)c * 6 + 2];
+    double dux, duy, dw;
+    reduced_rel(c, a.red, a.mf, a.t, dux, duy, dw);
+    o[42] = (float)dux;
+    o[43] = (float)duy;
+    o[44] = (float)dw;
 }
 
-// Density below which a cell's continuum state gives no velocity: P / rho is
-// meaningless in (nearly) open water, where the floes' number average it
-// stands for has no floes behind it (1 kg/m^2 ~ 1 mm of ice spread over the cell).
-constexpr double kRhoCoefMin = 1.0;
-
-__device__ __forceinline__ double coarse_velocity(const double* Q, int nc, int X, int f)
+// Features of every cell (cells == null) or of the listed cells into
+// consecutive rows of x.
+__global__ void features_kernel(const int32_t* cells, int ncl, const double* Q, ClosureArgs a, const float* desc,
+                                float* x)
 {
-    return Q[X] > kRhoCoefMin ? Q[(size_t)f * nc + X] / Q[X] : 0.0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    cell_features(cells ? cells[i] : i, Q, a, desc, x + (size_t)i * spmlp::kIn);
 }
 
-// The continuum update of a cell that the coarse state determines by itself
-// (the base of the closure) has two parts, applied in this order.
-//
-// Transport (transport_cell): the Lax-Friedrichs step of lf_cell with every
-// coefficient <v> taken as coarse_velocity (P_x, P_y) / rho of the continuum
-// state, without sources.
-//
-// Mean-field drag (relax_cell), local to the cell and applied to its
-// transported state (rho*, P*, P_w*): the cell's ice moving with P* / rho* and
-// spinning at P_w* / (rho* r2m) relaxes towards the ocean current and
-// half-curl at the cell centre over the step as one floe does under the drag
-// laws of Sec. 2.1 (dw/dt = -k |w| w has w(t) = w0 / (1 + k |w0| t), with
-// k = kappa_v for the velocity and kappa_w / r2m for the spin).  To first
-// order in dT the sources are dT rho kappa_v |du| du and dT rho kappa_w |dW| dW.
-//
-// Local physics acts on the transported state, not the old one, because the
-// averaging of the Lax-Friedrichs step maps a checkerboard pattern q to -q: a
-// source that damps the old value would push the new one further out (growth
-// by 1 + f / (1 + f) per step, f = k |w| dT), where damping the new value
-// shrinks it by 1 / (1 + f).  The learned residual is likewise a function of
-// the transported state.
-__device__ __forceinline__ void transport_cell(int C, const double* Q, int nx, int ny, double dT, double dX,
-                                               double dY, double out[4])
-{
-    const int nc = nx * ny;
-    const int ix = C % nx, iy = C / nx;
-    const int E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
-    const int W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
-    const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
-    const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
-    const double uE = coarse_velocity(Q, nc, E, 1), uW = coarse_velocity(Q, nc, W, 1);
-    const double vN = coarse_velocity(Q, nc, N, 2), vS = coarse_velocity(Q, nc, S, 2);
-    const double uC = coarse_velocity(Q, nc, C, 1), vC = coarse_velocity(Q, nc, C, 2);
-    const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
-        const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
-        const double avg = 0.25 * (qE + qW + qN + qS);
-        if (f == 0 || f == 3)
-            out[f] = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS);
-        else
-            out[f] = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY));
-    }
-}
-
-// Transported state of every cell: Qs [4][nc].
-__global__ void transport_kernel(const double* Q, double* Qs, int nx, int ny, double dT, double dX, double dY)
-{
-    const int C = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nc = nx * ny;
-    if (C >= nc) return;
-    double o[4];
-    transport_cell(C, Q, nx, ny, dT, dX, dY, o);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) Qs[(size_t)f * nc + C] = o[f];
-}
-
-__device__ __forceinline__ void relax_cell(int C, const double* Qs, int nc, const double* mf, const float2* phase,
-                                           int nmodes, const Modes& modes, float u0, float v0, double dT,
-                                           double out[4])
-{
-#pragma unroll
-    for (int f = 0; f < 4; ++f) out[f] = Qs[(size_t)f * nc + C];
-    double uo = u0, vo = v0, zeta = 0.0;
-    for (int m = 0; m < nmodes; ++m) {
-        const float2 sc = phase[(size_t)C * nmodes + m];
-        uo += (double)modes.au[m] * (double)sc.x;
-        vo += (double)modes.av[m] * (double)sc.x;
-        zeta += (double)modes.cz[m] * (double)sc.y;
-    }
-    const double* k = mf + (size_t)C * 4;
-    const bool moving = out[0] > kRhoCoefMin;
-    const double rho = out[0] > 0.0 ? out[0] : 0.0;
-    const double us = moving ? out[1] / out[0] : 0.0, vs = moving ? out[2] / out[0] : 0.0;
-    const double om = (moving && k[2] > 0.0) ? out[3] / (out[0] * k[2]) : 0.0;
-    const double du = uo - us, dv = vo - vs;
-    const double fv = dT * k[0] * sqrt(du * du + dv * dv);
-    const double dW = 0.5 * zeta - om;
-    const double fw = k[2] > 0.0 ? dT * k[1] / k[2] * fabs(dW) : 0.0;
-    out[1] += rho * du * fv / (1.0 + fv);
-    out[2] += rho * dv * fv / (1.0 + fv);
-    out[3] += rho * k[2] * dW * fw / (1.0 + fw);
-}
-
-// Tendency per cell, [nc][4] FP32: (Q_now - ref) / dt with ref = Qref (the
-// old state), or with `residual` ref = relax_cell of Qref (the transported old
-// state): the part of the update the coarse state does not determine.
-__global__ void tendency_kernel(const double* Qnow, const double* Qref, const double* mf, const float2* phase,
-                                int nmodes, Modes modes, float u0, float v0, int nc, double dt, int residual,
-                                float* t)
+// (Q_now - Q_ref) / dt per cell, [nc][4] FP32.
+__global__ void tendency_kernel(const double* Qnow, const double* Qref, int nc, double dt, float* t)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
-    double ref[4];
-    if (residual) {
-        relax_cell(c, Qref, nc, mf, phase, nmodes, modes, u0, v0, dt, ref);
-    } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ref[f] = Qref[(size_t)f * nc + c];
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) t[(size_t)c * 4 + f] = (float)((Qnow[(size_t)f * nc + c] - ref[f]) / dt);
+    for (int f = 0; f < 4; ++f)
+        t[(size_t)c * 4 + f] = (float)((Qnow[(size_t)f * nc + c] - Qref[(size_t)f * nc + c]) / dt);
 }
 
 // Per-column mean and standard deviation of X [n][cols] (FP64, fixed order).
@@ -682,18 +747,59 @@ sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const i
 
 namespace {
 
-// Descriptors and mean-field coefficients of every cell, computed once per
-// floe set (cells re-synchronised later refresh their own).
+// Static cell data of every cell, computed once per floe set (cells
+// re-synchronised later refresh their own).
 sp_status ensure_cell_data(sp_ctx* c)
 {
     if (c->desc && c->mf) return SP_OK;
     SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
     SP_TRY(dalloc(c, &c->mf, (size_t)c->ncells * 4));
     hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, nullptr, c->cell_start, c->r,
-                       c->h, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.cd * c->p.rho_ocean / c->p.rho_ice, c->desc,
+                       c->h, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.rho_ice, c->p.cd * c->p.rho_ocean, c->desc,
                        c->mf);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
+}
+
+ClosureArgs closure_args(const sp_ctx* c, double t)
+{
+    const StepArgs s = make_args(c, 0.0);
+    ClosureArgs a;
+    memset(&a, 0, sizeof a);
+    a.red = c->red;
+    a.mf = c->mf;
+    a.phase = c->phase;
+    a.nmodes = c->nmodes;
+    a.modes = s.modes;
+    a.u0 = s.u0;
+    a.v0 = s.v0;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.dX = c->p.cell_lx;
+    a.dY = c->p.cell_ly;
+    a.t = t;
+    return a;
+}
+
+// Reduced DEM of every cell from the statistics `mom` of the current floes.
+sp_status init_reduced_all(sp_ctx* c, const double* mom)
+{
+    SP_TRY(ensure_cell_data(c));
+    if (!c->red) SP_TRY(dalloc(c, &c->red, (size_t)c->ncells * 4));
+    hipLaunchKernelGGL(reduced_init_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, nullptr,
+                       c->ncells, nullptr, mom, closure_args(c, c->t_now), c->red);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
+// The same from freshly computed statistics (after the ocean changed).
+sp_status refresh_reduced_all(sp_ctx* c)
+{
+    StepArgs a = make_args(c, 0.0);
+    a.mom = c->mom2;
+    hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return init_reduced_all(c, c->mom2);
 }
 
 }  // namespace
@@ -707,9 +813,8 @@ sp_status sp_closure_features(sp_ctx* c, float* x)
     SP_TRY(flush_lf(c));
     SP_TRY(upload_phase(c));
     SP_TRY(ensure_cell_data(c));
-    const StepArgs a = make_args(c, 0.0);
-    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
-                       c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, x);
+    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, nullptr, c->ncells,
+                       c->Q[c->kstep & 1], closure_args(c, c->t_now), c->desc, x);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
@@ -726,22 +831,20 @@ sp_status sp_closure_sample(sp_ctx* c, double dt, int32_t mode, float* x, float*
     SP_TRY(ensure_cell_data(c));
     if (!c->qprev) SP_TRY(dalloc(c, &c->qprev, (size_t)c->ncells * 4));
     const double* Q = c->Q[c->kstep & 1];
+    const ClosureArgs a = closure_args(c, c->t_now);
     if (mode == SP_TEND_RESIDUAL) {
-        hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, Q, c->qprev,
-                           c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+        hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, Q, c->qprev, a, dt);
         HIP_TRY(c, hipGetLastError());
     } else {
         HIP_TRY(c, hipMemcpyAsync(c->qprev, Q, (size_t)c->ncells * 4 * 8, hipMemcpyDeviceToDevice, c->stream));
     }
-    const StepArgs a = make_args(c, dt);
-    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->qprev, c->p.nx,
-                       c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, x);
+    hipLaunchKernelGGL(features_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, nullptr, c->ncells,
+                       c->qprev, a, c->desc, x);
     HIP_TRY(c, hipGetLastError());
     SP_TRY(sp_step(c, dt, 1));
     SP_TRY(flush_lf(c));
     hipLaunchKernelGGL(tendency_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, c->Q[c->kstep & 1],
-                       c->qprev, c->mf, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->ncells, dt,
-                       mode == SP_TEND_RESIDUAL ? 1 : 0, t);
+                       c->qprev, c->ncells, dt, t);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }

@@ -9,37 +9,33 @@
 // on their targets.
 //
 // Hybrid step: cells flagged as closure cells skip the DEM.  Their continuum
-// state takes the part of the update the coarse state determines by itself
-// (transport_cell, the Lax-Friedrichs step with <v> = P / rho, then
-// relax_cell, mean-field drag) plus the network's residual tendency for the
-// features of the transported state Q*: Q <- relax(Q*) + dt T(features(Q*)).
-// The other
-// cells run the DEM step and the Lax-Friedrichs update, which reads the
-// coefficient <v> = P / rho of neighbouring closure cells.  Every check_every
-// steps a rotating sample of closure cells is re-synchronised to its continuum
-// state; its DEM statistics give the residual tendency the plain method would
-// apply there, and a cell whose network output misses it by more than the
-// tolerance runs the DEM for the next fallback_steps steps.
+// state takes the base update (the Lax-Friedrichs step with every cell's
+// statistics from its reduced DEM, closure_host.h) plus the network's residual
+// tendency for the features of the base-updated state Q_b:
+// Q <- Q_b + dt T(features(Q_b)).  The other cells run the DEM step and the
+// Lax-Friedrichs update, which reads the coefficient of a neighbouring closure
+// cell from its reduced DEM.  A closure cell's floes stay frozen.  Every
+// check_every steps a rotating sample of closure cells is checked: their floes
+// catch up with the DEM steps they missed (cells do not interact in the DEM,
+// so this is exactly the plain method's fine state), their statistics give the
+// residual tendency the plain method applies, and a cell whose closure misses
+// it by more than the tolerance runs the DEM for the next fallback_steps
+// steps; every checked cell's reduced DEM restarts from its true floes.
 #pragma once
 
 namespace spdem {
 
 enum { RS_OK = 0, RS_CLAMPED = 1, RS_INVALID = 2 };
 
-// One workgroup per listed cell.  Targets come from `targets` [ncl][4] or, if
-// null, from the continuum state Q [4][nc].  The radius scale is limited so
+// One workgroup per listed cell, targets [ncl][4].  The radius scale is limited so
 // that no radius exceeds r_lim (the contact-search bin radius); such a cell
 // reports RS_CLAMPED and keeps a smaller mass than its target.  A target that
 // cannot be met (rho <= 0 or not finite for a cell with floes, anything
-// nonzero for an empty cell, or, with max_ratio > 0, a mass more than
-// max_ratio times above or below the floes' mass, a mean speed |P| / rho above
-// max_speed or a mean spin above max_spin) leaves the cell unchanged and
-// reports RS_INVALID.
+// nonzero for an empty cell) leaves the cell unchanged and reports RS_INVALID.
 __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
                                                      const float* h, float* u, float* v, float* w,
-                                                     const double* targets, const double* Q, int nc,
-                                                     double rho_ice, double area, float r_lim, double max_ratio,
-                                                     double max_speed, double max_spin, int32_t* status)
+                                                     const double* targets, int nc, double rho_ice, double area,
+                                                     float r_lim, int32_t* status)
 {
     __shared__ double part[5][256];
     __shared__ double tot[5];
@@ -49,7 +45,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     const int tid = threadIdx.x;
     double tg[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) tg[f] = targets ? targets[(size_t)blockIdx.x * 4 + f] : Q[(size_t)f * nc + c];
+    for (int f = 0; f < 4; ++f) tg[f] = targets[(size_t)blockIdx.x * 4 + f];
     if (n == 0) {
         if (tid == 0)
             status[blockIdx.x] = (tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0 || tg[3] != 0.0) ? RS_INVALID : RS_OK;
@@ -62,40 +58,25 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         if (tid == 0) status[blockIdx.x] = RS_INVALID;
         return;
     }
-    // mass, inertia and largest radius of the cell
-    double m0 = 0.0, i0 = 0.0;
+    // mass and largest radius of the cell
+    double m0 = 0.0;
     float r0 = 0.0f;
     for (int l = tid; l < n; l += 256) {
         const double rl = r[s + l];
-        const double m = rho_ice * (double)h[s + l] * kPi * rl * rl;
-        m0 += m;
-        i0 += m * rl * rl;
+        m0 += rho_ice * (double)h[s + l] * kPi * rl * rl;
         r0 = fmaxf(r0, r[s + l]);
     }
     part[0][tid] = m0;
-    part[1][tid] = i0;
     rpart[tid] = r0;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (tid < k) {
             part[0][tid] += part[0][tid + k];
-            part[1][tid] += part[1][tid + k];
             rpart[tid] = fmaxf(rpart[tid], rpart[tid + k]);
         }
         __syncthreads();
     }
-    const double ratio = tg[0] * area / part[0][0];
-    if (max_ratio > 0.0) {
-        // inertia scales with the fourth power of the radius scale
-        const double spin = fabs(tg[3]) * area / (part[1][0] * ratio * ratio);
-        const double speed = sqrt(tg[1] * tg[1] + tg[2] * tg[2]) / tg[0];
-        if (ratio > max_ratio || ratio * max_ratio < 1.0 || speed > max_speed || spin > max_spin) {
-            if (tid == 0) status[blockIdx.x] = RS_INVALID;
-            return;
-        }
-    }
-    __syncthreads();
-    double sc = sqrt(ratio);
+    double sc = sqrt(tg[0] * area / part[0][0]);
     const double lim = (double)r_lim / (double)rpart[0];
     const bool clamped = sc > lim;
     if (clamped) sc = lim;
@@ -135,80 +116,34 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     if (tid == 0) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
 }
 
-// Features (layout of features_kernel) of the listed cells into consecutive rows.
-__global__ void features_list_kernel(const int32_t* cells, int ncl, const double* Q, int nx, int ny,
-                                     const float2* phase, int nmodes, Modes modes, float u0, float v0,
-                                     const float* desc, float* x)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const int c = cells[i];
-    const int nc = nx * ny;
-    const int ix = c % nx, iy = c / nx;
-    float* o = x + (size_t)i * spmlp::kIn;
-    int k = 0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = (iy + dy + ny) % ny;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int nb = yy * nx + (ix + dx + nx) % nx;
-#pragma unroll
-            for (int f = 0; f < 4; ++f) o[k++] = (float)Q[(size_t)f * nc + nb];
-        }
-    }
-    float uo = u0, vo = v0, zeta = 0.0f;
-    for (int m = 0; m < nmodes; ++m) {
-        const float2 sc = phase[(size_t)c * nmodes + m];
-        uo += modes.au[m] * sc.x;
-        vo += modes.av[m] * sc.x;
-        zeta += modes.cz[m] * sc.y;
-    }
-    o[36] = uo;
-    o[37] = vo;
-    o[38] = zeta;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) o[39 + q] = desc[(size_t)c * 6 + q];
-}
-
-// Continuum coefficient <v> = P / rho (coarse_velocity) of the listed closure cells.
-__global__ void closure_coeff_kernel(const int32_t* cells, int ncl, const double* Q, int nc, double* mom)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const int c = cells[i];
-    mom[(size_t)c * kMomStride + M_UBAR] = coarse_velocity(Q, nc, c, 1);
-    mom[(size_t)c * kMomStride + M_VBAR] = coarse_velocity(Q, nc, c, 2);
-}
-
-// Continuum step of the hybrid: closure cells relax_cell(Qs) + dT T (Qs: the
-// transported state, T: the network's residual tendency for its features), the
-// others the LF step of their statistics.
-__global__ void hybrid_continuum_kernel(const double* mom, const double* Q, const double* Qs, double* Qn,
-                                        const int32_t* row, const float* T, const double* mf, const float2* phase,
-                                        int nmodes, Modes modes, float u0, float v0, int nx, int ny, double dT,
-                                        double dX, double dY, double inv_area, unsigned long long* max_cfl_bits,
-                                        uint32_t* err)
+// Continuum step of the hybrid: closure cells Qb + dT T (Qb: the base-updated
+// state, T: the network's residual tendency, applied while the cell's reduced
+// DEM is younger than `window`, always if window <= 0), the others the LF
+// step of their statistics.
+__global__ void hybrid_continuum_kernel(const double* mom, const double* Q, const double* Qb, double* Qn,
+                                        const int32_t* row, const float* T, const double* red, double t,
+                                        double window, int nx, int ny, double dT, double dX, double dY,
+                                        double inv_area, unsigned long long* max_cfl_bits, uint32_t* err)
 {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     const int nc = nx * ny;
     if (C >= nc) return;
     const int q = row[C];
     if (q >= 0) {
-        double b[4];
-        relax_cell(C, Qs, nc, mf, phase, nmodes, modes, u0, v0, dT, b);
+        const double w = (window <= 0.0 || t - red[(size_t)C * 4 + 3] < window) ? dT : 0.0;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) Qn[(size_t)f * nc + C] = b[f] + dT * (double)T[(size_t)q * 4 + f];
+        for (int f = 0; f < 4; ++f) Qn[(size_t)f * nc + C] = Qb[(size_t)f * nc + C] + w * (double)T[(size_t)q * 4 + f];
     } else {
         lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
     }
 }
 
-// Plain-method residual tendency (LF(Q) - relax_cell(Qs)) / dT of the listed
-// cells: their own coefficients and sources from the statistics `fresh`, the
-// neighbours' coefficients from `mom`; Qs is the transported state.
+// Plain-method residual tendency (LF(Q) - Qb) / dT of the listed cells: their
+// own coefficients and sources from the statistics `fresh`, the neighbours'
+// coefficients from `mom`.
 __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const double* fresh, const double* mom,
-                                      const double* Q, const double* Qs, const double* mf, const float2* phase,
-                                      int nmodes, Modes modes, float u0, float v0, int nx, int ny, double dT,
-                                      double dX, double dY, double inv_area, float* T)
+                                      const double* Q, const double* Qb, int nx, int ny, double dT, double dX,
+                                      double dY, double inv_area, float* T)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncl) return;
@@ -226,8 +161,6 @@ __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const doubl
     const double vN = N == C ? vC : mom[(size_t)N * kMomStride + M_VBAR];
     const double vS = S == C ? vC : mom[(size_t)S * kMomStride + M_VBAR];
     const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
-    double base[4];
-    relax_cell(C, Qs, nc, mf, phase, nmodes, modes, u0, v0, dT, base);
     for (int f = 0; f < 4; ++f) {
         const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
         const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
@@ -240,7 +173,7 @@ __global__ void check_tendency_kernel(const int32_t* cells, int ncl, const doubl
             qn = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY)) +
                  dT * sC[f == 1 ? M_SVX : M_SVY] * inv_area;
         }
-        T[(size_t)i * 4 + f] = (float)((qn - base[f]) / dT);
+        T[(size_t)i * 4 + f] = (float)((qn - Qb[(size_t)f * nc + C]) / dT);
     }
 }
 
@@ -251,9 +184,12 @@ struct HybridState {
     std::vector<uint8_t> closure;        // cells flagged for the closure
     std::vector<int32_t> fallback_left;  // > 0: a flagged cell runs the DEM for that many more steps
     std::vector<int32_t> fallback_cells; // cells with fallback_left > 0
+    std::vector<int64_t> frozen_at;      // step up to which a closure-mode cell's floes are advanced
+    std::vector<double> red_t0;          // start time of each cell's reduced DEM (host copy)
     int check_every = 50, check_cells = 64, fallback_steps = 100;
     double tol = 0.2;
-    int64_t checks = 0, fallbacks = 0, clamped = 0, cursor = 0, hsteps = 0;
+    double net_window = 0.0;              // seconds after a reduced DEM's start the network acts (<= 0: always)
+    int64_t checks = 0, fallbacks = 0, cursor = 0, hsteps = 0;
     Bucket bk[kNumBuckets];               // DEM-mode cells only
     std::vector<int32_t> clos_h;          // closure-mode cells
     int32_t* clos_d = nullptr;
@@ -261,24 +197,15 @@ struct HybridState {
     float* X = nullptr;                   // [nclos][45]
     float* T = nullptr;                   // [nclos][4]
     int32_t* chk_d = nullptr;             // sampled cells of a check
-    int32_t* rs_d = nullptr;              // their re-synchronisation status
     float* Xk = nullptr;
     float* Tk = nullptr;
     float* Tdem = nullptr;
-    double* fresh = nullptr;              // statistics of re-synchronised cells [ncells][kMomStride]
-    double* Qs = nullptr;                 // transported continuum state [4][ncells]
+    double* Qs = nullptr;                 // base-updated continuum state [4][ncells]
+    int32_t* back_d = nullptr;            // cells whose fallback window ended [ncells]
     int ndem = 0;
 };
 
 namespace {
-
-// Limits of the state a check re-synchronises a cell to: beyond them the
-// closure has failed there and the cell falls back with its floes as they are.
-// The speed and spin limits keep the floes inside the range where the explicit
-// quadratic drag is stable (k |du| dt < 2 with k = C_d rho_o / (rho_ice h)).
-constexpr double kCheckMassRatio = 4.0;   // mass change factor
-constexpr double kCheckMaxSpeed = 2.0;    // m/s
-constexpr double kCheckMaxSpin = 1e-2;    // 1/s
 
 void hybrid_free_buffers(HybridState* h)
 {
@@ -288,12 +215,13 @@ void hybrid_free_buffers(HybridState* h)
         b.work_d = nullptr;
         b.q_d = nullptr;
     }
-    void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->rs_d, h->Xk, h->Tk, h->Tdem, h->fresh, h->Qs};
+    void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->Xk, h->Tk, h->Tdem, h->Qs,
+                  h->back_d};
     for (void* p : ps)
         if (p) (void)hipFree(p);
-    h->clos_d = h->row_d = h->chk_d = h->rs_d = nullptr;
+    h->clos_d = h->row_d = h->chk_d = h->back_d = nullptr;
     h->X = h->T = h->Xk = h->Tk = h->Tdem = nullptr;
-    h->fresh = h->Qs = nullptr;
+    h->Qs = nullptr;
 }
 
 // Rebuild the DEM buckets and the closure list from the current modes.
@@ -342,27 +270,90 @@ sp_status net_forward_on(sp_ctx* c, sp_mlp* net, const float* x, int rows, float
     return SP_OK;
 }
 
-// Re-synchronise the listed cells (device list); per-cell status into status_d;
-// descriptors refreshed if they exist.
-sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* targets_d, bool guarded,
-                      int32_t* status_d)
+// Restart the reduced DEM of the listed cells (device list) from their floes
+// (skipping cells whose status entry is RS_INVALID); their statistics land in
+// mom2.
+sp_status restart_reduced(sp_ctx* c, const int32_t* cells_d, int ncl, const int32_t* status_d)
 {
     if (ncl <= 0) return SP_OK;
-    hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
-                       c->v, c->w, targets_d, c->Q[c->kstep & 1], c->ncells, c->p.rho_ice,
-                       c->p.cell_lx * c->p.cell_ly, c->r_bin, guarded ? kCheckMassRatio : 0.0, kCheckMaxSpeed,
-                       kCheckMaxSpin, status_d);
+    StepArgs a = make_args(c, 0.0);
+    a.mom = c->mom2;
+    hipLaunchKernelGGL(stats_kernel, dim3(ncl), dim3(256), 0, c->stream, a, cells_d);
     HIP_TRY(c, hipGetLastError());
-    if (c->desc && c->mf) {
-        hipLaunchKernelGGL(descriptors_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h,
-                           1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.cd * c->p.rho_ocean / c->p.rho_ice, c->desc,
-                           c->mf);
-        HIP_TRY(c, hipGetLastError());
-    }
+    hipLaunchKernelGGL(reduced_init_kernel, dim3((ncl + 255) / 256), dim3(256), 0, c->stream, cells_d, ncl, status_d,
+                       c->mom2, closure_args(c, c->t_now), c->red);
+    HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
-// Check a rotating sample of closure cells after a step (Q at level kstep).
+// Re-synchronise the listed cells (device list) to targets_d; per-cell status
+// into status_d; descriptors, drag coefficients and reduced DEMs follow.
+sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* targets_d, int32_t* status_d)
+{
+    if (ncl <= 0) return SP_OK;
+    hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
+                       c->v, c->w, targets_d, c->ncells, c->p.rho_ice, c->p.cell_lx * c->p.cell_ly, c->r_bin,
+                       status_d);
+    HIP_TRY(c, hipGetLastError());
+    SP_TRY(ensure_cell_data(c));
+    hipLaunchKernelGGL(descriptors_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h,
+                       1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.rho_ice, c->p.cd * c->p.rho_ocean, c->desc, c->mf);
+    HIP_TRY(c, hipGetLastError());
+    SP_TRY(restart_reduced(c, cells_d, ncl, status_d));
+    return SP_OK;
+}
+
+// Advance the floes of the listed closure cells (host list), frozen since
+// they entered closure mode, by the DEM steps they missed, up to the current
+// step; their statistics of each step land in mom2 only.  Cells frozen at the
+// same step are advanced together, joined by the later ones as their time
+// comes.  The floes then equal those of the plain method: cells do not
+// interact in the DEM.
+sp_status catch_up(sp_ctx* c, std::vector<int32_t> cells, double dt)
+{
+    HybridState* h = c->hyb;
+    std::sort(cells.begin(), cells.end(),
+              [&](int32_t a, int32_t b) { return h->frozen_at[a] < h->frozen_at[b]; });
+    std::vector<uint8_t> include(c->ncells, 0);
+    Bucket tmp[kNumBuckets];
+    for (int q = 0; q < kNumBuckets; ++q) {
+        tmp[q].waves = c->bk[q].waves;
+        tmp[q].queue = c->bk[q].queue;
+    }
+    StepArgs base = make_args(c, dt);
+    base.mom = c->mom2;
+    base.lf = 0;
+    sp_status st = SP_OK;
+    size_t i = 0;
+    while (!st && i < cells.size()) {
+        const int64_t t0 = h->frozen_at[cells[i]];
+        while (i < cells.size() && h->frozen_at[cells[i]] == t0) include[cells[i++]] = 1;
+        const int64_t t1 = i < cells.size() ? h->frozen_at[cells[i]] : c->kstep;
+        if (t1 <= t0) continue;
+        st = build_buckets_into(c, tmp, c->counts_h.data(), include.data());
+        for (auto& b : tmp)
+            if (!st && !b.cells_h.empty()) st = prepare_bucket(c, b);
+        for (int64_t k = 0; !st && k < t1 - t0; ++k)
+            for (auto& b : tmp) {
+                st = launch_bucket(c, b, base, k, false, true);
+                if (st) break;
+            }
+    }
+    (void)hipStreamSynchronize(c->stream);   // the temporary work lists are freed below
+    for (auto& b : tmp) {
+        if (b.work_d) (void)hipFree(b.work_d);
+        if (b.q_d) (void)hipFree(b.q_d);
+    }
+    if (st) return st;
+    for (int32_t cell : cells) h->frozen_at[cell] = c->kstep;
+    return SP_OK;
+}
+
+// Check a rotating sample of closure cells after a step (Q at level kstep):
+// their floes catch up with the DEM, their true statistics give the plain
+// method's residual tendency, and a cell whose closure misses it by more than
+// tol of its state (projected over one check period) falls back to the DEM.
+// Every checked cell's reduced DEM then restarts from its true floes.
 sp_status hybrid_check(sp_ctx* c, double dt)
 {
     HybridState* h = c->hyb;
@@ -372,52 +363,57 @@ sp_status hybrid_check(sp_ctx* c, double dt)
     std::vector<int32_t> pick(nk);
     for (int i = 0; i < nk; ++i) pick[i] = h->clos_h[(size_t)((h->cursor + i) % nclos)];
     h->cursor = (h->cursor + nk) % nclos;
+    // 1. the sampled cells' floes to the current step
+    SP_TRY(catch_up(c, pick, dt));
     HIP_TRY(c, hipMemcpyAsync(h->chk_d, pick.data(), (size_t)nk * 4, hipMemcpyHostToDevice, c->stream));
-    // 1. the sampled cells' floes to their continuum state, unless it asks for a
-    //    mass change beyond kCheckMassRatio: the closure has then failed there
-    SP_TRY(resync_list(c, h->chk_d, nk, nullptr, true, h->rs_d));
-    // 2. their statistics and the plain method's tendency; the neighbours'
-    //    coefficients are those of the step just taken
+    // 2. their statistics and the plain method's residual tendency; the
+    //    neighbours' coefficients are those of the step just taken
     StepArgs a = make_args(c, dt);
-    a.mom = h->fresh;
+    a.mom = c->mom2;
     hipLaunchKernelGGL(stats_kernel, dim3(nk), dim3(256), 0, c->stream, a, h->chk_d);
     HIP_TRY(c, hipGetLastError());
     const int64_t k = c->kstep - 1;
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
-    hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
-                       h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+    const ClosureArgs ca = closure_args(c, c->t_now);
+    hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[c->kstep & 1],
+                       h->Qs, ca, dt);
     HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(check_tendency_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, h->fresh,
-                       c->momb[k & 1], c->Q[c->kstep & 1], h->Qs, c->mf, c->phase, c->nmodes, a.modes, a.u0, a.v0,
-                       c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly, inv_area, h->Tdem);
+    hipLaunchKernelGGL(check_tendency_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, c->mom2,
+                       c->momb[k & 1], c->Q[c->kstep & 1], h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
+                       inv_area, h->Tdem);
     HIP_TRY(c, hipGetLastError());
-    // 3. the network's tendency for the same cells
-    hipLaunchKernelGGL(features_list_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, h->Qs,
-                       c->p.nx, c->p.ny, c->phase, c->nmodes, a.modes, a.u0, a.v0, c->desc, h->Xk);
+    // 3. the closure's residual for the same cells
+    hipLaunchKernelGGL(features_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, h->Qs, ca,
+                       c->desc, h->Xk);
     HIP_TRY(c, hipGetLastError());
     SP_TRY(net_forward_on(c, h->net, h->Xk, nk, h->Tk));
-    std::vector<float> tm((size_t)nk * 4), td((size_t)nk * 4), ys(4);
-    std::vector<int32_t> rs(nk);
+    std::vector<float> tm((size_t)nk * 4), td((size_t)nk * 4), xk((size_t)nk * spmlp::kIn);
     HIP_TRY(c, hipMemcpyAsync(tm.data(), h->Tk, tm.size() * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(td.data(), h->Tdem, td.size() * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(rs.data(), h->rs_d, rs.size() * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(ys.data(), h->net->norm + 2 * spmlp::kIn + 2 * spmlp::kOut, 16,
-                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(xk.data(), h->Xk, xk.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    // 4. the reduced DEMs restart from the true floes
+    SP_TRY(restart_reduced(c, h->chk_d, nk, nullptr));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // the cell's own state is feature 16..19 (centre of the 3 x 3 stencil)
+    double floor[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nk; ++i)
+        for (int f = 0; f < 4; ++f) floor[f] += fabs((double)xk[(size_t)i * spmlp::kIn + 16 + f]) / nk;
     bool changed = false;
     for (int i = 0; i < nk; ++i) {
-        bool bad = rs[i] == RS_INVALID;
-        if (rs[i] == RS_CLAMPED) h->clamped++;
+        const int32_t cell = pick[i];
+        const bool net = h->net_window <= 0.0 || c->t_now - h->red_t0[cell] < h->net_window;
+        bool bad = false;
         for (int f = 0; f < 4 && !bad; ++f) {
-            // relative to the DEM tendency, with a floor of a tenth of its training spread
-            const double e = fabs((double)tm[i * 4 + f] - (double)td[i * 4 + f]);
-            if (!(e <= h->tol * (fabs((double)td[i * 4 + f]) + 0.1 * (double)ys[f]))) bad = true;
+            const double e = fabs((net ? (double)tm[i * 4 + f] : 0.0) - (double)td[i * 4 + f]);
+            const double q = fabs((double)xk[(size_t)i * spmlp::kIn + 16 + f]) + 0.01 * floor[f];
+            if (!(h->check_every * dt * e <= h->tol * q)) bad = true;
         }
+        h->red_t0[cell] = c->t_now;
         h->checks++;
         if (bad) {
             h->fallbacks++;
-            if (h->fallback_left[pick[i]] == 0) h->fallback_cells.push_back(pick[i]);
-            h->fallback_left[pick[i]] = h->fallback_steps;
+            if (h->fallback_left[cell] == 0) h->fallback_cells.push_back(cell);
+            h->fallback_left[cell] = h->fallback_steps;
             changed = true;
         }
     }
@@ -471,7 +467,7 @@ sp_status sp_resync_cells(sp_ctx* c, int32_t ncl, const int32_t* cells, const do
     if (!st && (hipMemcpyAsync(cd, cells, (size_t)ncl * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
                 hipMemcpyAsync(td, targets, (size_t)ncl * 4 * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess))
         st = fail(c, SP_EDEVICE, "target upload failed");
-    if (!st) st = resync_list(c, cd, ncl, td, false, sd);
+    if (!st) st = resync_list(c, cd, ncl, td, sd);
     if (!st && hipMemcpyAsync(rs.data(), sd, (size_t)ncl * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         st = fail(c, SP_EDEVICE, "status download failed");
     if (hipStreamSynchronize(c->stream) != hipSuccess && !st) st = fail(c, SP_EDEVICE, "synchronisation failed");
@@ -487,7 +483,7 @@ sp_status sp_resync_cells(sp_ctx* c, int32_t ncl, const int32_t* cells, const do
 }
 
 sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, int32_t check_every,
-                        int32_t check_cells, double tol, int32_t fallback_steps)
+                        int32_t check_cells, double tol, int32_t fallback_steps, double net_window)
 {
     if (!c) return SP_EINVAL;
     if (!closure_cells) {
@@ -497,7 +493,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     }
     if (!net) return fail(c, SP_EINVAL, "the hybrid needs a network");
     if (!c->have_floes) return fail(c, SP_ESTATE, "sp_hybrid_set before sp_set_floes");
-    if (check_every < 1 || check_cells < 0 || !(tol > 0) || fallback_steps < 1)
+    if (check_every < 1 || check_cells < 0 || !(tol > 0) || fallback_steps < 1 || !std::isfinite(net_window))
         return fail(c, SP_EINVAL, "check_every and fallback_steps must be >= 1, check_cells >= 0, tol > 0");
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "the hybrid needs the continuum update");
     HIP_TRY(c, hipStreamSynchronize(net->stream));   // parameters and normalisation in place
@@ -510,10 +506,12 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     for (int i = 0; i < c->ncells; ++i)   // a cell without floes has no DEM work: the plain update is exact
         if (c->counts_h[i] == 0) h->closure[i] = 0;
     h->fallback_left.assign(c->ncells, 0);
+    h->frozen_at.assign(c->ncells, c->kstep);
     h->check_every = check_every;
     h->check_cells = check_cells;
     h->tol = tol;
     h->fallback_steps = fallback_steps;
+    h->net_window = net_window;
     for (int q = 0; q < kNumBuckets; ++q) {
         h->bk[q].waves = c->bk[q].waves;
         h->bk[q].queue = c->bk[q].queue;
@@ -521,14 +519,20 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     const size_t nk = (size_t)std::max(1, check_cells);
     SP_TRY(dalloc(c, &h->row_d, (size_t)c->ncells));
     SP_TRY(dalloc(c, &h->chk_d, nk));
-    SP_TRY(dalloc(c, &h->rs_d, nk));
     SP_TRY(dalloc(c, &h->Xk, nk * spmlp::kIn));
     SP_TRY(dalloc(c, &h->Tk, nk * spmlp::kOut));
     SP_TRY(dalloc(c, &h->Tdem, nk * spmlp::kOut));
-    SP_TRY(dalloc(c, &h->fresh, (size_t)c->ncells * kMomStride));
     SP_TRY(dalloc(c, &h->Qs, (size_t)c->ncells * 4));
+    SP_TRY(dalloc(c, &h->back_d, (size_t)c->ncells));
     SP_TRY(upload_phase(c));
     SP_TRY(ensure_cell_data(c));
+    {
+        std::vector<double> red((size_t)c->ncells * 4);
+        HIP_TRY(c, hipMemcpyAsync(red.data(), c->red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        h->red_t0.resize(c->ncells);
+        for (int i = 0; i < c->ncells; ++i) h->red_t0[i] = red[(size_t)i * 4 + 3];
+    }
     drop_graph(c);
     return hybrid_rebuild(c);
 }
@@ -552,50 +556,60 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
         const int64_t k = c->kstep;
         const int nclos = (int)h->clos_h.size();
         if (nclos > 0) {
-            // transported level-k state, closure tendencies for its features,
-            // closure-cell coefficients of the level-k state
-            hipLaunchKernelGGL(transport_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
-                               h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly);
+            // base-updated level-k state, the network's residual for its
+            // features, the closure cells' coefficients from their reduced DEMs
+            const ClosureArgs ca = closure_args(c, c->t_now);
+            hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
+                               h->Qs, ca, dt);
             HIP_TRY(c, hipGetLastError());
-            hipLaunchKernelGGL(features_list_kernel, dim3((nclos + 127) / 128), dim3(128), 0, c->stream, h->clos_d,
-                               nclos, h->Qs, c->p.nx, c->p.ny, c->phase, c->nmodes, base.modes, base.u0, base.v0,
-                               c->desc, h->X);
+            hipLaunchKernelGGL(features_kernel, dim3((nclos + 127) / 128), dim3(128), 0, c->stream, h->clos_d, nclos,
+                               h->Qs, ca, c->desc, h->X);
             HIP_TRY(c, hipGetLastError());
             SP_TRY(net_forward_on(c, h->net, h->X, nclos, h->T));
-            hipLaunchKernelGGL(closure_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream, h->clos_d,
-                               nclos, c->Q[k & 1], c->ncells, c->momb[k & 1]);
+            hipLaunchKernelGGL(reduced_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream, h->clos_d,
+                               nclos, ca, c->momb[k & 1]);
             HIP_TRY(c, hipGetLastError());
         }
         // DEM step of the other cells (statistics of level k)
         for (auto& b : h->bk) SP_TRY(launch_bucket(c, b, base, k, false));
         hipLaunchKernelGGL(hybrid_continuum_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream,
-                           c->momb[k & 1], c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->mf, c->phase,
-                           c->nmodes, base.modes, base.u0, base.v0, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
-                           inv_area, c->cfl_bits_d, c->err_d);
+                           c->momb[k & 1], c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->red, c->t_now,
+                           h->net_window, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly, inv_area, c->cfl_bits_d,
+                           c->err_d);
         HIP_TRY(c, hipGetLastError());
         c->kstep++;
         c->steps++;
+        c->t_now += dt;
         h->hsteps++;
-        // fallback windows that end with this step
-        bool changed = false;
+        // fallback windows that end with this step: those cells' reduced DEMs
+        // restart from their floes
+        std::vector<int32_t> back;
         size_t keep = 0;
         for (size_t i = 0; i < h->fallback_cells.size(); ++i) {
             const int32_t cell = h->fallback_cells[i];
             if (--h->fallback_left[cell] == 0) {
-                changed = changed || h->closure[cell];
+                if (h->closure[cell]) back.push_back(cell);
             } else {
                 h->fallback_cells[keep++] = cell;
             }
         }
         h->fallback_cells.resize(keep);
-        if (changed) SP_TRY(hybrid_rebuild(c));
+        if (!back.empty()) {
+            HIP_TRY(c, hipMemcpyAsync(h->back_d, back.data(), back.size() * 4, hipMemcpyHostToDevice, c->stream));
+            SP_TRY(restart_reduced(c, h->back_d, (int)back.size(), nullptr));
+            for (int32_t cell : back) {
+                h->frozen_at[cell] = c->kstep;
+                h->red_t0[cell] = c->t_now;
+            }
+            SP_TRY(hybrid_rebuild(c));   // synchronises: `back` may go
+        }
         if (h->hsteps % h->check_every == 0) SP_TRY(hybrid_check(c, dt));
     }
     return SP_OK;
 }
 
 sp_status sp_hybrid_stats(sp_ctx* c, int32_t* dem_cells, int32_t* closure_cells, int64_t* checks,
-                          int64_t* fallbacks, int64_t* clamped)
+                          int64_t* fallbacks)
 {
     if (!c) return SP_EINVAL;
     if (!c->hyb) return fail(c, SP_ESTATE, "sp_hybrid_stats before sp_hybrid_set");
@@ -603,7 +617,6 @@ sp_status sp_hybrid_stats(sp_ctx* c, int32_t* dem_cells, int32_t* closure_cells,
     if (closure_cells) *closure_cells = (int32_t)c->hyb->clos_h.size();
     if (checks) *checks = c->hyb->checks;
     if (fallbacks) *fallbacks = c->hyb->fallbacks;
-    if (clamped) *clamped = c->hyb->clamped;
     return SP_OK;
 }
 

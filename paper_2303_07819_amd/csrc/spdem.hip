@@ -95,6 +95,8 @@ struct sp_ctx {
     unsigned long long* cfl_bits_d = nullptr;
     float* desc = nullptr;                  // closure descriptors [ncells][6] (lazy)
     double* mf = nullptr;                   // mean-field drag coefficients [ncells][4] (with desc)
+    double* red = nullptr;                  // reduced DEM of every cell [ncells][4]
+    double t_now = 0.0;                     // time of the current state since the floes were set
     double* qprev = nullptr;                // continuum snapshot for tendencies
 
     // time stepping
@@ -112,6 +114,11 @@ struct sp_ctx {
 };
 
 void hybrid_free(sp_ctx* c);   // hybrid_host.h
+
+namespace {
+sp_status init_reduced_all(sp_ctx* c, const double* mom);   // closure_host.h
+sp_status refresh_reduced_all(sp_ctx* c);
+}  // namespace
 
 namespace {
 
@@ -173,7 +180,7 @@ void free_all(sp_ctx* c)
     hybrid_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d, c->desc, c->mf, c->qprev};
+                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -192,6 +199,7 @@ void free_all(sp_ctx* c)
     c->contacts_d = c->cfl_bits_d = nullptr;
     c->desc = nullptr;
     c->mf = nullptr;
+    c->red = nullptr;
     c->qprev = nullptr;
 }
 
@@ -632,7 +640,13 @@ sp_status sp_set_ocean(sp_ctx* c, double u0, double v0, int32_t nmodes, const do
     }
     c->phase_dirty = true;
     drop_graph(c);
-    return upload_phase(c);
+    SP_TRY(upload_phase(c));
+    if (c->have_floes) {
+        // the reduced DEM is relative to the current: take it again from the floes
+        SP_TRY(flush_lf(c));
+        SP_TRY(refresh_reduced_all(c));
+    }
+    return SP_OK;
 }
 
 static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, const void* const* src,
@@ -661,6 +675,7 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     if (c->mf) (void)hipFree(c->mf);
     c->desc = nullptr;
     c->mf = nullptr;
+    c->t_now = 0.0;
     const size_t N = (size_t)n;
     SP_TRY(dalloc(c, &c->xi, N));
     SP_TRY(dalloc(c, &c->yi, N));
@@ -729,6 +744,7 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     c->steps = 0;
     SP_TRY(upload_phase(c));
     SP_TRY(reset_continuum(c));
+    SP_TRY(init_reduced_all(c, c->momb[0]));   // statistics of the initial state
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->have_floes = true;
     return SP_OK;
@@ -764,6 +780,7 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
     }
     const bool cont = !(c->p.flags & SP_NO_CONTINUUM);
     const StepArgs base = make_args(c, dt);
+    c->t_now += dt * (double)nsteps;
     int64_t left = nsteps;
     while (left > 0) {
         const bool steady = (c->kstep % 2 == 0) && (c->lf_pending == cont);
@@ -800,6 +817,7 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
     for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
     const StepArgs base = make_args(c, dt);
     sp_status st = SP_OK;
+    c->t_now += dt * (double)nsteps;
     for (int64_t k = 0; k < nsteps && !st; ++k) {
         HIP_TRY(c, hipEventRecord(ev[2 * k], c->stream));
         st = step_once(c, base);

@@ -9,7 +9,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import rel_err
-from closure_ref import base_update, transport
+import closure_ref as cref
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
@@ -136,19 +136,6 @@ def test_training_reduces_loss_on_a_smooth_target():
     net.close()
 
 
-def _descriptors(w):
-    st = w.start
-    out = np.zeros((w.ncells, 6))
-    for c in range(w.ncells):
-        r = w.r[st[c]:st[c + 1]].astype(np.float64)
-        h = w.h[st[c]:st[c + 1]].astype(np.float64)
-        n = r.size
-        if n:
-            out[c] = [n, np.sum(np.pi * r * r) / (w.Lx * w.Ly), r.mean(), (r * r).mean(), h.mean(),
-                      np.sum(h * r ** 4) / np.sum(h * r ** 2)]
-    return out
-
-
 def test_features_and_tendencies_match_oracle():
     w = fixtures.custom(6, 5, 25e3, 40, seed=21, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
     w.counts[3] = 0
@@ -164,20 +151,13 @@ def test_features_and_tendencies_match_oracle():
         s.closure_sample(w.dt, x, t)
         torch.cuda.synchronize()
         xs, ts = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
-    ref = np.zeros((w.ncells, 45))
-    for c in range(w.ncells):
-        ix, iy = c % w.nx, c // w.nx
-        k = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                nb = ((iy + dy) % w.ny) * w.nx + (ix + dx) % w.nx
-                ref[c, k:k + 4] = Q0[nb]
-                k += 4
-        ref[c, 36:39] = oracle.ocean_at(m, (ix + 0.5) * w.Lx, (iy + 0.5) * w.Ly)
-    ref[:, 39:] = _descriptors(w)
+    static = cref.cell_static(w)
+    oce = cref.ocean_centres(w, m)
+    red = cref.reduced_init(oracle.moments(m, oracle.State.from_workload(w)), static, oce, 0.0)
+    ref = cref.features(w, Q0, range(w.ncells), red, nsteps * w.dt, static, oce)
     e = rel_err(xs, ref)
     _say(f"features max rel err {e.max():.2e}")
-    assert e.max() <= 1e-5
+    assert e.max() <= 1e-5, np.unravel_index(e.argmax(), e.shape)
     tend = (Q1 - Q0) / w.dt
     et = np.abs(ts - tend) / np.maximum(np.abs(tend), 1e-2 * np.sqrt(np.mean(tend ** 2, axis=0)))
     _say(f"tendency max rel err {et.max():.2e}")
@@ -185,19 +165,23 @@ def test_features_and_tendencies_match_oracle():
 
 
 def test_residual_tendencies_match_oracle():
-    """Residual samples: the features of the transported state Q* and the
-    targets (Q_new - relax(Q*)) / dt of closure_ref.py."""
+    """Residual samples: the features of the base-updated state Q_b (every
+    cell's statistics from its reduced DEM) and the targets (Q_new - Q_b) / dt."""
     w = fixtures.custom(5, 4, 25e3, 40, seed=22, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
     rng = np.random.default_rng(22)
     w.u[:] = rng.normal(0, 0.1, w.nfloes)
     w.v[:] = rng.normal(0, 0.1, w.nfloes)
+    w.omega[:] = rng.normal(0, 1e-4, w.nfloes)
     nsteps = 2
     _, Q0, _, _ = oracle.run_plain(w, nsteps)
     _, Q1, _, _ = oracle.run_plain(w, nsteps + 1)
     m = oracle.Model(w)
-    Qb = base_update(w, m, Q0, w.dt)
+    static = cref.cell_static(w)
+    oce = cref.ocean_centres(w, m)
+    red = cref.reduced_init(oracle.moments(m, oracle.State.from_workload(w)), static, oce, 0.0)
+    Qb = cref.base_update(w, m, Q0, w.dt, red, nsteps * w.dt, static, oce)
     ref = (Q1 - Qb) / w.dt
-    Qs = transport(m, Q0, w.dt)
+    xref = cref.features(w, Qb, range(w.ncells), red, nsteps * w.dt, static, oce)
     with sp.Sim.from_workload(w) as s:
         s.step(w.dt, nsteps)
         x = torch.zeros((w.ncells, 45), device="cuda")
@@ -205,18 +189,9 @@ def test_residual_tendencies_match_oracle():
         s.closure_sample(w.dt, x, t, mode=sp.TEND_RESIDUAL)
         torch.cuda.synchronize()
         xs, ts = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
-    xref = np.zeros((w.ncells, 36))
-    for c in range(w.ncells):
-        ix, iy = c % w.nx, c // w.nx
-        k = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                nb = ((iy + dy) % w.ny) * w.nx + (ix + dx) % w.nx
-                xref[c, k:k + 4] = Qs[nb]
-                k += 4
-    ex = rel_err(xs[:, :36], xref)
-    _say(f"transported-state features max rel err {ex.max():.2e}")
-    assert ex.max() <= 1e-5
+    ex = rel_err(xs, xref)
+    _say(f"base-state features max rel err {ex.max():.2e}")
+    assert ex.max() <= 1e-5, np.unravel_index(ex.argmax(), ex.shape)
     # the residual is the small part of the update: measure against its own scale
     e = np.abs(ts - ref) / np.maximum(np.abs(ref), 1e-2 * np.sqrt(np.mean(ref ** 2, axis=0)))
     _say(f"residual tendency max rel err {e.max():.2e}")
