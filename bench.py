@@ -45,6 +45,41 @@ def cpu_baseline(w, budget_s=12.0):
                       f"(brute-force contacts, FP64, OpenMP over cells)"}
 
 
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "dem_cell_kernel_plain64.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_07819_amd", "csrc", "dem_kernels.h")
+
+
+def copy_calibration(nbytes=1 << 30, reps=4):
+    """A plain device copy of nbytes, reps times: FETCH_SIZE and WRITE_SIZE of
+    its dispatches against nbytes give the scale of those counters."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per DEM launch from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE_SUMMARY).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+            k, v = line.strip().strip("`").split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +92,12 @@ def main():
     ap.add_argument("--no-hybrid", action="store_true",
                     help="skip training the closure and the DEM + closure run on the 512 x 512 grid")
     ap.add_argument("--hybrid-steps", type=int, default=2000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "cells would shard as 2-D blocks with a one-cell halo of coarse moments", file=sys.stderr)
@@ -119,7 +159,7 @@ def main():
                    "continuum": "lax-friedrichs every step"},
         "roofline": {"bound": "hbm", "kernel": "dem_cell_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "kernel_ms": dem_ms, "lf_kernel_ms": lf_ms,
+                     "traffic": measured_traffic(), "kernel_ms": dem_ms, "lf_kernel_ms": lf_ms,
                      "algorithmic_bytes_per_launch": bytes_launch},
         "contacts_per_floe_step": contacts_per_floe_step,
         "wall_s_timed": wall,
