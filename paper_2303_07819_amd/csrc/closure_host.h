@@ -340,6 +340,7 @@ struct sp_mlp {
     uint16_t* dzH[2] = {nullptr, nullptr};
     float* sq = nullptr;
     float* loss_d = nullptr;
+    float* part = nullptr;       // split-K partial products [kSplitMax][kHid * kHid]
 };
 
 namespace {
@@ -404,9 +405,39 @@ sp_status ensure_rows(sp_mlp* mm, int64_t rows)
     return SP_OK;
 }
 
+// Largest number of K slices of a split product, and the K per slice below
+// which it does not split.
+constexpr int kSplitMax = 64;
+constexpr int kSplitMinK = 64;
+
 sp_status gemm(sp_mlp* mm, GemmArgs g)
 {
     if (g.M <= 0 || g.N <= 0) return SP_OK;
+    const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
+    int slices = 1;
+    if (g.mode == EPI_STORE && g.outF && !g.outH && (long)g.M * g.N <= (long)kHid * kHid && tiles < 256) {
+        // enough workgroups for the chip, at least kSplitMinK per slice
+        slices = std::min(kSplitMax, std::max(1, std::min(256 / tiles, g.K / kSplitMinK)));
+    }
+    if (slices > 1 && g.ldf != g.N) slices = 1;   // partial tiles are dense [M][N]
+    if (slices > 1) {
+        if (!mm->part) SP_TRY(malloc_m(mm, &mm->part, (size_t)kSplitMax * kHid * kHid));
+        const int kc = ((g.K + slices - 1) / slices + 15) / 16 * 16;
+        slices = (g.K + kc - 1) / kc;
+        float* out = g.outF;
+        g.outF = mm->part;
+        g.ldf = g.N;
+        g.kchunk = kc;
+        g.part_stride = (long)g.M * g.N;
+        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, slices);
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, mm->stream, g);
+        MLP_HIP(mm, hipGetLastError());
+        const long n = (long)g.M * g.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, mm->stream,
+                           (const float*)mm->part, slices, n, n, out);
+        MLP_HIP(mm, hipGetLastError());
+        return SP_OK;
+    }
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, mm->stream, g);
     MLP_HIP(mm, hipGetLastError());
@@ -580,7 +611,7 @@ void sp_mlp_destroy(sp_mlp* mm)
     if (mm->stream) (void)hipStreamSynchronize(mm->stream);
     void* ps[] = {mm->theta, mm->theta_h, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->a0, mm->z[0], mm->z[1],
                   mm->z[2], mm->a[0], mm->a[1], mm->a[2], mm->y, mm->dF, mm->dH, mm->dzF[0], mm->dzF[1],
-                  mm->dzH[0], mm->dzH[1], mm->sq};
+                  mm->dzH[0], mm->dzH[1], mm->sq, mm->part};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (mm->own_stream && mm->stream) (void)hipStreamDestroy(mm->stream);

@@ -6,7 +6,10 @@
 // B(k, n) addressed through strides, so the transposed products of the
 // backward pass need no copies.  A 256-thread workgroup computes a 64 x 64
 // output tile; each wavefront owns a 32 x 32 quarter as 2 x 2 MFMA tiles and
-// the K loop stages 64 x 16 and 16 x 64 bfloat16 tiles in LDS.  The epilogue
+// the K loop stages 64 x 16 and 16 x 64 bfloat16 tiles in LDS.  Products with
+// few output tiles and a long K (the weight gradients, K = batch) split K over
+// the grid's z dimension into partial tiles that a second kernel sums in a
+// fixed order.  The epilogue
 // adds the bias and applies GELU (forward), the GELU derivative (backward) or
 // an affine output map, and writes FP32 and/or bfloat16 results.
 #pragma once
@@ -62,6 +65,8 @@ struct GemmArgs {
     long ldh;
     const float* zsaved;    // EPI_GELU_BACK: pre-activations [M][ldz]
     long ldz;
+    int kchunk;             // split K: workgroup z covers k in [z kchunk, (z + 1) kchunk) (EPI_STORE into
+    long part_stride;       // outF + z part_stride; 0: one slice)
 };
 
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
@@ -71,20 +76,23 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kbeg = g.kchunk > 0 ? (int)blockIdx.z * g.kchunk : 0;
+    const int kend = g.kchunk > 0 ? min(g.K, kbeg + g.kchunk) : g.K;
+    if (g.kchunk > 0) g.outF += (long)blockIdx.z * g.part_stride;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
         {
             const int r = tid >> 2, kk = (tid & 3) * 4;
             const int m = m0 + r;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = k0 + kk + q;
-                As[r][kk + q] = (m < g.M && k < g.K) ? g.A[(long)m * g.sam + (long)k * g.sak] : (uint16_t)0;
+                As[r][kk + q] = (m < g.M && k < kend) ? g.A[(long)m * g.sam + (long)k * g.sak] : (uint16_t)0;
             }
         }
         {
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int n = n0 + cc + q;
-                Bs[kk][cc + q] = (k < g.K && n < g.N) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (uint16_t)0;
+                Bs[kk][cc + q] = (k < kend && n < g.N) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (uint16_t)0;
             }
         }
         __syncthreads();
@@ -141,6 +149,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
                     if (g.outH) g.outH[(long)row * g.ldh + col] = f2bf(v);
                 }
             }
+}
+
+// Sum of the `slices` partial products of a split-K product, in slice order:
+// out[i] = sum_z part[z stride + i], i < n.
+__global__ void splitk_reduce_kernel(const float* part, int slices, long stride, long n, float* out)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int z = 0; z < slices; ++z) s += part[(long)z * stride + i];
+    out[i] = s;
 }
 
 // x [M][kIn] FP32 -> bfloat16 of (x - mean) / std; optional row gather.
