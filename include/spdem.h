@@ -76,7 +76,8 @@ typedef enum {
 
 #define SP_MAX_MODES 16        /* ocean Fourier modes */
 #define SP_MAX_CELL_FLOES 1024 /* floes per cell (LDS-resident cell) */
-#define SP_CONTACT_CAP 16      /* contacts per floe per step */
+#define SP_CONTACT_CAP 24      /* contact candidates per floe: contacts and the
+                                  neighbours within the candidate-list skin */
 
 typedef struct {
     int32_t nx, ny;           /* coarse grid = one DEM per cell (Sec. 3.1) */
@@ -218,7 +219,10 @@ sp_status sp_set_graph_chunk(sp_ctx* ctx, int32_t chunk);
  * cell's reduced DEM is taken from its floes when they are set, when the
  * ocean is set, and when the cell is re-synchronised.
  * All data pointers of the sp_mlp_* calls are device pointers except where
- * marked host.  The object runs on its own stream (or the one given). */
+ * marked host.  The object runs on its own stream (or the one given), in
+ * stream order: device inputs must be ready on that stream when a call is
+ * made, and sp_mlp_forward's output is ready once the stream reaches it
+ * (calls that return host values synchronise the stream). */
 #define SP_MLP_NPARAMS 39428
 #define SP_MLP_IN 45
 #define SP_MLP_OUT 4

@@ -320,6 +320,7 @@ class MLP:
         if st != 0:
             raise SpdemError(st, "sp_mlp_create failed")
         self._h = h
+        self.stream = stream   # raw handle the calls run on (None: the library's own stream)
 
     def _check(self, st):
         if st != 0:

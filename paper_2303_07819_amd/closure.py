@@ -26,6 +26,16 @@ from . import MLP, Sim, TEND_RESIDUAL, MOMENTS_CONTINUUM
 MIZ_LO, MIZ_HI = 0.15, 0.8   # marginal ice zone: the DEM runs where lo <= c <= hi
 
 
+def _torch_stream(stream):
+    """A torch stream object for a raw stream handle (a new stream for None).
+
+    The library's calls run on the stream they are given; torch's own work on
+    the same tensors (allocation, indexing, noise, reductions) must run on that
+    stream too, inside ``torch.cuda.stream(...)``, or the two race."""
+    import torch
+    return torch.cuda.Stream() if stream is None else torch.cuda.ExternalStream(stream)
+
+
 def training_workload(seed: int, n: int = 64, nmax: int = 256, domain_cells: int = 512):
     """A 64 x 64 window of 25 km cells drawn from the recipe of a
     domain_cells x domain_cells grid: Poisson(nmax c) floes per cell with a
@@ -67,14 +77,16 @@ def generate_samples(workloads, schedule=None, stream=None, log=None):
     of a run of each workload from its initial state; device tensors [n, 45]
     and [n, 4]."""
     import torch
+    ts = _torch_stream(stream)
     schedule = sample_schedule() if schedule is None else sorted(schedule)
     n = sum(w.ncells for w in workloads) * len(schedule)
-    X = torch.empty((n, 45), device="cuda", dtype=torch.float32)
-    T = torch.empty((n, 4), device="cuda", dtype=torch.float32)
+    with torch.cuda.stream(ts):
+        X = torch.empty((n, 45), device="cuda", dtype=torch.float32)
+        T = torch.empty((n, 4), device="cuda", dtype=torch.float32)
     row = 0
     for w in workloads:
         t0 = time.perf_counter()
-        with Sim.from_workload(w, stream=stream) as s:
+        with Sim.from_workload(w, stream=ts.cuda_stream) as s:
             at = 0
             for k in schedule:
                 if k > at:
@@ -101,6 +113,13 @@ def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int
     clean inputs).  With use_stencil False the stencil inputs are dropped
     (zero input scale)."""
     import torch
+    ts = _torch_stream(stream)
+    with torch.cuda.stream(ts):
+        return _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, ts, log)
+
+
+def _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, ts, log):
+    import torch
     import fixtures
     n = X.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -108,7 +127,7 @@ def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int
     nval = int(n * holdout)
     val = order[:nval].to("cuda", torch.int32)
     tr = order[nval:]
-    net = MLP(stream)
+    net = MLP(ts.cuda_stream)
     net.set_params(fixtures.mlp_init(seed))
     Xtr = X[tr.to("cuda")].contiguous()
     Ttr = T[tr.to("cuda")].contiguous()
@@ -141,7 +160,14 @@ def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int
 
 
 def validation_loss(net, X, T, rows, chunk: int = 1 << 17) -> float:
-    """Mean squared error on normalised targets over the listed rows."""
+    """Mean squared error on normalised targets over the listed rows (torch's
+    work runs on the network's stream)."""
+    import torch
+    with torch.cuda.stream(_torch_stream(net.stream)):
+        return _validation_loss(net, X, T, rows, chunk)
+
+
+def _validation_loss(net, X, T, rows, chunk):
     import torch
     x_mean, x_inv, y_mean, y_std = net.get_norm()
     ym = torch.as_tensor(y_mean, device="cuda")

@@ -14,13 +14,16 @@
 // list, or through a per-launch work counter (persistent workgroups).
 //
 // Per cell and step the group:
-//   1. stages positions, radii, velocities and spins in LDS; binned schedule:
-//      counting sort into sub-bins of side >= 2 r_max;
-//   2. screens contact candidates in FP32 (all pairs, or a half shell over the
-//      bin-sorted copy) and appends each candidate pair to both floes' LDS
-//      contact lists; pairs within a 2^-19 relative guard band of touching are
-//      decided later by the FP64 expression (dx dx + dy dy) < R R without
-//      contraction, so the contact set is the one that expression defines;
+//   1. stages positions, radii, velocities and spins in LDS;
+//   2. when the cell's candidate lists are stale (its floes may have moved by
+//      half the skin since they were built), rebuilds them: binned schedule
+//      counting sort into sub-bins of side >= 2 r_max + skin, FP32 screen of
+//      candidate pairs with R + skin (all pairs, or a half shell over the
+//      bin-sorted copy), each pair appended to both floes' lists, sorted and
+//      kept in HBM; otherwise reads the kept lists.  Every listed candidate is
+//      decided each step: within a 2^-19 relative guard band of touching by the
+//      FP64 expression (dx dx + dy dy) < R R without contraction, outside it by
+//      the FP32 screen, so the contact set is the one that expression defines;
 //   3. per floe: ocean current and curl (angle addition around the cell centre,
 //      Taylor sincos), FP64 drag and drag torque, contacts in ascending partner
 //      index (FP64), semi-implicit update, FP32 / fixed-point store;
@@ -40,6 +43,7 @@ namespace spdem {
 
 constexpr int kMomStride = 16;          // doubles per cell in the statistics buffers (128 B)
 constexpr int kListCap = SP_CONTACT_CAP;
+static_assert(kListCap % 8 == 0 && kListCap <= 32, "candidate lists: groups of eight, one 32-bit contact mask");
 constexpr int kMaxBinsSide = 32;
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kGuard = 1.0f / 524288.0f;  // 2^-19
@@ -75,7 +79,17 @@ struct StepArgs {
     const float2* phase;       // [ncells][nmodes]: (sin, cos) of the phase at the cell centre
     double* mom;               // statistics written by this step [ncells][kMomStride]
     uint32_t* err;
-    unsigned long long* contacts;
+    unsigned long long* contacts;   // [ncells] contacts counted per cell since the floes were set
+    // candidate lists kept between steps (Verlet lists with a skin): per cell,
+    // from floe-index start * kListCap, [kListCap / 8][n][8] (groups of eight
+    // entries per floe), partner indices in ascending order; per floe its
+    // candidate count; per cell a bound on the
+    // largest floe displacement since the lists were built (a cell rebuilds when
+    // it passes skin / 2, or is not finite)
+    uint16_t* vlist;
+    uint8_t* vcount;
+    float* vdisp;
+    float skin;                // m, added to R when the lists are built
     // work list
     const int4* work;          // (cell, first floe, floe count, -) of this launch, costliest first
     int32_t ncl;
@@ -112,6 +126,13 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ float wave_max_f32(float x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
     return x;
 }
 
@@ -311,6 +332,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     __shared__ float4 mode_k[SP_MAX_MODES];            // kx Lx, ky Ly, au, av
     __shared__ float4 mode_c[GPB][SP_MAX_MODES];       // curl coefficient, sin, cos of centre phase
     __shared__ int wsum[GPB][W];
+    __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
     __shared__ int qbase;
 
@@ -349,6 +371,14 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         const bool valid = item < a.ncl;
         const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
         const int c = wk.x, s = wk.y, n = wk.z;
+        const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;   // loaded early
+        // rebuild the cell's candidate lists when its floes may have moved by
+        // skin / 2 since they were built (every pair then changed its distance
+        // by less than the skin); the same for the whole group
+        const float vd = valid ? a.vdisp[c] : 0.0f;
+        const bool build = valid && !(vd <= 0.5f * a.skin);
+        const int nb_build = build ? n : 0;        // loop bound of the build work
+        uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
 
         if (valid && gt < a.nmodes) {
             const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
@@ -356,14 +386,29 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         }
         for (int i = gt; i < n; i += G) {
             P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), 0u);
-            V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], 0.0f);
-            cnt[i] = 0;
+            V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], a.h[s + i]);
+            if (build) {
+                cnt[i] = 0;
+            } else {
+                // kept candidates: the first eight in one 16-byte load issued with
+                // the floe state, the rest (rare) after the count
+                const int k = a.vcount[s + i];
+                cnt[i] = k;
+                uint16_t* my = lst + (size_t)i * kListCap;
+                *reinterpret_cast<uint4*>(my) = *reinterpret_cast<const uint4*>(vlst + (size_t)i * 8);
+                for (int q = 8; q < k; q += 8)
+                    *reinterpret_cast<uint4*>(my + q) =
+                        *reinterpret_cast<const uint4*>(vlst + (size_t)q * n + (size_t)i * 8);
+            }
         }
-        if (SCHED == 2) {
+        // the search runs only in workgroups where some cell rebuilds its lists
+        // (the barriers below are workgroup-wide)
+        const bool any_build = __syncthreads_or(build);
+        if (SCHED == 2 && any_build) {
             const int nb = a.nbx * a.nby;
             for (int b = gt; b < nb; b += G) bcnt[b] = 0;
             __syncthreads();
-            for (int i = gt; i < n; i += G) {
+            for (int i = gt; i < nb_build; i += G) {
                 const int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
                 const int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
                 const int b = by * a.nbx + bx;
@@ -372,21 +417,21 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             }
             __syncthreads();
             group_exclusive_scan<G>(bcnt, bstart, nb, gt, wsum[g]);
-            for (int i = gt; i < n; i += G) {
+            for (int i = gt; i < nb_build; i += G) {
                 uint4 p = P[i];
                 p.w = (uint32_t)i | ((uint32_t)binof[i] << 16);
                 S[bstart[binof[i]] + rank[i]] = p;
             }
+            __syncthreads();
         }
-        __syncthreads();
 
         // ---- phase 1: contact candidates -> per-floe lists
         if (SCHED == 1) {
             // every floe against every floe (itself included, skipped later);
             // the list comes out in ascending partner order
-            for (int l = gt; l < n; l += G) {
+            for (int l = gt; l < nb_build; l += G) {
                 const uint4 pl = P[l];
-                const float rl = __uint_as_float(pl.z);
+                const float rl = __uint_as_float(pl.z) + a.skin;
                 uint16_t* my = lst + (size_t)l * kListCap;
                 int k = 0;
                 for (int j = 0; j < n; ++j) {
@@ -406,12 +451,12 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             // floes (neighbouring lanes share their neighbourhood); each pair is
             // screened once, from the bin whose offset to the other is in
             // {own bin (later sorted index), E, NW, N, NE}, and appended to both lists
-            for (int t = gt; t < n; t += G) {
+            for (int t = gt; t < nb_build; t += G) {
                 const uint4 own = S[t];
                 const int o = (int)(own.w & 0xffffu);
                 const int b = (int)(own.w >> 16);
                 const int bx = b % a.nbx, by = b / a.nbx;
-                const float rl = __uint_as_float(own.z);
+                const float rl = __uint_as_float(own.z) + a.skin;
                 if (a.nbx >= 3 && bx + 1 < a.nbx) {
                     // own-bin tail and the east bin are contiguous
                     sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
@@ -447,6 +492,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 #pragma unroll
         for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
         unsigned long long ncontact = 0;
+        float maxdisp = 0.0f;
 
         for (int l = gt; l < n; l += G) {
             const uint4 pl = P[l];
@@ -487,36 +533,61 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 const double beta = a.cdrho * kPi * r2 * r2 * rld;
                 tdr = beta * dW * fabs(dW);
             }
-            const double md = a.rho_ice_d * (double)a.h[s + l] * kPi * rld * rld;
+            const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
 
             uint16_t* my = lst + (size_t)l * kListCap;
-            int k = cnt[l];
-            if (k > kListCap) {
-                atomicOr(a.err, kErrCapacity);
-                k = kListCap;
-            }
-            if (SCHED == 2) {
-                // ascending partner order: insertion sort of the short list
-                for (int i = 1; i < k; ++i) {
-                    const uint16_t key = my[i];
-                    int j = i - 1;
-                    while (j >= 0 && my[j] > key) {
-                        my[j + 1] = my[j];
-                        --j;
+            int k;
+            if (build) {
+                k = cnt[l];
+                if (k > kListCap) {
+                    atomicOr(a.err, kErrCapacity);
+                    k = kListCap;
+                }
+                if (SCHED == 2) {
+                    // ascending partner order: insertion sort of the short list
+                    for (int i = 1; i < k; ++i) {
+                        const uint16_t key = my[i];
+                        int j = i - 1;
+                        while (j >= 0 && my[j] > key) {
+                            my[j + 1] = my[j];
+                            --j;
+                        }
+                        my[j + 1] = key;
                     }
-                    my[j + 1] = key;
+                }
+                // keep the list for the steps until the next rebuild
+                for (int q = 0; q < k; ++q) vlst[(size_t)(q & ~7) * n + (size_t)l * 8 + (q & 7)] = my[q];
+                a.vcount[s + l] = (uint8_t)k;
+            } else {
+                k = cnt[l];   // staged with the floe state
+            }
+
+            // ---- contact decisions: every candidate, eight indices per LDS read;
+            // the contacts become a bit mask over the (ascending) list
+            uint32_t cmask = 0;
+            for (int q0 = 0; q0 < k; q0 += 8) {
+                const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
+                const int qe = min(8, k - q0);
+                for (int t = 0; t < qe; ++t) {
+                    const uint32_t wv = t < 2 ? ix.x : t < 4 ? ix.y : t < 6 ? ix.z : ix.w;
+                    const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
+                    if (j == l) continue;
+                    const uint4 pj = P[j];
+                    if (decide((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a))
+                        cmask |= 1u << (q0 + t);
                 }
             }
 
-            // ---- contact forces and torques in ascending partner order (FP64)
+            // ---- contact forces and torques in ascending partner order (FP64);
+            // a wave runs as many rounds as its lanes have contacts at most
             double Fx = fdx, Fy = fdy, T = tdr;
-            for (int q = 0; q < k; ++q) {
+            while (cmask) {
+                const int q = __builtin_ctz(cmask);
+                cmask &= cmask - 1u;
                 const int j = my[q];
-                if (j == l) continue;
                 const uint4 pj = P[j];
                 const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
                 const float rj = __uint_as_float(pj.z);
-                if (!decide(dxi, dyi, rl, rj, a)) continue;
                 const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
                 const double d2 = dx * dx + dy * dy;
                 if (!(d2 > 0.0)) {
@@ -564,6 +635,10 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
             const int sx = __double2int_rn(dt * ux * a.inv_qxd);
             const int sy = __double2int_rn(dt * vx * a.inv_qyd);
+            {
+                const float ddx = (float)sx * a.qx, ddy = (float)sy * a.qy;
+                maxdisp = fmaxf(maxdisp, sqrtf(ddx * ddx + ddy * ddy));
+            }
             const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
             a.xi[s + l] = xl + (uint32_t)sx;
             a.yi[s + l] = yl + (uint32_t)sy;
@@ -587,18 +662,30 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         // ---- group reduction through LDS: lane partials -> 16 segment sums per
         // quantity -> DPP row sum (fixed order, deterministic)
         const unsigned long long cs = wave_sum_u64(ncontact);
-        if ((tid & 63) == 0) csum[tid >> 6] = cs;
+        const float wd = wave_max_f32(maxdisp);
+        if ((tid & 63) == 0) {
+            csum[tid >> 6] = cs;
+            wdisp[tid >> 6] = wd;
+        }
         __syncthreads();   // every lane is done with the cell's LDS data
+        if (valid && gt == 0) {
+            float d = 0.0f;
+            for (int q = 0; q < W; ++q) d = fmaxf(d, wdisp[g * W + q]);
+            // the bound grows by the largest displacement of this step (rounded up)
+            a.vdisp[c] = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
+        }
 #pragma unroll
         for (int k = 0; k < kDyn; ++k) red[k * G + gt] = acc[k];
         __syncthreads();
         constexpr int SEG = G / 16;                 // values per segment
         for (int kq = gt >> 4; kq < kDyn; kq += G / 16) {
+            // segment seg sums lanes seg, seg + 16, ... in order (neighbouring
+            // lanes read neighbouring words: no bank conflicts)
             const int seg = gt & 15;
-            const double* src = red + kq * G + seg * SEG;
+            const double* src = red + kq * G + seg;
             double x = 0.0;
 #pragma unroll
-            for (int i = 0; i < SEG; ++i) x += src[i];
+            for (int i = 0; i < SEG; ++i) x += src[16 * i];
             x = row_sum(x);
             if (seg == 15 && valid) {
                 const int slot = dyn_slot(kq);
@@ -608,10 +695,12 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                         n > 0 ? x / (double)n : 0.0;
             }
         }
-        if (tid == 0) {
+        if (valid && gt == 0) {
+            // per-cell running count, written by the cell's own group only (one
+            // shared counter would serialise every workgroup on one address)
             unsigned long long t = 0;
-            for (int q = 0; q < (int)(blockDim.x / 64); ++q) t += csum[q];
-            if (t) atomicAdd(a.contacts, t);
+            for (int q = 0; q < W; ++q) t += csum[g * W + q];
+            a.contacts[c] = ccell + t;
         }
         // continuum update of the previous level for this cell; it reads only
         // buffers this launch does not write, so it runs last, where its memory

@@ -295,6 +295,7 @@ sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* 
                        c->v, c->w, targets_d, c->ncells, c->p.rho_ice, c->p.cell_lx * c->p.cell_ly, c->r_bin,
                        status_d);
     HIP_TRY(c, hipGetLastError());
+    SP_TRY(invalidate_lists(c, cells_d, ncl));   // radii changed
     SP_TRY(ensure_cell_data(c));
     hipLaunchKernelGGL(descriptors_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h,
                        1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.rho_ice, c->p.cd * c->p.rho_ocean, c->desc, c->mf);

@@ -38,6 +38,7 @@ using namespace spdem;
 namespace {
 
 constexpr int kNumBuckets = 5;
+constexpr double kSkinFrac = 0.3;   // smallest candidate-list skin, in units of the largest radius
 constexpr int kBucketHi[kNumBuckets] = {64, 128, 256, 512, SP_MAX_CELL_FLOES};
 constexpr int kDefaultWaves[kNumBuckets] = {1, 2, 4, 4, 8};
 constexpr int kDefaultGraphChunk = 16;
@@ -79,6 +80,7 @@ struct sp_ctx {
     std::vector<int32_t> counts_h;
     Bucket bk[kNumBuckets];
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
+    float skin = 0.0f;          // candidate-list skin (m)
     struct HybridState* hyb = nullptr;
     bool plain_queues_stale = false;   // hybrid steps ran since the last plain launch
 
@@ -98,6 +100,9 @@ struct sp_ctx {
     double* red = nullptr;                  // reduced DEM of every cell [ncells][4]
     double t_now = 0.0;                     // time of the current state since the floes were set
     double* qprev = nullptr;                // continuum snapshot for tendencies
+    uint16_t* vlist = nullptr;              // candidate lists [n][kListCap], entry-major per cell
+    uint8_t* vcount = nullptr;              // candidates per floe [n]
+    float* vdisp = nullptr;                 // per-cell displacement bound since the lists were built
 
     // time stepping
     int64_t kstep = 0;          // DEM steps since the floes were set
@@ -180,7 +185,7 @@ void free_all(sp_ctx* c)
     hybrid_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev};
+                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -201,6 +206,9 @@ void free_all(sp_ctx* c)
     c->mf = nullptr;
     c->red = nullptr;
     c->qprev = nullptr;
+    c->vlist = nullptr;
+    c->vcount = nullptr;
+    c->vdisp = nullptr;
 }
 
 // LDS bytes of one group (one cell) for a schedule, capacity and W.
@@ -237,6 +245,10 @@ StepArgs make_args(const sp_ctx* c, double dt)
     a.h = c->h;
     a.cell_start = c->cell_start;
     a.phase = c->phase;
+    a.vlist = c->vlist;
+    a.vcount = c->vcount;
+    a.vdisp = c->vdisp;
+    a.skin = c->skin;
     a.err = c->err_d;
     a.contacts = c->contacts_d;
     a.max_cfl_bits = c->cfl_bits_d;
@@ -293,6 +305,22 @@ sp_status upload_phase(sp_ctx* c)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->phase_dirty = false;
     drop_graph(c);
+    return SP_OK;
+}
+
+// Mark the candidate lists of every cell (cells == null) or of the listed
+// cells stale: their next step rebuilds them.
+__global__ void invalidate_lists_kernel(float* vdisp, const int32_t* cells, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) vdisp[cells ? cells[i] : i] = __int_as_float(0x7f800000);   // +inf
+}
+
+sp_status invalidate_lists(sp_ctx* c, const int32_t* cells_d, int n)
+{
+    if (!c->vdisp || n <= 0) return SP_OK;
+    hipLaunchKernelGGL(invalidate_lists_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->vdisp, cells_d, n);
+    HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
@@ -582,7 +610,7 @@ sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out)
     }
     sp_status st = SP_OK;
     if (!st) st = dalloc(c, &c->err_d, 1);
-    if (!st) st = dalloc(c, &c->contacts_d, 1);
+    if (!st) st = dalloc(c, &c->contacts_d, std::max<size_t>(1, (size_t)c->ncells));
     if (!st) st = dalloc(c, &c->cfl_bits_d, 1);
     if (!st) st = dalloc(c, &c->momb[0], (size_t)c->ncells * kMomStride);
     if (!st) st = dalloc(c, &c->momb[1], (size_t)c->ncells * kMomStride);
@@ -590,7 +618,7 @@ sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out)
     if (!st) st = dalloc(c, &c->Q[0], (size_t)c->ncells * 4);
     if (!st) st = dalloc(c, &c->Q[1], (size_t)c->ncells * 4);
     if (!st && hipMemsetAsync(c->err_d, 0, sizeof(uint32_t), c->stream) != hipSuccess) st = SP_EDEVICE;
-    if (!st && hipMemsetAsync(c->contacts_d, 0, 8, c->stream) != hipSuccess) st = SP_EDEVICE;
+    if (!st && hipMemsetAsync(c->contacts_d, 0, (size_t)c->ncells * 8, c->stream) != hipSuccess) st = SP_EDEVICE;
     if (!st && hipMemsetAsync(c->cfl_bits_d, 0, 8, c->stream) != hipSuccess) st = SP_EDEVICE;
     if (st) {
         sp_destroy(c);
@@ -686,6 +714,9 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     SP_TRY(dalloc(c, &c->r, N));
     SP_TRY(dalloc(c, &c->h, N));
     SP_TRY(dalloc(c, &c->cell_start, (size_t)c->ncells + 1));
+    SP_TRY(dalloc(c, &c->vlist, std::max<size_t>(1, N) * kListCap));
+    SP_TRY(dalloc(c, &c->vcount, std::max<size_t>(1, N)));
+    SP_TRY(dalloc(c, &c->vdisp, (size_t)c->ncells));
     void* dst[8] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h};
     if (n > 0) {
         for (int k = 0; k < 8; ++k) {
@@ -719,9 +750,12 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     c->r_bin = rmax;
     HIP_TRY(c, hipMemcpyAsync(c->cell_start, c->start_h.data(), ((size_t)c->ncells + 1) * 4,
                               hipMemcpyHostToDevice, c->stream));
-    // sub-bins of side >= 2 r_max
-    int bx = n > 0 ? (int)floor(c->p.cell_lx / (2.0 * (double)rmax)) : 1;
-    int by = n > 0 ? (int)floor(c->p.cell_ly / (2.0 * (double)rmax)) : 1;
+    // candidate lists are kept while the floes move less than half a skin of
+    // at least kSkinFrac r_max; sub-bins of side >= 2 r_max + skin, and any
+    // slack of the sub-bins goes to the skin
+    const double skin0 = kSkinFrac * (double)rmax;
+    int bx = n > 0 ? (int)floor(c->p.cell_lx / (2.0 * (double)rmax + skin0)) : 1;
+    int by = n > 0 ? (int)floor(c->p.cell_ly / (2.0 * (double)rmax + skin0)) : 1;
     bx = std::min(bx, kMaxBinsSide);
     by = std::min(by, kMaxBinsSide);
     if (bx < 3) bx = 1;
@@ -735,11 +769,20 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     } else {
         c->nbx = c->nby = 1;
     }
+    // binned axes: all the slack of the sub-bins (at least skin0); an axis
+    // searched whole sets no limit
+    double skin = INFINITY;
+    if (c->nbx >= 3) skin = std::min(skin, c->p.cell_lx / c->nbx - 2.0 * (double)rmax);
+    if (c->nby >= 3) skin = std::min(skin, c->p.cell_ly / c->nby - 2.0 * (double)rmax);
+    if (!std::isfinite(skin)) skin = skin0;
+    // float rounding must not let a pair at the bin side escape the sweep
+    c->skin = n > 0 ? (float)(skin * (1.0 - 1e-6)) : 0.0f;
+    SP_TRY(invalidate_lists(c, nullptr, c->ncells));
     c->n = n;
     SP_TRY(build_buckets(c, counts));
     SP_TRY(prepare_buckets(c));
     HIP_TRY(c, hipMemsetAsync(c->err_d, 0, 4, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->contacts_d, 0, 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->contacts_d, 0, (size_t)c->ncells * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->cfl_bits_d, 0, 8, c->stream));
     c->steps = 0;
     SP_TRY(upload_phase(c));
@@ -941,9 +984,12 @@ sp_status sp_get_stats(sp_ctx* c, int64_t* contacts, int64_t* steps, double* max
     if (!c) return SP_EINVAL;
     if (c->have_floes) SP_TRY(flush_lf(c));
     unsigned long long cnt = 0, bits = 0;
-    HIP_TRY(c, hipMemcpyAsync(&cnt, c->contacts_d, 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<unsigned long long> per_cell((size_t)c->ncells);
+    HIP_TRY(c, hipMemcpyAsync(per_cell.data(), c->contacts_d, per_cell.size() * 8, hipMemcpyDeviceToHost,
+                              c->stream));
     HIP_TRY(c, hipMemcpyAsync(&bits, c->cfl_bits_d, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (unsigned long long x : per_cell) cnt += x;
     if (contacts) *contacts = (int64_t)cnt;
     if (steps) *steps = c->steps;
     if (max_cfl) {
@@ -1025,7 +1071,7 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     if (!st) st = dalloc(c, &sw, N);
     if (!st) st = dalloc(c, &sth, N);
     if (!st) st = dalloc(c, &serr, 1);
-    if (!st) st = dalloc(c, &scnt, 1);
+    if (!st) st = dalloc(c, &scnt, std::max<size_t>(1, (size_t)c->ncells));
     if (!st) st = dalloc(c, &smom, (size_t)c->ncells * kMomStride);
     if (!st) st = dalloc(c, &sq, 2);
     auto cleanup = [&]() {
@@ -1103,6 +1149,7 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     cleanup();
     if (st) return st == SP_EDEVICE ? fail(c, st, "autotune timing failed") : st;
     SP_TRY(prepare_buckets(c));
+    SP_TRY(invalidate_lists(c, nullptr, c->ncells));   // the trials stepped a scratch state with them
     c->plain_queues_stale = true;   // a bucket may have changed to persistent workgroups
     drop_graph(c);
     if (best_ms) *best_ms = total;
