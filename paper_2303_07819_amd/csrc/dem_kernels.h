@@ -63,6 +63,7 @@ struct Modes {
     float au[SP_MAX_MODES];
     float av[SP_MAX_MODES];
     float cz[SP_MAX_MODES];   // curl coefficient av kx - au ky
+    int direct;               // every phase offset |kxL fx + kyL fy| (|fx|, |fy| <= 1/2) is <= 1.6
 };
 
 struct StepArgs {
@@ -192,6 +193,61 @@ __device__ __forceinline__ void sincos_small(float x, float& s, float& c)
     c = ((q + 1) & 2) ? -c1 : c1;
 }
 
+// sin and cos of |x| <= 1.6 from their Taylor polynomials to degree 13 and
+// 14 (truncation below 1e-9 there), without range reduction.
+__device__ __forceinline__ void sincos_direct(float x, float& s, float& c)
+{
+    const float x2 = x * x;
+    float sp = fmaf(x2, 1.6059043837e-10f, -2.5052108385e-8f);   // 1/13!, -1/11!
+    sp = fmaf(x2, sp, 2.7557319224e-6f);                          // 1/9!
+    sp = fmaf(x2, sp, -1.9841269841e-4f);                         // -1/7!
+    sp = fmaf(x2, sp, 8.3333333333e-3f);                          // 1/5!
+    sp = fmaf(x2, sp, -1.6666666667e-1f);                         // -1/3!
+    s = fmaf(x * x2, sp, x);
+    float cp = fmaf(x2, -1.1470745597e-11f, 2.0876756988e-9f);    // -1/14!, 1/12!
+    cp = fmaf(x2, cp, -2.7557319224e-7f);                         // -1/10!
+    cp = fmaf(x2, cp, 2.4801587302e-5f);                          // 1/8!
+    cp = fmaf(x2, cp, -1.3888888889e-3f);                         // -1/6!
+    cp = fmaf(x2, cp, 4.1666666667e-2f);                          // 1/4!
+    cp = fmaf(x2, cp, -0.5f);
+    c = fmaf(x2, cp, 1.0f);
+}
+
+// Ocean current (sum of a sin theta) and curl (sum of cz cos theta) at cell
+// fraction (fx, fy), by angle addition around the cell centre: theta = theta_c
+// + d with d = kxL fx + kyL fy.  mk[m] = (kxL, kyL, au, av); mc[m] = (cz,
+// sin theta_c, cos theta_c, -).  DIRECT: every |d| <= 1.6.
+template <bool DIRECT>
+__device__ __forceinline__ void ocean_modes_t(float fx, float fy, const float4* mk, const float4* mc, int nmodes,
+                                              float& uo, float& vo, float& zeta)
+{
+#pragma unroll 2
+    for (int m = 0; m < nmodes; ++m) {
+        const float4 k = mk[m];
+        const float4 q = mc[m];
+        const float d = k.x * fx + k.y * fy;
+        float sd, cd;
+        if (DIRECT)
+            sincos_direct(d, sd, cd);
+        else
+            sincos_small(d, sd, cd);
+        const float sn = q.y * cd + q.z * sd;    // sin and cos of the full phase
+        const float cn = q.z * cd - q.y * sd;
+        uo += k.z * sn;
+        vo += k.w * sn;
+        zeta += q.x * cn;
+    }
+}
+
+__device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mk, const float4* mc, int nmodes,
+                                            bool direct, float& uo, float& vo, float& zeta)
+{
+    if (direct)
+        ocean_modes_t<true>(fx, fy, mk, mc, nmodes, uo, vo, zeta);
+    else
+        ocean_modes_t<false>(fx, fy, mk, mc, nmodes, uo, vo, zeta);
+}
+
 // Sum over a row of 16 lanes with DPP row shifts (deterministic order); the
 // row total lands in the row's last lane.
 template <int CTRL>
@@ -279,35 +335,72 @@ __device__ __forceinline__ void sweep(const uint4* S, int q0, int q1, uint32_t x
 // One Lax-Friedrichs step of eq. pde for cell C (Sec. 3.2): mass and spin
 // angular momentum in conservative form with flux <v> q, momentum with the
 // Oseen approximation <v>.grad<rho v>, drag sources S / A; periodic grid.
-__device__ __forceinline__ void lf_cell(int C, const double* mom, const double* Q, double* Qn,
-                                        int nx, int ny, double dT, double dX, double dY,
-                                        double inv_area, unsigned long long* max_cfl_bits,
-                                        uint32_t* err)
+// The step reads kLfOps operands (lf_operand), so that a caller can load them
+// early and spread over lanes, then combines them (lf_from_ops).
+constexpr int kLfOps = 25;
+
+struct LfNeighbours {
+    int E, W, N, S;
+};
+
+__device__ __forceinline__ LfNeighbours lf_neighbours(int C, int nx, int ny)
 {
-    const int nc = nx * ny;
     const int ix = C % nx, iy = C / nx;
-    const int E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
-    const int W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
-    const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
-    const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
-    const double uE = mom[(size_t)E * kMomStride + M_UBAR], uW = mom[(size_t)W * kMomStride + M_UBAR];
-    const double vN = mom[(size_t)N * kMomStride + M_VBAR], vS = mom[(size_t)S * kMomStride + M_VBAR];
-    const double uC = mom[(size_t)C * kMomStride + M_UBAR], vC = mom[(size_t)C * kMomStride + M_VBAR];
+    LfNeighbours b;
+    b.E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
+    b.W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
+    b.N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
+    b.S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
+    return b;
+}
+
+// Operand t of the step of cell C: 0..15 Q[f][E, W, N, S] (f = t / 4);
+// 16..21 <u>_E, <u>_W, <v>_N, <v>_S, <u>_C, <v>_C; 22..24 the sources S_w,
+// S_vx, S_vy of C.
+__device__ __forceinline__ double lf_operand(int C, int t, const double* mom, const double* Q, int nx,
+                                            int ny)
+{
+    const LfNeighbours b = lf_neighbours(C, nx, ny);
+    const int nc = nx * ny;
+    if (t < 16) {
+        const int k = t & 3;
+        const int cell = k == 0 ? b.E : k == 1 ? b.W : k == 2 ? b.N : b.S;
+        return Q[(size_t)(t >> 2) * nc + cell];
+    }
+    int cell, slot;
+    switch (t) {
+    case 16: cell = b.E; slot = M_UBAR; break;
+    case 17: cell = b.W; slot = M_UBAR; break;
+    case 18: cell = b.N; slot = M_VBAR; break;
+    case 19: cell = b.S; slot = M_VBAR; break;
+    case 20: cell = C; slot = M_UBAR; break;
+    case 21: cell = C; slot = M_VBAR; break;
+    case 22: cell = C; slot = M_SW; break;
+    case 23: cell = C; slot = M_SVX; break;
+    default: cell = C; slot = M_SVY; break;
+    }
+    return mom[(size_t)cell * kMomStride + slot];
+}
+
+__device__ __forceinline__ void lf_from_ops(int C, const double* o, double* Qn, int nc, double dT, double dX,
+                                            double dY, double inv_area, unsigned long long* max_cfl_bits,
+                                            uint32_t* err)
+{
+    const double uE = o[16], uW = o[17], vN = o[18], vS = o[19], uC = o[20], vC = o[21];
     const double cx = dT / (2.0 * dX), cy = dT / (2.0 * dY);
-    const double* sC = mom + (size_t)C * kMomStride;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        const double qE = Q[(size_t)f * nc + E], qW = Q[(size_t)f * nc + W];
-        const double qN = Q[(size_t)f * nc + N], qS = Q[(size_t)f * nc + S];
+        const double qE = o[4 * f], qW = o[4 * f + 1];
+        const double qN = o[4 * f + 2], qS = o[4 * f + 3];
         const double avg = 0.25 * (qE + qW + qN + qS);
         double q;
         if (f == 0) {
             q = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS);
         } else if (f == 3) {
-            q = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS) + dT * sC[M_SW] * inv_area;
+            q = avg - cx * (uE * qE - uW * qW) - cy * (vN * qN - vS * qS) + dT * o[22] * inv_area;
         } else {
             q = avg - dT * (uC * (qE - qW) / (2.0 * dX) + vC * (qN - qS) / (2.0 * dY)) +
-                dT * sC[f == 1 ? M_SVX : M_SVY] * inv_area;
+                dT * o[f == 1 ? 23 : 24] * inv_area;
         }
         Qn[(size_t)f * nc + C] = q;
     }
@@ -315,6 +408,17 @@ __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* 
     const unsigned long long bits = (unsigned long long)__double_as_longlong(cfl);
     if (bits > *max_cfl_bits) atomicMax(max_cfl_bits, bits);
     if (cfl > 1.0) atomicOr(err, kErrCFL);
+}
+
+__device__ __forceinline__ void lf_cell(int C, const double* mom, const double* Q, double* Qn,
+                                        int nx, int ny, double dT, double dX, double dY,
+                                        double inv_area, unsigned long long* max_cfl_bits,
+                                        uint32_t* err)
+{
+    double o[kLfOps];
+#pragma unroll
+    for (int t = 0; t < kLfOps; ++t) o[t] = lf_operand(C, t, mom, Q, nx, ny);
+    lf_from_ops(C, o, Qn, nx * ny, dT, dX, dY, inv_area, max_cfl_bits, err);
 }
 
 // ------------------------------------------------------------- DEM step
@@ -334,6 +438,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     __shared__ int wsum[GPB][W];
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
+    __shared__ double lfops[GPB][kLfOps];
     __shared__ int qbase;
 
     const int tid = threadIdx.x;
@@ -372,6 +477,10 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
         const int c = wk.x, s = wk.y, n = wk.z;
         const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;   // loaded early
+        // the continuum update of the previous level for this cell reads only
+        // buffers this launch does not write: its operands are loaded now, one
+        // per lane, and combined after the floes are done
+        const double lfo = (valid && a.lf && gt < kLfOps) ? lf_operand(c, gt, a.mom_prev, a.Qp, a.nx, a.ny) : 0.0;
         // rebuild the cell's candidate lists when its floes may have moved by
         // skin / 2 since they were built (every pair then changed its distance
         // by less than the skin); the same for the whole group
@@ -510,19 +619,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
                 const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
-#pragma unroll 2
-                for (int m = 0; m < a.nmodes; ++m) {
-                    const float4 mk = mode_k[m];
-                    const float4 mc = mode_c[g][m];
-                    const float dth = mk.x * fx + mk.y * fy;
-                    float sd, cd;
-                    sincos_small(dth, sd, cd);
-                    const float sn = mc.y * cd + mc.z * sd;    // sin and cos of the full phase
-                    const float cn = mc.z * cd - mc.y * sd;
-                    uo += mk.z * sn;
-                    vo += mk.w * sn;
-                    zeta += mc.x * cn;
-                }
+                ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
                 const double sp = sqrt(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
@@ -676,6 +773,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         }
 #pragma unroll
         for (int k = 0; k < kDyn; ++k) red[k * G + gt] = acc[k];
+        if (gt < kLfOps) lfops[g][gt] = lfo;
         __syncthreads();
         constexpr int SEG = G / 16;                 // values per segment
         for (int kq = gt >> 4; kq < kDyn; kq += G / 16) {
@@ -702,12 +800,10 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             for (int q = 0; q < W; ++q) t += csum[g * W + q];
             a.contacts[c] = ccell + t;
         }
-        // continuum update of the previous level for this cell; it reads only
-        // buffers this launch does not write, so it runs last, where its memory
-        // latency overlaps other workgroups' work
+        // continuum update of the previous level for this cell (operands loaded
+        // at the start of the cell)
         if (valid && a.lf && gt == G - 1)
-            lf_cell(c, a.mom_prev, a.Qp, a.Qn, a.nx, a.ny, a.dtd, a.dX, a.dY, a.inv_area,
-                    a.max_cfl_bits, a.err);
+            lf_from_ops(c, lfops[g], a.Qn, a.nx * a.ny, a.dtd, a.dX, a.dY, a.inv_area, a.max_cfl_bits, a.err);
         if (!QUEUE) break;
     }
 }
@@ -741,17 +837,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
             const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
             const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
             float uo = a.u0, vo = a.v0, zeta = 0.0f;
-            for (int m = 0; m < a.nmodes; ++m) {
-                const float4 mk = mode_k[m];
-                const float4 mc = mode_c[m];
-                float sd, cd;
-                sincos_small(mk.x * fx + mk.y * fy, sd, cd);
-                const float sn = mc.y * cd + mc.z * sd;
-                const float cn = mc.z * cd - mc.y * sd;
-                uo += mk.z * sn;
-                vo += mk.w * sn;
-                zeta += mc.x * cn;
-            }
+            ocean_modes(fx, fy, mode_k, mode_c, a.nmodes, a.modes.direct != 0, uo, vo, zeta);
             const double du = (double)uo - uld, dv = (double)vo - vld;
             const double sp = sqrt(du * du + dv * dv);
             const double alpha = a.cdrho * kPi * rld * rld;

@@ -283,6 +283,12 @@ StepArgs make_args(const sp_ctx* c, double dt)
         a.modes.av[m] = (float)c->av[m];
         a.modes.cz[m] = (float)(c->av[m] * c->kx[m] - c->au[m] * c->ky[m]);
     }
+    // phase offsets within a cell stay inside [-1.6, 1.6]: sin and cos
+    // straight from their polynomials (no range reduction)
+    float reach = 0.0f;
+    for (int m = 0; m < c->nmodes; ++m)
+        reach = std::max(reach, 0.5f * (fabsf(a.modes.kxL[m]) + fabsf(a.modes.kyL[m])));
+    a.modes.direct = reach <= 1.6f ? 1 : 0;
     return a;
 }
 
