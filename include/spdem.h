@@ -167,8 +167,10 @@ sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_m
  * SP_NUM_BUCKETS buckets (<= 64, <= 128, <= 256, <= 512, <= 1024 floes); each
  * bucket is one launch per step over its cells, costliest first, with W
  * wavefronts per cell (W = 1, 2, 4 or 8: one wavefront per small cell up to a
- * tile of 8 wavefronts per large cell) and either grid-ordered or persistent
- * workgroups that pull cells from a work counter.  Every choice gives the same
+ * tile of 8 wavefronts per large cell) and either one workgroup per cell group
+ * or persistent workgroups: as many as are resident at once, each striding
+ * over the cells and loading the next cell's floes while it processes one.
+ * Every choice gives the same
  * floe state bit for bit; cell statistics agree to FP64 rounding (the
  * reduction tree follows W).
  * sp_get_batching: cells[b], waves[b], persistent[b] for each bucket (any may be NULL).

@@ -94,8 +94,6 @@ struct StepArgs {
     // work list
     const int4* work;          // (cell, first floe, floe count, -) of this launch, costliest first
     int32_t ncl;
-    int32_t* queue;            // persistent workgroups: this step's work counter (null: grid order)
-    int32_t* queue_reset;      // the other counter, zeroed for the step after this one
     int32_t group_bytes;       // LDS bytes per group
     int32_t cap;               // LDS floe capacity per group
     // fused continuum update of the previous time level
@@ -423,8 +421,8 @@ __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* 
 
 // ------------------------------------------------------------- DEM step
 // SCHED: 1 all pairs, 2 binned half shell.  W: wavefronts per cell.
-// QUEUE: workgroups fetch cells from a work counter until the list is empty.
-template <int SCHED, int W, bool QUEUE>
+// PERSIST: a grid of resident workgroups strides over the work list.
+template <int SCHED, int W, bool PERSIST>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArgs a)
 {
     constexpr int G = 64 * W;                  // threads per group
@@ -439,7 +437,6 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
     __shared__ double lfops[GPB][kLfOps];
-    __shared__ int qbase;
 
     const int tid = threadIdx.x;
     const int g = tid / G, gt = tid % G;
@@ -448,9 +445,8 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 
     if (tid < a.nmodes)
         mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
-    if (QUEUE && blockIdx.x == 0 && tid == 0) *a.queue_reset = 0;
 
-    uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, -
+    uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, theta bits
     float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, -
     uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy: xi, yi, r bits, index | bin << 16
     uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));  // [cap][kListCap]
@@ -461,17 +457,8 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
     double* red = reinterpret_cast<double*>(gsm);             // [kDyn][G], after the floes are done
 
-    for (int iter = 0;; ++iter) {
-        int base;
-        if (QUEUE) {
-            __syncthreads();
-            if (tid == 0) qbase = atomicAdd(a.queue, gpb);
-            __syncthreads();
-            base = qbase;
-            if (base >= a.ncl) break;
-        } else {
-            base = blockIdx.x * gpb;
-        }
+    const int stride = PERSIST ? (int)gridDim.x * gpb : 0;
+    for (int base = blockIdx.x * gpb; base < a.ncl; base += stride) {
         const int item = base + g;
         const bool valid = item < a.ncl;
         const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
@@ -494,7 +481,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
         }
         for (int i = gt; i < n; i += G) {
-            P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), 0u);
+            P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), __float_as_uint(a.th[s + i]));
             V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], a.h[s + i]);
             if (build) {
                 cnt[i] = 0;
@@ -742,7 +729,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             a.u[s + l] = un;
             a.v[s + l] = vn;
             a.w[s + l] = wn;
-            a.th[s + l] = (float)((double)a.th[s + l] + dt * wx);
+            a.th[s + l] = (float)((double)__uint_as_float(pl.w) + dt * wx);
             if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
 
             // ---- statistics of the pre-step state (FP64)
@@ -804,7 +791,8 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         // at the start of the cell)
         if (valid && a.lf && gt == G - 1)
             lf_from_ops(c, lfops[g], a.Qn, a.nx * a.ny, a.dtd, a.dX, a.dY, a.inv_area, a.max_cfl_bits, a.err);
-        if (!QUEUE) break;
+        if (!PERSIST) break;
+        __syncthreads();   // the cell's LDS data is free
     }
 }
 

@@ -211,9 +211,7 @@ void hybrid_free_buffers(HybridState* h)
 {
     for (auto& b : h->bk) {
         if (b.work_d) (void)hipFree(b.work_d);
-        if (b.q_d) (void)hipFree(b.q_d);
         b.work_d = nullptr;
-        b.q_d = nullptr;
     }
     void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->Xk, h->Tk, h->Tdem, h->Qs,
                   h->back_d};
@@ -319,7 +317,7 @@ sp_status catch_up(sp_ctx* c, std::vector<int32_t> cells, double dt)
     Bucket tmp[kNumBuckets];
     for (int q = 0; q < kNumBuckets; ++q) {
         tmp[q].waves = c->bk[q].waves;
-        tmp[q].queue = c->bk[q].queue;
+        tmp[q].persist = c->bk[q].persist;
     }
     StepArgs base = make_args(c, dt);
     base.mom = c->mom2;
@@ -341,10 +339,8 @@ sp_status catch_up(sp_ctx* c, std::vector<int32_t> cells, double dt)
             }
     }
     (void)hipStreamSynchronize(c->stream);   // the temporary work lists are freed below
-    for (auto& b : tmp) {
+    for (auto& b : tmp)
         if (b.work_d) (void)hipFree(b.work_d);
-        if (b.q_d) (void)hipFree(b.q_d);
-    }
     if (st) return st;
     for (int32_t cell : cells) h->frozen_at[cell] = c->kstep;
     return SP_OK;
@@ -515,7 +511,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     h->net_window = net_window;
     for (int q = 0; q < kNumBuckets; ++q) {
         h->bk[q].waves = c->bk[q].waves;
-        h->bk[q].queue = c->bk[q].queue;
+        h->bk[q].persist = c->bk[q].persist;
     }
     const size_t nk = (size_t)std::max(1, check_cells);
     SP_TRY(dalloc(c, &h->row_d, (size_t)c->ncells));
@@ -548,9 +544,6 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     SP_TRY(upload_phase(c));
     SP_TRY(flush_lf(c));
     if (nsteps == 0) return SP_OK;
-    // plain steps may have run since the last hybrid one
-    SP_TRY(zero_queues(c, h->bk));
-    c->plain_queues_stale = true;
     const StepArgs base = make_args(c, dt);
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
     for (int64_t it = 0; it < nsteps; ++it) {

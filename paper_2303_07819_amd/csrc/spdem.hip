@@ -45,12 +45,11 @@ constexpr int kDefaultGraphChunk = 16;
 
 struct Bucket {
     int waves = 4;
-    int queue = 0;
+    int persist = 0;                    // resident workgroups stride over the cells
     int cap = 0;                        // LDS floe capacity per group
     int resident = 1;                   // workgroups resident at once (persistent grid size)
     std::vector<int32_t> cells_h;       // costliest first
     int4* work_d = nullptr;             // (cell, first floe, count, -) per entry of cells_h
-    int32_t* q_d = nullptr;             // two work counters (alternating steps)
 };
 
 }  // namespace
@@ -82,7 +81,6 @@ struct sp_ctx {
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
     float skin = 0.0f;          // candidate-list skin (m)
     struct HybridState* hyb = nullptr;
-    bool plain_queues_stale = false;   // hybrid steps ran since the last plain launch
 
     // device buffers
     uint32_t *xi = nullptr, *yi = nullptr;
@@ -190,9 +188,7 @@ void free_all(sp_ctx* c)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
         if (b.work_d) (void)hipFree(b.work_d);
-        if (b.q_d) (void)hipFree(b.q_d);
         b.work_d = nullptr;
-        b.q_d = nullptr;
     }
     c->xi = c->yi = nullptr;
     c->u = c->v = c->w = c->th = c->r = c->h = nullptr;
@@ -343,19 +339,19 @@ sp_status check_device_err(sp_ctx* c)
 }
 
 // --------------------------------------------------------- kernel launches
-template <int SCHED, int W, bool QUEUE>
+template <int SCHED, int W, bool PERSIST>
 sp_status launch_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds)
 {
-    hipLaunchKernelGGL((dem_step_kernel<SCHED, W, QUEUE>), dim3(grid), dim3(threads), lds, c->stream, a);
+    hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST>), dim3(grid), dim3(threads), lds, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
-template <int SCHED, int W, bool QUEUE>
+template <int SCHED, int W, bool PERSIST>
 sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int* resident)
 {
     const int BT = threads;
-    const void* k = (const void*)dem_step_kernel<SCHED, W, QUEUE>;
+    const void* k = (const void*)dem_step_kernel<SCHED, W, PERSIST>;
     if (lds > 65536) HIP_TRY(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BT, lds));
@@ -364,7 +360,7 @@ sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int* resident)
 }
 
 #define SP_DISPATCH(FN, ...)                                                                  \
-    switch ((sched == SP_SCHED_BINNED ? 100 : 0) + waves * 2 + (queue ? 1 : 0)) {              \
+    switch ((sched == SP_SCHED_BINNED ? 100 : 0) + waves * 2 + (persist ? 1 : 0)) {              \
     case 2: return FN<1, 1, false>(__VA_ARGS__);                                               \
     case 3: return FN<1, 1, true>(__VA_ARGS__);                                                \
     case 4: return FN<1, 2, false>(__VA_ARGS__);                                               \
@@ -384,13 +380,13 @@ sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int* resident)
     default: return fail(c, SP_EINVAL, "no kernel for waves=%d", waves);                      \
     }
 
-sp_status launch_sel(sp_ctx* c, int sched, int waves, int queue, const StepArgs& a, int grid, int threads,
+sp_status launch_sel(sp_ctx* c, int sched, int waves, int persist, const StepArgs& a, int grid, int threads,
                      size_t lds)
 {
     SP_DISPATCH(launch_t, c, a, grid, threads, lds)
 }
 
-sp_status prepare_sel(sp_ctx* c, int sched, int waves, int queue, int threads, size_t lds, int* resident)
+sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads, size_t lds, int* resident)
 {
     SP_DISPATCH(prepare_t, c, threads, lds, resident)
 }
@@ -408,7 +404,7 @@ int bucket_threads(const sp_ctx* c, const Bucket& b) { return bucket_gpb(c, b) *
 
 sp_status prepare_bucket(sp_ctx* c, Bucket& b)
 {
-    return prepare_sel(c, c->sched, b.waves, b.queue, bucket_threads(c, b), bucket_lds(c, b), &b.resident);
+    return prepare_sel(c, c->sched, b.waves, b.persist, bucket_threads(c, b), bucket_lds(c, b), &b.resident);
 }
 
 // One DEM launch for bucket b at time level k (writes the statistics of level
@@ -423,8 +419,6 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     a.ncl = (int32_t)b.cells_h.size();
     a.cap = b.cap;
     a.group_bytes = (int32_t)bucket_group_bytes(c, b);
-    a.queue = b.q_d + (k & 1);
-    a.queue_reset = b.q_d + ((k + 1) & 1);
     if (!fixed) {
         a.mom = c->momb[k & 1];
         a.lf = lf ? 1 : 0;
@@ -434,8 +428,8 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     }
     const int gpb = bucket_gpb(c, b);
     const int groups = (int)((b.cells_h.size() + gpb - 1) / gpb);
-    const int grid = b.queue ? std::min(groups, b.resident) : groups;
-    return launch_sel(c, c->sched, b.waves, b.queue, a, grid, bucket_threads(c, b), bucket_lds(c, b));
+    const int grid = b.persist ? std::min(groups, b.resident) : groups;
+    return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
 sp_status step_once(sp_ctx* c, const StepArgs& base)
@@ -496,22 +490,11 @@ sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const
             work[i] = make_int4(cell, c->start_h[cell], counts[cell], 0);
         }
         SP_TRY(dalloc(c, &b.work_d, std::max<size_t>(1, work.size())));
-        SP_TRY(dalloc(c, &b.q_d, 2));
-        HIP_TRY(c, hipMemsetAsync(b.q_d, 0, 2 * sizeof(int32_t), c->stream));
         if (!work.empty())
             HIP_TRY(c, hipMemcpyAsync(b.work_d, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice,
                                       c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));   // `work` is a host temporary
     }
-    return SP_OK;
-}
-
-// Zero both work counters of every bucket: needed when the buckets did not
-// run the step before the next one (their in-kernel reset then did not happen).
-sp_status zero_queues(sp_ctx* c, Bucket* bk)
-{
-    for (int q = 0; q < kNumBuckets; ++q)
-        if (bk[q].q_d) HIP_TRY(c, hipMemsetAsync(bk[q].q_d, 0, 2 * sizeof(int32_t), c->stream));
     return SP_OK;
 }
 
@@ -823,10 +806,6 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
         return fail(c, SP_EINVAL, "dt must be positive and nsteps non-negative");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));   // pending update of another dt
-    if (c->plain_queues_stale) {
-        SP_TRY(zero_queues(c, c->bk));
-        c->plain_queues_stale = false;
-    }
     const bool cont = !(c->p.flags & SP_NO_CONTINUUM);
     const StepArgs base = make_args(c, dt);
     c->t_now += dt * (double)nsteps;
@@ -858,10 +837,6 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
     if (!(dt > 0.0) || nsteps < 1) return fail(c, SP_EINVAL, "dt must be positive and nsteps >= 1");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));
-    if (c->plain_queues_stale) {
-        SP_TRY(zero_queues(c, c->bk));
-        c->plain_queues_stale = false;
-    }
     std::vector<hipEvent_t> ev((size_t)nsteps * 2);
     for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
     const StepArgs base = make_args(c, dt);
@@ -1021,7 +996,7 @@ sp_status sp_get_batching(sp_ctx* c, int32_t* cells, int32_t* waves, int32_t* pe
     for (int q = 0; q < kNumBuckets; ++q) {
         if (cells) cells[q] = (int32_t)c->bk[q].cells_h.size();
         if (waves) waves[q] = c->bk[q].waves;
-        if (persistent) persistent[q] = c->bk[q].queue;
+        if (persistent) persistent[q] = c->bk[q].persist;
     }
     return SP_OK;
 }
@@ -1037,7 +1012,7 @@ sp_status sp_set_batching(sp_ctx* c, const int32_t* waves, const int32_t* persis
     drop_graph(c);
     for (int q = 0; q < kNumBuckets; ++q) {
         c->bk[q].waves = waves[q];
-        c->bk[q].queue = persistent[q];
+        c->bk[q].persist = persistent[q];
     }
     if (c->have_floes) SP_TRY(prepare_buckets(c));
     return SP_OK;
@@ -1068,7 +1043,6 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     float *su = nullptr, *sv = nullptr, *sw = nullptr, *sth = nullptr;
     double* smom = nullptr;
     unsigned long long* scnt = nullptr;
-    int32_t* sq = nullptr;
     sp_status st = SP_OK;
     if (!st) st = dalloc(c, &sx, N);
     if (!st) st = dalloc(c, &sy, N);
@@ -1079,9 +1053,8 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     if (!st) st = dalloc(c, &serr, 1);
     if (!st) st = dalloc(c, &scnt, std::max<size_t>(1, (size_t)c->ncells));
     if (!st) st = dalloc(c, &smom, (size_t)c->ncells * kMomStride);
-    if (!st) st = dalloc(c, &sq, 2);
     auto cleanup = [&]() {
-        void* ps[] = {sx, sy, su, sv, sw, sth, serr, scnt, smom, sq};
+        void* ps[] = {sx, sy, su, sv, sw, sth, serr, scnt, smom};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     };
@@ -1095,7 +1068,6 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
             if (hipMemcpyAsync(dsts[k], srcs[k], B, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
                 st = SP_EDEVICE;
     }
-    if (!st && hipMemsetAsync(sq, 0, 8, c->stream) != hipSuccess) st = SP_EDEVICE;
     if (!st && hipMemsetAsync(serr, 0, 4, c->stream) != hipSuccess) st = SP_EDEVICE;
     StepArgs a = make_args(c, dt);
     a.xi = sx;
@@ -1117,16 +1089,14 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
         trial.cap = b.cap;
         trial.cells_h = b.cells_h;
         trial.work_d = b.work_d;
-        trial.q_d = sq;
         double best = 1e30;
-        int bw = b.waves, bq = b.queue;
+        int bw = b.waves, bq = b.persist;
         for (int wi = 0; wi < 4 && !st; ++wi)
             for (int pq = 0; pq < 2 && !st; ++pq) {
                 trial.waves = wv[wi];
-                trial.queue = pq;
+                trial.persist = pq;
                 if (prepare_bucket(c, trial) != SP_OK) continue;   // variant does not fit this device
-                // two launches per trial keep the alternating work counters consistent
-                for (int k = 0; k < 2 && !st; ++k) st = launch_bucket(c, trial, a, k, false, true);
+                for (int k = 0; k < 2 && !st; ++k) st = launch_bucket(c, trial, a, k, false, true);   // warm-up
                 double t_best = 1e30;
                 for (int r = 0; r < reps && !st; ++r) {
                     if (hipEventRecord(e0, c->stream) != hipSuccess) st = SP_EDEVICE;
@@ -1144,9 +1114,8 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
                 }
             }
         trial.work_d = nullptr;    // owned by the real bucket
-        trial.q_d = nullptr;
         b.waves = bw;
-        b.queue = bq;
+        b.persist = bq;
         total += best;
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -1156,7 +1125,6 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     if (st) return st == SP_EDEVICE ? fail(c, st, "autotune timing failed") : st;
     SP_TRY(prepare_buckets(c));
     SP_TRY(invalidate_lists(c, nullptr, c->ncells));   // the trials stepped a scratch state with them
-    c->plain_queues_stale = true;   // a bucket may have changed to persistent workgroups
     drop_graph(c);
     if (best_ms) *best_ms = total;
     return SP_OK;
