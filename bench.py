@@ -23,6 +23,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLOE_STEP = 56      # read xi, yi, u, v, w, th, r, h; write xi, yi, u, v, w, th
 BYTES_PER_CELL_STEP = 88      # the 11 FP64 cell statistics written
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# closure network 45 -> 128 -> 128 -> 128 -> 4: multiply-adds per sample of the
+# forward pass, and of the backward pass (weight gradients of every layer,
+# input gradients of the three upper layers)
+MLP_FWD_MACS = 45 * 128 + 2 * 128 * 128 + 128 * 4
+MLP_BWD_MACS = MLP_FWD_MACS + 2 * 128 * 128 + 128 * 4
+TRAIN_FLOPS_PER_SAMPLE = 2 * (MLP_FWD_MACS + MLP_BWD_MACS)
 
 
 def cpu_baseline(w, budget_s=12.0):
@@ -94,9 +101,14 @@ def main():
     ap.add_argument("--hybrid-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--closure-probe", action="store_true",
+                    help="only sample one 64 x 64 window and train the closure for two epochs (for counters)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.closure_probe:
+        closure_probe()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -172,6 +184,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def training_rate(hist):
+    """Closure training throughput against the bfloat16 MFMA peak."""
+    flops = hist["steps"] * hist["batch"] * TRAIN_FLOPS_PER_SAMPLE
+    tf = flops / max(hist["step_seconds"], 1e-12) / 1e12
+    return {"bound": "mfma", "kernel": "closure training (Adam steps)", "flops": flops,
+            "seconds": hist["step_seconds"], "achieved": tf, "peak": MFMA_BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+
+
+def closure_probe():
+    """One 64 x 64 window sampled, two epochs of training (for rocprofv3 counters)."""
+    import torch
+    from paper_2303_07819_amd import closure as cl
+    stream = torch.cuda.Stream()
+    X, T = cl.generate_samples([cl.training_workload(230307900)], stream=stream.cuda_stream)
+    net, hist = cl.train(X, T, epochs=2, stream=stream.cuda_stream)
+    net.close()
+    print(json.dumps({"closure_probe": {"samples": hist["samples"], "adam_steps": hist["steps"],
+                                        "seconds": hist["seconds"], "training": training_rate(hist)}}), flush=True)
+
+
 def hybrid_leg(args, stream):
     """Plain DEM vs DEM + closure on the 512 x 512 grid (33.6M floes): the
     closure is trained here, on the GPU, from the method's own runs."""
@@ -195,7 +228,8 @@ def hybrid_leg(args, stream):
     net.close()
     res["training"] = {"samples": hist["samples"], "epochs": len(hist["train"]), "adam_steps": hist["steps"],
                        "seconds": hist["seconds"], "sampling_seconds": t1 - t0,
-                       "final_train_loss": hist["train"][-1], "held_out_loss": hist["val"][-1]}
+                       "final_train_loss": hist["train"][-1], "held_out_loss": hist["val"][-1],
+                       "mfma_roofline": training_rate(hist)}
     res["workload"] = "hybrid512"
     res["metric"] = "floe-steps/s, plain DEM vs DEM + closure, relative L2 moment error vs full DEM"
     return res

@@ -137,7 +137,7 @@ def _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, t
         xs = np.where(xinv > 0, 1.0 / np.where(xinv > 0, xinv, 1.0), 0.0).astype(np.float32)
         xs[:36] = 0.0
         net.set_norm(xm, xs, ym, ys)
-    hist = {"train": [], "val": [], "seconds": 0.0}
+    hist = {"train": [], "val": [], "seconds": 0.0, "step_seconds": 0.0, "batch": batch}
     sd = Xtr[:, :36].std(dim=0, keepdim=True)
     gd = torch.Generator(device="cuda").manual_seed(seed + 1)
     t0 = time.perf_counter()
@@ -147,7 +147,10 @@ def _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, t
         if stencil_noise > 0:
             Xe = Xtr.clone()
             Xe[:, :36] += stencil_noise * sd * torch.randn(Xe.shape[0], 36, device="cuda", generator=gd)
-        hist["train"].append(net.train_epoch(Xe, Ttr, perm, batch, lr))
+        ts.synchronize()
+        t_ep = time.perf_counter()
+        hist["train"].append(net.train_epoch(Xe, Ttr, perm, batch, lr))   # returns synchronised
+        hist["step_seconds"] += time.perf_counter() - t_ep
         del Xe
         hist["val"].append(validation_loss(net, X, T, val))
         if log:

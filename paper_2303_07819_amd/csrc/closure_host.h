@@ -319,9 +319,12 @@ __global__ __launch_bounds__(256) void column_stats_kernel(const float* X, long 
 struct sp_mlp {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int num_cus = 256;           // compute units of the device (grid of the fused forward)
     std::string err;
     float* theta = nullptr;      // FP32 master parameters
     uint16_t* theta_h = nullptr; // bfloat16 copy read by the matrix products
+    spmlp::bf16x4* wsw = nullptr; // weight tiles of the fused forward (swizzled theta_h)
+    bool wsw_stale = true;       // theta_h changed since wsw was made
     float* m = nullptr;          // Adam moments
     float* v = nullptr;
     float* grad = nullptr;
@@ -504,6 +507,25 @@ sp_status mlp_forward(sp_mlp* mm, const float* X, const int32_t* rows, int B, bo
     return gemm(mm, g);
 }
 
+// Inference forward pass of M rows in one fused launch (no scratch, nothing
+// kept), on `stream`.
+sp_status mlp_infer(sp_mlp* mm, const float* x, int64_t M, float* y, hipStream_t stream)
+{
+    if (M <= 0) return SP_OK;
+    if (mm->wsw_stale) {
+        hipLaunchKernelGGL(swizzle_weights_kernel, dim3(kFwdTiles * 64 / 256), dim3(256), 0, stream, mm->theta_h,
+                           mm->wsw);
+        MLP_HIP(mm, hipGetLastError());
+        mm->wsw_stale = false;
+    }
+    const int64_t per_block = (int64_t)kFwdWaves * 16;
+    const int64_t blocks = std::min<int64_t>((M + per_block - 1) / per_block, 2 * (int64_t)mm->num_cus);
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(64 * kFwdWaves), kFwdLds, stream, x,
+                       (long)M, mm->wsw, mm->theta, mm->norm, y);
+    MLP_HIP(mm, hipGetLastError());
+    return SP_OK;
+}
+
 // Backward pass of the mean squared error on normalised targets into mm->grad;
 // the loss into mm->loss_d.
 sp_status mlp_backward(sp_mlp* mm, const float* T, const int32_t* rows, int B)
@@ -557,6 +579,7 @@ sp_status mlp_adam(sp_mlp* mm, float lr)
     const float c2 = (float)(1.0 - pow(b2, (double)mm->adam_t));
     hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, mm->m, mm->v,
                        mm->grad, kNParams, lr, (float)b1, (float)b2, 1e-8f, c1, c2, mm->theta_h);
+    mm->wsw_stale = true;
     MLP_HIP(mm, hipGetLastError());
     return SP_OK;
 }
@@ -580,8 +603,16 @@ sp_status sp_mlp_create(void* stream, sp_mlp** out)
         mm->own_stream = true;
     }
     sp_status st = SP_OK;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        mm->num_cus = cus;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_forward_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds) != hipSuccess)
+        st = SP_EDEVICE;
     if (!st) st = malloc_m(mm, &mm->theta, kNParams);
     if (!st) st = malloc_m(mm, &mm->theta_h, kNParams);
+    if (!st) st = malloc_m(mm, &mm->wsw, (size_t)kFwdTiles * 64);
     if (!st) st = malloc_m(mm, &mm->m, kNParams);
     if (!st) st = malloc_m(mm, &mm->v, kNParams);
     if (!st) st = malloc_m(mm, &mm->grad, kNParams);
@@ -609,7 +640,7 @@ void sp_mlp_destroy(sp_mlp* mm)
 {
     if (!mm) return;
     if (mm->stream) (void)hipStreamSynchronize(mm->stream);
-    void* ps[] = {mm->theta, mm->theta_h, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->a0, mm->z[0], mm->z[1],
+    void* ps[] = {mm->theta, mm->theta_h, mm->wsw, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->a0, mm->z[0], mm->z[1],
                   mm->z[2], mm->a[0], mm->a[1], mm->a[2], mm->y, mm->dF, mm->dH, mm->dzF[0], mm->dzF[1],
                   mm->dzH[0], mm->dzH[1], mm->sq, mm->part};
     for (void* p : ps)
@@ -628,6 +659,7 @@ sp_status sp_mlp_set_params(sp_mlp* mm, const float* params)
     MLP_HIP(mm, hipMemcpyAsync(mm->theta, params, kNParams * 4, hipMemcpyHostToDevice, mm->stream));
     hipLaunchKernelGGL(to_bf16_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, kNParams,
                        mm->theta_h);
+    mm->wsw_stale = true;
     MLP_HIP(mm, hipGetLastError());
     MLP_HIP(mm, hipMemsetAsync(mm->m, 0, kNParams * 4, mm->stream));
     MLP_HIP(mm, hipMemsetAsync(mm->v, 0, kNParams * 4, mm->stream));
@@ -705,8 +737,7 @@ sp_status sp_mlp_forward(sp_mlp* mm, const float* x, int64_t M, float* y)
     if (!mm || (M > 0 && (!x || !y)) || M < 0 || M > INT32_MAX / kHid)
         return mm ? mfail(mm, SP_EINVAL, "bad forward arguments") : SP_EINVAL;
     if (M == 0) return SP_OK;
-    SP_TRY(ensure_rows(mm, M));
-    return mlp_forward(mm, x, nullptr, (int)M, false, y);
+    return mlp_infer(mm, x, M, y, mm->stream);
 }
 
 sp_status sp_mlp_gradient(sp_mlp* mm, const float* X, const float* T, int32_t B, float* grad_host, float* loss)

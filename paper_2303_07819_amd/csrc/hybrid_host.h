@@ -259,11 +259,7 @@ sp_status hybrid_rebuild(sp_ctx* c)
 sp_status net_forward_on(sp_ctx* c, sp_mlp* net, const float* x, int rows, float* y)
 {
     if (rows <= 0) return SP_OK;
-    hipStream_t keep = net->stream;
-    net->stream = c->stream;
-    sp_status st = ensure_rows(net, rows);
-    if (!st) st = mlp_forward(net, x, nullptr, rows, false, y);
-    net->stream = keep;
+    const sp_status st = mlp_infer(net, x, rows, y, c->stream);
     if (st) return fail(c, st, "closure network: %s", net->err.c_str());
     return SP_OK;
 }

@@ -151,6 +151,141 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             }
 }
 
+// ------------------------------------------------ fused forward (inference)
+// Normalisation, the three GELU layers and the output map in one launch, for
+// inference (nothing is kept for a backward pass).  Each product runs
+// transposed, H^T = W X^T, with the weights as the MFMA A operand and the
+// activations as the B operand: the output tile of a 16 x 16 x 16 step holds in
+// each lane four consecutive output features of row lane % 16, which is exactly
+// the B operand of the next layer's step, so activations stay in registers.
+// A wavefront carries 16 rows through all layers; the workgroup stages every
+// weight tile in LDS once, swizzled so that each lane's four A values are one
+// 8-byte read (80 KB: two workgroups per CU).
+constexpr int kFwdWaves = 8;
+constexpr int kFwdT1 = 8 * 3, kFwdT2 = 64, kFwdT3 = 64, kFwdT4 = 8;   // 16 x 16 tiles: W1 (K 45 -> 48), W2, W3,
+constexpr int kFwdTiles = kFwdT1 + kFwdT2 + kFwdT3 + kFwdT4;          // W4 (4 outputs -> 16)
+constexpr size_t kFwdLds = (size_t)kFwdTiles * 64 * sizeof(bf16x4);   // 160 tiles: 81,920 B
+
+// A operand of weight tile (ob, kb) of a layer with nin inputs and nout
+// outputs: lane l holds W[ob 16 + l % 16][kb 16 + 4 (l / 16) + q], q < 4 (zero
+// outside the matrix); W row-major [nout][nin].
+__device__ __forceinline__ bf16x4 weight_tile_operand(const uint16_t* W, int nin, int nout, int ob, int kb,
+                                                      int lane)
+{
+    const int o = ob * 16 + (lane & 15);
+    const int k0 = kb * 16 + 4 * (lane >> 4);
+    bf16x4 a;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = (short)((o < nout && k0 + q < nin) ? W[o * nin + k0 + q] : 0);
+    return a;
+}
+
+// Bias, GELU and bfloat16 rounding of an output tile: element r of ob's tile
+// is feature ob 16 + 4 (lane / 16) + r.
+__device__ __forceinline__ bf16x4 hidden_operand(const f32x4 acc, const float* bias, int ob, int lane)
+{
+    const int f0 = ob * 16 + 4 * (lane >> 4);
+    bf16x4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = (short)f2bf(gelu_f(acc[r] + bias[f0 + r]));
+    return h;
+}
+
+// One hidden layer: out[ob] = sum over kb of W(ob, kb) in[kb], 8 x 8 steps,
+// weight tiles from LDS (tile index base + ob 8 + kb).
+__device__ __forceinline__ void hidden_layer(const bf16x4* wt, int base, const bf16x4 in[8], const float* bias,
+                                             int lane, bf16x4 out[8])
+{
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) {
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[(base + ob * 8 + kb) * 64 + lane], in[kb], acc, 0, 0,
+                                                             0);
+        out[ob] = hidden_operand(acc, bias, ob, lane);
+        __builtin_amdgcn_sched_barrier(0);   // keep each tile row's weight reads next to its steps
+    }
+}
+
+// The weight tiles in the order and lane layout the fused forward stages in
+// LDS (tile t, lane l at wsw[t 64 + l]), from the bfloat16 parameters.
+__global__ void swizzle_weights_kernel(const uint16_t* th, bf16x4* wsw)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kFwdTiles * 64) return;
+    const int t = e >> 6, l = e & 63;
+    bf16x4 a;
+    if (t < kFwdT1)
+        a = weight_tile_operand(th + kOffW1, kIn, kHid, t / 3, t % 3, l);
+    else if (t < kFwdT1 + kFwdT2)
+        a = weight_tile_operand(th + kOffW2, kHid, kHid, (t - kFwdT1) >> 3, (t - kFwdT1) & 7, l);
+    else if (t < kFwdT1 + kFwdT2 + kFwdT3)
+        a = weight_tile_operand(th + kOffW3, kHid, kHid, (t - kFwdT1 - kFwdT2) >> 3, (t - kFwdT1 - kFwdT2) & 7, l);
+    else
+        a = weight_tile_operand(th + kOffW4, kHid, kOut, 0, t - kFwdT1 - kFwdT2 - kFwdT3, l);
+    wsw[e] = a;
+}
+
+// wsw: weight tiles from swizzle_weights_kernel; theta: FP32 parameters (biases); norm: x_mean[45],
+// x_inv_std[45], y_mean[4], (target inverse std)[4], y_std[4]; y [M][4].
+__global__ __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(4))) void mlp_forward_kernel(const float* x, long M, const bf16x4* wsw,
+                                                                     const float* theta, const float* norm,
+                                                                     float* y)
+{
+    extern __shared__ __align__(16) unsigned char fwd_smem[];
+    bf16x4* wt = reinterpret_cast<bf16x4*>(fwd_smem);   // [kFwdTiles][64]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(wsw);   // two tile lanes per 16 bytes
+        uint4* dst = reinterpret_cast<uint4*>(wt);
+        for (int e = tid; e < kFwdTiles * 32; e += blockDim.x) dst[e] = src[e];
+    }
+    __syncthreads();
+
+    const float* xm = norm;
+    const float* xis = norm + kIn;
+    const float* ym = norm + 2 * kIn;
+    const float* ys = norm + 2 * kIn + 2 * kOut;
+    const long step = (long)gridDim.x * kFwdWaves * 16;
+    for (long r0 = ((long)blockIdx.x * kFwdWaves + wave) * 16; r0 < M; r0 += step) {
+        const long row = r0 + (lane & 15);
+        const bool ok = row < M;
+        // layer 1: inputs 4 (lane / 16) + q of each 16-feature block, normalised
+        bf16x4 xb[3];
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = kb * 16 + 4 * (lane >> 4) + q;
+                xb[kb][q] = (short)((ok && f < kIn) ? f2bf((x[row * kIn + f] - xm[f]) * xis[f]) : 0);
+            }
+        bf16x4 h1[8];
+#pragma unroll
+        for (int ob = 0; ob < 8; ++ob) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kb = 0; kb < 3; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[(ob * 3 + kb) * 64 + lane], xb[kb], acc, 0, 0, 0);
+            h1[ob] = hidden_operand(acc, theta + kOffB1, ob, lane);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        bf16x4 h2[8], h3[8];
+        hidden_layer(wt, kFwdT1, h1, theta + kOffB2, lane, h2);
+        hidden_layer(wt, kFwdT1 + kFwdT2, h2, theta + kOffB3, lane, h3);
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[(kFwdT1 + kFwdT2 + kFwdT3 + kb) * 64 + lane], h3[kb],
+                                                             acc, 0, 0, 0);
+        // lanes 0-15 hold outputs 0-3 of row lane
+        if (lane < 16 && ok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[row * kOut + r] = (acc[r] + theta[kOffB4 + r]) * ys[r] + ym[r];
+        }
+    }
+}
+
 // Sum of the `slices` partial products of a split-K product, in slice order:
 // out[i] = sum_z part[z stride + i], i < n.
 __global__ void splitk_reduce_kernel(const float* part, int slices, long stride, long n, float* out)
