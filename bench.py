@@ -80,8 +80,10 @@ def measured_traffic():
     vals = {}
     for line in text.splitlines():
         if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
-            k, v = line.strip().strip("`").split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
+            k, v = line.strip().split(":", 1)
+            parts = v.split("`")
+            if len(parts) >= 3:
+                vals[k.strip()] = parts[1]   # the first `quoted` value
     if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
@@ -194,15 +196,29 @@ def training_rate(hist):
 
 
 def closure_probe():
-    """One 64 x 64 window sampled, two epochs of training (for rocprofv3 counters)."""
+    """One 64 x 64 window sampled, two epochs of training, then the fused
+    inference forward over every sample (for rocprofv3 counters)."""
     import torch
     from paper_2303_07819_amd import closure as cl
     stream = torch.cuda.Stream()
     X, T = cl.generate_samples([cl.training_workload(230307900)], stream=stream.cuda_stream)
     net, hist = cl.train(X, T, epochs=2, stream=stream.cuda_stream)
+    with torch.cuda.stream(stream):
+        y = torch.empty((X.shape[0], 4), device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        net.forward(X, y)                     # weight tiles staged once
+        e0.record(stream)
+        net.forward(X, y)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3
+    flops = 2 * MLP_FWD_MACS * X.shape[0]
     net.close()
-    print(json.dumps({"closure_probe": {"samples": hist["samples"], "adam_steps": hist["steps"],
-                                        "seconds": hist["seconds"], "training": training_rate(hist)}}), flush=True)
+    print(json.dumps({"closure_probe": {
+        "samples": hist["samples"], "adam_steps": hist["steps"], "seconds": hist["seconds"],
+        "training": training_rate(hist),
+        "inference": {"rows": int(X.shape[0]), "us": us, "achieved": flops / us / 1e6, "unit": "TFLOP/s",
+                      "peak": MFMA_BF16_PEAK_TFLOPS, "frac": flops / us / 1e6 / MFMA_BF16_PEAK_TFLOPS}}}), flush=True)
 
 
 def hybrid_leg(args, stream):

@@ -304,39 +304,43 @@ sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* 
 // same step are advanced together, joined by the later ones as their time
 // comes.  The floes then equal those of the plain method: cells do not
 // interact in the DEM.
-sp_status catch_up(sp_ctx* c, std::vector<int32_t> cells, double dt)
+sp_status catch_up(sp_ctx* c, const std::vector<int32_t>& cells, double dt)
 {
     HybridState* h = c->hyb;
-    std::sort(cells.begin(), cells.end(),
-              [&](int32_t a, int32_t b) { return h->frozen_at[a] < h->frozen_at[b]; });
     std::vector<uint8_t> include(c->ncells, 0);
-    Bucket tmp[kNumBuckets];
-    for (int q = 0; q < kNumBuckets; ++q) {
-        tmp[q].waves = c->bk[q].waves;
-        tmp[q].persist = c->bk[q].persist;
+    std::vector<int32_t> nsub(c->ncells, 0);
+    bool any = false;
+    for (int32_t cell : cells) {
+        include[cell] = 1;
+        nsub[cell] = (int32_t)(c->kstep - h->frozen_at[cell]);
+        any = any || nsub[cell] > 0;
     }
-    StepArgs base = make_args(c, dt);
-    base.mom = c->mom2;
-    base.lf = 0;
     sp_status st = SP_OK;
-    size_t i = 0;
-    while (!st && i < cells.size()) {
-        const int64_t t0 = h->frozen_at[cells[i]];
-        while (i < cells.size() && h->frozen_at[cells[i]] == t0) include[cells[i++]] = 1;
-        const int64_t t1 = i < cells.size() ? h->frozen_at[cells[i]] : c->kstep;
-        if (t1 <= t0) continue;
-        st = build_buckets_into(c, tmp, c->counts_h.data(), include.data());
+    if (any) {
+        // one multi-step launch per count bucket: each cell runs its own number
+        // of steps inside the launch (cells are independent DEMs)
+        Bucket tmp[kNumBuckets];
+        for (int q = 0; q < kNumBuckets; ++q) tmp[q].waves = c->bk[q].waves;
+        StepArgs base = make_args(c, dt);
+        base.mom = c->mom2;
+        base.lf = 0;
+        st = build_buckets_into(c, tmp, c->counts_h.data(), include.data(), nsub.data());
+        for (auto& b : tmp) {
+            if (st || b.cells_h.empty()) continue;
+            const size_t gb = bucket_group_bytes(c, b);
+            const int threads = 64 * b.waves;
+            st = prepare_multi_sel(c, c->sched, b.waves, threads, gb);
+            StepArgs a = base;
+            a.work = b.work_d;
+            a.ncl = (int32_t)b.cells_h.size();
+            a.cap = b.cap;
+            a.group_bytes = (int32_t)gb;
+            if (!st) st = launch_multi_sel(c, c->sched, b.waves, a, a.ncl, threads, gb);
+        }
+        (void)hipStreamSynchronize(c->stream);   // the temporary work lists are freed below
         for (auto& b : tmp)
-            if (!st && !b.cells_h.empty()) st = prepare_bucket(c, b);
-        for (int64_t k = 0; !st && k < t1 - t0; ++k)
-            for (auto& b : tmp) {
-                st = launch_bucket(c, b, base, k, false, true);
-                if (st) break;
-            }
+            if (b.work_d) (void)hipFree(b.work_d);
     }
-    (void)hipStreamSynchronize(c->stream);   // the temporary work lists are freed below
-    for (auto& b : tmp)
-        if (b.work_d) (void)hipFree(b.work_d);
     if (st) return st;
     for (int32_t cell : cells) h->frozen_at[cell] = c->kstep;
     return SP_OK;
