@@ -297,16 +297,18 @@ sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const 
  * SP_TEND_RESIDUAL and T the output of a network trained on its targets.  All
  * other cells run the DEM step and the continuum update of Sec. 3.2, which
  * takes the reduced DEM's <v> as the coefficient of a neighbouring closure
- * cell.  A closure cell's floes stay frozen.  Every check_every steps the next
- * check_cells closure cells (round robin) are checked: their floes catch up
- * with the DEM steps they missed (the cells' DEMs do not interact, so these
- * are the plain method's floes), their statistics give the plain method's
- * residual tendency T_dem, and a cell whose closure residual T (T = 0 once
- * its reduced DEM is older than net_window) misses it so much that
- * check_every dt |T - T_dem| exceeds tol (|Q_cell| + 0.01 mean |Q| of the
- * sample) in any component runs the DEM for the next fallback_steps steps,
- * after which its reduced DEM restarts from its floes.  Every checked cell's
- * reduced DEM restarts from its caught-up floes.  With net_window > 0 the
+ * cell.  A closure cell's floes stay frozen, except in the check pool: up to
+ * 4 check_cells closure cells spread evenly over them, whose DEMs keep
+ * stepping (their statistics unused), so that their floes are the plain
+ * method's (the cells' DEMs do not interact).  Every check_every steps the
+ * next check_cells pool cells in closure mode (round robin) are checked:
+ * their statistics give the plain method's residual tendency T_dem, and a
+ * cell whose closure residual T (T = 0 once its reduced DEM is older than
+ * net_window) misses it so much that check_every dt |T - T_dem| exceeds tol
+ * (|Q_cell| + 0.01 mean |Q| of the sample) in any component runs the DEM for
+ * the next fallback_steps steps, after which its reduced DEM restarts from
+ * its floes.  Every checked cell's reduced DEM restarts from its floes.  With
+ * net_window > 0 the
  * network's term is applied to a closure cell only during the first
  * net_window seconds of its reduced DEM (the relaxation transient the network
  * is trained on); later the reduced DEM alone carries the cell.  A null

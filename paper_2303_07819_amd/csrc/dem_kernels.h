@@ -79,6 +79,7 @@ struct StepArgs {
     const int32_t* cell_start;
     const float2* phase;       // [ncells][nmodes]: (sin, cos) of the phase at the cell centre
     double* mom;               // statistics written by this step [ncells][kMomStride]
+    double* mom_alt;           // where the statistics of work entries with w = 1 go instead
     uint32_t* err;
     unsigned long long* contacts;   // [ncells] contacts counted per cell since the floes were set
     // candidate lists kept between steps (Verlet lists with a skin): per cell,
@@ -92,7 +93,7 @@ struct StepArgs {
     float* vdisp;
     float skin;                // m, added to R when the lists are built
     // work list
-    const int4* work;          // (cell, first floe, floe count, -) of this launch, costliest first
+    const int4* work;          // (cell, first floe, floe count, statistics to mom_alt) of this launch, costliest first
     int32_t ncl;
     int32_t group_bytes;       // LDS bytes per group
     int32_t cap;               // LDS floe capacity per group
@@ -422,10 +423,7 @@ __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* 
 // ------------------------------------------------------------- DEM step
 // SCHED: 1 all pairs, 2 binned half shell.  W: wavefronts per cell.
 // PERSIST: a grid of resident workgroups strides over the work list.
-// MULTI: each cell runs the number of steps in its work entry's fourth field
-// within the launch (one group per workgroup; no continuum update): catching
-// cells up without a launch per step.
-template <int SCHED, int W, bool PERSIST, bool MULTI>
+template <int SCHED, int W, bool PERSIST>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArgs a)
 {
     constexpr int G = 64 * W;                  // threads per group
@@ -440,7 +438,6 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
     __shared__ double lfops[GPB][kLfOps];
-    __shared__ float vdl[GPB];                         // MULTI: the displacement bound between steps
 
     const int tid = threadIdx.x;
     const int g = tid / G, gt = tid % G;
@@ -467,340 +464,335 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         const bool valid = item < a.ncl;
         const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
         const int c = wk.x, s = wk.y, n = wk.z;
-        const int nsub = MULTI ? wk.w : 1;
-        for (int sub = 0; sub < nsub; ++sub) {
-            const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;   // loaded early
-            // the continuum update of the previous level for this cell reads only
-            // buffers this launch does not write: its operands are loaded now, one
-            // per lane, and combined after the floes are done
-            const double lfo = (valid && a.lf && gt < kLfOps) ? lf_operand(c, gt, a.mom_prev, a.Qp, a.nx, a.ny) : 0.0;
-            // rebuild the cell's candidate lists when its floes may have moved by
-            // skin / 2 since they were built (every pair then changed its distance
-            // by less than the skin); the same for the whole group
-            const float vd = valid ? ((MULTI && sub > 0) ? vdl[g] : a.vdisp[c]) : 0.0f;
-            const bool build = valid && !(vd <= 0.5f * a.skin);
-            const int nb_build = build ? n : 0;        // loop bound of the build work
-            uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
+        const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;   // loaded early
+        // the continuum update of the previous level for this cell reads only
+        // buffers this launch does not write: its operands are loaded now, one
+        // per lane, and combined after the floes are done
+        const double lfo = (valid && a.lf && gt < kLfOps) ? lf_operand(c, gt, a.mom_prev, a.Qp, a.nx, a.ny) : 0.0;
+        // rebuild the cell's candidate lists when its floes may have moved by
+        // skin / 2 since they were built (every pair then changed its distance
+        // by less than the skin); the same for the whole group
+        const float vd = valid ? a.vdisp[c] : 0.0f;
+        const bool build = valid && !(vd <= 0.5f * a.skin);
+        const int nb_build = build ? n : 0;        // loop bound of the build work
+        uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
 
-            if (valid && gt < a.nmodes) {
-                const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
-                mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
-            }
-            for (int i = gt; i < n; i += G) {
-                P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), __float_as_uint(a.th[s + i]));
-                V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], a.h[s + i]);
-                if (build) {
-                    cnt[i] = 0;
-                } else {
-                    // kept candidates: the first eight in one 16-byte load issued with
-                    // the floe state, the rest (rare) after the count
-                    const int k = a.vcount[s + i];
-                    cnt[i] = k;
-                    uint16_t* my = lst + (size_t)i * kListCap;
-                    *reinterpret_cast<uint4*>(my) = *reinterpret_cast<const uint4*>(vlst + (size_t)i * 8);
-                    for (int q = 8; q < k; q += 8)
-                        *reinterpret_cast<uint4*>(my + q) =
-                            *reinterpret_cast<const uint4*>(vlst + (size_t)q * n + (size_t)i * 8);
-                }
-            }
-            // the search runs only in workgroups where some cell rebuilds its lists
-            // (the barriers below are workgroup-wide)
-            const bool any_build = __syncthreads_or(build);
-            if (SCHED == 2 && any_build) {
-                const int nb = a.nbx * a.nby;
-                for (int b = gt; b < nb; b += G) bcnt[b] = 0;
-                __syncthreads();
-                for (int i = gt; i < nb_build; i += G) {
-                    const int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
-                    const int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
-                    const int b = by * a.nbx + bx;
-                    binof[i] = b;
-                    rank[i] = atomicAdd(&bcnt[b], 1);
-                }
-                __syncthreads();
-                group_exclusive_scan<G>(bcnt, bstart, nb, gt, wsum[g]);
-                for (int i = gt; i < nb_build; i += G) {
-                    uint4 p = P[i];
-                    p.w = (uint32_t)i | ((uint32_t)binof[i] << 16);
-                    S[bstart[binof[i]] + rank[i]] = p;
-                }
-                __syncthreads();
-            }
-
-            // ---- phase 1: contact candidates -> per-floe lists
-            if (SCHED == 1) {
-                // every floe against every floe (itself included, skipped later);
-                // the list comes out in ascending partner order
-                for (int l = gt; l < nb_build; l += G) {
-                    const uint4 pl = P[l];
-                    const float rl = __uint_as_float(pl.z) + a.skin;
-                    uint16_t* my = lst + (size_t)l * kListCap;
-                    int k = 0;
-                    for (int j = 0; j < n; ++j) {
-                        const uint4 pj = P[j];
-                        float diff, R2;
-                        screen((int)(pj.x - pl.x), (int)(pj.y - pl.y), rl, __uint_as_float(pj.z), a.qx,
-                               a.qy, diff, R2);
-                        if (diff < kGuard * R2) {
-                            if (k < kListCap) my[k] = (uint16_t)j;
-                            ++k;
-                        }
-                    }
-                    cnt[l] = k;
-                }
-            } else {
-                // half shell over the bin-sorted copy: lanes take consecutive sorted
-                // floes (neighbouring lanes share their neighbourhood); each pair is
-                // screened once, from the bin whose offset to the other is in
-                // {own bin (later sorted index), E, NW, N, NE}, and appended to both lists
-                for (int t = gt; t < nb_build; t += G) {
-                    const uint4 own = S[t];
-                    const int o = (int)(own.w & 0xffffu);
-                    const int b = (int)(own.w >> 16);
-                    const int bx = b % a.nbx, by = b / a.nbx;
-                    const float rl = __uint_as_float(own.z) + a.skin;
-                    if (a.nbx >= 3 && bx + 1 < a.nbx) {
-                        // own-bin tail and the east bin are contiguous
-                        sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
-                    } else {
-                        sweep(S, t + 1, bstart[b + 1], own.x, own.y, rl, o, lst, cnt, a);
-                        if (a.nbx >= 3) {
-                            const int be = by * a.nbx;   // east neighbour across the seam
-                            sweep(S, bstart[be], bstart[be + 1], own.x, own.y, rl, o, lst, cnt, a);
-                        }
-                    }
-                    if (a.nby >= 3) {
-                        const int row = (by + 1 == a.nby ? 0 : by + 1) * a.nbx;
-                        if (a.nbx < 3) {
-                            sweep(S, bstart[row], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
-                        } else if (bx == 0) {
-                            sweep(S, bstart[row], bstart[row + 2], own.x, own.y, rl, o, lst, cnt, a);
-                            sweep(S, bstart[row + a.nbx - 1], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
-                                  cnt, a);
-                        } else if (bx == a.nbx - 1) {
-                            sweep(S, bstart[row + a.nbx - 2], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
-                                  cnt, a);
-                            sweep(S, bstart[row], bstart[row + 1], own.x, own.y, rl, o, lst, cnt, a);
-                        } else {
-                            sweep(S, bstart[row + bx - 1], bstart[row + bx + 2], own.x, own.y, rl, o, lst,
-                                  cnt, a);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-
-            double acc[kDyn];
-    #pragma unroll
-            for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
-            unsigned long long ncontact = 0;
-            float maxdisp = 0.0f;
-
-            for (int l = gt; l < n; l += G) {
-                const uint4 pl = P[l];
-                const float4 vv = V[l];
-                const uint32_t xl = pl.x, yl = pl.y;
-                const float rl = __uint_as_float(pl.z);
-                const float ul = vv.x, vl = vv.y, wl = vv.z;
-
-                // ---- ocean current and curl at the floe centre (angle addition around
-                // the cell centre keeps the FP32 arguments below (|kx| Lx + |ky| Ly) / 2),
-                // then drag and drag torque in FP64
-                const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
-                double fdx = 0.0, fdy = 0.0, tdr = 0.0;
-                if (!(a.flags & SP_OCEAN_OFF)) {
-                    const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
-                    const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
-                    float uo = a.u0, vo = a.v0, zeta = 0.0f;
-                    ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
-                    const double du = (double)uo - uld, dv = (double)vo - vld;
-                    const double sp = sqrt(du * du + dv * dv);
-                    const double alpha = a.cdrho * kPi * rld * rld;
-                    fdx = alpha * du * sp;
-                    fdy = alpha * dv * sp;
-                    const double dW = 0.5 * (double)zeta - wld;
-                    const double r2 = rld * rld;
-                    const double beta = a.cdrho * kPi * r2 * r2 * rld;
-                    tdr = beta * dW * fabs(dW);
-                }
-                const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
-
-                uint16_t* my = lst + (size_t)l * kListCap;
-                int k;
-                if (build) {
-                    k = cnt[l];
-                    if (k > kListCap) {
-                        atomicOr(a.err, kErrCapacity);
-                        k = kListCap;
-                    }
-                    if (SCHED == 2) {
-                        // ascending partner order: insertion sort of the short list
-                        for (int i = 1; i < k; ++i) {
-                            const uint16_t key = my[i];
-                            int j = i - 1;
-                            while (j >= 0 && my[j] > key) {
-                                my[j + 1] = my[j];
-                                --j;
-                            }
-                            my[j + 1] = key;
-                        }
-                    }
-                    // keep the list for the steps until the next rebuild
-                    for (int q = 0; q < k; ++q) vlst[(size_t)(q & ~7) * n + (size_t)l * 8 + (q & 7)] = my[q];
-                    a.vcount[s + l] = (uint8_t)k;
-                } else {
-                    k = cnt[l];   // staged with the floe state
-                }
-
-                // ---- contact decisions: every candidate, eight indices per LDS read;
-                // the contacts become a bit mask over the (ascending) list
-                uint32_t cmask = 0;
-                for (int q0 = 0; q0 < k; q0 += 8) {
-                    const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
-                    const int qe = min(8, k - q0);
-                    for (int t = 0; t < qe; ++t) {
-                        const uint32_t wv = t < 2 ? ix.x : t < 4 ? ix.y : t < 6 ? ix.z : ix.w;
-                        const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
-                        if (j == l) continue;
-                        const uint4 pj = P[j];
-                        if (decide((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a))
-                            cmask |= 1u << (q0 + t);
-                    }
-                }
-
-                // ---- contact forces and torques in ascending partner order (FP64);
-                // a wave runs as many rounds as its lanes have contacts at most
-                double Fx = fdx, Fy = fdy, T = tdr;
-                while (cmask) {
-                    const int q = __builtin_ctz(cmask);
-                    cmask &= cmask - 1u;
-                    const int j = my[q];
-                    const uint4 pj = P[j];
-                    const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
-                    const float rj = __uint_as_float(pj.z);
-                    const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
-                    const double d2 = dx * dx + dy * dy;
-                    if (!(d2 > 0.0)) {
-                        atomicOr(a.err, kErrOverlap);
-                        continue;
-                    }
-                    const double rjd = (double)rj;
-                    const double d = sqrt(d2);
-                    const double inv_d = 1.0 / d;
-                    const double nx = dx * inv_d, ny = dy * inv_d;
-                    const double tx = -ny, ty = nx;
-                    const double R = rld + rjd;
-                    const double delta = d - R;
-                    const double dr = fabs(rld - rjd);
-                    double cc;
-                    if (d <= dr) {
-                        cc = 2.0 * fmin(rld, rjd);
-                    } else {
-                        const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
-                        cc = sqrt(fmax(p, 0.0)) * inv_d;
-                    }
-                    const double Fn = cc * a.Ed * delta;
-                    const float4 vj = V[j];
-                    const double wjd = (double)vj.z;
-                    // spin sum in a fixed operand order (lower floe index first) so that
-                    // the pair forces are exactly antisymmetric
-                    const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
-                    const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
-                    const double capf = a.mud * fabs(Fn);
-                    const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
-                    Fx += Fn * nx + Ft * tx;
-                    Fy += Fn * ny + Ft * ty;
-                    T += rld * Ft;
-                    ncontact += (l < j) ? 1ull : 0ull;
-                }
-
-                // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
-                // FP32 / fixed-point storage
-                const double inv_m = 1.0 / md;
-                const double dt = a.dtd;
-                const double und = uld + dt * (Fx * inv_m);
-                const double vnd = vld + dt * (Fy * inv_m);
-                const double wnd = wld + dt * (T * inv_m / (rld * rld));
-                const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
-                const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
-                const int sx = __double2int_rn(dt * ux * a.inv_qxd);
-                const int sy = __double2int_rn(dt * vx * a.inv_qyd);
-                {
-                    const float ddx = (float)sx * a.qx, ddy = (float)sy * a.qy;
-                    maxdisp = fmaxf(maxdisp, sqrtf(ddx * ddx + ddy * ddy));
-                }
-                const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
-                a.xi[s + l] = xl + (uint32_t)sx;
-                a.yi[s + l] = yl + (uint32_t)sy;
-                a.u[s + l] = un;
-                a.v[s + l] = vn;
-                a.w[s + l] = wn;
-                a.th[s + l] = (float)((double)__uint_as_float(pl.w) + dt * wx);
-                if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
-
-                // ---- statistics of the pre-step state (FP64)
-                acc[0] += md * uld;
-                acc[1] += md * vld;
-                acc[2] += md * rld * rld * wld;
-                acc[3] += uld;
-                acc[4] += vld;
-                acc[5] += fdx;
-                acc[6] += fdy;
-                acc[7] += tdr;
-            }
-
-            // ---- group reduction through LDS: lane partials -> 16 segment sums per
-            // quantity -> DPP row sum (fixed order, deterministic)
-            const unsigned long long cs = wave_sum_u64(ncontact);
-            const float wd = wave_max_f32(maxdisp);
-            if ((tid & 63) == 0) {
-                csum[tid >> 6] = cs;
-                wdisp[tid >> 6] = wd;
-            }
-            __syncthreads();   // every lane is done with the cell's LDS data
-            if (valid && gt == 0) {
-                float d = 0.0f;
-                for (int q = 0; q < W; ++q) d = fmaxf(d, wdisp[g * W + q]);
-                // the bound grows by the largest displacement of this step (rounded up)
-                const float nvd = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
-                a.vdisp[c] = nvd;
-                if (MULTI) vdl[g] = nvd;   // read back by every lane at the next step
-            }
-    #pragma unroll
-            for (int k = 0; k < kDyn; ++k) red[k * G + gt] = acc[k];
-            if (gt < kLfOps) lfops[g][gt] = lfo;
-            __syncthreads();
-            constexpr int SEG = G / 16;                 // values per segment
-            for (int kq = gt >> 4; kq < kDyn; kq += G / 16) {
-                // segment seg sums lanes seg, seg + 16, ... in order (neighbouring
-                // lanes read neighbouring words: no bank conflicts)
-                const int seg = gt & 15;
-                const double* src = red + kq * G + seg;
-                double x = 0.0;
-    #pragma unroll
-                for (int i = 0; i < SEG; ++i) x += src[16 * i];
-                x = row_sum(x);
-                if (seg == 15 && valid) {
-                    const int slot = dyn_slot(kq);
-                    a.mom[(size_t)c * kMomStride + slot] = x;
-                    if (slot == M_UX || slot == M_UY)   // continuum coefficient <v> = U / n
-                        a.mom[(size_t)c * kMomStride + (slot == M_UX ? M_UBAR : M_VBAR)] =
-                            n > 0 ? x / (double)n : 0.0;
-                }
-            }
-            if (valid && gt == 0) {
-                // per-cell running count, written by the cell's own group only (one
-                // shared counter would serialise every workgroup on one address)
-                unsigned long long t = 0;
-                for (int q = 0; q < W; ++q) t += csum[g * W + q];
-                a.contacts[c] = ccell + t;
-            }
-            // continuum update of the previous level for this cell (operands loaded
-            // at the start of the cell)
-            if (valid && a.lf && gt == G - 1)
-                lf_from_ops(c, lfops[g], a.Qn, a.nx * a.ny, a.dtd, a.dX, a.dY, a.inv_area, a.max_cfl_bits, a.err);
-            if (MULTI) __syncthreads();   // the step's LDS data is free; its floe state is written
+        if (valid && gt < a.nmodes) {
+            const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
+            mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
         }
+        for (int i = gt; i < n; i += G) {
+            P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), __float_as_uint(a.th[s + i]));
+            V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], a.h[s + i]);
+            if (build) {
+                cnt[i] = 0;
+            } else {
+                // kept candidates: the first eight in one 16-byte load issued with
+                // the floe state, the rest (rare) after the count
+                const int k = a.vcount[s + i];
+                cnt[i] = k;
+                uint16_t* my = lst + (size_t)i * kListCap;
+                *reinterpret_cast<uint4*>(my) = *reinterpret_cast<const uint4*>(vlst + (size_t)i * 8);
+                for (int q = 8; q < k; q += 8)
+                    *reinterpret_cast<uint4*>(my + q) =
+                        *reinterpret_cast<const uint4*>(vlst + (size_t)q * n + (size_t)i * 8);
+            }
+        }
+        // the search runs only in workgroups where some cell rebuilds its lists
+        // (the barriers below are workgroup-wide)
+        const bool any_build = __syncthreads_or(build);
+        if (SCHED == 2 && any_build) {
+            const int nb = a.nbx * a.nby;
+            for (int b = gt; b < nb; b += G) bcnt[b] = 0;
+            __syncthreads();
+            for (int i = gt; i < nb_build; i += G) {
+                const int bx = (int)__umulhi(P[i].x, (uint32_t)a.nbx);
+                const int by = (int)__umulhi(P[i].y, (uint32_t)a.nby);
+                const int b = by * a.nbx + bx;
+                binof[i] = b;
+                rank[i] = atomicAdd(&bcnt[b], 1);
+            }
+            __syncthreads();
+            group_exclusive_scan<G>(bcnt, bstart, nb, gt, wsum[g]);
+            for (int i = gt; i < nb_build; i += G) {
+                uint4 p = P[i];
+                p.w = (uint32_t)i | ((uint32_t)binof[i] << 16);
+                S[bstart[binof[i]] + rank[i]] = p;
+            }
+            __syncthreads();
+        }
+
+        // ---- phase 1: contact candidates -> per-floe lists
+        if (SCHED == 1) {
+            // every floe against every floe (itself included, skipped later);
+            // the list comes out in ascending partner order
+            for (int l = gt; l < nb_build; l += G) {
+                const uint4 pl = P[l];
+                const float rl = __uint_as_float(pl.z) + a.skin;
+                uint16_t* my = lst + (size_t)l * kListCap;
+                int k = 0;
+                for (int j = 0; j < n; ++j) {
+                    const uint4 pj = P[j];
+                    float diff, R2;
+                    screen((int)(pj.x - pl.x), (int)(pj.y - pl.y), rl, __uint_as_float(pj.z), a.qx,
+                           a.qy, diff, R2);
+                    if (diff < kGuard * R2) {
+                        if (k < kListCap) my[k] = (uint16_t)j;
+                        ++k;
+                    }
+                }
+                cnt[l] = k;
+            }
+        } else {
+            // half shell over the bin-sorted copy: lanes take consecutive sorted
+            // floes (neighbouring lanes share their neighbourhood); each pair is
+            // screened once, from the bin whose offset to the other is in
+            // {own bin (later sorted index), E, NW, N, NE}, and appended to both lists
+            for (int t = gt; t < nb_build; t += G) {
+                const uint4 own = S[t];
+                const int o = (int)(own.w & 0xffffu);
+                const int b = (int)(own.w >> 16);
+                const int bx = b % a.nbx, by = b / a.nbx;
+                const float rl = __uint_as_float(own.z) + a.skin;
+                if (a.nbx >= 3 && bx + 1 < a.nbx) {
+                    // own-bin tail and the east bin are contiguous
+                    sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
+                } else {
+                    sweep(S, t + 1, bstart[b + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    if (a.nbx >= 3) {
+                        const int be = by * a.nbx;   // east neighbour across the seam
+                        sweep(S, bstart[be], bstart[be + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    }
+                }
+                if (a.nby >= 3) {
+                    const int row = (by + 1 == a.nby ? 0 : by + 1) * a.nbx;
+                    if (a.nbx < 3) {
+                        sweep(S, bstart[row], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                    } else if (bx == 0) {
+                        sweep(S, bstart[row], bstart[row + 2], own.x, own.y, rl, o, lst, cnt, a);
+                        sweep(S, bstart[row + a.nbx - 1], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    } else if (bx == a.nbx - 1) {
+                        sweep(S, bstart[row + a.nbx - 2], bstart[row + a.nbx], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                        sweep(S, bstart[row], bstart[row + 1], own.x, own.y, rl, o, lst, cnt, a);
+                    } else {
+                        sweep(S, bstart[row + bx - 1], bstart[row + bx + 2], own.x, own.y, rl, o, lst,
+                              cnt, a);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        double acc[kDyn];
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
+        unsigned long long ncontact = 0;
+        float maxdisp = 0.0f;
+
+        for (int l = gt; l < n; l += G) {
+            const uint4 pl = P[l];
+            const float4 vv = V[l];
+            const uint32_t xl = pl.x, yl = pl.y;
+            const float rl = __uint_as_float(pl.z);
+            const float ul = vv.x, vl = vv.y, wl = vv.z;
+
+            // ---- ocean current and curl at the floe centre (angle addition around
+            // the cell centre keeps the FP32 arguments below (|kx| Lx + |ky| Ly) / 2),
+            // then drag and drag torque in FP64
+            const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
+            double fdx = 0.0, fdy = 0.0, tdr = 0.0;
+            if (!(a.flags & SP_OCEAN_OFF)) {
+                const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
+                const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
+                float uo = a.u0, vo = a.v0, zeta = 0.0f;
+                ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
+                const double du = (double)uo - uld, dv = (double)vo - vld;
+                const double sp = sqrt(du * du + dv * dv);
+                const double alpha = a.cdrho * kPi * rld * rld;
+                fdx = alpha * du * sp;
+                fdy = alpha * dv * sp;
+                const double dW = 0.5 * (double)zeta - wld;
+                const double r2 = rld * rld;
+                const double beta = a.cdrho * kPi * r2 * r2 * rld;
+                tdr = beta * dW * fabs(dW);
+            }
+            const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
+
+            uint16_t* my = lst + (size_t)l * kListCap;
+            int k;
+            if (build) {
+                k = cnt[l];
+                if (k > kListCap) {
+                    atomicOr(a.err, kErrCapacity);
+                    k = kListCap;
+                }
+                if (SCHED == 2) {
+                    // ascending partner order: insertion sort of the short list
+                    for (int i = 1; i < k; ++i) {
+                        const uint16_t key = my[i];
+                        int j = i - 1;
+                        while (j >= 0 && my[j] > key) {
+                            my[j + 1] = my[j];
+                            --j;
+                        }
+                        my[j + 1] = key;
+                    }
+                }
+                // keep the list for the steps until the next rebuild
+                for (int q = 0; q < k; ++q) vlst[(size_t)(q & ~7) * n + (size_t)l * 8 + (q & 7)] = my[q];
+                a.vcount[s + l] = (uint8_t)k;
+            } else {
+                k = cnt[l];   // staged with the floe state
+            }
+
+            // ---- contact decisions: every candidate, eight indices per LDS read;
+            // the contacts become a bit mask over the (ascending) list
+            uint32_t cmask = 0;
+            for (int q0 = 0; q0 < k; q0 += 8) {
+                const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
+                const int qe = min(8, k - q0);
+                for (int t = 0; t < qe; ++t) {
+                    const uint32_t wv = t < 2 ? ix.x : t < 4 ? ix.y : t < 6 ? ix.z : ix.w;
+                    const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
+                    if (j == l) continue;
+                    const uint4 pj = P[j];
+                    if (decide((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a))
+                        cmask |= 1u << (q0 + t);
+                }
+            }
+
+            // ---- contact forces and torques in ascending partner order (FP64);
+            // a wave runs as many rounds as its lanes have contacts at most
+            double Fx = fdx, Fy = fdy, T = tdr;
+            while (cmask) {
+                const int q = __builtin_ctz(cmask);
+                cmask &= cmask - 1u;
+                const int j = my[q];
+                const uint4 pj = P[j];
+                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
+                const float rj = __uint_as_float(pj.z);
+                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
+                const double d2 = dx * dx + dy * dy;
+                if (!(d2 > 0.0)) {
+                    atomicOr(a.err, kErrOverlap);
+                    continue;
+                }
+                const double rjd = (double)rj;
+                const double d = sqrt(d2);
+                const double inv_d = 1.0 / d;
+                const double nx = dx * inv_d, ny = dy * inv_d;
+                const double tx = -ny, ty = nx;
+                const double R = rld + rjd;
+                const double delta = d - R;
+                const double dr = fabs(rld - rjd);
+                double cc;
+                if (d <= dr) {
+                    cc = 2.0 * fmin(rld, rjd);
+                } else {
+                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
+                    cc = sqrt(fmax(p, 0.0)) * inv_d;
+                }
+                const double Fn = cc * a.Ed * delta;
+                const float4 vj = V[j];
+                const double wjd = (double)vj.z;
+                // spin sum in a fixed operand order (lower floe index first) so that
+                // the pair forces are exactly antisymmetric
+                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
+                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
+                const double capf = a.mud * fabs(Fn);
+                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+                Fx += Fn * nx + Ft * tx;
+                Fy += Fn * ny + Ft * ty;
+                T += rld * Ft;
+                ncontact += (l < j) ? 1ull : 0ull;
+            }
+
+            // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
+            // FP32 / fixed-point storage
+            const double inv_m = 1.0 / md;
+            const double dt = a.dtd;
+            const double und = uld + dt * (Fx * inv_m);
+            const double vnd = vld + dt * (Fy * inv_m);
+            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
+            const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
+            const int sx = __double2int_rn(dt * ux * a.inv_qxd);
+            const int sy = __double2int_rn(dt * vx * a.inv_qyd);
+            {
+                const float ddx = (float)sx * a.qx, ddy = (float)sy * a.qy;
+                maxdisp = fmaxf(maxdisp, sqrtf(ddx * ddx + ddy * ddy));
+            }
+            const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
+            a.xi[s + l] = xl + (uint32_t)sx;
+            a.yi[s + l] = yl + (uint32_t)sy;
+            a.u[s + l] = un;
+            a.v[s + l] = vn;
+            a.w[s + l] = wn;
+            a.th[s + l] = (float)((double)__uint_as_float(pl.w) + dt * wx);
+            if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
+
+            // ---- statistics of the pre-step state (FP64)
+            acc[0] += md * uld;
+            acc[1] += md * vld;
+            acc[2] += md * rld * rld * wld;
+            acc[3] += uld;
+            acc[4] += vld;
+            acc[5] += fdx;
+            acc[6] += fdy;
+            acc[7] += tdr;
+        }
+
+        // ---- group reduction through LDS: lane partials -> 16 segment sums per
+        // quantity -> DPP row sum (fixed order, deterministic)
+        const unsigned long long cs = wave_sum_u64(ncontact);
+        const float wd = wave_max_f32(maxdisp);
+        if ((tid & 63) == 0) {
+            csum[tid >> 6] = cs;
+            wdisp[tid >> 6] = wd;
+        }
+        __syncthreads();   // every lane is done with the cell's LDS data
+        if (valid && gt == 0) {
+            float d = 0.0f;
+            for (int q = 0; q < W; ++q) d = fmaxf(d, wdisp[g * W + q]);
+            // the bound grows by the largest displacement of this step (rounded up)
+            a.vdisp[c] = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
+        }
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) red[k * G + gt] = acc[k];
+        if (gt < kLfOps) lfops[g][gt] = lfo;
+        __syncthreads();
+        constexpr int SEG = G / 16;                 // values per segment
+        for (int kq = gt >> 4; kq < kDyn; kq += G / 16) {
+            // segment seg sums lanes seg, seg + 16, ... in order (neighbouring
+            // lanes read neighbouring words: no bank conflicts)
+            const int seg = gt & 15;
+            const double* src = red + kq * G + seg;
+            double x = 0.0;
+#pragma unroll
+            for (int i = 0; i < SEG; ++i) x += src[16 * i];
+            x = row_sum(x);
+            if (seg == 15 && valid) {
+                const int slot = dyn_slot(kq);
+                double* const mo = wk.w ? a.mom_alt : a.mom;
+                mo[(size_t)c * kMomStride + slot] = x;
+                if (slot == M_UX || slot == M_UY)   // continuum coefficient <v> = U / n
+                    mo[(size_t)c * kMomStride + (slot == M_UX ? M_UBAR : M_VBAR)] =
+                        n > 0 ? x / (double)n : 0.0;
+            }
+        }
+        if (valid && gt == 0) {
+            // per-cell running count, written by the cell's own group only (one
+            // shared counter would serialise every workgroup on one address)
+            unsigned long long t = 0;
+            for (int q = 0; q < W; ++q) t += csum[g * W + q];
+            a.contacts[c] = ccell + t;
+        }
+        // continuum update of the previous level for this cell (operands loaded
+        // at the start of the cell)
+        if (valid && a.lf && gt == G - 1)
+            lf_from_ops(c, lfops[g], a.Qn, a.nx * a.ny, a.dtd, a.dX, a.dY, a.inv_area, a.max_cfl_bits, a.err);
         if (!PERSIST) break;
         __syncthreads();   // the cell's LDS data is free
     }

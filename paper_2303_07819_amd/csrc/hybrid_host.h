@@ -184,13 +184,15 @@ struct HybridState {
     std::vector<uint8_t> closure;        // cells flagged for the closure
     std::vector<int32_t> fallback_left;  // > 0: a flagged cell runs the DEM for that many more steps
     std::vector<int32_t> fallback_cells; // cells with fallback_left > 0
-    std::vector<int64_t> frozen_at;      // step up to which a closure-mode cell's floes are advanced
+    std::vector<uint8_t> pool;           // closure cells the checks draw from; their floes keep stepping
+    std::vector<int32_t> pool_h;         // the same cells in check order
     std::vector<double> red_t0;          // start time of each cell's reduced DEM (host copy)
     int check_every = 50, check_cells = 64, fallback_steps = 100;
     double tol = 0.2;
     double net_window = 0.0;              // seconds after a reduced DEM's start the network acts (<= 0: always)
     int64_t checks = 0, fallbacks = 0, cursor = 0, hsteps = 0;
-    Bucket bk[kNumBuckets];               // DEM-mode cells only
+    Bucket bk[kNumBuckets];               // DEM-mode cells, and the pool's closure-mode cells (shadow DEM:
+                                          // their statistics go to scratch)
     std::vector<int32_t> clos_h;          // closure-mode cells
     int32_t* clos_d = nullptr;
     int32_t* row_d = nullptr;             // [ncells] row of a closure-mode cell in X and T, else -1
@@ -226,12 +228,13 @@ void hybrid_free_buffers(HybridState* h)
 sp_status hybrid_rebuild(sp_ctx* c)
 {
     HybridState* h = c->hyb;
-    std::vector<uint8_t> dem(c->ncells);
+    std::vector<uint8_t> step(c->ncells), shadow(c->ncells);
     std::vector<int32_t> row(c->ncells, -1);
     h->clos_h.clear();
     for (int i = 0; i < c->ncells; ++i) {
         const bool clos = h->closure[i] && h->fallback_left[i] == 0;
-        dem[i] = clos ? 0 : 1;
+        shadow[i] = clos && h->pool[i];
+        step[i] = !clos || shadow[i];
         if (clos) {
             row[i] = (int32_t)h->clos_h.size();
             h->clos_h.push_back(i);
@@ -239,7 +242,7 @@ sp_status hybrid_rebuild(sp_ctx* c)
     }
     h->ndem = c->ncells - (int)h->clos_h.size();
     HIP_TRY(c, hipStreamSynchronize(c->stream));   // queued work may still read the buffers replaced below
-    SP_TRY(build_buckets_into(c, h->bk, c->counts_h.data(), dem.data()));
+    SP_TRY(build_buckets_into(c, h->bk, c->counts_h.data(), step.data(), shadow.data()));
     for (auto& b : h->bk)
         if (!b.cells_h.empty()) SP_TRY(prepare_bucket(c, b));
     const size_t nclos = std::max<size_t>(1, h->clos_h.size());
@@ -298,70 +301,26 @@ sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* 
     return SP_OK;
 }
 
-// Advance the floes of the listed closure cells (host list), frozen since
-// they entered closure mode, by the DEM steps they missed, up to the current
-// step; their statistics of each step land in mom2 only.  Cells frozen at the
-// same step are advanced together, joined by the later ones as their time
-// comes.  The floes then equal those of the plain method: cells do not
-// interact in the DEM.
-sp_status catch_up(sp_ctx* c, const std::vector<int32_t>& cells, double dt)
-{
-    HybridState* h = c->hyb;
-    std::vector<uint8_t> include(c->ncells, 0);
-    std::vector<int32_t> nsub(c->ncells, 0);
-    bool any = false;
-    for (int32_t cell : cells) {
-        include[cell] = 1;
-        nsub[cell] = (int32_t)(c->kstep - h->frozen_at[cell]);
-        any = any || nsub[cell] > 0;
-    }
-    sp_status st = SP_OK;
-    if (any) {
-        // one multi-step launch per count bucket: each cell runs its own number
-        // of steps inside the launch (cells are independent DEMs)
-        Bucket tmp[kNumBuckets];
-        for (int q = 0; q < kNumBuckets; ++q) tmp[q].waves = c->bk[q].waves;
-        StepArgs base = make_args(c, dt);
-        base.mom = c->mom2;
-        base.lf = 0;
-        st = build_buckets_into(c, tmp, c->counts_h.data(), include.data(), nsub.data());
-        for (auto& b : tmp) {
-            if (st || b.cells_h.empty()) continue;
-            const size_t gb = bucket_group_bytes(c, b);
-            const int threads = 64 * b.waves;
-            st = prepare_multi_sel(c, c->sched, b.waves, threads, gb);
-            StepArgs a = base;
-            a.work = b.work_d;
-            a.ncl = (int32_t)b.cells_h.size();
-            a.cap = b.cap;
-            a.group_bytes = (int32_t)gb;
-            if (!st) st = launch_multi_sel(c, c->sched, b.waves, a, a.ncl, threads, gb);
-        }
-        (void)hipStreamSynchronize(c->stream);   // the temporary work lists are freed below
-        for (auto& b : tmp)
-            if (b.work_d) (void)hipFree(b.work_d);
-    }
-    if (st) return st;
-    for (int32_t cell : cells) h->frozen_at[cell] = c->kstep;
-    return SP_OK;
-}
-
-// Check a rotating sample of closure cells after a step (Q at level kstep):
-// their floes catch up with the DEM, their true statistics give the plain
-// method's residual tendency, and a cell whose closure misses it by more than
-// tol of its state (projected over one check period) falls back to the DEM.
-// Every checked cell's reduced DEM then restarts from its true floes.
+// Check the next check_cells closure-mode cells of the pool after a step (Q
+// at level kstep): the pool's floes have kept stepping with the DEM, so they
+// are the plain method's floes; their statistics give the plain method's
+// residual tendency, and a cell whose closure misses it by more than tol of
+// its state (projected over one check period) falls back to the DEM.  Every
+// checked cell's reduced DEM then restarts from its floes.
 sp_status hybrid_check(sp_ctx* c, double dt)
 {
     HybridState* h = c->hyb;
-    const int nclos = (int)h->clos_h.size();
-    if (nclos == 0 || h->check_cells <= 0) return SP_OK;
-    const int nk = std::min(h->check_cells, nclos);
-    std::vector<int32_t> pick(nk);
-    for (int i = 0; i < nk; ++i) pick[i] = h->clos_h[(size_t)((h->cursor + i) % nclos)];
-    h->cursor = (h->cursor + nk) % nclos;
-    // 1. the sampled cells' floes to the current step
-    SP_TRY(catch_up(c, pick, dt));
+    const int npool = (int)h->pool_h.size();
+    if (npool == 0 || h->check_cells <= 0) return SP_OK;
+    std::vector<int32_t> pick;   // round robin over the pool; cells in fallback run the DEM anyway
+    for (int scanned = 0; scanned < npool && (int)pick.size() < h->check_cells; ++scanned) {
+        const int32_t cell = h->pool_h[(size_t)h->cursor];
+        h->cursor = (h->cursor + 1) % npool;
+        if (h->fallback_left[cell] == 0) pick.push_back(cell);
+    }
+    const int nk = (int)pick.size();
+    if (nk == 0) return SP_OK;
+    // 1. the sampled cells' current floes
     HIP_TRY(c, hipMemcpyAsync(h->chk_d, pick.data(), (size_t)nk * 4, hipMemcpyHostToDevice, c->stream));
     // 2. their statistics and the plain method's residual tendency; the
     //    neighbours' coefficients are those of the step just taken
@@ -503,7 +462,21 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     for (int i = 0; i < c->ncells; ++i)   // a cell without floes has no DEM work: the plain update is exact
         if (c->counts_h[i] == 0) h->closure[i] = 0;
     h->fallback_left.assign(c->ncells, 0);
-    h->frozen_at.assign(c->ncells, c->kstep);
+    // the check pool: up to 4 check_cells closure cells spread evenly over the
+    // closure cells; they keep running the DEM (shadow), so a check compares
+    // against the plain method's current floes and a fallback starts from them
+    {
+        std::vector<int32_t> clos;
+        for (int i = 0; i < c->ncells; ++i)
+            if (h->closure[i]) clos.push_back(i);
+        const size_t np = std::min(clos.size(), (size_t)4 * (size_t)std::max(0, check_cells));
+        h->pool.assign(c->ncells, 0);
+        for (size_t i = 0; i < np; ++i) {
+            const int32_t cell = clos[i * clos.size() / np];
+            h->pool[cell] = 1;
+            h->pool_h.push_back(cell);
+        }
+    }
     h->check_every = check_every;
     h->check_cells = check_cells;
     h->tol = tol;
@@ -544,7 +517,8 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     SP_TRY(upload_phase(c));
     SP_TRY(flush_lf(c));
     if (nsteps == 0) return SP_OK;
-    const StepArgs base = make_args(c, dt);
+    StepArgs base = make_args(c, dt);
+    base.mom_alt = c->mom2;
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
     for (int64_t it = 0; it < nsteps; ++it) {
         const int64_t k = c->kstep;
@@ -564,7 +538,8 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
                                nclos, ca, c->momb[k & 1]);
             HIP_TRY(c, hipGetLastError());
         }
-        // DEM step of the other cells (statistics of level k)
+        // DEM step of the other cells (statistics of level k), and of the check
+        // pool's closure cells (statistics into scratch: the closure drives them)
         for (auto& b : h->bk) SP_TRY(launch_bucket(c, b, base, k, false));
         hipLaunchKernelGGL(hybrid_continuum_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream,
                            c->momb[k & 1], c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->red, c->t_now,
@@ -591,10 +566,7 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
         if (!back.empty()) {
             HIP_TRY(c, hipMemcpyAsync(h->back_d, back.data(), back.size() * 4, hipMemcpyHostToDevice, c->stream));
             SP_TRY(restart_reduced(c, h->back_d, (int)back.size(), nullptr));
-            for (int32_t cell : back) {
-                h->frozen_at[cell] = c->kstep;
-                h->red_t0[cell] = c->t_now;
-            }
+            for (int32_t cell : back) h->red_t0[cell] = c->t_now;
             SP_TRY(hybrid_rebuild(c));   // synchronises: `back` may go
         }
         if (h->hsteps % h->check_every == 0) SP_TRY(hybrid_check(c, dt));

@@ -339,19 +339,19 @@ sp_status check_device_err(sp_ctx* c)
 }
 
 // --------------------------------------------------------- kernel launches
-template <int SCHED, int W, bool PERSIST, bool MULTI = false>
+template <int SCHED, int W, bool PERSIST>
 sp_status launch_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds)
 {
-    hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST, MULTI>), dim3(grid), dim3(threads), lds, c->stream, a);
+    hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST>), dim3(grid), dim3(threads), lds, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
-template <int SCHED, int W, bool PERSIST, bool MULTI = false>
+template <int SCHED, int W, bool PERSIST>
 sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int* resident)
 {
     const int BT = threads;
-    const void* k = (const void*)dem_step_kernel<SCHED, W, PERSIST, MULTI>;
+    const void* k = (const void*)dem_step_kernel<SCHED, W, PERSIST>;
     if (lds > 65536) HIP_TRY(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BT, lds));
@@ -384,30 +384,6 @@ sp_status launch_sel(sp_ctx* c, int sched, int waves, int persist, const StepArg
                      size_t lds)
 {
     SP_DISPATCH(launch_t, c, a, grid, threads, lds)
-}
-
-// Multi-step variants (one group per workgroup, grid order).
-#define SP_DISPATCH_MULTI(FN, ...)                                                            \
-    switch ((sched == SP_SCHED_BINNED ? 100 : 0) + waves) {                                    \
-    case 1: return FN<1, 1, false, true>(__VA_ARGS__);                                         \
-    case 2: return FN<1, 2, false, true>(__VA_ARGS__);                                         \
-    case 4: return FN<1, 4, false, true>(__VA_ARGS__);                                         \
-    case 8: return FN<1, 8, false, true>(__VA_ARGS__);                                         \
-    case 101: return FN<2, 1, false, true>(__VA_ARGS__);                                       \
-    case 102: return FN<2, 2, false, true>(__VA_ARGS__);                                       \
-    case 104: return FN<2, 4, false, true>(__VA_ARGS__);                                       \
-    case 108: return FN<2, 8, false, true>(__VA_ARGS__);                                       \
-    default: return fail(c, SP_EINVAL, "no kernel for waves=%d", waves);                      \
-    }
-
-sp_status launch_multi_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, int grid, int threads, size_t lds)
-{
-    SP_DISPATCH_MULTI(launch_t, c, a, grid, threads, lds)
-}
-
-sp_status prepare_multi_sel(sp_ctx* c, int sched, int waves, int threads, size_t lds)
-{
-    SP_DISPATCH_MULTI(prepare_t, c, threads, lds, nullptr)
 }
 
 sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads, size_t lds, int* resident)
@@ -490,10 +466,9 @@ sp_status prepare_buckets(sp_ctx* c)
 }
 
 // Count buckets over the cells with include[cell] != 0 (all cells if null).
-// substeps (per cell, may be null) goes to each work entry's fourth field (the
-// step count of the multi-step kernels).
+// alt (per cell, may be null): 1 sends a cell's statistics to mom_alt.
 sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const uint8_t* include,
-                             const int32_t* substeps = nullptr)
+                             const uint8_t* alt = nullptr)
 {
     for (int q = 0; q < kNumBuckets; ++q) bk[q].cells_h.clear();
     std::vector<int32_t> order;
@@ -514,7 +489,7 @@ sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const
         std::vector<int4> work(b.cells_h.size());
         for (size_t i = 0; i < work.size(); ++i) {
             const int32_t cell = b.cells_h[i];
-            work[i] = make_int4(cell, c->start_h[cell], counts[cell], substeps ? substeps[cell] : 0);
+            work[i] = make_int4(cell, c->start_h[cell], counts[cell], alt ? (int)alt[cell] : 0);
         }
         SP_TRY(dalloc(c, &b.work_d, std::max<size_t>(1, work.size())));
         if (!work.empty())
