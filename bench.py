@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-hybrid", action="store_true",
                     help="skip training the closure and the DEM + closure run on the 512 x 512 grid")
     ap.add_argument("--hybrid-steps", type=int, default=2000)
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the autotuned run of the uneven 128 x 128 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--closure-probe", action="store_true",
@@ -178,12 +180,45 @@ def main():
         "contacts_per_floe_step": contacts_per_floe_step,
         "wall_s_timed": wall,
     }
+    if not args.no_uneven:
+        out["uneven"] = uneven_leg(stream)
     if not args.no_hybrid:
         out["hybrid"] = hybrid_leg(args, stream)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def uneven_leg(stream, steps=500, warmup=20):
+    """The uneven 128 x 128 workload (Poisson counts, 0 to about 700 floes per
+    cell): default batching, then the autotuner's choice, each over graph-replayed
+    steps timed with HIP events."""
+    import torch
+    import fixtures
+    import paper_2303_07819_amd as sp
+    w = fixtures.make_config("uneven128")
+
+    def timed(sim):
+        sim.step(w.dt, warmup)
+        sim.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(w.dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        ms_default = timed(sim)
+        cells, waves0, _ = sim.batching()
+        sim.autotune(w.dt)
+        ms_tuned = timed(sim)
+        _, waves, persist = sim.batching()
+    return {"workload": "uneven128", "cells": [w.nx, w.ny], "floes": w.nfloes, "steps": steps,
+            "bucket_cells": cells.tolist(), "default_waves": waves0.tolist(), "default_ms_per_step": ms_default,
+            "tuned_waves": waves.tolist(), "tuned_persistent": persist.tolist(), "tuned_ms_per_step": ms_tuned,
+            "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}
 
 
 def training_rate(hist):

@@ -423,7 +423,9 @@ __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* 
 // ------------------------------------------------------------- DEM step
 // SCHED: 1 all pairs, 2 binned half shell.  W: wavefronts per cell.
 // PERSIST: a grid of resident workgroups strides over the work list.
-template <int SCHED, int W, bool PERSIST>
+// ONE: no cell has more floes than the group has lanes (one floe per lane:
+// the floe loop carries nothing, which frees registers for occupancy).
+template <int SCHED, int W, bool PERSIST, bool ONE>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArgs a)
 {
     constexpr int G = 64 * W;                  // threads per group
@@ -592,6 +594,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         float maxdisp = 0.0f;
 
         for (int l = gt; l < n; l += G) {
+            if (ONE && l >= G) break;   // not reached: the launch guarantees n <= G
             const uint4 pl = P[l];
             const float4 vv = V[l];
             const uint32_t xl = pl.x, yl = pl.y;

@@ -342,16 +342,20 @@ sp_status check_device_err(sp_ctx* c)
 template <int SCHED, int W, bool PERSIST>
 sp_status launch_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds)
 {
-    hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST>), dim3(grid), dim3(threads), lds, c->stream, a);
+    if (a.cap <= 64 * W)   // one floe per lane
+        hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST, true>), dim3(grid), dim3(threads), lds, c->stream, a);
+    else
+        hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST, false>), dim3(grid), dim3(threads), lds, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
 template <int SCHED, int W, bool PERSIST>
-sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int* resident)
+sp_status prepare_t(sp_ctx* c, int threads, size_t lds, int cap, int* resident)
 {
     const int BT = threads;
-    const void* k = (const void*)dem_step_kernel<SCHED, W, PERSIST>;
+    const void* k = cap <= 64 * W ? (const void*)dem_step_kernel<SCHED, W, PERSIST, true>
+                                  : (const void*)dem_step_kernel<SCHED, W, PERSIST, false>;
     if (lds > 65536) HIP_TRY(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BT, lds));
@@ -386,9 +390,10 @@ sp_status launch_sel(sp_ctx* c, int sched, int waves, int persist, const StepArg
     SP_DISPATCH(launch_t, c, a, grid, threads, lds)
 }
 
-sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads, size_t lds, int* resident)
+sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads, size_t lds, int cap,
+                      int* resident)
 {
-    SP_DISPATCH(prepare_t, c, threads, lds, resident)
+    SP_DISPATCH(prepare_t, c, threads, lds, cap, resident)
 }
 
 size_t bucket_group_bytes(const sp_ctx* c, const Bucket& b)
@@ -404,7 +409,7 @@ int bucket_threads(const sp_ctx* c, const Bucket& b) { return bucket_gpb(c, b) *
 
 sp_status prepare_bucket(sp_ctx* c, Bucket& b)
 {
-    return prepare_sel(c, c->sched, b.waves, b.persist, bucket_threads(c, b), bucket_lds(c, b), &b.resident);
+    return prepare_sel(c, c->sched, b.waves, b.persist, bucket_threads(c, b), bucket_lds(c, b), b.cap, &b.resident);
 }
 
 // One DEM launch for bucket b at time level k (writes the statistics of level
