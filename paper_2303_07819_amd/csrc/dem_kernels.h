@@ -454,9 +454,12 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy: xi, yi, r bits, index | bin << 16
     uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));  // [cap][kListCap]
     int* cnt = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
-    int* binof = cnt + cap;
-    int* rank = binof + (SCHED == 2 ? cap : 0);
-    int* bcnt = rank + (SCHED == 2 ? cap : 0);
+    // sort scratch of the binned schedule, inside the list region: a group that
+    // rebuilds its lists fills them only after the sort
+    static_assert(2 * sizeof(int) <= kListCap * sizeof(uint16_t), "sort scratch fits the list region");
+    int* binof = reinterpret_cast<int*>(lst);
+    int* rank = binof + cap;
+    int* bcnt = cnt + cap;
     int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
     double* red = reinterpret_cast<double*>(gsm);             // [kDyn][G], after the floes are done
 

@@ -211,7 +211,7 @@ void free_all(sp_ctx* c)
 size_t group_bytes(int sched, int cap, int nb, int waves)
 {
     size_t b = (size_t)cap * (16 + 16 + 2 * kListCap + 4);
-    if (sched == SP_SCHED_BINNED) b += (size_t)cap * (16 + 4 + 4) + (size_t)(2 * nb + 1) * 4;
+    if (sched == SP_SCHED_BINNED) b += (size_t)cap * 16 + (size_t)(2 * nb + 1) * 4;   // sorted copy, bins
     b = std::max(b, (size_t)kDyn * 64 * waves * sizeof(double));   // reduction buffer
     return (b + 15) & ~(size_t)15;
 }
