@@ -145,9 +145,20 @@ struct ClosureArgs {
     int nx, ny;
     double dX, dY;
     double t;       // time of the pre-step state
+    const double* rs;   // [ncells][5] reduced_stats of every cell at t, or null: computed where needed
 };
 
 // The base update of cell C (lf_cell with the reduced DEM statistics of every cell).
+__device__ __forceinline__ void cell_rstats(int C, const ClosureArgs& a, double out[5])
+{
+    if (a.rs) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) out[k] = a.rs[(size_t)C * 5 + k];
+    } else {
+        reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, out);
+    }
+}
+
 __device__ __forceinline__ void base_cell(int C, const double* Q, const ClosureArgs& a, double dT, double out[4])
 {
     const int nx = a.nx, ny = a.ny, nc = nx * ny;
@@ -157,11 +168,11 @@ __device__ __forceinline__ void base_cell(int C, const double* Q, const ClosureA
     const int N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
     const int S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
     double sC[5], sE[5], sW[5], sN[5], sS[5];
-    reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sC);
-    reduced_stats(E, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sE);
-    reduced_stats(W, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sW);
-    reduced_stats(N, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sN);
-    reduced_stats(S, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, sS);
+    cell_rstats(C, a, sC);
+    cell_rstats(E, a, sE);
+    cell_rstats(W, a, sW);
+    cell_rstats(N, a, sN);
+    cell_rstats(S, a, sS);
     const double cx = dT / (2.0 * a.dX), cy = dT / (2.0 * a.dY);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -177,6 +188,17 @@ __device__ __forceinline__ void base_cell(int C, const double* Q, const ClosureA
 }
 
 // Base-updated state of every cell: Qb [4][nc].
+// The reduced DEM statistics of every cell at a.t (a.rs must be null).
+__global__ void reduced_stats_kernel(ClosureArgs a, double* rs)
+{
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= a.nx * a.ny) return;
+    double o[5];
+    reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, o);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) rs[(size_t)C * 5 + k] = o[k];
+}
+
 __global__ void base_kernel(const double* Q, double* Qb, ClosureArgs a, double dT)
 {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,7 +241,7 @@ __global__ void reduced_coeff_kernel(const int32_t* cells, int ncl, ClosureArgs 
     if (i >= ncl) return;
     const int c = cells[i];
     double st[5];
-    reduced_stats(c, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, st);
+    cell_rstats(c, a, st);
     mom[(size_t)c * kMomStride + M_UBAR] = st[0];
     mom[(size_t)c * kMomStride + M_VBAR] = st[1];
 }
@@ -258,12 +280,18 @@ __device__ __forceinline__ void cell_features(int c, const double* Q, const Clos
 
 // Features of every cell (cells == null) or of the listed cells into
 // consecutive rows of x.
-__global__ void features_kernel(const int32_t* cells, int ncl, const double* Q, ClosureArgs a, const float* desc,
-                                float* x)
+// One row per thread (blocks of at most 128 threads): the rows are built in
+// LDS and the block's contiguous span of x is written coalesced.
+__global__ __launch_bounds__(128) void features_kernel(const int32_t* cells, int ncl, const double* Q, ClosureArgs a,
+                                                       const float* desc, float* x)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    cell_features(cells ? cells[i] : i, Q, a, desc, x + (size_t)i * spmlp::kIn);
+    __shared__ float tile[128 * spmlp::kIn];
+    const int i0 = blockIdx.x * blockDim.x;
+    const int i = i0 + threadIdx.x;
+    if (i < ncl) cell_features(cells ? cells[i] : i, Q, a, desc, tile + threadIdx.x * spmlp::kIn);
+    __syncthreads();
+    const int rows = min((int)blockDim.x, ncl - i0);
+    for (int e = threadIdx.x; e < rows * spmlp::kIn; e += blockDim.x) x[(size_t)i0 * spmlp::kIn + e] = tile[e];
 }
 
 // (Q_now - Q_ref) / dt per cell, [nc][4] FP32.

@@ -203,6 +203,7 @@ struct HybridState {
     float* Tk = nullptr;
     float* Tdem = nullptr;
     double* Qs = nullptr;                 // base-updated continuum state [4][ncells]
+    double* rs = nullptr;                 // reduced DEM statistics of every cell at the step's time [ncells][5]
     int32_t* back_d = nullptr;            // cells whose fallback window ended [ncells]
     int ndem = 0;
 };
@@ -216,12 +217,13 @@ void hybrid_free_buffers(HybridState* h)
         b.work_d = nullptr;
     }
     void* ps[] = {h->clos_d, h->row_d, h->X, h->T, h->chk_d, h->Xk, h->Tk, h->Tdem, h->Qs,
-                  h->back_d};
+                  h->back_d, h->rs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     h->clos_d = h->row_d = h->chk_d = h->back_d = nullptr;
     h->X = h->T = h->Xk = h->Tk = h->Tdem = nullptr;
     h->Qs = nullptr;
+    h->rs = nullptr;
 }
 
 // Rebuild the DEM buckets and the closure list from the current modes.
@@ -245,10 +247,12 @@ sp_status hybrid_rebuild(sp_ctx* c)
     SP_TRY(build_buckets_into(c, h->bk, c->counts_h.data(), step.data(), shadow.data()));
     for (auto& b : h->bk)
         if (!b.cells_h.empty()) SP_TRY(prepare_bucket(c, b));
-    const size_t nclos = std::max<size_t>(1, h->clos_h.size());
-    SP_TRY(dalloc(c, &h->clos_d, nclos));
-    SP_TRY(dalloc(c, &h->X, nclos * spmlp::kIn));
-    SP_TRY(dalloc(c, &h->T, nclos * spmlp::kOut));
+    if (!h->clos_d) {   // sized for every cell once: modes change without reallocation
+        const size_t nc = (size_t)c->ncells;
+        SP_TRY(dalloc(c, &h->clos_d, nc));
+        SP_TRY(dalloc(c, &h->X, nc * spmlp::kIn));
+        SP_TRY(dalloc(c, &h->T, nc * spmlp::kOut));
+    }
     if (!h->clos_h.empty())
         HIP_TRY(c, hipMemcpyAsync(h->clos_d, h->clos_h.data(), h->clos_h.size() * 4, hipMemcpyHostToDevice,
                                   c->stream));
@@ -493,6 +497,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     SP_TRY(dalloc(c, &h->Tk, nk * spmlp::kOut));
     SP_TRY(dalloc(c, &h->Tdem, nk * spmlp::kOut));
     SP_TRY(dalloc(c, &h->Qs, (size_t)c->ncells * 4));
+    SP_TRY(dalloc(c, &h->rs, (size_t)c->ncells * 5));
     SP_TRY(dalloc(c, &h->back_d, (size_t)c->ncells));
     SP_TRY(upload_phase(c));
     SP_TRY(ensure_cell_data(c));
@@ -526,7 +531,11 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
         if (nclos > 0) {
             // base-updated level-k state, the network's residual for its
             // features, the closure cells' coefficients from their reduced DEMs
-            const ClosureArgs ca = closure_args(c, c->t_now);
+            ClosureArgs ca = closure_args(c, c->t_now);
+            hipLaunchKernelGGL(reduced_stats_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, ca,
+                               h->rs);
+            HIP_TRY(c, hipGetLastError());
+            ca.rs = h->rs;   // every cell's reduced statistics once, read by the stencils below
             hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
                                h->Qs, ca, dt);
             HIP_TRY(c, hipGetLastError());

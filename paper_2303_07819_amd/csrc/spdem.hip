@@ -50,6 +50,7 @@ struct Bucket {
     int resident = 1;                   // workgroups resident at once (persistent grid size)
     std::vector<int32_t> cells_h;       // costliest first
     int4* work_d = nullptr;             // (cell, first floe, count, -) per entry of cells_h
+    size_t work_cap = 0;                // entries work_d holds
 };
 
 }  // namespace
@@ -77,6 +78,7 @@ struct sp_ctx {
     bool have_floes = false;
     std::vector<int32_t> start_h;
     std::vector<int32_t> counts_h;
+    std::vector<int32_t> order_h;       // cells by floe count, largest first (stable)
     Bucket bk[kNumBuckets];
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
     float skin = 0.0f;          // candidate-list skin (m)
@@ -470,38 +472,40 @@ sp_status prepare_buckets(sp_ctx* c)
     return SP_OK;
 }
 
-// Count buckets over the cells with include[cell] != 0 (all cells if null).
-// alt (per cell, may be null): 1 sends a cell's statistics to mom_alt.
+// Count buckets over the cells with include[cell] != 0 (all cells if null),
+// costliest first (the order fixed when the floes were set); counts must be
+// the context's counts.  alt (per cell, may be null): 1 sends a cell's
+// statistics to mom_alt.  Work lists keep their device buffers while they fit.
 sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const uint8_t* include,
                              const uint8_t* alt = nullptr)
 {
     for (int q = 0; q < kNumBuckets; ++q) bk[q].cells_h.clear();
-    std::vector<int32_t> order;
-    order.reserve(c->ncells);
-    for (int32_t cell = 0; cell < c->ncells; ++cell)
-        if (!include || include[cell]) order.push_back(cell);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return counts[x] > counts[y]; });
-    for (int32_t cell : order) {
+    for (int32_t cell : c->order_h) {
+        if (include && !include[cell]) continue;
         int q = 0;
         while (counts[cell] > kBucketHi[q]) ++q;
         bk[q].cells_h.push_back(cell);
     }
+    std::vector<int4> work[kNumBuckets];
     for (int q = 0; q < kNumBuckets; ++q) {
         Bucket& b = bk[q];
         int mx = 0;
         for (int32_t cell : b.cells_h) mx = std::max(mx, counts[cell]);
         b.cap = std::max(16, (mx + 15) / 16 * 16);
-        std::vector<int4> work(b.cells_h.size());
-        for (size_t i = 0; i < work.size(); ++i) {
+        work[q].resize(b.cells_h.size());
+        for (size_t i = 0; i < work[q].size(); ++i) {
             const int32_t cell = b.cells_h[i];
-            work[i] = make_int4(cell, c->start_h[cell], counts[cell], alt ? (int)alt[cell] : 0);
+            work[q][i] = make_int4(cell, c->start_h[cell], counts[cell], alt ? (int)alt[cell] : 0);
         }
-        SP_TRY(dalloc(c, &b.work_d, std::max<size_t>(1, work.size())));
-        if (!work.empty())
-            HIP_TRY(c, hipMemcpyAsync(b.work_d, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice,
-                                      c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));   // `work` is a host temporary
+        if (!b.work_d || work[q].size() > b.work_cap) {
+            b.work_cap = std::max<size_t>(1, work[q].size());
+            SP_TRY(dalloc(c, &b.work_d, b.work_cap));
+        }
+        if (!work[q].empty())
+            HIP_TRY(c, hipMemcpyAsync(b.work_d, work[q].data(), work[q].size() * sizeof(int4),
+                                      hipMemcpyHostToDevice, c->stream));
     }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));   // `work` is a host temporary
     return SP_OK;
 }
 
@@ -743,6 +747,10 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     c->start_h.assign((size_t)c->ncells + 1, 0);
     for (int i = 0; i < c->ncells; ++i) c->start_h[i + 1] = c->start_h[i] + counts[i];
     c->counts_h.assign(counts, counts + c->ncells);
+    c->order_h.resize(c->ncells);
+    for (int32_t i = 0; i < c->ncells; ++i) c->order_h[i] = i;
+    std::stable_sort(c->order_h.begin(), c->order_h.end(),
+                     [&](int32_t x, int32_t y) { return c->counts_h[x] > c->counts_h[y]; });
     c->r_bin = rmax;
     HIP_TRY(c, hipMemcpyAsync(c->cell_start, c->start_h.data(), ((size_t)c->ncells + 1) * 4,
                               hipMemcpyHostToDevice, c->stream));
