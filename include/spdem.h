@@ -163,8 +163,9 @@ sp_status sp_get_stats(sp_ctx* ctx, int64_t* contacts, int64_t* steps, double* m
  * with sp_step.  Synchronises. */
 sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_ms, double* lf_ms);
 
-/* Batching of cells with uneven floe counts.  Cells are grouped by count into
- * SP_NUM_BUCKETS buckets (<= 64, <= 128, <= 256, <= 512, <= 1024 floes); each
+/* Batching of cells with uneven floe counts.  Cells with floes are grouped by
+ * count into SP_NUM_BUCKETS buckets (<= 64, <= 128, <= 256, <= 512, <= 1024
+ * floes; cells without floes take only the continuum update); each
  * bucket is one launch per step over its cells, costliest first, with W
  * wavefronts per cell (W = 1, 2, 4 or 8: one wavefront per small cell up to a
  * tile of 8 wavefronts per large cell) and either one workgroup per cell group

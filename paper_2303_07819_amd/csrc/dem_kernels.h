@@ -883,6 +883,17 @@ __global__ __launch_bounds__(64) void lf_kernel(const double* mom, const double*
     if (C < nx * ny) lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
 }
 
+// The same update for the listed cells only (the cells without floes, which
+// stay out of the DEM launches).
+__global__ __launch_bounds__(64) void lf_list_kernel(const int32_t* cells, int ncl, const double* mom, const double* Q,
+                                                     double* Qn, int nx, int ny, double dT, double dX, double dY,
+                                                     double inv_area, unsigned long long* max_cfl_bits,
+                                                     uint32_t* err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncl) lf_cell(cells[i], mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
+}
+
 __global__ void q_from_moments_kernel(const double* mom, double* Q, int nc, double inv_area)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;

@@ -509,29 +509,6 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
         h->red_t0.resize(c->ncells);
         for (int i = 0; i < c->ncells; ++i) h->red_t0[i] = red[(size_t)i * 4 + 3];
     }
-    // cells without floes stay out of the DEM launches: their statistics rows
-    // (both time levels) hold the zeros of an empty cell
-    {
-        std::vector<int32_t> empty;
-        for (int i = 0; i < c->ncells; ++i)
-            if (c->counts_h[i] == 0) empty.push_back(i);
-        if (!empty.empty()) {
-            int32_t* ed = nullptr;
-            SP_TRY(dalloc(c, &ed, empty.size()));
-            sp_status st = SP_OK;
-            if (hipMemcpyAsync(ed, empty.data(), empty.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess)
-                st = SP_EDEVICE;
-            for (int q = 0; q < 2 && !st; ++q) {
-                StepArgs a = make_args(c, 0.0);
-                a.mom = c->momb[q];
-                hipLaunchKernelGGL(stats_kernel, dim3((unsigned)empty.size()), dim3(256), 0, c->stream, a, ed);
-                if (hipGetLastError() != hipSuccess) st = SP_EDEVICE;
-            }
-            (void)hipStreamSynchronize(c->stream);
-            (void)hipFree(ed);
-            if (st) return fail(c, st, "statistics of empty cells");
-        }
-    }
     drop_graph(c);
     return hybrid_rebuild(c);
 }

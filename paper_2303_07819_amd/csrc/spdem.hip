@@ -79,6 +79,8 @@ struct sp_ctx {
     std::vector<int32_t> start_h;
     std::vector<int32_t> counts_h;
     std::vector<int32_t> order_h;       // cells by floe count, largest first (stable)
+    int32_t* empty_d = nullptr;         // cells without floes: no DEM work, continuum update only
+    int nempty = 0;
     Bucket bk[kNumBuckets];
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
     float skin = 0.0f;          // candidate-list skin (m)
@@ -185,7 +187,7 @@ void free_all(sp_ctx* c)
     hybrid_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp};
+                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -207,6 +209,8 @@ void free_all(sp_ctx* c)
     c->vlist = nullptr;
     c->vcount = nullptr;
     c->vdisp = nullptr;
+    c->empty_d = nullptr;
+    c->nempty = 0;
 }
 
 // LDS bytes of one group (one cell) for a schedule, capacity and W.
@@ -439,10 +443,13 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
+sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k);
+
 sp_status step_once(sp_ctx* c, const StepArgs& base)
 {
     const bool lf = c->lf_pending;
     for (auto& b : c->bk) SP_TRY(launch_bucket(c, b, base, c->kstep, lf));
+    if (lf) SP_TRY(launch_empty_lf(c, base, c->kstep));
     c->kstep++;
     c->lf_pending = !(c->p.flags & SP_NO_CONTINUUM);
     c->lf_dt = base.dtd;
@@ -509,7 +516,34 @@ sp_status build_buckets_into(sp_ctx* c, Bucket* bk, const int32_t* counts, const
     return SP_OK;
 }
 
-sp_status build_buckets(sp_ctx* c, const int32_t* counts) { return build_buckets_into(c, c->bk, counts, nullptr); }
+// Buckets of the cells with floes, and the list of the others.
+sp_status build_buckets(sp_ctx* c, const int32_t* counts)
+{
+    std::vector<uint8_t> has(c->ncells);
+    std::vector<int32_t> empty;
+    for (int i = 0; i < c->ncells; ++i) {
+        has[i] = counts[i] > 0;
+        if (!has[i]) empty.push_back(i);
+    }
+    c->nempty = (int)empty.size();
+    SP_TRY(dalloc(c, &c->empty_d, std::max<size_t>(1, empty.size())));
+    if (!empty.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->empty_d, empty.data(), empty.size() * 4, hipMemcpyHostToDevice, c->stream));
+    SP_TRY(build_buckets_into(c, c->bk, counts, has.data()));   // synchronises
+    return SP_OK;
+}
+
+// The continuum update of level k - 1 for the cells without floes (the DEM
+// launches of step k do it for the others).
+sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k)
+{
+    if (c->nempty == 0) return SP_OK;
+    hipLaunchKernelGGL(lf_list_kernel, dim3((c->nempty + 63) / 64), dim3(64), 0, c->stream, c->empty_d, c->nempty,
+                       c->momb[(k + 1) & 1], c->Q[(k + 1) & 1], c->Q[k & 1], c->p.nx, c->p.ny, base.dtd,
+                       c->p.cell_lx, c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
 
 sp_status reset_continuum(sp_ctx* c)
 {
@@ -543,11 +577,13 @@ sp_status capture_graph(sp_ctx* c, double dt)
         return SP_OK;
     }
     sp_status st = SP_OK;
-    for (int i = 0; i < c->graph_chunk && !st; ++i)
+    for (int i = 0; i < c->graph_chunk && !st; ++i) {
         for (auto& b : c->bk) {
             st = launch_bucket(c, b, base, i, cont);
             if (st) break;
         }
+        if (!st && cont) st = launch_empty_lf(c, base, i);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st) {
