@@ -148,7 +148,7 @@ def main():
     ms_per_step = ms / args.steps
     value = w.nfloes * args.steps / (ms / 1e3)
 
-    # dominant kernel, timed live with events around each launch on the same stream
+    # dominant kernel, timed live with one event pair around back-to-back launches on its stream
     dem_ms, lf_ms = sim.profile_steps(w.dt, args.profile_steps)
     stats = sim.stats()
     bytes_launch = BYTES_PER_FLOE_STEP * w.nfloes + BYTES_PER_CELL_STEP * w.ncells

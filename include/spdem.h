@@ -156,11 +156,13 @@ sp_status sp_read_pairs(sp_ctx* ctx, int64_t cap, int32_t* l, int32_t* j, int64_
  * number seen.  Synchronises. */
 sp_status sp_get_stats(sp_ctx* ctx, int64_t* contacts, int64_t* steps, double* max_cfl);
 
-/* Run nsteps steps like sp_step (without graph replay), with HIP events
- * recorded on the context's stream around every step's DEM launches, and
- * return their mean duration (ms) in *dem_ms; *lf_ms is 0 because the
- * continuum update runs inside those launches.  The state advances exactly as
- * with sp_step.  Synchronises. */
+/* Run nsteps steps like sp_step but launched one by one (no graph replay),
+ * with one pair of HIP events recorded on the context's stream before the
+ * first and after the last step's launches, and return the mean duration of a
+ * step's DEM launches (ms) in *dem_ms: the elapsed time over nsteps, which
+ * holds the kernels and the short gaps between back-to-back launches.  *lf_ms
+ * is 0 because the continuum update runs inside those launches.  The state
+ * advances exactly as with sp_step.  Synchronises. */
 sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_ms, double* lf_ms);
 
 /* Batching of cells with uneven floe counts.  Cells with floes are grouped by
