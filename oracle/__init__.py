@@ -6,8 +6,10 @@ meet only in the seeded inputs of ``fixtures``.
 
 The DEM step, the cell statistics, the Lax-Friedrichs continuum update and the
 coarse-to-fine re-synchronisation are plain C in ``dem_oracle.c`` (FP64,
-compiled with gcc, no fused multiply-add); the closure network's reference
-(forward, backward, Adam) is numpy FP64 in ``mlp.py``.
+compiled with gcc, no fused multiply-add); ``run_plain`` and ``run_coupled``
+compose them into the plain path and the two-way coupling of Algorithm 1; the
+closure network's reference (forward, backward, Adam) is numpy FP64 in
+``mlp.py``.
 """
 from __future__ import annotations
 
@@ -214,4 +216,48 @@ def run_plain(w, nsteps: int, flags: int = 0, state: State | None = None, Q0=Non
     cfl = 0.0
     for k in range(nsteps):
         Q, cfl = lf_step(model, Q, mom[k], w.dt)
+    return st, Q, moments(model, st), cfl
+
+
+def run_coupled(w, nsteps: int, N0: int, N1: int, n_t: int, flags: int = 0, state: State | None = None):
+    """Two-way coupling of the coarse model and the cell DEMs (Algorithm 1;
+    coarse step Sec. 3.2, coarse-to-fine update Sec. 3.3).
+
+    The coarse state starts from the statistics of the initial floes.  Fine
+    step j (j = 1 .. nsteps) advances every cell DEM by dt and adds the
+    statistics of its pre-step state to the window's data.  When j is a
+    multiple of N0 the coarse model advances by dT = N0 dt in N1 Lax-Friedrichs
+    sub-steps of dT / N1, driven by the window's mean statistics, and the DEM
+    cell values (rho, P, P_w) of the state reached are kept as the start values
+    X0 of the next coarse step.  Otherwise, from the second coarse step on,
+    when r = j mod N0 is a multiple of n_t, every cell with floes is
+    re-synchronised to X0 + (r / N0) (Q - X0): the increments toward the latest
+    coarse solution Q grow in proportion to the elapsed part of the coarse step.
+    With N0 = N1 = 1 this is run_plain.  Returns (state, Q, moments of the final
+    state, largest CFL number)."""
+    if min(N0, N1, n_t) < 1:
+        raise ValueError("N0, N1 and n_t must be positive")
+    model = Model(w, flags)
+    st = State.from_workload(w) if state is None else state
+    Q = q_from_moments(model, moments(model, st))
+    counts = np.diff(model.start)
+    window = np.zeros((model.ncells, NMOM))
+    x0 = None
+    dT = N0 * w.dt
+    cfl = 0.0
+    for j in range(1, nsteps + 1):
+        mom, _ = dem_steps(model, st, w.dt, 1, record=True)
+        window += mom[0]
+        r = j % N0
+        if r == 0:
+            mean = window / N0
+            for _ in range(N1):
+                Q, c = lf_step(model, Q, mean, dT / N1)
+                cfl = max(cfl, c)
+            window[:] = 0.0
+            x0 = q_from_moments(model, moments(model, st))
+        elif j > N0 and r % n_t == 0:
+            f = r / N0
+            for cell in np.flatnonzero(counts):
+                resync_cell(model, st, int(cell), x0[cell] + f * (Q[cell] - x0[cell]))
     return st, Q, moments(model, st), cfl
