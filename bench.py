@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--hybrid-steps", type=int, default=2000)
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the autotuned run of the uneven 128 x 128 workload")
+    ap.add_argument("--no-coupled", action="store_true",
+                    help="skip the plain64 run under the two-way coupling (N0 = 100, n_t = 10)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--closure-probe", action="store_true",
@@ -182,6 +184,8 @@ def main():
     }
     if not args.no_uneven:
         out["uneven"] = uneven_leg(stream)
+    if not args.no_coupled:
+        out["coupled"] = coupled_leg(stream)
     if not args.no_hybrid:
         out["hybrid"] = hybrid_leg(args, stream)
     if not args.no_cpu_baseline:
@@ -219,6 +223,33 @@ def uneven_leg(stream, steps=500, warmup=20):
             "bucket_cells": cells.tolist(), "default_waves": waves0.tolist(), "default_ms_per_step": ms_default,
             "tuned_waves": waves.tolist(), "tuned_persistent": persist.tolist(), "tuned_ms_per_step": ms_tuned,
             "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}
+
+
+def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):
+    """plain64 under the two-way coupling at the paper's default cadence
+    (N0 = 100 fine steps per coarse step, gradual updates every n_t = 10):
+    the first coarse step untimed, then `windows` coarse steps timed with HIP
+    events (their fine steps, coarse steps and coarse-to-fine updates)."""
+    import torch
+    import fixtures
+    import paper_2303_07819_amd as sp
+    w = fixtures.make_config("plain64")
+    steps = windows * N0
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        sim.set_coupling(N0, N1, n_t)
+        sim.step(w.dt, N0)
+        sim.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(w.dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        cp = sim.coupling()
+        cfl = sim.stats()["max_cfl"]
+    return {"workload": "plain64", "N0": N0, "N1": N1, "n_t": n_t, "steps": steps, "ms_per_step": ms,
+            "floe_steps_per_s": w.nfloes / (ms * 1e-3), "nudge_passes": cp["nudges"],
+            "clamped_cell_updates": cp["clamped"], "invalid_cell_updates": cp["invalid"], "max_cfl": cfl}
 
 
 def training_rate(hist):

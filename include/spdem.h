@@ -129,9 +129,44 @@ sp_status sp_set_floes_device(sp_ctx* ctx, int64_t n, const int32_t* counts, con
 /* Advance nsteps fine steps of size dt (s): each step is one DEM step of every
  * cell fused with the statistics of the pre-step state, then (unless
  * SP_NO_CONTINUUM) one Lax-Friedrichs step of the continuum driven by those
- * statistics (coarse step = fine step, N0 = N1 = 1 in Algorithm 1).
+ * statistics (coarse step = fine step, N0 = N1 = 1 in Algorithm 1).  With a
+ * cadence N0 > 1 set by sp_set_coupling, the steps follow that cadence instead.
  * Asynchronous.  Errors: SP_EINVAL (dt <= 0, nsteps < 0), SP_ESTATE. */
 sp_status sp_step(sp_ctx* ctx, double dt, int64_t nsteps);
+
+/* Two-way coupling cadence of sp_step (Algorithm 1: coupling loop; Sec. 3.2
+ * coarse step; Sec. 3.3 gradual coarse-to-fine update).  The next sp_step call
+ * starts a new run of the algorithm at fine step j = 1 from the current floes
+ * and coarse state.  Fine step j advances every cell DEM and keeps the
+ * statistics of its pre-step state; at j = k N0 the coarse model advances by
+ * dT = N0 dt in N1 Lax-Friedrichs sub-steps of dT / N1, driven by the mean of
+ * the window's N0 statistics, and the DEM cell values X0 = (M, P_x, P_y, L) / A
+ * of the state reached are kept; from the second coarse step on, at fine steps
+ * whose r = j mod N0 is a nonzero multiple of n_t, every cell with floes is
+ * re-synchronised (radii scaled by one factor, then uniform velocity and spin
+ * shifts, as sp_resync_cells) to X0 + (r / N0) (Q - X0), Q the latest coarse
+ * state.  The contact search is planned for radii up to
+ * (1 + radius_headroom) x the largest current radius (at most a quarter of the
+ * cell); a cell whose radii would pass that is scaled up to it ("clamped"), a
+ * target with rho <= 0 leaves its cell unchanged ("invalid").  A larger
+ * headroom means larger sub-bins (costlier list rebuilds), never a different
+ * result for cells that are not clamped.  dt is the dt of each sp_step call; a coarse step uses N0 times
+ * the dt of the call that completes it.  N0 = N1 = n_t = 1 is the plain step.
+ * Between coarse steps SP_MOMENTS_CONTINUUM reads the latest coarse state.
+ * Cadence state lives in the context: ring of N0 x ncells x 128 B statistics.
+ * Errors: SP_EINVAL (a value < 1, N0 or N1 > SP_MAX_COUPLING, headroom < 0 or
+ * not finite), SP_ESTATE
+ * (N0 > 1 with SP_NO_CONTINUUM or an active hybrid), SP_ENOMEM at the first
+ * coupled sp_step.  sp_hybrid_set, sp_step_hybrid, sp_closure_sample and
+ * sp_profile_steps return SP_ESTATE while N0 > 1. */
+#define SP_MAX_COUPLING 65536
+sp_status sp_set_coupling(sp_ctx* ctx, int32_t N0, int32_t N1, int32_t n_t, double radius_headroom);
+
+/* The cadence, the coarse-to-fine update passes taken and the clamped and
+ * invalid cell updates counted since the last sp_set_coupling (or
+ * sp_set_floes).  Any pointer may be NULL.  Synchronises. */
+sp_status sp_get_coupling(sp_ctx* ctx, int32_t* N0, int32_t* N1, int32_t* n_t, int64_t* nudges,
+                          int64_t* clamped, int64_t* invalid);
 
 /* Block until the stream is idle; returns the first latched device fault. */
 sp_status sp_synchronize(sp_ctx* ctx);

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libspdem.so")
 SP_OCEAN_OFF = 1
 SP_FORWARD_EULER = 2
 SP_NO_CONTINUUM = 4
+SP_MAX_COUPLING = 65536
 SCHED_AUTO, SCHED_ALLPAIRS, SCHED_BINNED = 0, 1, 2
 MOMENTS_DEM, MOMENTS_CONTINUUM = 0, 1
 NMOM = 11
@@ -36,7 +37,8 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_mlp_create", "sp_mlp_destroy", "sp_mlp_last_error", "sp_mlp_set_params", "sp_mlp_get_params",
             "sp_mlp_set_norm", "sp_mlp_get_norm", "sp_mlp_fit_norm", "sp_mlp_forward", "sp_mlp_gradient",
             "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample",
-            "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats"]
+            "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
+            "sp_get_coupling"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -86,6 +88,9 @@ def load_library(path: str = LIB_PATH):
     lib.sp_set_batching.argtypes = [P, P, P]
     lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
     lib.sp_set_graph_chunk.argtypes = [P, I32]
+    lib.sp_set_coupling.argtypes = [P, I32, I32, I32, D]
+    PI32, PI64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    lib.sp_get_coupling.argtypes = [P, PI32, PI32, PI32, PI64, PI64, PI64]
     F = ctypes.POINTER(ctypes.c_float)
     lib.sp_mlp_create.argtypes = [P, ctypes.POINTER(P)]
     lib.sp_mlp_destroy.argtypes = [P]
@@ -259,6 +264,17 @@ class Sim:
 
     def set_graph_chunk(self, chunk: int):
         self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))
+
+    def set_coupling(self, N0: int, N1: int = 1, n_t: int = 1, radius_headroom: float = 0.25):
+        """Coupling cadence of step(): coarse step of N0 fine steps in N1
+        sub-steps, coarse-to-fine updates every n_t fine steps; the contact
+        search allows radii to grow by radius_headroom."""
+        self._check(self._lib.sp_set_coupling(self._h, int(N0), int(N1), int(n_t), float(radius_headroom)))
+
+    def coupling(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(3)] + [ctypes.c_int64() for _ in range(3)]
+        self._check(self._lib.sp_get_coupling(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["N0", "N1", "n_t", "nudges", "clamped", "invalid"], [int(x.value) for x in v]))
 
     def closure_features(self, x):
         """Closure inputs of every cell into the device tensor x [ncells, 45] (float32)."""

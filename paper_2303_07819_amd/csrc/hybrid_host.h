@@ -32,10 +32,16 @@ enum { RS_OK = 0, RS_CLAMPED = 1, RS_INVALID = 2 };
 // reports RS_CLAMPED and keeps a smaller mass than its target.  A target that
 // cannot be met (rho <= 0 or not finite for a cell with floes, anything
 // nonzero for an empty cell) leaves the cell unchanged and reports RS_INVALID.
+// With vdisp, the cell's candidate lists stay valid: the largest radius growth
+// of its floes (rounded up) is added to its displacement bound, since a radius
+// that grows by g moves every contact threshold of the floe as a displacement
+// by g would.  With counters, clamped and invalid cells are also counted into
+// counters[0] and counters[1].
 __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
                                                      const float* h, float* u, float* v, float* w,
                                                      const double* targets, int nc, double rho_ice, double area,
-                                                     float r_lim, int32_t* status)
+                                                     float r_lim, int32_t* status, float* vdisp,
+                                                     unsigned long long* counters)
 {
     __shared__ double part[5][256];
     __shared__ double tot[5];
@@ -55,7 +61,10 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
 #pragma unroll
     for (int f = 0; f < 4; ++f) finite = finite && isfinite(tg[f]);
     if (!finite || !(tg[0] > 0.0)) {
-        if (tid == 0) status[blockIdx.x] = RS_INVALID;
+        if (tid == 0) {
+            status[blockIdx.x] = RS_INVALID;
+            if (counters) atomicAdd(&counters[1], 1ull);
+        }
         return;
     }
     // mass and largest radius of the cell
@@ -83,8 +92,11 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     __syncthreads();
     // rescale the radii, then the sums of the rescaled cell
     double acc[5] = {0, 0, 0, 0, 0};   // M, sum m u, sum m v, L, sum I
+    float grow = 0.0f;
     for (int l = tid; l < n; l += 256) {
-        const float rn = fminf((float)((double)r[s + l] * sc), r_lim);
+        const float ro = r[s + l];
+        const float rn = fminf((float)((double)ro * sc), r_lim);
+        grow = fmaxf(grow, rn - ro);   // rounded to nearest; rounded up below
         r[s + l] = rn;
         const double rl = rn;
         const double m = rho_ice * (double)h[s + l] * kPi * rl * rl;
@@ -96,13 +108,23 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) part[k][tid] = acc[k];
+    rpart[tid] = grow;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (tid < k)
+        if (tid < k) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) part[q][tid] += part[q][tid + k];
+            rpart[tid] = fmaxf(rpart[tid], rpart[tid + k]);
+        }
         __syncthreads();
     }
+    if (tid == 0 && vdisp && rpart[0] > 0.0f) {
+        // rn - ro is exact or one rounding off; two ulps of margin on the
+        // difference and on the sum keep the bound an upper bound
+        const float g = rpart[0] * (1.0f + 0x1p-22f);
+        vdisp[c] = (vdisp[c] + g) * (1.0f + 0x1p-22f);
+    }
+    if (tid == 0 && counters && clamped) atomicAdd(&counters[0], 1ull);
     if (tid < 5) tot[tid] = part[tid][0];
     __syncthreads();
     const double dvx = (tg[1] * area - tot[1]) / tot[0];
@@ -295,7 +317,7 @@ sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* 
     if (ncl <= 0) return SP_OK;
     hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
                        c->v, c->w, targets_d, c->ncells, c->p.rho_ice, c->p.cell_lx * c->p.cell_ly, c->r_bin,
-                       status_d);
+                       status_d, nullptr, nullptr);
     HIP_TRY(c, hipGetLastError());
     SP_TRY(invalidate_lists(c, cells_d, ncl));   // radii changed
     SP_TRY(ensure_cell_data(c));
@@ -457,6 +479,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     if (check_every < 1 || check_cells < 0 || !(tol > 0) || fallback_steps < 1 || !std::isfinite(net_window))
         return fail(c, SP_EINVAL, "check_every and fallback_steps must be >= 1, check_cells >= 0, tol > 0");
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "the hybrid needs the continuum update");
+    if (c->N0 > 1) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
     HIP_TRY(c, hipStreamSynchronize(net->stream));   // parameters and normalisation in place
     SP_TRY(flush_lf(c));
     hybrid_free(c);

@@ -112,6 +112,21 @@ struct sp_ctx {
     double lf_dt = 0.0;         // step size of that update
     int64_t steps = 0;
 
+    // coupling cadence (Algorithm 1): coarse step of N0 fine steps in N1
+    // sub-steps, coarse-to-fine updates every n_t fine steps
+    int32_t N0 = 1, N1 = 1, n_t = 1;
+    int64_t cpl_j = 0;                      // fine steps since the cadence was set
+    int64_t cpl_nudges = 0;                 // coarse-to-fine update passes since then
+    double* cpl_ring = nullptr;             // [N0][ncells][kMomStride] window statistics
+    int32_t cpl_ring_slots = 0;
+    double* cpl_mean = nullptr;             // [ncells][kMomStride] mean of the window
+    double* cpl_x0 = nullptr;               // [ncells][kMomStride] statistics at the coarse-step start
+    int32_t* cpl_cells = nullptr;           // cells with floes
+    int32_t cpl_ncl = 0;
+    double* cpl_tg = nullptr;               // [cpl_ncl][4] update targets
+    int32_t* cpl_status = nullptr;          // [cpl_ncl]
+    unsigned long long* cpl_count = nullptr;   // clamped, invalid cell updates
+
     // graph replay
     int graph_chunk = kDefaultGraphChunk;
     bool graph_ok = true;
@@ -121,10 +136,12 @@ struct sp_ctx {
 };
 
 void hybrid_free(sp_ctx* c);   // hybrid_host.h
+sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps);   // coupling_host.h
 
 namespace {
 sp_status init_reduced_all(sp_ctx* c, const double* mom);   // closure_host.h
 sp_status refresh_reduced_all(sp_ctx* c);
+void coupling_free(sp_ctx* c);                              // coupling_host.h
 }  // namespace
 
 namespace {
@@ -185,6 +202,7 @@ void free_all(sp_ctx* c)
 {
     drop_graph(c);
     hybrid_free(c);
+    coupling_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
                   c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d};
@@ -420,9 +438,10 @@ sp_status prepare_bucket(sp_ctx* c, Bucket& b)
 
 // One DEM launch for bucket b at time level k (writes the statistics of level
 // k); with lf, the continuum update of level k - 1 runs in the same launch.
-// `fixed` (autotuning) supplies every buffer pointer itself.
+// `fixed` (autotuning) supplies every buffer pointer itself; mom_to (coupled
+// cadence) takes the statistics instead, with no continuum update.
 sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_t k, bool lf,
-                        bool fixed = false)
+                        bool fixed = false, double* mom_to = nullptr)
 {
     if (b.cells_h.empty()) return SP_OK;
     StepArgs a = base;
@@ -436,6 +455,10 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
         a.mom_prev = c->momb[(k + 1) & 1];
         a.Qp = c->Q[(k + 1) & 1];
         a.Qn = c->Q[k & 1];
+        if (mom_to) {
+            a.mom = mom_to;
+            a.lf = 0;
+        }
     }
     const int gpb = bucket_gpb(c, b);
     const int groups = (int)((b.cells_h.size() + gpb - 1) / gpb);
@@ -558,9 +581,13 @@ sp_status reset_continuum(sp_ctx* c)
         hipLaunchKernelGGL(q_from_moments_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream,
                            c->momb[0], c->Q[0], c->ncells, 1.0 / (c->p.cell_lx * c->p.cell_ly));
         HIP_TRY(c, hipGetLastError());
+        // both buffers: the coupled cadence keeps the coarse state in each
+        HIP_TRY(c, hipMemcpyAsync(c->Q[1], c->Q[0], (size_t)c->ncells * 4 * 8, hipMemcpyDeviceToDevice,
+                                  c->stream));
     }
     c->kstep = 0;
     c->lf_pending = false;
+    c->cpl_j = 0;
     return SP_OK;
 }
 
@@ -713,6 +740,43 @@ sp_status sp_set_ocean(sp_ctx* c, double u0, double v0, int32_t nmodes, const do
     return SP_OK;
 }
 
+// Contact-search geometry for radii up to rmax: sub-bins, schedule, skin and
+// the radius limit of re-synchronisation; every cell's candidate lists are
+// invalidated.
+static sp_status plan_bins(sp_ctx* c, float rmax, bool any)
+{
+    c->r_bin = rmax;
+    // candidate lists are kept while the floes move less than half a skin of
+    // at least kSkinFrac r_max; sub-bins of side >= 2 r_max + skin, and any
+    // slack of the sub-bins goes to the skin
+    const double skin0 = kSkinFrac * (double)rmax;
+    int bx = any ? (int)floor(c->p.cell_lx / (2.0 * (double)rmax + skin0)) : 1;
+    int by = any ? (int)floor(c->p.cell_ly / (2.0 * (double)rmax + skin0)) : 1;
+    bx = std::min(bx, kMaxBinsSide);
+    by = std::min(by, kMaxBinsSide);
+    if (bx < 3) bx = 1;
+    if (by < 3) by = 1;
+    int sched = c->p.schedule;
+    if (sched == SP_SCHED_AUTO) sched = (bx >= 3 || by >= 3) ? SP_SCHED_BINNED : SP_SCHED_ALLPAIRS;
+    c->sched = sched;
+    if (sched == SP_SCHED_BINNED) {
+        c->nbx = bx;
+        c->nby = by;
+    } else {
+        c->nbx = c->nby = 1;
+    }
+    // binned axes: all the slack of the sub-bins (at least skin0); an axis
+    // searched whole sets no limit
+    double skin = INFINITY;
+    if (c->nbx >= 3) skin = std::min(skin, c->p.cell_lx / c->nbx - 2.0 * (double)rmax);
+    if (c->nby >= 3) skin = std::min(skin, c->p.cell_ly / c->nby - 2.0 * (double)rmax);
+    if (!std::isfinite(skin)) skin = skin0;
+    // float rounding must not let a pair at the bin side escape the sweep
+    c->skin = any ? (float)(skin * (1.0 - 1e-6)) : 0.0f;
+    SP_TRY(invalidate_lists(c, nullptr, c->ncells));
+    return SP_OK;
+}
+
 static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, const void* const* src,
                                   hipMemcpyKind kind)
 {
@@ -734,6 +798,8 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     hybrid_free(c);   // its cell lists follow the floes
+    coupling_free(c);   // so do the coupled cadence's
+    c->cpl_nudges = 0;
     c->have_floes = false;
     if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
     if (c->mf) (void)hipFree(c->mf);
@@ -787,37 +853,9 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     for (int32_t i = 0; i < c->ncells; ++i) c->order_h[i] = i;
     std::stable_sort(c->order_h.begin(), c->order_h.end(),
                      [&](int32_t x, int32_t y) { return c->counts_h[x] > c->counts_h[y]; });
-    c->r_bin = rmax;
     HIP_TRY(c, hipMemcpyAsync(c->cell_start, c->start_h.data(), ((size_t)c->ncells + 1) * 4,
                               hipMemcpyHostToDevice, c->stream));
-    // candidate lists are kept while the floes move less than half a skin of
-    // at least kSkinFrac r_max; sub-bins of side >= 2 r_max + skin, and any
-    // slack of the sub-bins goes to the skin
-    const double skin0 = kSkinFrac * (double)rmax;
-    int bx = n > 0 ? (int)floor(c->p.cell_lx / (2.0 * (double)rmax + skin0)) : 1;
-    int by = n > 0 ? (int)floor(c->p.cell_ly / (2.0 * (double)rmax + skin0)) : 1;
-    bx = std::min(bx, kMaxBinsSide);
-    by = std::min(by, kMaxBinsSide);
-    if (bx < 3) bx = 1;
-    if (by < 3) by = 1;
-    int sched = c->p.schedule;
-    if (sched == SP_SCHED_AUTO) sched = (bx >= 3 || by >= 3) ? SP_SCHED_BINNED : SP_SCHED_ALLPAIRS;
-    c->sched = sched;
-    if (sched == SP_SCHED_BINNED) {
-        c->nbx = bx;
-        c->nby = by;
-    } else {
-        c->nbx = c->nby = 1;
-    }
-    // binned axes: all the slack of the sub-bins (at least skin0); an axis
-    // searched whole sets no limit
-    double skin = INFINITY;
-    if (c->nbx >= 3) skin = std::min(skin, c->p.cell_lx / c->nbx - 2.0 * (double)rmax);
-    if (c->nby >= 3) skin = std::min(skin, c->p.cell_ly / c->nby - 2.0 * (double)rmax);
-    if (!std::isfinite(skin)) skin = skin0;
-    // float rounding must not let a pair at the bin side escape the sweep
-    c->skin = n > 0 ? (float)(skin * (1.0 - 1e-6)) : 0.0f;
-    SP_TRY(invalidate_lists(c, nullptr, c->ncells));
+    SP_TRY(plan_bins(c, rmax, n > 0));
     c->n = n;
     SP_TRY(build_buckets(c, counts));
     SP_TRY(prepare_buckets(c));
@@ -860,6 +898,7 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
     const bool cont = !(c->p.flags & SP_NO_CONTINUUM);
     const StepArgs base = make_args(c, dt);
     c->t_now += dt * (double)nsteps;
+    if (c->N0 > 1) return coupled_steps(c, base, nsteps);
     int64_t left = nsteps;
     while (left > 0) {
         const bool steady = (c->kstep % 2 == 0) && (c->lf_pending == cont);
@@ -886,6 +925,7 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
     if (!c) return SP_EINVAL;
     if (!c->have_floes) return fail(c, SP_ESTATE, "sp_profile_steps before sp_set_floes");
     if (!(dt > 0.0) || nsteps < 1) return fail(c, SP_EINVAL, "dt must be positive and nsteps >= 1");
+    if (c->N0 > 1) return fail(c, SP_ESTATE, "sp_profile_steps times the cadence N0 = 1");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));
     // One event pair around the whole run of back-to-back launches: an event
@@ -1185,3 +1225,4 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
 
 #include "closure_host.h"
 #include "hybrid_host.h"
+#include "coupling_host.h"

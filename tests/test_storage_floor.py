@@ -13,21 +13,8 @@ import pytest
 import fixtures
 import oracle
 from metrics import rel_err
+from storage import coupled_floor, run_plain_stored
 from workloads import dense_workload, ragged_workload, uneven_workload
-
-
-def run_stored(w, nsteps):
-    m = oracle.Model(w)
-    st = oracle.State.from_workload(w)
-    Q = oracle.q_from_moments(m, oracle.moments(m, st))
-    for _ in range(nsteps):
-        mom, _ = oracle.dem_steps(m, st, w.dt, 1, record=True)
-        Q, _ = oracle.lf_step(m, Q, mom[0], w.dt)
-        for a in (st.u, st.v, st.w):
-            a[:] = a.astype(np.float32)
-        for a in (st.xs, st.ys):
-            a[:] = np.round(a * 2.0 ** 32) / 2.0 ** 32 % 1.0
-    return Q, oracle.moments(m, st)
 
 
 @pytest.mark.parametrize("name", ["small", "dense", "ragged", "uneven"])
@@ -35,10 +22,23 @@ def test_storage_floor(name):
     w = {"small": lambda: fixtures.make_config(0), "dense": dense_workload, "ragged": ragged_workload,
          "uneven": uneven_workload}[name]()
     _, Q, mom, _ = oracle.run_plain(w, 10)
-    Qs, moms = run_stored(w, 10)
+    Qs, moms = run_plain_stored(w, 10)
     floor = max(rel_err(moms, mom).max(), rel_err(Qs, Q).max())
     print(f"{name}: storage-only deviation after 10 steps {floor:.2e}")
     if name == "small":
         assert floor < 2e-6          # no contacts: storage rounding is not amplified
     else:
         assert 1e-7 < floor < 1e-5   # contacts amplify it, but it stays below the bar
+
+
+@pytest.mark.parametrize("case", [(13, 4, 2, 2), (12, 6, 1, 4), (9, 3, 3, 1)])
+def test_coupled_storage_floor(case):
+    """Coupled cadence on the small configuration: a coarse-to-fine update sets
+    each cell's momentum to a target close to its current value, so the FP32
+    rounding of the shifted velocities is amplified in the drag sums that feed
+    the next coarse step; updates every fine step (n_t = 1) lift the floor above
+    1e-5, which is why the GPU parity of the coupled runs is held to five times
+    this floor where it exceeds the stated tolerance."""
+    floor = coupled_floor(fixtures.make_config(0), *case)
+    print(f"coupled {case}: storage-only deviation {floor:.2e}")
+    assert 1e-8 < floor < 1e-3
