@@ -145,28 +145,30 @@ sp_status sp_step(sp_ctx* ctx, double dt, int64_t nsteps);
  * whose r = j mod N0 is a nonzero multiple of n_t, every cell with floes is
  * re-synchronised (radii scaled by one factor, then uniform velocity and spin
  * shifts, as sp_resync_cells) to X0 + (r / N0) (Q - X0), Q the latest coarse
- * state.  The contact search is planned for radii up to
- * (1 + radius_headroom) x the largest current radius (at most a quarter of the
- * cell); a cell whose radii would pass that is scaled up to it ("clamped"), a
- * target with rho <= 0 leaves its cell unchanged ("invalid").  A larger
- * headroom means larger sub-bins (costlier list rebuilds), never a different
- * result for cells that are not clamped.  dt is the dt of each sp_step call; a coarse step uses N0 times
- * the dt of the call that completes it.  N0 = N1 = n_t = 1 is the plain step.
- * Between coarse steps SP_MOMENTS_CONTINUUM reads the latest coarse state.
- * Cadence state lives in the context: ring of N0 x ncells x 128 B statistics.
- * Errors: SP_EINVAL (a value < 1, N0 or N1 > SP_MAX_COUPLING, headroom < 0 or
- * not finite), SP_ESTATE
+ * state.  At each coarse step the contact search (sub-bins, skin) is
+ * re-planned, when needed, for the largest radius the next coarse step's
+ * updates can produce (a cell's radii scale by sqrt(rho_target / rho_X0) and
+ * its targets lie between X0 and Q), so no update is limited by it; only a
+ * cell whose radii would pass a quarter of the cell (the limit of the periodic
+ * cell DEM) is scaled up to that ("clamped"), and a target with rho <= 0
+ * leaves its cell unchanged ("invalid").  Each coarse step synchronises the
+ * stream once (a 4-byte read of that radius).  dt is the dt of each sp_step
+ * call; a coarse step uses N0 times the dt of the call that completes it.
+ * N0 = N1 = n_t = 1 is the plain step.  Between coarse steps
+ * SP_MOMENTS_CONTINUUM reads the latest coarse state.  Cadence state lives in
+ * the context: a ring of N0 x ncells x 128 B statistics.
+ * Errors: SP_EINVAL (a value < 1, N0 or N1 > SP_MAX_COUPLING), SP_ESTATE
  * (N0 > 1 with SP_NO_CONTINUUM or an active hybrid), SP_ENOMEM at the first
  * coupled sp_step.  sp_hybrid_set, sp_step_hybrid, sp_closure_sample and
  * sp_profile_steps return SP_ESTATE while N0 > 1. */
 #define SP_MAX_COUPLING 65536
-sp_status sp_set_coupling(sp_ctx* ctx, int32_t N0, int32_t N1, int32_t n_t, double radius_headroom);
+sp_status sp_set_coupling(sp_ctx* ctx, int32_t N0, int32_t N1, int32_t n_t);
 
-/* The cadence, the coarse-to-fine update passes taken and the clamped and
- * invalid cell updates counted since the last sp_set_coupling (or
- * sp_set_floes).  Any pointer may be NULL.  Synchronises. */
+/* The cadence, then counted since the last sp_set_coupling (or sp_set_floes):
+ * coarse-to-fine update passes, contact-search re-plans, clamped and invalid
+ * cell updates.  Any pointer may be NULL.  Synchronises. */
 sp_status sp_get_coupling(sp_ctx* ctx, int32_t* N0, int32_t* N1, int32_t* n_t, int64_t* nudges,
-                          int64_t* clamped, int64_t* invalid);
+                          int64_t* replans, int64_t* clamped, int64_t* invalid);
 
 /* Block until the stream is idle; returns the first latched device fault. */
 sp_status sp_synchronize(sp_ctx* ctx);

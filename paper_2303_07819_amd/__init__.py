@@ -88,9 +88,9 @@ def load_library(path: str = LIB_PATH):
     lib.sp_set_batching.argtypes = [P, P, P]
     lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
     lib.sp_set_graph_chunk.argtypes = [P, I32]
-    lib.sp_set_coupling.argtypes = [P, I32, I32, I32, D]
+    lib.sp_set_coupling.argtypes = [P, I32, I32, I32]
     PI32, PI64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
-    lib.sp_get_coupling.argtypes = [P, PI32, PI32, PI32, PI64, PI64, PI64]
+    lib.sp_get_coupling.argtypes = [P, PI32, PI32, PI32, PI64, PI64, PI64, PI64]
     F = ctypes.POINTER(ctypes.c_float)
     lib.sp_mlp_create.argtypes = [P, ctypes.POINTER(P)]
     lib.sp_mlp_destroy.argtypes = [P]
@@ -265,16 +265,15 @@ class Sim:
     def set_graph_chunk(self, chunk: int):
         self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))
 
-    def set_coupling(self, N0: int, N1: int = 1, n_t: int = 1, radius_headroom: float = 0.25):
+    def set_coupling(self, N0: int, N1: int = 1, n_t: int = 1):
         """Coupling cadence of step(): coarse step of N0 fine steps in N1
-        sub-steps, coarse-to-fine updates every n_t fine steps; the contact
-        search allows radii to grow by radius_headroom."""
-        self._check(self._lib.sp_set_coupling(self._h, int(N0), int(N1), int(n_t), float(radius_headroom)))
+        sub-steps, coarse-to-fine updates every n_t fine steps."""
+        self._check(self._lib.sp_set_coupling(self._h, int(N0), int(N1), int(n_t)))
 
     def coupling(self) -> dict:
-        v = [ctypes.c_int32() for _ in range(3)] + [ctypes.c_int64() for _ in range(3)]
+        v = [ctypes.c_int32() for _ in range(3)] + [ctypes.c_int64() for _ in range(4)]
         self._check(self._lib.sp_get_coupling(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(["N0", "N1", "n_t", "nudges", "clamped", "invalid"], [int(x.value) for x in v]))
+        return dict(zip(["N0", "N1", "n_t", "nudges", "replans", "clamped", "invalid"], [int(x.value) for x in v]))
 
     def closure_features(self, x):
         """Closure inputs of every cell into the device tensor x [ncells, 45] (float32)."""

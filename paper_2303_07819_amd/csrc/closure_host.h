@@ -841,9 +841,10 @@ namespace {
 // re-synchronised later refresh their own).
 sp_status ensure_cell_data(sp_ctx* c)
 {
-    if (c->desc && c->mf) return SP_OK;
-    SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
-    SP_TRY(dalloc(c, &c->mf, (size_t)c->ncells * 4));
+    if (c->desc && c->mf && !c->desc_stale) return SP_OK;
+    if (!c->desc) SP_TRY(dalloc(c, &c->desc, (size_t)c->ncells * 6));
+    if (!c->mf) SP_TRY(dalloc(c, &c->mf, (size_t)c->ncells * 4));
+    c->desc_stale = false;
     hipLaunchKernelGGL(descriptors_kernel, dim3(c->ncells), dim3(256), 0, c->stream, nullptr, c->cell_start, c->r,
                        c->h, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->p.rho_ice, c->p.cd * c->p.rho_ocean, c->desc,
                        c->mf);

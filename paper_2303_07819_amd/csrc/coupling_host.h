@@ -13,7 +13,11 @@
 // Both continuum buffers hold the current coarse state between coarse steps,
 // so readers that take the level of the current step find it at either
 // parity.  Re-synchronised cells keep their candidate lists: the radius growth
-// goes into the lists' displacement bound.
+// goes into the lists' displacement bound.  The contact search is re-planned
+// at coarse steps for the largest radius the next coarse step's updates can
+// produce (known then: a cell's radii scale by sqrt(rho_target / rho_X0) and
+// its targets lie between X0 and Q), so radii are limited only by a quarter of
+// the cell, the limit of the periodic cell DEM.
 #pragma once
 
 namespace spdem {
@@ -29,33 +33,64 @@ __global__ __launch_bounds__(256) void window_mean_kernel(const double* ring, in
     mean[i] = s / (double)N0;
 }
 
-// Targets X0 + frac (Q - X0) of the listed cells; X0 from the statistics x0m
-// (M, P_x, P_y, L over the cell area), Q [4][nc].
-__global__ __launch_bounds__(256) void nudge_targets_kernel(const int32_t* cells, int ncl, const double* x0m,
-                                                            const double* Q, int nc, double frac, double inv_area,
-                                                            double* targets)
+// Largest radius the next coarse step's updates can produce: a cell's radii
+// stay below rmax_cell sqrt(max(1, Q_rho / X0_rho)).  One wavefront per listed
+// cell; the maximum over cells (plus a rounding margin) into *out as float
+// bits (positive floats order as their bit patterns).
+__global__ __launch_bounds__(64) void window_radius_kernel(const int32_t* cells, int ncl, const int32_t* cell_start,
+                                                           const float* r, const double* x0m, const double* Q, int nc,
+                                                           double inv_area, unsigned int* out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
     if (i >= ncl) return;
     const int c = cells[i];
-    const double* s = x0m + (size_t)c * kMomStride;
-    const double x0[4] = {s[M_MASS] * inv_area, s[M_PX] * inv_area, s[M_PY] * inv_area, s[M_L] * inv_area};
+    const int s = cell_start[c], n = cell_start[c + 1] - s;
+    float m = 0.0f;
+    for (int l = threadIdx.x; l < n; l += 64) m = fmaxf(m, r[s + l]);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) targets[(size_t)i * 4 + f] = x0[f] + frac * (Q[(size_t)f * nc + c] - x0[f]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (threadIdx.x == 0) {
+        const double x0 = x0m[(size_t)c * kMomStride + M_MASS] * inv_area;
+        const double q = Q[c];
+        const double f = (x0 > 0.0 && q > x0) ? sqrt(q / x0) : 1.0;
+        const float req = (float)((double)m * f * (1.0 + 1e-5));
+        atomicMax(out, __float_as_uint(req));
+    }
 }
 
 }  // namespace spdem
 
 namespace {
 
+// Re-planning of the contact search at coarse steps: grow to the required
+// radius plus kPlanMargin; shrink once the requirement falls below
+// r_bin / kShrinkRatio.  The skin stays at most the one planned for the floes
+// as they were set: sub-bins sized for a few grown floes must not widen every
+// floe's candidate list (its capacity is fixed).
+constexpr double kPlanMargin = 0.05;
+constexpr double kShrinkRatio = 1.2;
+
+sp_status plan_for_radius(sp_ctx* c, float req)
+{
+    const double quarter = 0.25 * std::min(c->p.cell_lx, c->p.cell_ly) * (1.0 - 1e-6);
+    if (req <= c->r_bin && (double)req * kShrinkRatio >= (double)c->r_bin) return SP_OK;
+    const float rplan = (float)std::min((double)req * (1.0 + kPlanMargin), quarter);
+    if (rplan == c->r_bin) return SP_OK;
+    SP_TRY(plan_bins(c, rplan, true, c->skin_set));
+    SP_TRY(prepare_buckets(c));
+    c->cpl_replans++;
+    return SP_OK;
+}
+
 void coupling_free(sp_ctx* c)
 {
-    void* ps[] = {c->cpl_ring, c->cpl_mean, c->cpl_x0, c->cpl_cells, c->cpl_tg, c->cpl_status, c->cpl_count};
+    void* ps[] = {c->cpl_ring, c->cpl_mean, c->cpl_x0, c->cpl_cells, c->cpl_count, c->cpl_rreq};
     for (void* p : ps)
         if (p) (void)hipFree(p);
-    c->cpl_ring = c->cpl_mean = c->cpl_x0 = c->cpl_tg = nullptr;
-    c->cpl_cells = c->cpl_status = nullptr;
+    c->cpl_ring = c->cpl_mean = c->cpl_x0 = nullptr;
+    c->cpl_cells = nullptr;
     c->cpl_count = nullptr;
+    c->cpl_rreq = nullptr;
     c->cpl_ring_slots = 0;
     c->cpl_ncl = 0;
 }
@@ -71,6 +106,7 @@ sp_status coupling_prepare(sp_ctx* c)
     SP_TRY(dalloc(c, &c->cpl_mean, slot));
     SP_TRY(dalloc(c, &c->cpl_x0, slot));
     SP_TRY(dalloc(c, &c->cpl_count, 2));
+    SP_TRY(dalloc(c, &c->cpl_rreq, 1));
     HIP_TRY(c, hipMemsetAsync(c->cpl_ring, 0, slot * (size_t)c->N0 * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->cpl_count, 0, 2 * sizeof(unsigned long long), c->stream));
     std::vector<int32_t> cells;
@@ -79,8 +115,6 @@ sp_status coupling_prepare(sp_ctx* c)
     c->cpl_ncl = (int)cells.size();
     const size_t m = std::max<size_t>(1, cells.size());
     SP_TRY(dalloc(c, &c->cpl_cells, m));
-    SP_TRY(dalloc(c, &c->cpl_tg, m * 4));
-    SP_TRY(dalloc(c, &c->cpl_status, m));
     if (!cells.empty())
         HIP_TRY(c, hipMemcpyAsync(c->cpl_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));   // `cells` is a host temporary
@@ -110,7 +144,17 @@ sp_status coarse_step(sp_ctx* c, double dt)
     a.mom = c->cpl_x0;
     hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
     HIP_TRY(c, hipGetLastError());
-    return SP_OK;
+    if (c->cpl_ncl == 0 || c->N0 <= c->n_t) return SP_OK;   // no update in the next coarse step
+    HIP_TRY(c, hipMemsetAsync(c->cpl_rreq, 0, sizeof(unsigned int), c->stream));
+    hipLaunchKernelGGL(window_radius_kernel, dim3(c->cpl_ncl), dim3(64), 0, c->stream, c->cpl_cells, c->cpl_ncl,
+                       c->cell_start, c->r, c->cpl_x0, c->Q[0], c->ncells, inv_area, c->cpl_rreq);
+    HIP_TRY(c, hipGetLastError());
+    unsigned int bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->cpl_rreq, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float req;
+    memcpy(&req, &bits, sizeof req);
+    return plan_for_radius(c, req);
 }
 
 // Re-synchronise every cell with floes to X0 + frac (Q - X0).
@@ -118,18 +162,11 @@ sp_status nudge(sp_ctx* c, double frac)
 {
     if (c->cpl_ncl == 0) return SP_OK;
     const double area = c->p.cell_lx * c->p.cell_ly;
-    hipLaunchKernelGGL(nudge_targets_kernel, dim3((c->cpl_ncl + 255) / 256), dim3(256), 0, c->stream, c->cpl_cells,
-                       c->cpl_ncl, c->cpl_x0, c->Q[0], c->ncells, frac, 1.0 / area, c->cpl_tg);
-    HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(resync_kernel, dim3(c->cpl_ncl), dim3(256), 0, c->stream, c->cpl_cells, c->cell_start, c->r,
-                       c->h, c->u, c->v, c->w, c->cpl_tg, c->ncells, c->p.rho_ice, area, c->r_bin, c->cpl_status,
-                       c->vdisp, c->cpl_count);
+                       c->h, c->u, c->v, c->w, nullptr, c->cpl_x0, c->Q[0], frac, c->ncells, c->p.rho_ice, area,
+                       c->r_bin, nullptr, c->vdisp, c->cpl_count);
     HIP_TRY(c, hipGetLastError());
-    if (c->desc) {   // closure descriptors follow the radii
-        hipLaunchKernelGGL(descriptors_kernel, dim3(c->cpl_ncl), dim3(256), 0, c->stream, c->cpl_cells, c->cell_start,
-                           c->r, c->h, 1.0 / area, c->p.rho_ice, c->p.cd * c->p.rho_ocean, c->desc, c->mf);
-        HIP_TRY(c, hipGetLastError());
-    }
+    c->desc_stale = true;   // closure descriptors follow the radii (recomputed when next needed)
     c->cpl_nudges++;
     return SP_OK;
 }
@@ -159,13 +196,11 @@ sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
 
 extern "C" {
 
-sp_status sp_set_coupling(sp_ctx* c, int32_t N0, int32_t N1, int32_t n_t, double radius_headroom)
+sp_status sp_set_coupling(sp_ctx* c, int32_t N0, int32_t N1, int32_t n_t)
 {
     if (!c) return SP_EINVAL;
     if (N0 < 1 || N1 < 1 || n_t < 1 || N0 > SP_MAX_COUPLING || N1 > SP_MAX_COUPLING)
         return fail(c, SP_EINVAL, "N0, N1 and n_t must be >= 1 and N0, N1 <= %d", SP_MAX_COUPLING);
-    if (!(radius_headroom >= 0.0) || !std::isfinite(radius_headroom))
-        return fail(c, SP_EINVAL, "radius_headroom must be finite and >= 0");
     if (N0 > 1 && (c->p.flags & SP_NO_CONTINUUM)) return fail(c, SP_ESTATE, "coupling needs the continuum update");
     if (N0 > 1 && c->hyb) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
     SP_TRY(flush_lf(c));
@@ -185,32 +220,31 @@ sp_status sp_set_coupling(sp_ctx* c, int32_t N0, int32_t N1, int32_t n_t, double
     c->n_t = n_t;
     c->cpl_j = 0;
     c->cpl_nudges = 0;
+    c->cpl_replans = 0;
     if (c->have_floes && c->n > 0) {
-        // contact search sized for the radii the updates may reach: with
-        // N0 > 1, radius_headroom above the current largest radius (below a
-        // quarter of the cell), else the current largest radius
+        // contact search sized for the current radii (they may have changed
+        // since the floes were set); later coarse steps re-plan it
         std::vector<float> rh((size_t)c->n);
         HIP_TRY(c, hipMemcpyAsync(rh.data(), c->r, rh.size() * 4, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const float rcur = *std::max_element(rh.begin(), rh.end());
-        const double quarter = 0.25 * std::min(c->p.cell_lx, c->p.cell_ly) * (1.0 - 1e-6);
-        const float rplan = N0 > 1 ? (float)std::min((double)rcur * (1.0 + radius_headroom), quarter) : rcur;
-        if (rplan != c->r_bin) {
-            SP_TRY(plan_bins(c, rplan, true));
+        if (rcur != c->r_bin) {
+            SP_TRY(plan_bins(c, rcur, true, c->skin_set));
             SP_TRY(prepare_buckets(c));
         }
     }
     return SP_OK;
 }
 
-sp_status sp_get_coupling(sp_ctx* c, int32_t* N0, int32_t* N1, int32_t* n_t, int64_t* nudges, int64_t* clamped,
-                          int64_t* invalid)
+sp_status sp_get_coupling(sp_ctx* c, int32_t* N0, int32_t* N1, int32_t* n_t, int64_t* nudges, int64_t* replans,
+                          int64_t* clamped, int64_t* invalid)
 {
     if (!c) return SP_EINVAL;
     if (N0) *N0 = c->N0;
     if (N1) *N1 = c->N1;
     if (n_t) *n_t = c->n_t;
     if (nudges) *nudges = c->cpl_nudges;
+    if (replans) *replans = c->cpl_replans;
     unsigned long long cnt[2] = {0, 0};
     if (c->cpl_count) {
         HIP_TRY(c, hipMemcpyAsync(cnt, c->cpl_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));

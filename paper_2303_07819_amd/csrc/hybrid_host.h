@@ -27,33 +27,70 @@ namespace spdem {
 
 enum { RS_OK = 0, RS_CLAMPED = 1, RS_INVALID = 2 };
 
-// One workgroup per listed cell, targets [ncl][4].  The radius scale is limited so
-// that no radius exceeds r_lim (the contact-search bin radius); such a cell
-// reports RS_CLAMPED and keeps a smaller mass than its target.  A target that
-// cannot be met (rho <= 0 or not finite for a cell with floes, anything
-// nonzero for an empty cell) leaves the cell unchanged and reports RS_INVALID.
-// With vdisp, the cell's candidate lists stay valid: the largest radius growth
-// of its floes (rounded up) is added to its displacement bound, since a radius
-// that grows by g moves every contact threshold of the floe as a displacement
-// by g would.  With counters, clamped and invalid cells are also counted into
-// counters[0] and counters[1].
+// Sum / max over a 256-thread workgroup: xor butterflies within each
+// wavefront, then the four wavefront results in a fixed order (every thread
+// gets the same value; the order does not depend on timing).
+__device__ __forceinline__ double block_sum256(double x, double* sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wv] = x;
+    __syncthreads();
+    const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ float block_max256(float x, float* sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wv] = x;
+    __syncthreads();
+    const float t = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    __syncthreads();
+    return t;
+}
+
+// One workgroup of 256 threads per listed cell.  Targets: targets[ncl][4], or
+// with x0m the coarse-to-fine update X0 + frac (Q - X0) of the cell (X0 =
+// (M, P_x, P_y, L) / area from the statistics x0m, Q [4][nc]).  The radius
+// scale is limited so that no radius exceeds r_lim (the contact-search bin
+// radius); such a cell reports RS_CLAMPED and keeps a smaller mass than its
+// target.  A target that cannot be met (rho <= 0 or not finite for a cell with
+// floes, anything nonzero for an empty cell) leaves the cell unchanged and
+// reports RS_INVALID.  status may be null.  With vdisp, the cell's candidate
+// lists stay valid: the largest radius growth of its floes (rounded up) is
+// added to its displacement bound, since a radius that grows by g moves every
+// contact threshold of the floe as a displacement by g would.  With counters,
+// clamped and invalid cells are also counted into counters[0] and counters[1].
 __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
                                                      const float* h, float* u, float* v, float* w,
-                                                     const double* targets, int nc, double rho_ice, double area,
+                                                     const double* targets, const double* x0m, const double* Qc,
+                                                     double frac, int nc, double rho_ice, double area,
                                                      float r_lim, int32_t* status, float* vdisp,
                                                      unsigned long long* counters)
 {
-    __shared__ double part[5][256];
-    __shared__ double tot[5];
-    __shared__ float rpart[256];
+    __shared__ double dsh[4];
+    __shared__ float fsh[4];
     const int c = cells[blockIdx.x];
     const int s = cell_start[c], n = cell_start[c + 1] - s;
     const int tid = threadIdx.x;
     double tg[4];
+    if (x0m) {
+        const double* st = x0m + (size_t)c * kMomStride;
+        const double inv_area = 1.0 / area;
+        const double x0[4] = {st[M_MASS] * inv_area, st[M_PX] * inv_area, st[M_PY] * inv_area, st[M_L] * inv_area};
 #pragma unroll
-    for (int f = 0; f < 4; ++f) tg[f] = targets[(size_t)blockIdx.x * 4 + f];
+        for (int f = 0; f < 4; ++f) tg[f] = x0[f] + frac * (Qc[(size_t)f * nc + c] - x0[f]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) tg[f] = targets[(size_t)blockIdx.x * 4 + f];
+    }
     if (n == 0) {
-        if (tid == 0)
+        if (tid == 0 && status)
             status[blockIdx.x] = (tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0 || tg[3] != 0.0) ? RS_INVALID : RS_OK;
         return;
     }
@@ -62,7 +99,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     for (int f = 0; f < 4; ++f) finite = finite && isfinite(tg[f]);
     if (!finite || !(tg[0] > 0.0)) {
         if (tid == 0) {
-            status[blockIdx.x] = RS_INVALID;
+            if (status) status[blockIdx.x] = RS_INVALID;
             if (counters) atomicAdd(&counters[1], 1ull);
         }
         return;
@@ -75,21 +112,12 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         m0 += rho_ice * (double)h[s + l] * kPi * rl * rl;
         r0 = fmaxf(r0, r[s + l]);
     }
-    part[0][tid] = m0;
-    rpart[tid] = r0;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (tid < k) {
-            part[0][tid] += part[0][tid + k];
-            rpart[tid] = fmaxf(rpart[tid], rpart[tid + k]);
-        }
-        __syncthreads();
-    }
-    double sc = sqrt(tg[0] * area / part[0][0]);
-    const double lim = (double)r_lim / (double)rpart[0];
+    const double mass = block_sum256(m0, dsh);
+    const float rmax = block_max256(r0, fsh);
+    double sc = sqrt(tg[0] * area / mass);
+    const double lim = (double)r_lim / (double)rmax;
     const bool clamped = sc > lim;
     if (clamped) sc = lim;
-    __syncthreads();
     // rescale the radii, then the sums of the rescaled cell
     double acc[5] = {0, 0, 0, 0, 0};   // M, sum m u, sum m v, L, sum I
     float grow = 0.0f;
@@ -106,27 +134,17 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         acc[3] += m * rl * rl * (double)w[s + l];
         acc[4] += m * rl * rl;
     }
+    double tot[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) part[k][tid] = acc[k];
-    rpart[tid] = grow;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (tid < k) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) part[q][tid] += part[q][tid + k];
-            rpart[tid] = fmaxf(rpart[tid], rpart[tid + k]);
-        }
-        __syncthreads();
-    }
-    if (tid == 0 && vdisp && rpart[0] > 0.0f) {
+    for (int k = 0; k < 5; ++k) tot[k] = block_sum256(acc[k], dsh);
+    const float gmax = block_max256(grow, fsh);
+    if (tid == 0 && vdisp && gmax > 0.0f) {
         // rn - ro is exact or one rounding off; two ulps of margin on the
         // difference and on the sum keep the bound an upper bound
-        const float g = rpart[0] * (1.0f + 0x1p-22f);
+        const float g = gmax * (1.0f + 0x1p-22f);
         vdisp[c] = (vdisp[c] + g) * (1.0f + 0x1p-22f);
     }
     if (tid == 0 && counters && clamped) atomicAdd(&counters[0], 1ull);
-    if (tid < 5) tot[tid] = part[tid][0];
-    __syncthreads();
     const double dvx = (tg[1] * area - tot[1]) / tot[0];
     const double dvy = (tg[2] * area - tot[2]) / tot[0];
     const double dw = (tg[3] * area - tot[3]) / tot[4];
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         v[s + l] = (float)((double)v[s + l] + dvy);
         w[s + l] = (float)((double)w[s + l] + dw);
     }
-    if (tid == 0) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
+    if (tid == 0 && status) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
 }
 
 // Continuum step of the hybrid: closure cells Qb + dT T (Qb: the base-updated
@@ -316,8 +334,8 @@ sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* 
 {
     if (ncl <= 0) return SP_OK;
     hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
-                       c->v, c->w, targets_d, c->ncells, c->p.rho_ice, c->p.cell_lx * c->p.cell_ly, c->r_bin,
-                       status_d, nullptr, nullptr);
+                       c->v, c->w, targets_d, nullptr, nullptr, 0.0, c->ncells, c->p.rho_ice,
+                       c->p.cell_lx * c->p.cell_ly, c->r_bin, status_d, nullptr, nullptr);
     HIP_TRY(c, hipGetLastError());
     SP_TRY(invalidate_lists(c, cells_d, ncl));   // radii changed
     SP_TRY(ensure_cell_data(c));

@@ -84,6 +84,7 @@ struct sp_ctx {
     Bucket bk[kNumBuckets];
     float r_bin = 0.0f;         // largest radius the sub-bins are sized for
     float skin = 0.0f;          // candidate-list skin (m)
+    float skin_set = 0.0f;      // the skin planned for the floes as set (re-plans stay below it)
     struct HybridState* hyb = nullptr;
 
     // device buffers
@@ -98,6 +99,7 @@ struct sp_ctx {
     unsigned long long* contacts_d = nullptr;
     unsigned long long* cfl_bits_d = nullptr;
     float* desc = nullptr;                  // closure descriptors [ncells][6] (lazy)
+    bool desc_stale = false;                // radii changed since desc and mf were computed
     double* mf = nullptr;                   // mean-field drag coefficients [ncells][4] (with desc)
     double* red = nullptr;                  // reduced DEM of every cell [ncells][4]
     double t_now = 0.0;                     // time of the current state since the floes were set
@@ -123,9 +125,9 @@ struct sp_ctx {
     double* cpl_x0 = nullptr;               // [ncells][kMomStride] statistics at the coarse-step start
     int32_t* cpl_cells = nullptr;           // cells with floes
     int32_t cpl_ncl = 0;
-    double* cpl_tg = nullptr;               // [cpl_ncl][4] update targets
-    int32_t* cpl_status = nullptr;          // [cpl_ncl]
     unsigned long long* cpl_count = nullptr;   // clamped, invalid cell updates
+    unsigned int* cpl_rreq = nullptr;       // radius the next coarse step's updates may reach (float bits)
+    int64_t cpl_replans = 0;                // contact-search re-plans at coarse steps
 
     // graph replay
     int graph_chunk = kDefaultGraphChunk;
@@ -740,10 +742,10 @@ sp_status sp_set_ocean(sp_ctx* c, double u0, double v0, int32_t nmodes, const do
     return SP_OK;
 }
 
-// Contact-search geometry for radii up to rmax: sub-bins, schedule, skin and
-// the radius limit of re-synchronisation; every cell's candidate lists are
-// invalidated.
-static sp_status plan_bins(sp_ctx* c, float rmax, bool any)
+// Contact-search geometry for radii up to rmax: sub-bins, schedule, skin (at
+// most skin_cap) and the radius limit of re-synchronisation; every cell's
+// candidate lists are invalidated.
+static sp_status plan_bins(sp_ctx* c, float rmax, bool any, double skin_cap = INFINITY)
 {
     c->r_bin = rmax;
     // candidate lists are kept while the floes move less than half a skin of
@@ -771,6 +773,7 @@ static sp_status plan_bins(sp_ctx* c, float rmax, bool any)
     if (c->nbx >= 3) skin = std::min(skin, c->p.cell_lx / c->nbx - 2.0 * (double)rmax);
     if (c->nby >= 3) skin = std::min(skin, c->p.cell_ly / c->nby - 2.0 * (double)rmax);
     if (!std::isfinite(skin)) skin = skin0;
+    skin = std::min(skin, skin_cap);
     // float rounding must not let a pair at the bin side escape the sweep
     c->skin = any ? (float)(skin * (1.0 - 1e-6)) : 0.0f;
     SP_TRY(invalidate_lists(c, nullptr, c->ncells));
@@ -856,6 +859,7 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     HIP_TRY(c, hipMemcpyAsync(c->cell_start, c->start_h.data(), ((size_t)c->ncells + 1) * 4,
                               hipMemcpyHostToDevice, c->stream));
     SP_TRY(plan_bins(c, rmax, n > 0));
+    c->skin_set = c->skin;
     c->n = n;
     SP_TRY(build_buckets(c, counts));
     SP_TRY(prepare_buckets(c));
