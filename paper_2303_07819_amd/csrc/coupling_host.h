@@ -34,27 +34,34 @@ __global__ __launch_bounds__(256) void window_mean_kernel(const double* ring, in
 }
 
 // Largest radius the next coarse step's updates can produce: a cell's radii
-// stay below rmax_cell sqrt(max(1, Q_rho / X0_rho)).  One wavefront per listed
-// cell; the maximum over cells (plus a rounding margin) into *out as float
-// bits (positive floats order as their bit patterns).
-__global__ __launch_bounds__(64) void window_radius_kernel(const int32_t* cells, int ncl, const int32_t* cell_start,
-                                                           const float* r, const double* x0m, const double* Q, int nc,
-                                                           double inv_area, unsigned int* out)
+// stay below rmax_cell sqrt(max(1, Q_rho / X0_rho)).  Each wavefront strides
+// over the listed cells; one atomic maximum per workgroup (plus a rounding
+// margin) into *out as float bits (positive floats order as their bit
+// patterns).
+__global__ __launch_bounds__(256) void window_radius_kernel(const int32_t* cells, int ncl, const int32_t* cell_start,
+                                                            const float* r, const double* x0m, const double* Q,
+                                                            int nc, double inv_area, unsigned int* out)
 {
-    const int i = blockIdx.x;
-    if (i >= ncl) return;
-    const int c = cells[i];
-    const int s = cell_start[c], n = cell_start[c + 1] - s;
-    float m = 0.0f;
-    for (int l = threadIdx.x; l < n; l += 64) m = fmaxf(m, r[s + l]);
+    __shared__ float wmax[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float best = 0.0f;
+    for (int i = blockIdx.x * 4 + wv; i < ncl; i += gridDim.x * 4) {
+        const int c = cells[i];
+        const int s = cell_start[c], n = cell_start[c + 1] - s;
+        float m = 0.0f;
+        for (int l = lane; l < n; l += 64) m = fmaxf(m, r[s + l]);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if (threadIdx.x == 0) {
+        for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
         const double x0 = x0m[(size_t)c * kMomStride + M_MASS] * inv_area;
         const double q = Q[c];
         const double f = (x0 > 0.0 && q > x0) ? sqrt(q / x0) : 1.0;
-        const float req = (float)((double)m * f * (1.0 + 1e-5));
-        atomicMax(out, __float_as_uint(req));
+        best = fmaxf(best, (float)((double)m * f * (1.0 + 1e-5)));
+    }
+    if (lane == 0) wmax[wv] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float b = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        atomicMax(out, __float_as_uint(b));
     }
 }
 
@@ -146,7 +153,8 @@ sp_status coarse_step(sp_ctx* c, double dt)
     HIP_TRY(c, hipGetLastError());
     if (c->cpl_ncl == 0 || c->N0 <= c->n_t) return SP_OK;   // no update in the next coarse step
     HIP_TRY(c, hipMemsetAsync(c->cpl_rreq, 0, sizeof(unsigned int), c->stream));
-    hipLaunchKernelGGL(window_radius_kernel, dim3(c->cpl_ncl), dim3(64), 0, c->stream, c->cpl_cells, c->cpl_ncl,
+    const int rgrid = std::min((c->cpl_ncl + 3) / 4, 2 * c->num_cus);
+    hipLaunchKernelGGL(window_radius_kernel, dim3(rgrid), dim3(256), 0, c->stream, c->cpl_cells, c->cpl_ncl,
                        c->cell_start, c->r, c->cpl_x0, c->Q[0], c->ncells, inv_area, c->cpl_rreq);
     HIP_TRY(c, hipGetLastError());
     unsigned int bits = 0;
@@ -162,7 +170,7 @@ sp_status nudge(sp_ctx* c, double frac)
 {
     if (c->cpl_ncl == 0) return SP_OK;
     const double area = c->p.cell_lx * c->p.cell_ly;
-    hipLaunchKernelGGL(resync_kernel, dim3(c->cpl_ncl), dim3(256), 0, c->stream, c->cpl_cells, c->cell_start, c->r,
+    hipLaunchKernelGGL(resync_kernel, dim3(c->cpl_ncl), dim3(64), 0, c->stream, c->cpl_cells, c->cell_start, c->r,
                        c->h, c->u, c->v, c->w, nullptr, c->cpl_x0, c->Q[0], frac, c->ncells, c->p.rho_ice, area,
                        c->r_bin, nullptr, c->vdisp, c->cpl_count);
     HIP_TRY(c, hipGetLastError());

@@ -27,34 +27,23 @@ namespace spdem {
 
 enum { RS_OK = 0, RS_CLAMPED = 1, RS_INVALID = 2 };
 
-// Sum / max over a 256-thread workgroup: xor butterflies within each
-// wavefront, then the four wavefront results in a fixed order (every thread
-// gets the same value; the order does not depend on timing).
-__device__ __forceinline__ double block_sum256(double x, double* sh)
+// Sum / max over one wavefront, taken from lane 0 so that every lane uses the
+// same value (xor butterflies leave each lane a sum in its own order).
+__device__ __forceinline__ double wave_sum_d(double x)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[wv] = x;
-    __syncthreads();
-    const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    __syncthreads();
-    return t;
+    return __shfl(x, 0, 64);
 }
 
-__device__ __forceinline__ float block_max256(float x, float* sh)
+__device__ __forceinline__ float wave_max_f(float x)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[wv] = x;
-    __syncthreads();
-    const float t = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-    __syncthreads();
-    return t;
+    return __shfl(x, 0, 64);
 }
 
-// One workgroup of 256 threads per listed cell.  Targets: targets[ncl][4], or
+// One wavefront (64 threads) per listed cell.  Targets: targets[ncl][4], or
 // with x0m the coarse-to-fine update X0 + frac (Q - X0) of the cell (X0 =
 // (M, P_x, P_y, L) / area from the statistics x0m, Q [4][nc]).  The radius
 // scale is limited so that no radius exceeds r_lim (the contact-search bin
@@ -66,18 +55,15 @@ __device__ __forceinline__ float block_max256(float x, float* sh)
 // added to its displacement bound, since a radius that grows by g moves every
 // contact threshold of the floe as a displacement by g would.  With counters,
 // clamped and invalid cells are also counted into counters[0] and counters[1].
-__global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
-                                                     const float* h, float* u, float* v, float* w,
-                                                     const double* targets, const double* x0m, const double* Qc,
-                                                     double frac, int nc, double rho_ice, double area,
-                                                     float r_lim, int32_t* status, float* vdisp,
-                                                     unsigned long long* counters)
+__global__ __launch_bounds__(64) void resync_kernel(const int32_t* cells, const int32_t* cell_start, float* r,
+                                                    const float* h, float* u, float* v, float* w,
+                                                    const double* targets, const double* x0m, const double* Qc,
+                                                    double frac, int nc, double rho_ice, double area, float r_lim,
+                                                    int32_t* status, float* vdisp, unsigned long long* counters)
 {
-    __shared__ double dsh[4];
-    __shared__ float fsh[4];
     const int c = cells[blockIdx.x];
     const int s = cell_start[c], n = cell_start[c + 1] - s;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     double tg[4];
     if (x0m) {
         const double* st = x0m + (size_t)c * kMomStride;
@@ -90,7 +76,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
         for (int f = 0; f < 4; ++f) tg[f] = targets[(size_t)blockIdx.x * 4 + f];
     }
     if (n == 0) {
-        if (tid == 0 && status)
+        if (lane == 0 && status)
             status[blockIdx.x] = (tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0 || tg[3] != 0.0) ? RS_INVALID : RS_OK;
         return;
     }
@@ -98,7 +84,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
 #pragma unroll
     for (int f = 0; f < 4; ++f) finite = finite && isfinite(tg[f]);
     if (!finite || !(tg[0] > 0.0)) {
-        if (tid == 0) {
+        if (lane == 0) {
             if (status) status[blockIdx.x] = RS_INVALID;
             if (counters) atomicAdd(&counters[1], 1ull);
         }
@@ -107,13 +93,14 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     // mass and largest radius of the cell
     double m0 = 0.0;
     float r0 = 0.0f;
-    for (int l = tid; l < n; l += 256) {
-        const double rl = r[s + l];
+    for (int l = lane; l < n; l += 64) {
+        const float rf = r[s + l];
+        const double rl = rf;
         m0 += rho_ice * (double)h[s + l] * kPi * rl * rl;
-        r0 = fmaxf(r0, r[s + l]);
+        r0 = fmaxf(r0, rf);
     }
-    const double mass = block_sum256(m0, dsh);
-    const float rmax = block_max256(r0, fsh);
+    const double mass = wave_sum_d(m0);
+    const float rmax = wave_max_f(r0);
     double sc = sqrt(tg[0] * area / mass);
     const double lim = (double)r_lim / (double)rmax;
     const bool clamped = sc > lim;
@@ -121,7 +108,7 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     // rescale the radii, then the sums of the rescaled cell
     double acc[5] = {0, 0, 0, 0, 0};   // M, sum m u, sum m v, L, sum I
     float grow = 0.0f;
-    for (int l = tid; l < n; l += 256) {
+    for (int l = lane; l < n; l += 64) {
         const float ro = r[s + l];
         const float rn = fminf((float)((double)ro * sc), r_lim);
         grow = fmaxf(grow, rn - ro);   // rounded to nearest; rounded up below
@@ -136,24 +123,24 @@ __global__ __launch_bounds__(256) void resync_kernel(const int32_t* cells, const
     }
     double tot[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) tot[k] = block_sum256(acc[k], dsh);
-    const float gmax = block_max256(grow, fsh);
-    if (tid == 0 && vdisp && gmax > 0.0f) {
+    for (int k = 0; k < 5; ++k) tot[k] = wave_sum_d(acc[k]);
+    const float gmax = wave_max_f(grow);
+    if (lane == 0 && vdisp && gmax > 0.0f) {
         // rn - ro is exact or one rounding off; two ulps of margin on the
         // difference and on the sum keep the bound an upper bound
         const float g = gmax * (1.0f + 0x1p-22f);
         vdisp[c] = (vdisp[c] + g) * (1.0f + 0x1p-22f);
     }
-    if (tid == 0 && counters && clamped) atomicAdd(&counters[0], 1ull);
+    if (lane == 0 && counters && clamped) atomicAdd(&counters[0], 1ull);
     const double dvx = (tg[1] * area - tot[1]) / tot[0];
     const double dvy = (tg[2] * area - tot[2]) / tot[0];
     const double dw = (tg[3] * area - tot[3]) / tot[4];
-    for (int l = tid; l < n; l += 256) {
+    for (int l = lane; l < n; l += 64) {
         u[s + l] = (float)((double)u[s + l] + dvx);
         v[s + l] = (float)((double)v[s + l] + dvy);
         w[s + l] = (float)((double)w[s + l] + dw);
     }
-    if (tid == 0 && status) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
+    if (lane == 0 && status) status[blockIdx.x] = clamped ? RS_CLAMPED : RS_OK;
 }
 
 // Continuum step of the hybrid: closure cells Qb + dT T (Qb: the base-updated
@@ -333,7 +320,7 @@ sp_status restart_reduced(sp_ctx* c, const int32_t* cells_d, int ncl, const int3
 sp_status resync_list(sp_ctx* c, const int32_t* cells_d, int ncl, const double* targets_d, int32_t* status_d)
 {
     if (ncl <= 0) return SP_OK;
-    hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(256), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
+    hipLaunchKernelGGL(resync_kernel, dim3(ncl), dim3(64), 0, c->stream, cells_d, c->cell_start, c->r, c->h, c->u,
                        c->v, c->w, targets_d, nullptr, nullptr, 0.0, c->ncells, c->p.rho_ice,
                        c->p.cell_lx * c->p.cell_ly, c->r_bin, status_d, nullptr, nullptr);
     HIP_TRY(c, hipGetLastError());
