@@ -329,3 +329,73 @@ def mlp_init(seed: int) -> np.ndarray:
         parts.append(rng.uniform(-bound, bound, (MLP_SIZES[l], fan_in)).reshape(-1))
         parts.append(np.zeros(MLP_SIZES[l]))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ------------------------------------------------ the paper's error scenarios
+# Sec. 4.1-4.3 are nondimensional: domain [0, 4] x [0, 2], floes of radius
+# r = r_c (0.2 + 0.8 sin(0.25 pi x)) at the centres of a 480 x 240 fine grid
+# (r_c = 1/240, half the fine-cell side), all moving with (0.3, 0) at first.
+# The paper gives no densities, drag coefficient or contact constants; these
+# are proposed: unit densities and thickness, a drag rate Cd rho_o / (rho_ice h)
+# = 50 (relaxation time 0.2 at a 0.1 velocity difference), E = 1e4 and G = 1
+# (contact frequency times dt = 0.1 or less at dt = 1e-4, light damping).
+SCENARIO_CONSTANTS = dict(rho_ice=1.0, rho_ocean=1.0, cd=50.0, E=1.0e4, G=1.0, mu=0.3)
+
+
+def scenario_ocean(k: int) -> Ocean:
+    """Prescribed currents of Sec. 4.1 (uniform), 4.2 (0.3 - 0.1 cos(pi x), 0)
+    and 4.3 (0.3 - 0.1 sin(0.1 pi x) cos(pi y), 0.05 cos(0.1 pi x) sin(pi y)),
+    the last written as two plane modes."""
+    p = math.pi
+    u0 = float(np.float32(0.3))           # equal to the floes' stored velocity
+    if k == 1:
+        return Ocean(u0, 0.0)
+    if k == 2:
+        return Ocean(u0, 0.0, np.array([p]), np.array([0.0]), np.array([-0.1]), np.array([0.0]),
+                     np.array([0.5 * p]))
+    if k == 3:
+        return Ocean(u0, 0.0, np.array([0.1 * p, 0.1 * p]), np.array([p, -p]), np.array([-0.05, -0.05]),
+                     np.array([0.025, -0.025]), np.zeros(2))
+    raise ValueError(f"no scenario 4.{k}")
+
+
+def scenario_global(k: int, nfx: int = 480, nfy: int = 240, Lx: float = 4.0, Ly: float = 2.0,
+                    dt: float = 1e-4) -> Workload:
+    """The initial state of scenario 4.k as one global periodic DEM (a single
+    cell spanning the domain; positions are fractions of the domain)."""
+    fx = (np.arange(nfx) + 0.5) / nfx
+    fy = (np.arange(nfy) + 0.5) / nfy
+    X, Y = np.meshgrid(fx, fy)
+    xs, ys = X.reshape(-1), Y.reshape(-1)
+    rc = 0.5 * Ly / nfy
+    r = rc * (0.2 + 0.8 * np.sin(0.25 * math.pi * xs * Lx))
+    n = xs.size
+    xi = (np.round(xs * 2.0 ** 32) % 2.0 ** 32).astype(np.uint64).astype(np.uint32)
+    yi = (np.round(ys * 2.0 ** 32) % 2.0 ** 32).astype(np.uint64).astype(np.uint32)
+    z = np.zeros(n, np.float32)
+    w = Workload(f"scenario4.{k}", 1, 1, Lx, Ly, dt, 0, np.array([n], np.int32), xi, yi,
+                 np.full(n, 0.3, np.float32), z.copy(), z.copy(), z.copy(), r.astype(np.float32),
+                 np.ones(n, np.float32), scenario_ocean(k))
+    for key, val in SCENARIO_CONSTANTS.items():
+        setattr(w, key, val)
+    return w
+
+
+def split_cells(w: Workload, nxc: int, nyc: int) -> Workload:
+    """The floes of a global workload distributed over nxc x nyc cells: each
+    floe goes to the cell holding its centre, with cell-local fractions (the
+    superparameterised model's initial state on that coarse grid)."""
+    sx = w.xi.astype(np.uint64) * np.uint64(nxc)
+    sy = w.yi.astype(np.uint64) * np.uint64(nyc)
+    cx, cy = (sx >> np.uint64(32)).astype(np.int64), (sy >> np.uint64(32)).astype(np.int64)
+    lx = (sx & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    ly = (sy & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    cell = cy * nxc + cx
+    order = np.argsort(cell, kind="stable")
+    counts = np.bincount(cell, minlength=nxc * nyc).astype(np.int32)
+    out = Workload(f"{w.name}@{nxc}x{nyc}", nxc, nyc, w.Lx / nxc, w.Ly / nyc, w.dt, w.steps, counts,
+                   lx[order], ly[order], w.u[order], w.v[order], w.omega[order], w.theta[order], w.r[order],
+                   w.h[order], w.ocean)
+    for key in ("rho_ice", "rho_ocean", "cd", "E", "G", "mu"):
+        setattr(out, key, getattr(w, key))
+    return out

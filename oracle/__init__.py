@@ -261,3 +261,41 @@ def run_coupled(w, nsteps: int, N0: int, N1: int, n_t: int, flags: int = 0, stat
             for cell in np.flatnonzero(counts):
                 resync_cell(model, st, int(cell), x0[cell] + f * (Q[cell] - x0[cell]))
     return st, Q, moments(model, st), cfl
+
+
+def run_global(w, nsteps: int, flags: int = 0, state: State | None = None):
+    """The global DEM of the paper's error study (Sec. 4: one DEM over the whole
+    periodic domain, floes free to cross coarse cells, every pair a potential
+    contact): the cell DEM of a workload with a single cell spanning the domain.
+    Returns (state, stats)."""
+    if w.nx != 1 or w.ny != 1:
+        raise ValueError("a global workload has one cell spanning the domain")
+    model = Model(w, flags)
+    st = State.from_workload(w) if state is None else state
+    _, stats = dem_steps(model, st, w.dt, nsteps)
+    return st, stats
+
+
+def coarse_moments(w, state: State, nxc: int, nyc: int, flags: int = 0) -> np.ndarray:
+    """Statistics [nyc * nxc, 11] of a global state (positions as fractions of
+    the domain) on a coarse grid of nxc x nyc cells: each floe counts in the
+    cell that holds its centre (eq. meang over the cell's floes)."""
+    cx = np.minimum((state.xs * nxc).astype(np.int64), nxc - 1)
+    cy = np.minimum((state.ys * nyc).astype(np.int64), nyc - 1)
+    cell = cy * nxc + cx
+    order = np.argsort(cell, kind="stable")
+    counts = np.bincount(cell, minlength=nxc * nyc)
+    sub = Model.__new__(Model)
+    oc = w.ocean
+    sub._keep = [_f64(oc.kx), _f64(oc.ky), _f64(oc.au), _f64(oc.av), _f64(oc.phase)]
+    sub.c = _Model(nxc, nyc, w.Lx / nxc, w.Ly / nyc, w.rho_ice, w.rho_ocean, w.cd, w.E, w.G, w.mu,
+                   flags, oc.u0, oc.v0, oc.nmodes, *[_p(a) for a in sub._keep])
+    sub.nx, sub.ny, sub.Lx, sub.Ly = nxc, nyc, w.Lx / nxc, w.Ly / nyc
+    sub.ncells = nxc * nyc
+    sub.start = np.zeros(sub.ncells + 1, np.int64)
+    np.cumsum(counts, out=sub.start[1:])
+    xs = state.xs[order] * nxc - cx[order]
+    ys = state.ys[order] * nyc - cy[order]
+    part = State(xs, ys, state.u[order], state.v[order], state.w[order], state.th[order], state.r[order],
+                 state.h[order])
+    return moments(sub, part)
