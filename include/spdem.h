@@ -372,6 +372,58 @@ sp_status sp_hybrid_stats(sp_ctx* ctx, int32_t* dem_cells, int32_t* closure_cell
  * sub-bins per side it uses (1 for all-pairs). */
 sp_status sp_get_schedule(sp_ctx* ctx, int32_t* schedule, int32_t* bins_x, int32_t* bins_y);
 
+/* ------------------------------------------------------------ global DEM
+ * The reference of the paper's error study (Sec. 4): one DEM of the same floe
+ * system (Sec. 2.1: contact law, ocean drag and torque, semi-implicit update)
+ * over the whole doubly periodic domain, floes free to cross coarse cells and
+ * every pair a potential contact.  Positions are unsigned 32-bit fractions of
+ * the domain: X = lx * xi / 2^32; the ocean is evaluated at X as for sp_ctx.
+ * Contacts are searched in sub-bins of side >= 2 r_max (3 x 3 sweep, one
+ * sub-bin along an axis with fewer than 3), re-binned every step by a stable
+ * radix sort; decisions and forces match the cell DEM's.  Statistics for any
+ * coarse grid are read with sp_gdem_coarse_moments. */
+typedef struct sp_gdem sp_gdem;
+
+typedef struct {
+    double lx, ly;            /* domain size (length unit of the inputs) */
+    double rho_ice, rho_ocean, cd, E, G, mu;   /* as sp_params */
+    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER */
+} sp_gdem_params;
+
+/* Create a context on the current device (stream as sp_create).
+ * Errors: SP_EINVAL (null, non-positive size or density, negative constant),
+ * SP_EDEVICE. */
+sp_status sp_gdem_create(const sp_gdem_params* params, void* stream, sp_gdem** out);
+/* Release the context; NULL is ignored. */
+void sp_gdem_destroy(sp_gdem* g);
+/* Message of the last failing call (never NULL). */
+const char* sp_gdem_last_error(const sp_gdem* g);
+/* Ocean current, as sp_set_ocean.  Errors: SP_EINVAL. */
+sp_status sp_gdem_set_ocean(sp_gdem* g, double u0, double v0, int32_t nmodes, const double* kx,
+                            const double* ky, const double* au, const double* av, const double* phase);
+/* n >= 1 floes from host arrays of length n (copied; omega and theta may be
+ * NULL).  Floe i keeps index i in sp_gdem_read_floes.  Synchronises.
+ * Errors: SP_EINVAL (r <= 0, h <= 0, r_max >= min(lx, ly) / 4), SP_ENOMEM. */
+sp_status sp_gdem_set_floes(sp_gdem* g, int64_t n, const uint32_t* xi, const uint32_t* yi,
+                            const float* u, const float* v, const float* omega, const float* theta,
+                            const float* r, const float* h);
+/* nsteps fine steps of size dt.  Asynchronous.  Errors: SP_EINVAL, SP_ESTATE. */
+sp_status sp_gdem_step(sp_gdem* g, double dt, int64_t nsteps);
+/* Floe state into caller-owned host arrays of length n in input order (any
+ * may be NULL).  Synchronises; returns a latched device fault. */
+sp_status sp_gdem_read_floes(sp_gdem* g, uint32_t* xi, uint32_t* yi, float* u, float* v, float* omega,
+                             float* theta, float* r);
+/* The SP_NMOM statistics (order as SP_MOMENTS_DEM, drag at the current state)
+ * of every cell of an nxc x nyc coarse grid over the domain into out
+ * [nyc * nxc][SP_NMOM] (cell iy * nxc + ix); a floe counts in the cell holding
+ * its centre.  Synchronises.  Errors: SP_EINVAL (nxc, nyc < 1, more than 2^26
+ * cells, null out), SP_ESTATE. */
+sp_status sp_gdem_coarse_moments(sp_gdem* g, int32_t nxc, int32_t nyc, double* out);
+/* Contacts summed over steps (each pair once per step), steps taken and the
+ * sub-bins per side.  Synchronises. */
+sp_status sp_gdem_get_stats(sp_gdem* g, int64_t* contacts, int64_t* steps, int32_t* bins_x,
+                            int32_t* bins_y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,9 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_mlp_set_norm", "sp_mlp_get_norm", "sp_mlp_fit_norm", "sp_mlp_forward", "sp_mlp_gradient",
             "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample",
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
-            "sp_get_coupling"]
+            "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
+            "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
+            "sp_gdem_get_stats"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -55,6 +57,12 @@ class _Params(ctypes.Structure):
                 ("rho_ice", ctypes.c_double), ("rho_ocean", ctypes.c_double),
                 ("cd", ctypes.c_double), ("E", ctypes.c_double), ("G", ctypes.c_double),
                 ("mu", ctypes.c_double), ("flags", ctypes.c_uint32), ("schedule", ctypes.c_int32)]
+
+
+class _GParams(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_double), ("ly", ctypes.c_double), ("rho_ice", ctypes.c_double),
+                ("rho_ocean", ctypes.c_double), ("cd", ctypes.c_double), ("E", ctypes.c_double),
+                ("G", ctypes.c_double), ("mu", ctypes.c_double), ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -112,12 +120,25 @@ def load_library(path: str = LIB_PATH):
     lib.sp_step_hybrid.argtypes = [P, D, I64]
     lib.sp_hybrid_stats.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64),
                                     ctypes.POINTER(I64)]
+    lib.sp_gdem_create.argtypes = [ctypes.POINTER(_GParams), P, ctypes.POINTER(P)]
+    lib.sp_gdem_destroy.argtypes = [P]
+    lib.sp_gdem_last_error.argtypes = [P]
+    lib.sp_gdem_set_ocean.argtypes = [P, D, D, I32, P, P, P, P, P]
+    lib.sp_gdem_set_floes.argtypes = [P, I64, P, P, P, P, P, P, P, P]
+    lib.sp_gdem_step.argtypes = [P, D, I64]
+    lib.sp_gdem_read_floes.argtypes = [P, P, P, P, P, P, P, P]
+    lib.sp_gdem_coarse_moments.argtypes = [P, I32, I32, P]
+    lib.sp_gdem_get_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32),
+                                      ctypes.POINTER(I32)]
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error"):
+        if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error", "sp_gdem_destroy",
+                        "sp_gdem_last_error"):
             fn.restype = ctypes.c_int
     lib.sp_mlp_destroy.restype = None
     lib.sp_mlp_last_error.restype = ctypes.c_char_p
+    lib.sp_gdem_destroy.restype = None
+    lib.sp_gdem_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -401,3 +422,79 @@ class MLP:
         self._check(self._lib.sp_mlp_train_epoch(self._h, _p(X), _p(T), _p(perm), int(perm.shape[0]), int(batch),
                                                  float(lr), ctypes.byref(loss)))
         return float(loss.value)
+
+
+class GlobalDEM:
+    """The global DEM of the paper's error study (one context of the C
+    library): one periodic DEM over the whole domain, floes crossing cells."""
+
+    def __init__(self, lx, ly, rho_ice, rho_ocean, cd, E, G, mu, flags: int = 0, stream=None):
+        self._lib = load_library()
+        self.n = 0
+        prm = _GParams(lx, ly, rho_ice, rho_ocean, cd, E, G, mu, flags)
+        h = ctypes.c_void_p()
+        st = self._lib.sp_gdem_create(ctypes.byref(prm), None if stream is None else ctypes.c_void_p(stream),
+                                      ctypes.byref(h))
+        if st != 0:
+            raise SpdemError(st, "sp_gdem_create failed")
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, flags: int = 0, stream=None) -> "GlobalDEM":
+        """A global workload: one cell spanning the domain, positions as domain fractions."""
+        if w.nx != 1 or w.ny != 1:
+            raise ValueError("a global workload has one cell spanning the domain")
+        g = cls(w.Lx, w.Ly, w.rho_ice, w.rho_ocean, w.cd, w.E, w.G, w.mu, flags, stream)
+        oc = w.ocean
+        arrs = [_c(a, np.float64) for a in (oc.kx, oc.ky, oc.au, oc.av, oc.phase)]
+        g._check(g._lib.sp_gdem_set_ocean(g._h, float(oc.u0), float(oc.v0), int(arrs[0].size),
+                                          *[_p(a) for a in arrs]))
+        fl = [_c(w.xi, np.uint32), _c(w.yi, np.uint32)] + [_c(a, np.float32) for a in
+                                                         (w.u, w.v, w.omega, w.theta, w.r, w.h)]
+        g.n = int(fl[0].size)
+        g._check(g._lib.sp_gdem_set_floes(g._h, g.n, *[_p(a) for a in fl]))
+        return g
+
+    def _check(self, st):
+        if st != 0:
+            raise SpdemError(st, self._lib.sp_gdem_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sp_gdem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, dt: float, nsteps: int = 1):
+        self._check(self._lib.sp_gdem_step(self._h, float(dt), int(nsteps)))
+
+    def read_floes(self) -> dict:
+        n = self.n
+        out = dict(xi=np.zeros(n, np.uint32), yi=np.zeros(n, np.uint32), u=np.zeros(n, np.float32),
+                   v=np.zeros(n, np.float32), omega=np.zeros(n, np.float32), theta=np.zeros(n, np.float32),
+                   r=np.zeros(n, np.float32))
+        self._check(self._lib.sp_gdem_read_floes(self._h, *[_p(out[k]) for k in
+                                                          ("xi", "yi", "u", "v", "omega", "theta", "r")]))
+        return out
+
+    def coarse_moments(self, nxc: int, nyc: int) -> np.ndarray:
+        out = np.zeros((int(nxc) * int(nyc), NMOM), np.float64)
+        self._check(self._lib.sp_gdem_coarse_moments(self._h, int(nxc), int(nyc), _p(out)))
+        return out
+
+    def stats(self) -> dict:
+        c, s, bx, by = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.sp_gdem_get_stats(self._h, ctypes.byref(c), ctypes.byref(s), ctypes.byref(bx),
+                                                ctypes.byref(by)))
+        return dict(contacts=int(c.value), steps=int(s.value), bins=(int(bx.value), int(by.value)))

@@ -16,6 +16,7 @@
 // step k runs inside the DEM launch of step k + 1, and chunks of steady-state
 // steps are replayed as one captured HIP graph.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <math.h>
 #include <stdarg.h>
@@ -1230,3 +1231,4 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
 #include "closure_host.h"
 #include "hybrid_host.h"
 #include "coupling_host.h"
+#include "global_dem.h"
