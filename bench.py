@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--hybrid-steps", type=int, default=2000)
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the autotuned run of the uneven 128 x 128 workload")
+    ap.add_argument("--no-scenarios", action="store_true",
+                    help="skip the error study of Sec. 4.1-4.3 against the global DEM")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the plain64 run under the two-way coupling (N0 = 100, n_t = 10)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -186,6 +188,8 @@ def main():
         out["uneven"] = uneven_leg(stream)
     if not args.no_coupled:
         out["coupled"] = coupled_leg(stream)
+    if not args.no_scenarios:
+        out["scenarios"] = scenario_leg(stream)
     if not args.no_hybrid:
         out["hybrid"] = hybrid_leg(args, stream)
     if not args.no_cpu_baseline:
@@ -250,6 +254,24 @@ def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):
     return {"workload": "plain64", "N0": N0, "N1": N1, "n_t": n_t, "steps": steps, "ms_per_step": ms,
             "floe_steps_per_s": w.nfloes / (ms * 1e-3), "nudge_passes": cp["nudges"],
             "clamped_cell_updates": cp["clamped"], "invalid_cell_updates": cp["invalid"], "max_cfl": cfl}
+
+
+def scenario_leg(stream, ks=(1, 2, 3)):
+    """The paper's error study (Sec. 4.1-4.3): the superparameterised model at
+    N0 = 100, n_t = 10 on 24 x 12, 48 x 24 and 96 x 48 coarse grids against the
+    global DEM of the same 115,200 floes, L^2 errors at T = 0.2 and 1."""
+    from paper_2303_07819_amd import scenarios
+    out = {}
+    for k in ks:
+        r = scenarios.study(k, stream=stream.cuda_stream)
+        g = r["global_dem"]
+        out[r["scenario"]] = {"grids": r["grids"], "dX": r["dX"], "l2_conc": r["l2"]["conc"],
+                              "l2_vx": r["l2"]["vx"], "order_conc": r["order"]["conc"],
+                              "order_vx": r["order"]["vx"],
+                              "global_dem": {"floes": r["floes"], "steps": g["steps"], "seconds": g["seconds"],
+                                             "contacts": g["contacts"],
+                                             "floe_steps_per_s": r["floes"] * g["steps"] / g["seconds"]}}
+    return out
 
 
 def training_rate(hist):
