@@ -197,8 +197,11 @@ sp_status sp_get_stats(sp_ctx* ctx, int64_t* contacts, int64_t* steps, double* m
  * with one pair of HIP events recorded on the context's stream before the
  * first and after the last step's launches, and return the mean duration of a
  * step's DEM launches (ms) in *dem_ms: the elapsed time over nsteps, which
- * holds the kernels and the short gaps between back-to-back launches.  *lf_ms
- * is 0 because the continuum update runs inside those launches.  The state
+ * holds the kernels and the short gaps between back-to-back launches; *lf_ms
+ * is 0 because the continuum update runs inside those launches.  With blocked
+ * steps (sp_set_step_block) whole blocks run (nsteps rounded up to a multiple
+ * of k), events bracket every block's DEM launches, *dem_ms is their time per
+ * step and *lf_ms the time of the continuum updates per step.  The state
  * advances exactly as with sp_step.  Synchronises. */
 sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_ms, double* lf_ms);
 
@@ -226,6 +229,25 @@ sp_status sp_set_batching(sp_ctx* ctx, const int32_t* waves, const int32_t* pers
  * (may be NULL) receives the summed best step time of the buckets.
  * Synchronises.  Errors: SP_EINVAL, SP_ESTATE, SP_ENOMEM, SP_EDEVICE. */
 sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
+
+/* Temporal blocking of the plain step (coarse step = fine step): with k > 1,
+ * sp_step runs whole blocks of k steps as one DEM launch per count bucket in
+ * which every cell keeps its floes and candidate lists in LDS for the k steps
+ * (the cell DEMs never read the continuum at this cadence), each step's
+ * statistics going to a k-slot ring, followed by the k continuum updates;
+ * steps left over run one by one.  Applies when every bucket's cells fit one
+ * floe per lane, N0 = 1 and no hybrid is active.  The floe state is the same
+ * bit for bit as with k = 1; statistics are summed in another fixed order.
+ * Ring: k x ncells x 128 B.  Default 32.  Errors: SP_EINVAL (k outside
+ * [1, SP_MAX_STEP_BLOCK]). */
+#define SP_MAX_STEP_BLOCK 1024
+sp_status sp_set_step_block(sp_ctx* ctx, int32_t k);
+/* The block length and whether blocked steps currently apply (1) or not (0). */
+sp_status sp_get_step_block(sp_ctx* ctx, int32_t* k, int32_t* active);
+/* Work counted by blocked steps since sp_set_floes: candidate-list entries
+ * tested (over floes and steps) and the steps taken in blocks (either may be
+ * NULL).  Synchronises. */
+sp_status sp_get_work(sp_ctx* ctx, int64_t* candidate_tests, int64_t* blocked_steps);
 
 /* sp_step replays runs of `chunk` steps as one captured HIP graph (default 16;
  * 0 disables capture; must be even).  Results are identical either way. */

@@ -23,6 +23,7 @@ SP_OCEAN_OFF = 1
 SP_FORWARD_EULER = 2
 SP_NO_CONTINUUM = 4
 SP_MAX_COUPLING = 65536
+SP_MAX_STEP_BLOCK = 1024
 SCHED_AUTO, SCHED_ALLPAIRS, SCHED_BINNED = 0, 1, 2
 MOMENTS_DEM, MOMENTS_CONTINUUM = 0, 1
 NMOM = 11
@@ -40,7 +41,7 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
-            "sp_gdem_get_stats"]
+            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     lib.sp_set_batching.argtypes = [P, P, P]
     lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
     lib.sp_set_graph_chunk.argtypes = [P, I32]
+    lib.sp_set_step_block.argtypes = [P, I32]
+    lib.sp_get_step_block.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.sp_get_work.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.sp_set_coupling.argtypes = [P, I32, I32, I32]
     PI32, PI64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
     lib.sp_get_coupling.argtypes = [P, PI32, PI32, PI32, PI64, PI64, PI64, PI64]
@@ -285,6 +289,21 @@ class Sim:
 
     def set_graph_chunk(self, chunk: int):
         self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))
+
+    def set_step_block(self, k: int):
+        """Blocked plain steps: k steps per DEM launch (1: one launch per step)."""
+        self._check(self._lib.sp_set_step_block(self._h, int(k)))
+
+    def step_block(self) -> tuple:
+        k, act = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.sp_get_step_block(self._h, ctypes.byref(k), ctypes.byref(act)))
+        return int(k.value), bool(act.value)
+
+    def work(self) -> dict:
+        """Candidate tests and steps counted by blocked steps since the floes were set."""
+        t, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.sp_get_work(self._h, ctypes.byref(t), ctypes.byref(b)))
+        return dict(candidate_tests=int(t.value), blocked_steps=int(b.value))
 
     def set_coupling(self, N0: int, N1: int = 1, n_t: int = 1):
         """Coupling cadence of step(): coarse step of N0 fine steps in N1

@@ -1,0 +1,368 @@
+// K fine steps of a cell per launch (temporal blocking of the plain path).
+//
+// With the coarse step equal to the fine step the continuum never feeds back
+// into the cell DEMs (Algorithm 1 with N0 = 1 takes no coarse-to-fine update),
+// so a cell's floes can stay in LDS for K consecutive steps: the floe state and
+// candidate lists are read once, every step's statistics go to their own slot
+// of a K-slot ring for the continuum updates that follow the launch, and the
+// state is written back once.  Per step the work is the per-step kernel's:
+// list rebuild when the displacement bound passes half the skin (binned or
+// all-pairs search), the exact contact decision of every candidate, FP64 drag,
+// contact forces in ascending partner order, the update, the FP64 statistics
+// of the pre-step state.  Statistics are reduced by DPP row sums and four row
+// totals per wavefront (a fixed order).  One floe per lane: every cell of the
+// launch has at most 64 W floes.  Candidate tests (list entries examined) are
+// counted per cell, for the VALU accounting of the step.
+#pragma once
+
+namespace spdem {
+
+template <int SCHED, int W>
+// Five waves per SIMD: the step loop keeps more state live than one step does,
+// and five resident waves with a few spilled registers beat three without.
+__global__ __launch_bounds__(W >= 4 ? 64 * W : 256) __attribute__((amdgpu_waves_per_eu(5)))
+void dem_block_kernel(StepArgs a, int K)
+{
+    constexpr int G = 64 * W;                  // threads per group (one floe per lane)
+    constexpr int BT = G >= 256 ? G : 256;
+    constexpr int GPB = BT / G;
+    const int gpb = blockDim.x / G;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float4 mode_k[SP_MAX_MODES];
+    __shared__ float4 mode_c[GPB][SP_MAX_MODES];
+    __shared__ int wsum[GPB][W];
+    __shared__ float wdisp[BT / 64];
+    __shared__ unsigned long long csum[BT / 64];
+    __shared__ unsigned long long tsum[BT / 64];
+    __shared__ double rows[GPB][kDyn][4 * W];  // row totals of every statistic
+    __shared__ float vds[GPB];
+
+    const int tid = threadIdx.x;
+    const int g = tid / G, gt = tid % G;
+    unsigned char* gsm = smem + (size_t)g * a.group_bytes;
+    const int cap = a.cap;
+
+    if (tid < a.nmodes)
+        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
+
+    uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, theta bits
+    float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, h
+    uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy (binned search)
+    uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));
+    int* cnt = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
+    int* binof = reinterpret_cast<int*>(lst);                 // sort scratch inside the lists
+    int* rank = binof + cap;
+    int* bcnt = cnt + cap;
+    int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
+
+    const int item = blockIdx.x * gpb + g;
+    const bool valid = item < a.ncl;
+    const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
+    const int c = wk.x, s = wk.y, n = wk.z;
+    const bool has = valid && gt < n;          // this lane's floe
+    const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;
+    const unsigned long long tcell = (valid && gt == 0) ? a.cands[c] : 0ull;
+    const size_t slot_len = (size_t)a.ncells * kMomStride;
+    uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
+
+    if (valid && gt < a.nmodes) {
+        const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
+        mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
+    }
+    float vd = valid ? a.vdisp[c] : 0.0f;
+    if (has) {
+        P[gt] = make_uint4(a.xi[s + gt], a.yi[s + gt], __float_as_uint(a.r[s + gt]), __float_as_uint(a.th[s + gt]));
+        V[gt] = make_float4(a.u[s + gt], a.v[s + gt], a.w[s + gt], a.h[s + gt]);
+        if (vd <= 0.5f * a.skin) {   // the kept lists are valid for the first step
+            const int k = a.vcount[s + gt];
+            cnt[gt] = k;
+            uint16_t* my = lst + (size_t)gt * kListCap;
+            for (int q = 0; q < k; q += 8)
+                *reinterpret_cast<uint4*>(my + q) = *reinterpret_cast<const uint4*>(vlst + (size_t)q * n + (size_t)gt * 8);
+        }
+    }
+    bool rebuilt = false;
+    unsigned long long ctot = 0, ttot = 0;
+
+    for (int step = 0; step < K; ++step) {
+        const bool build = valid && !(vd <= 0.5f * a.skin);
+        const int nb_build = build ? n : 0;
+        if (build && has) cnt[gt] = 0;
+        const bool any_build = __syncthreads_or(build);
+        if (SCHED == 2 && any_build) {
+            const int nb = a.nbx * a.nby;
+            for (int b = gt; b < nb; b += G) bcnt[b] = 0;
+            __syncthreads();
+            if (gt < nb_build) {
+                const int bx = (int)__umulhi(P[gt].x, (uint32_t)a.nbx);
+                const int by = (int)__umulhi(P[gt].y, (uint32_t)a.nby);
+                const int b = by * a.nbx + bx;
+                binof[gt] = b;
+                rank[gt] = atomicAdd(&bcnt[b], 1);
+            }
+            __syncthreads();
+            group_exclusive_scan<G>(bcnt, bstart, nb, gt, wsum[g]);
+            if (gt < nb_build) {
+                uint4 p = P[gt];
+                p.w = (uint32_t)gt | ((uint32_t)binof[gt] << 16);
+                S[bstart[binof[gt]] + rank[gt]] = p;
+            }
+            __syncthreads();
+        }
+        // ---- candidate lists (rebuilding cells only)
+        if (SCHED == 1) {
+            if (gt < nb_build) {
+                const uint4 pl = P[gt];
+                const float rl = __uint_as_float(pl.z) + a.skin;
+                uint16_t* my = lst + (size_t)gt * kListCap;
+                int k = 0;
+                for (int j = 0; j < n; ++j) {
+                    const uint4 pj = P[j];
+                    float diff, R2;
+                    screen((int)(pj.x - pl.x), (int)(pj.y - pl.y), rl, __uint_as_float(pj.z), a.qx, a.qy, diff, R2);
+                    if (diff < kGuard * R2) {
+                        if (k < kListCap) my[k] = (uint16_t)j;
+                        ++k;
+                    }
+                }
+                cnt[gt] = k;
+            }
+        } else if (gt < nb_build) {
+            const int t = gt;
+            const uint4 own = S[t];
+            const int o = (int)(own.w & 0xffffu);
+            const int b = (int)(own.w >> 16);
+            const int bx = b % a.nbx, by = b / a.nbx;
+            const float rl = __uint_as_float(own.z) + a.skin;
+            if (a.nbx >= 3 && bx + 1 < a.nbx) {
+                sweep(S, t + 1, bstart[b + 2], own.x, own.y, rl, o, lst, cnt, a);
+            } else {
+                sweep(S, t + 1, bstart[b + 1], own.x, own.y, rl, o, lst, cnt, a);
+                if (a.nbx >= 3) {
+                    const int be = by * a.nbx;
+                    sweep(S, bstart[be], bstart[be + 1], own.x, own.y, rl, o, lst, cnt, a);
+                }
+            }
+            if (a.nby >= 3) {
+                const int row = (by + 1 == a.nby ? 0 : by + 1) * a.nbx;
+                if (a.nbx < 3) {
+                    sweep(S, bstart[row], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                } else if (bx == 0) {
+                    sweep(S, bstart[row], bstart[row + 2], own.x, own.y, rl, o, lst, cnt, a);
+                    sweep(S, bstart[row + a.nbx - 1], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                } else if (bx == a.nbx - 1) {
+                    sweep(S, bstart[row + a.nbx - 2], bstart[row + a.nbx], own.x, own.y, rl, o, lst, cnt, a);
+                    sweep(S, bstart[row], bstart[row + 1], own.x, own.y, rl, o, lst, cnt, a);
+                } else {
+                    sweep(S, bstart[row + bx - 1], bstart[row + bx + 2], own.x, own.y, rl, o, lst, cnt, a);
+                }
+            }
+        }
+        __syncthreads();
+
+        double acc[kDyn];
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
+        unsigned long long ncontact = 0, ntest = 0;
+        float maxdisp = 0.0f;
+        uint4 pn = make_uint4(0, 0, 0, 0);
+        float4 vn4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (has) {
+            const int l = gt;
+            const uint4 pl = P[l];
+            const float4 vv = V[l];
+            const uint32_t xl = pl.x, yl = pl.y;
+            const float rl = __uint_as_float(pl.z);
+            const float ul = vv.x, vl = vv.y, wl = vv.z;
+            const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
+            double fdx = 0.0, fdy = 0.0, tdr = 0.0;
+            if (!(a.flags & SP_OCEAN_OFF)) {
+                const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
+                const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
+                float uo = a.u0, vo = a.v0, zeta = 0.0f;
+                ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
+                const double du = (double)uo - uld, dv = (double)vo - vld;
+                const double sp = sqrt(du * du + dv * dv);
+                const double alpha = a.cdrho * kPi * rld * rld;
+                fdx = alpha * du * sp;
+                fdy = alpha * dv * sp;
+                const double dW = 0.5 * (double)zeta - wld;
+                const double r2 = rld * rld;
+                const double beta = a.cdrho * kPi * r2 * r2 * rld;
+                tdr = beta * dW * fabs(dW);
+            }
+            const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
+
+            uint16_t* my = lst + (size_t)l * kListCap;
+            int k = cnt[l];
+            if (build) {
+                if (k > kListCap) {
+                    atomicOr(a.err, kErrCapacity);
+                    k = kListCap;
+                    cnt[l] = k;
+                }
+                if (SCHED == 2) {
+                    for (int i = 1; i < k; ++i) {
+                        const uint16_t key = my[i];
+                        int j = i - 1;
+                        while (j >= 0 && my[j] > key) {
+                            my[j + 1] = my[j];
+                            --j;
+                        }
+                        my[j + 1] = key;
+                    }
+                }
+            }
+            ntest = (unsigned long long)k;
+            uint32_t cmask = 0;
+            for (int q0 = 0; q0 < k; q0 += 8) {
+                const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
+                const int qe = min(8, k - q0);
+                for (int t = 0; t < qe; ++t) {
+                    const uint32_t wv = t < 2 ? ix.x : t < 4 ? ix.y : t < 6 ? ix.z : ix.w;
+                    const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
+                    if (j == l) continue;
+                    const uint4 pj = P[j];
+                    if (decide((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a))
+                        cmask |= 1u << (q0 + t);
+                }
+            }
+            double Fx = fdx, Fy = fdy, T = tdr;
+            while (cmask) {
+                const int q = __builtin_ctz(cmask);
+                cmask &= cmask - 1u;
+                const int j = my[q];
+                const uint4 pj = P[j];
+                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
+                const float rj = __uint_as_float(pj.z);
+                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
+                const double d2 = dx * dx + dy * dy;
+                if (!(d2 > 0.0)) {
+                    atomicOr(a.err, kErrOverlap);
+                    continue;
+                }
+                const double rjd = (double)rj;
+                const double d = sqrt(d2);
+                const double inv_d = 1.0 / d;
+                const double nx = dx * inv_d, ny = dy * inv_d;
+                const double tx = -ny, ty = nx;
+                const double R = rld + rjd;
+                const double delta = d - R;
+                const double dr = fabs(rld - rjd);
+                double cc;
+                if (d <= dr) {
+                    cc = 2.0 * fmin(rld, rjd);
+                } else {
+                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
+                    cc = sqrt(fmax(p, 0.0)) * inv_d;
+                }
+                const double Fn = cc * a.Ed * delta;
+                const float4 vj = V[j];
+                const double wjd = (double)vj.z;
+                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
+                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
+                const double capf = a.mud * fabs(Fn);
+                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+                Fx += Fn * nx + Ft * tx;
+                Fy += Fn * ny + Ft * ty;
+                T += rld * Ft;
+                ncontact += (l < j) ? 1ull : 0ull;
+            }
+            const double inv_m = 1.0 / md;
+            const double dt = a.dtd;
+            const double und = uld + dt * (Fx * inv_m);
+            const double vnd = vld + dt * (Fy * inv_m);
+            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
+            const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
+            const int sx = __double2int_rn(dt * ux * a.inv_qxd);
+            const int sy = __double2int_rn(dt * vx * a.inv_qyd);
+            {
+                const float ddx = (float)sx * a.qx, ddy = (float)sy * a.qy;
+                maxdisp = sqrtf(ddx * ddx + ddy * ddy);
+            }
+            const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
+            pn = make_uint4(xl + (uint32_t)sx, yl + (uint32_t)sy, pl.z,
+                            __float_as_uint((float)((double)__uint_as_float(pl.w) + dt * wx)));
+            vn4 = make_float4(un, vn, wn, vv.w);
+            if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);
+            acc[0] = md * uld;
+            acc[1] = md * vld;
+            acc[2] = md * rld * rld * wld;
+            acc[3] = uld;
+            acc[4] = vld;
+            acc[5] = fdx;
+            acc[6] = fdy;
+            acc[7] = tdr;
+        }
+        // ---- group reductions (the floe data is still read by nobody after this barrier)
+        const unsigned long long cs = wave_sum_u64(ncontact);
+        const unsigned long long ts = wave_sum_u64(ntest);
+        const float wd = wave_max_f32(maxdisp);
+#pragma unroll
+        for (int k = 0; k < kDyn; ++k) {
+            const double x = row_sum(acc[k]);
+            if ((gt & 15) == 15) rows[g][k][gt >> 4] = x;
+        }
+        if ((tid & 63) == 0) {
+            csum[tid >> 6] = cs;
+            tsum[tid >> 6] = ts;
+            wdisp[tid >> 6] = wd;
+        }
+        __syncthreads();
+        if (has) {                               // the new state, for the next step
+            P[gt] = pn;
+            V[gt] = vn4;
+        }
+        if (valid && gt < kDyn) {
+            double x = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4 * W; ++q) x += rows[g][gt][q];
+            const int slot = dyn_slot(gt);
+            double* const mo = a.mom + (size_t)step * slot_len + (size_t)c * kMomStride;
+            mo[slot] = x;
+            if (slot == M_UX || slot == M_UY) mo[slot == M_UX ? M_UBAR : M_VBAR] = n > 0 ? x / (double)n : 0.0;
+        }
+        if (valid && gt == 0) {
+            float d = 0.0f;
+            unsigned long long t = 0, tt = 0;
+            for (int q = 0; q < W; ++q) {
+                d = fmaxf(d, wdisp[g * W + q]);
+                t += csum[g * W + q];
+                tt += tsum[g * W + q];
+            }
+            ctot += t;
+            ttot += tt;
+            vds[g] = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
+        }
+        rebuilt = rebuilt || build;
+        __syncthreads();
+        vd = valid ? vds[g] : 0.0f;
+    }
+
+    // ---- state, lists, bound and contact count back to HBM
+    if (has) {
+        const uint4 p = P[gt];
+        const float4 v = V[gt];
+        a.xi[s + gt] = p.x;
+        a.yi[s + gt] = p.y;
+        a.th[s + gt] = __uint_as_float(p.w);
+        a.u[s + gt] = v.x;
+        a.v[s + gt] = v.y;
+        a.w[s + gt] = v.z;
+        if (rebuilt) {
+            const int k = cnt[gt];
+            const uint16_t* my = lst + (size_t)gt * kListCap;
+            for (int q = 0; q < k; ++q) vlst[(size_t)(q & ~7) * n + (size_t)gt * 8 + (q & 7)] = my[q];
+            a.vcount[s + gt] = (uint8_t)k;
+        }
+    }
+    if (valid && gt == 0) {
+        a.vdisp[c] = vd;
+        a.contacts[c] = ccell + ctot;
+        a.cands[c] = tcell + ttot;
+    }
+}
+
+}  // namespace spdem

@@ -82,6 +82,7 @@ struct StepArgs {
     double* mom_alt;           // where the statistics of work entries with w = 1 go instead
     uint32_t* err;
     unsigned long long* contacts;   // [ncells] contacts counted per cell since the floes were set
+    unsigned long long* cands;      // [ncells] candidate tests counted per cell by blocked steps
     // candidate lists kept between steps (Verlet lists with a skin): per cell,
     // from floe-index start * kListCap, [kListCap / 8][n][8] (groups of eight
     // entries per floe), partner indices in ascending order; per floe its

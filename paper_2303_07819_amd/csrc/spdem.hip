@@ -33,6 +33,7 @@
 
 #include "../../include/spdem.h"
 #include "dem_kernels.h"
+#include "block_kernels.h"
 
 using namespace spdem;
 
@@ -43,6 +44,7 @@ constexpr double kSkinFrac = 0.3;   // smallest candidate-list skin, in units of
 constexpr int kBucketHi[kNumBuckets] = {64, 128, 256, 512, SP_MAX_CELL_FLOES};
 constexpr int kDefaultWaves[kNumBuckets] = {1, 2, 4, 4, 8};
 constexpr int kDefaultGraphChunk = 16;
+constexpr int kDefaultStepBlock = 32;   // steps per blocked DEM launch
 
 struct Bucket {
     int waves = 4;
@@ -98,6 +100,7 @@ struct sp_ctx {
     double* Q[2] = {nullptr, nullptr};      // continuum of time level k in Q[k & 1]
     uint32_t* err_d = nullptr;
     unsigned long long* contacts_d = nullptr;
+    unsigned long long* cands_d = nullptr;  // candidate tests per cell (blocked steps)
     unsigned long long* cfl_bits_d = nullptr;
     float* desc = nullptr;                  // closure descriptors [ncells][6] (lazy)
     bool desc_stale = false;                // radii changed since desc and mf were computed
@@ -129,6 +132,12 @@ struct sp_ctx {
     unsigned long long* cpl_count = nullptr;   // clamped, invalid cell updates
     unsigned int* cpl_rreq = nullptr;       // radius the next coarse step's updates may reach (float bits)
     int64_t cpl_replans = 0;                // contact-search re-plans at coarse steps
+
+    // temporal blocking of the plain step: K steps per DEM launch (1: per step)
+    int32_t block_k = kDefaultStepBlock;
+    double* blk_ring = nullptr;             // [block_k][ncells][kMomStride] statistics of a block's steps
+    int32_t blk_ring_slots = 0;
+    int64_t blk_steps = 0;                  // steps taken in blocks since the floes were set
 
     // graph replay
     int graph_chunk = kDefaultGraphChunk;
@@ -208,7 +217,8 @@ void free_all(sp_ctx* c)
     coupling_free(c);
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
-                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d};
+                  c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d,
+                  c->blk_ring, c->cands_d};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -232,6 +242,9 @@ void free_all(sp_ctx* c)
     c->vdisp = nullptr;
     c->empty_d = nullptr;
     c->nempty = 0;
+    c->blk_ring = nullptr;
+    c->blk_ring_slots = 0;
+    c->cands_d = nullptr;
 }
 
 // LDS bytes of one group (one cell) for a schedule, capacity and W.
@@ -274,6 +287,7 @@ StepArgs make_args(const sp_ctx* c, double dt)
     a.skin = c->skin;
     a.err = c->err_d;
     a.contacts = c->contacts_d;
+    a.cands = c->cands_d;
     a.max_cfl_bits = c->cfl_bits_d;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -423,6 +437,30 @@ sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads,
     SP_DISPATCH(prepare_t, c, threads, lds, cap, resident)
 }
 
+template <int SCHED, int W>
+sp_status launch_block_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K)
+{
+    if (lds > 65536)
+        HIP_TRY(c, hipFuncSetAttribute((const void*)dem_block_kernel<SCHED, W>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((dem_block_kernel<SCHED, W>), dim3(grid), dim3(threads), lds, c->stream, a, K);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
+sp_status launch_block_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, int grid, int threads, size_t lds,
+                           int K)
+{
+    const bool binned = sched == SP_SCHED_BINNED;
+    switch (waves) {
+    case 1: return binned ? launch_block_t<2, 1>(c, a, grid, threads, lds, K) : launch_block_t<1, 1>(c, a, grid, threads, lds, K);
+    case 2: return binned ? launch_block_t<2, 2>(c, a, grid, threads, lds, K) : launch_block_t<1, 2>(c, a, grid, threads, lds, K);
+    case 4: return binned ? launch_block_t<2, 4>(c, a, grid, threads, lds, K) : launch_block_t<1, 4>(c, a, grid, threads, lds, K);
+    case 8: return binned ? launch_block_t<2, 8>(c, a, grid, threads, lds, K) : launch_block_t<1, 8>(c, a, grid, threads, lds, K);
+    default: return fail(c, SP_EINVAL, "no blocked kernel for waves=%d", waves);
+    }
+}
+
 size_t bucket_group_bytes(const sp_ctx* c, const Bucket& b)
 {
     return group_bytes(c->sched, b.cap, c->nbx * c->nby, b.waves);
@@ -492,6 +530,60 @@ sp_status flush_lf(sp_ctx* c)
                        c->Q[k & 1], c->Q[(k + 1) & 1], c->p.nx, c->p.ny, c->lf_dt, c->p.cell_lx,
                        c->p.cell_ly, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->cfl_bits_d, c->err_d);
     HIP_TRY(c, hipGetLastError());
+    c->lf_pending = false;
+    return SP_OK;
+}
+
+// Blocked steps apply when every cell of every bucket has one floe per lane,
+// the cadence is the plain one and no hybrid is active.
+bool block_eligible(const sp_ctx* c)
+{
+    if (c->block_k <= 1 || c->N0 > 1 || c->hyb) return false;
+    for (const auto& b : c->bk)
+        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
+    return true;
+}
+
+// One blocked launch per bucket: K steps of the plain path from level kstep,
+// statistics of step t into ring slot t; then the K continuum updates.
+sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr)
+{
+    const int K = c->block_k;
+    const size_t slot = (size_t)c->ncells * kMomStride;
+    if (!c->blk_ring || c->blk_ring_slots != K) {
+        SP_TRY(dalloc(c, &c->blk_ring, slot * (size_t)K));
+        HIP_TRY(c, hipMemsetAsync(c->blk_ring, 0, slot * (size_t)K * 8, c->stream));   // cells without floes
+        c->blk_ring_slots = K;
+    }
+    SP_TRY(flush_lf(c));
+    if (time_dem) HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (const auto& b : c->bk) {
+        if (b.cells_h.empty()) continue;
+        StepArgs a = base;
+        a.work = b.work_d;
+        a.ncl = (int32_t)b.cells_h.size();
+        a.cap = b.cap;
+        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
+        a.mom = c->blk_ring;
+        a.lf = 0;
+        const int gpb = bucket_gpb(c, b);
+        const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
+        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K));
+    }
+    if (time_dem) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    if (!(c->p.flags & SP_NO_CONTINUUM)) {
+        for (int t = 0; t < K; ++t) {
+            const int64_t k = c->kstep + t;
+            hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->blk_ring + t * slot,
+                               c->Q[k & 1], c->Q[(k + 1) & 1], c->p.nx, c->p.ny, base.dtd, c->p.cell_lx,
+                               c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d);
+            HIP_TRY(c, hipGetLastError());
+        }
+    }
+    c->kstep += K;
+    c->steps += K;
+    c->blk_steps += K;
     c->lf_pending = false;
     return SP_OK;
 }
@@ -677,6 +769,7 @@ sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out)
     sp_status st = SP_OK;
     if (!st) st = dalloc(c, &c->err_d, 1);
     if (!st) st = dalloc(c, &c->contacts_d, std::max<size_t>(1, (size_t)c->ncells));
+    if (!st) st = dalloc(c, &c->cands_d, std::max<size_t>(1, (size_t)c->ncells));
     if (!st) st = dalloc(c, &c->cfl_bits_d, 1);
     if (!st) st = dalloc(c, &c->momb[0], (size_t)c->ncells * kMomStride);
     if (!st) st = dalloc(c, &c->momb[1], (size_t)c->ncells * kMomStride);
@@ -685,6 +778,7 @@ sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out)
     if (!st) st = dalloc(c, &c->Q[1], (size_t)c->ncells * 4);
     if (!st && hipMemsetAsync(c->err_d, 0, sizeof(uint32_t), c->stream) != hipSuccess) st = SP_EDEVICE;
     if (!st && hipMemsetAsync(c->contacts_d, 0, (size_t)c->ncells * 8, c->stream) != hipSuccess) st = SP_EDEVICE;
+    if (!st && hipMemsetAsync(c->cands_d, 0, (size_t)c->ncells * 8, c->stream) != hipSuccess) st = SP_EDEVICE;
     if (!st && hipMemsetAsync(c->cfl_bits_d, 0, 8, c->stream) != hipSuccess) st = SP_EDEVICE;
     if (st) {
         sp_destroy(c);
@@ -804,6 +898,9 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     hybrid_free(c);   // its cell lists follow the floes
     coupling_free(c);   // so do the coupled cadence's
     c->cpl_nudges = 0;
+    if (c->blk_ring) (void)hipFree(c->blk_ring);   // and the blocked steps' statistics
+    c->blk_ring = nullptr;
+    c->blk_ring_slots = 0;
     c->have_floes = false;
     if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
     if (c->mf) (void)hipFree(c->mf);
@@ -866,6 +963,8 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     SP_TRY(prepare_buckets(c));
     HIP_TRY(c, hipMemsetAsync(c->err_d, 0, 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->contacts_d, 0, (size_t)c->ncells * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->cands_d, 0, (size_t)c->ncells * 8, c->stream));
+    c->blk_steps = 0;
     HIP_TRY(c, hipMemsetAsync(c->cfl_bits_d, 0, 8, c->stream));
     c->steps = 0;
     SP_TRY(upload_phase(c));
@@ -905,6 +1004,12 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
     c->t_now += dt * (double)nsteps;
     if (c->N0 > 1) return coupled_steps(c, base, nsteps);
     int64_t left = nsteps;
+    if (block_eligible(c)) {
+        while (left >= c->block_k) {
+            SP_TRY(block_chunk(c, base));
+            left -= c->block_k;
+        }
+    }
     while (left > 0) {
         const bool steady = (c->kstep % 2 == 0) && (c->lf_pending == cont);
         if (c->graph_chunk > 0 && c->graph_ok && steady && left >= c->graph_chunk) {
@@ -933,6 +1038,35 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
     if (c->N0 > 1) return fail(c, SP_ESTATE, "sp_profile_steps times the cadence N0 = 1");
     SP_TRY(upload_phase(c));
     if (c->lf_pending && c->lf_dt != dt) SP_TRY(flush_lf(c));
+    if (block_eligible(c)) {
+        // blocked steps: events around each chunk's DEM launches and around the
+        // whole run; the DEM time per step, and the rest (continuum updates) per step
+        const int64_t chunks = (nsteps + c->block_k - 1) / c->block_k;
+        std::vector<hipEvent_t> ev((size_t)chunks * 2 + 2);
+        for (auto& e : ev) HIP_TRY(c, hipEventCreate(&e));
+        const StepArgs base = make_args(c, dt);
+        c->t_now += dt * (double)(chunks * c->block_k);
+        sp_status st = SP_OK;
+        HIP_TRY(c, hipEventRecord(ev[2 * chunks], c->stream));
+        for (int64_t q = 0; q < chunks && !st; ++q) st = block_chunk(c, base, true, ev[2 * q], ev[2 * q + 1]);
+        HIP_TRY(c, hipEventRecord(ev[2 * chunks + 1], c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        double sd = 0.0;
+        float all = 0.0f;
+        for (int64_t q = 0; q < chunks && !st; ++q) {
+            float x = 0.0f;
+            if (hipEventElapsedTime(&x, ev[2 * q], ev[2 * q + 1]) != hipSuccess) st = fail(c, SP_EDEVICE, "event timing");
+            sd += x;
+        }
+        if (!st && hipEventElapsedTime(&all, ev[2 * chunks], ev[2 * chunks + 1]) != hipSuccess)
+            st = fail(c, SP_EDEVICE, "event timing");
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        if (st) return st;
+        const double per = (double)(chunks * c->block_k);
+        if (dem_ms) *dem_ms = sd / per;
+        if (lf_ms) *lf_ms = ((double)all - sd) / per;
+        return check_device_err(c);
+    }
     // One event pair around the whole run of back-to-back launches: an event
     // recorded between two launches costs a few microseconds of its own.
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1111,6 +1245,37 @@ sp_status sp_set_batching(sp_ctx* c, const int32_t* waves, const int32_t* persis
         c->bk[q].persist = persistent[q];
     }
     if (c->have_floes) SP_TRY(prepare_buckets(c));
+    return SP_OK;
+}
+
+sp_status sp_set_step_block(sp_ctx* c, int32_t k)
+{
+    if (!c) return SP_EINVAL;
+    if (k < 1 || k > SP_MAX_STEP_BLOCK) return fail(c, SP_EINVAL, "step block must be in [1, %d]", SP_MAX_STEP_BLOCK);
+    SP_TRY(flush_lf(c));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->block_k = k;
+    return SP_OK;
+}
+
+sp_status sp_get_work(sp_ctx* c, int64_t* candidate_tests, int64_t* blocked_steps)
+{
+    if (!c) return SP_EINVAL;
+    std::vector<unsigned long long> per_cell((size_t)c->ncells);
+    HIP_TRY(c, hipMemcpyAsync(per_cell.data(), c->cands_d, per_cell.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned long long t = 0;
+    for (unsigned long long x : per_cell) t += x;
+    if (candidate_tests) *candidate_tests = (int64_t)t;
+    if (blocked_steps) *blocked_steps = c->blk_steps;
+    return SP_OK;
+}
+
+sp_status sp_get_step_block(sp_ctx* c, int32_t* k, int32_t* active)
+{
+    if (!c) return SP_EINVAL;
+    if (k) *k = c->block_k;
+    if (active) *active = block_eligible(c) ? 1 : 0;
     return SP_OK;
 }
 
