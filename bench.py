@@ -52,8 +52,27 @@ def cpu_baseline(w, budget_s=12.0):
                       f"(brute-force contacts, FP64, OpenMP over cells)"}
 
 
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "dem_cell_kernel_plain64.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_07819_amd", "csrc", "dem_kernels.h")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "dem_block_kernel_plain64.md")
+# the blocked kernel and the helpers it shares with the per-step kernel
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_07819_amd", "csrc", "dem_kernels.h"),
+                  os.path.join(ROOT, "paper_2303_07819_amd", "csrc", "block_kernels.h")]
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one wave64 instruction occupies a SIMD for 4 cycles; non-packed FP32)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def valu_ops_per_floe_step(candidates_per_floe: float, contacts_per_floe: float) -> float:
+    """Algorithmic VALU operations of one floe-step: 12 per candidate test, 70
+    per contact, 160 for an 8-mode ocean, 50 for drag, update and statistics."""
+    return 12.0 * candidates_per_floe + 70.0 * contacts_per_floe + 160.0 + 50.0
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def copy_calibration(nbytes=1 << 30, reps=4):
@@ -71,10 +90,9 @@ def copy_calibration(nbytes=1 << 30, reps=4):
 def measured_traffic():
     """HBM bytes per DEM launch from the committed rocprofv3 counter summary,
     or None when the kernel source has changed since the counters were taken."""
-    import hashlib
     try:
         text = open(PROFILE_SUMMARY).read()
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        src = kernel_source_hash()
     except OSError:
         return None
     vals = {}
@@ -152,13 +170,39 @@ def main():
     ms_per_step = ms / args.steps
     value = w.nfloes * args.steps / (ms / 1e3)
 
-    # dominant kernel, timed live with one event pair around back-to-back launches on its stream
+    # dominant kernel, timed live with HIP events on its stream (blocked steps:
+    # events around every block's DEM launch); its work counted over the same steps
+    k_block, blocked = sim.step_block()
+    st0, wk0 = sim.stats(), sim.work()
     dem_ms, lf_ms = sim.profile_steps(w.dt, args.profile_steps)
-    stats = sim.stats()
-    bytes_launch = BYTES_PER_FLOE_STEP * w.nfloes + BYTES_PER_CELL_STEP * w.ncells
-    achieved = bytes_launch / (dem_ms * 1e-3) / 1e9
-    contacts_per_floe_step = stats["contacts"] * 2.0 / max(1, w.nfloes * stats["steps"])
+    st1, wk1 = sim.stats(), sim.work()
+    stats = st1
+    dsteps = st1["steps"] - st0["steps"]
+    contacts_per_floe_step = (st1["contacts"] - st0["contacts"]) * 2.0 / max(1, w.nfloes * dsteps)
+    candidates_per_floe_step = (wk1["candidate_tests"] - wk0["candidate_tests"]) / max(
+        1, w.nfloes * (wk1["blocked_steps"] - wk0["blocked_steps"]))
     sim.close()
+    if blocked:
+        # floes resident in LDS for k_block steps: VALU binds (state read and
+        # written once per launch, statistics every step)
+        ops = valu_ops_per_floe_step(candidates_per_floe_step, contacts_per_floe_step)
+        tops = ops * w.nfloes / (dem_ms * 1e-3) / 1e12
+        bytes_step = BYTES_PER_FLOE_STEP * w.nfloes / k_block + BYTES_PER_CELL_STEP * w.ncells
+        roofline = {"bound": "alu", "kernel": "dem_block_kernel", "achieved": tops, "peak": VALU_PEAK_TOPS,
+                    "unit": "TFLOP/s", "frac": tops / VALU_PEAK_TOPS, "traffic": measured_traffic(),
+                    "kernel_ms": dem_ms * k_block, "steps_per_launch": k_block, "lf_ms_per_step": lf_ms,
+                    "ops_per_floe_step": ops, "candidates_per_floe_step": candidates_per_floe_step,
+                    "contacts_per_floe_step": contacts_per_floe_step,
+                    "algorithmic_ops_per_launch": ops * w.nfloes * k_block,
+                    "hbm": {"algorithmic_bytes_per_launch": bytes_step * k_block,
+                            "achieved_GBs": bytes_step / (dem_ms * 1e-3) / 1e9,
+                            "frac": bytes_step / (dem_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    else:
+        bytes_launch = BYTES_PER_FLOE_STEP * w.nfloes + BYTES_PER_CELL_STEP * w.ncells
+        achieved = bytes_launch / (dem_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "dem_cell_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dem_ms,
+                    "lf_kernel_ms": lf_ms, "algorithmic_bytes_per_launch": bytes_launch}
 
     out = {
         "metric": "floe-steps/sec at 1 GPU (plain DEM vs DEM+closure) at stated moment error",
@@ -177,10 +221,7 @@ def main():
                    "floes": w.nfloes, "floes_per_cell": float(w.nfloes) / w.ncells, "dt_s": w.dt,
                    "schedule": ["auto", "allpairs", "binned"][sched[0]], "sub_bins": [sched[1], sched[2]],
                    "continuum": "lax-friedrichs every step"},
-        "roofline": {"bound": "hbm", "kernel": "dem_cell_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "kernel_ms": dem_ms, "lf_kernel_ms": lf_ms,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+        "roofline": roofline,
         "contacts_per_floe_step": contacts_per_floe_step,
         "wall_s_timed": wall,
     }
