@@ -135,8 +135,14 @@ struct sp_ctx {
 
     // temporal blocking of the plain step: K steps per DEM launch (1: per step)
     int32_t block_k = kDefaultStepBlock;
-    double* blk_ring = nullptr;             // [block_k][ncells][kMomStride] statistics of a block's steps
+    double* blk_ring = nullptr;             // [2][block_k][ncells][kMomStride] statistics of two blocks' steps
     int32_t blk_ring_slots = 0;
+    int blk_parity = 0;                     // ring half of the next block
+    hipStream_t lf_stream = nullptr;        // continuum updates of blocks (default priority)
+    hipEvent_t dem_done[2] = {nullptr, nullptr};
+    hipEvent_t lf_done[2] = {nullptr, nullptr};
+    bool lf_used[2] = {false, false};       // lf_done[i] was recorded
+    int lf_last = -1;                       // ring half whose updates were enqueued last, not yet joined
     int64_t blk_steps = 0;                  // steps taken in blocks since the floes were set
 
     // graph replay
@@ -544,19 +550,45 @@ bool block_eligible(const sp_ctx* c)
     return true;
 }
 
+// Make the library stream wait for the continuum updates of the last block
+// (they run on a stream of their own, beside the next block's DEM launch).
+sp_status join_block_lf(sp_ctx* c)
+{
+    if (c->lf_last < 0) return SP_OK;
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lf_done[c->lf_last], 0));
+    c->lf_last = -1;
+    return SP_OK;
+}
+
 // One blocked launch per bucket: K steps of the plain path from level kstep,
-// statistics of step t into ring slot t; then the K continuum updates.
+// statistics of step t into slot t of one half of the ring; then the K
+// continuum updates on the update stream, which overlap the next block's DEM
+// launch (that launch writes the other half; a half is written again only
+// after its updates are done).
 sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr)
 {
     const int K = c->block_k;
     const size_t slot = (size_t)c->ncells * kMomStride;
     if (!c->blk_ring || c->blk_ring_slots != K) {
-        SP_TRY(dalloc(c, &c->blk_ring, slot * (size_t)K));
-        HIP_TRY(c, hipMemsetAsync(c->blk_ring, 0, slot * (size_t)K * 8, c->stream));   // cells without floes
+        SP_TRY(join_block_lf(c));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        SP_TRY(dalloc(c, &c->blk_ring, 2 * slot * (size_t)K));
+        HIP_TRY(c, hipMemsetAsync(c->blk_ring, 0, 2 * slot * (size_t)K * 8, c->stream));   // cells without floes
         c->blk_ring_slots = K;
+        c->lf_used[0] = c->lf_used[1] = false;
+    }
+    if (!c->lf_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->lf_stream, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            HIP_TRY(c, hipEventCreateWithFlags(&c->dem_done[i], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->lf_done[i], hipEventDisableTiming));
+        }
     }
     SP_TRY(flush_lf(c));
+    const int r = c->blk_parity;
+    double* const ring = c->blk_ring + (size_t)r * K * slot;
+    if (c->lf_used[r]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lf_done[r], 0));
     if (time_dem) HIP_TRY(c, hipEventRecord(e0, c->stream));
     for (const auto& b : c->bk) {
         if (b.cells_h.empty()) continue;
@@ -565,7 +597,7 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hi
         a.ncl = (int32_t)b.cells_h.size();
         a.cap = b.cap;
         a.group_bytes = (int32_t)bucket_group_bytes(c, b);
-        a.mom = c->blk_ring;
+        a.mom = ring;
         a.lf = 0;
         const int gpb = bucket_gpb(c, b);
         const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
@@ -573,14 +605,22 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hi
     }
     if (time_dem) HIP_TRY(c, hipEventRecord(e1, c->stream));
     if (!(c->p.flags & SP_NO_CONTINUUM)) {
+        // everything enqueued on the library stream so far (this block's
+        // statistics, earlier continuum work) precedes the updates
+        HIP_TRY(c, hipEventRecord(c->dem_done[r], c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->lf_stream, c->dem_done[r], 0));
         for (int t = 0; t < K; ++t) {
             const int64_t k = c->kstep + t;
-            hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->blk_ring + t * slot,
+            hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->lf_stream, ring + t * slot,
                                c->Q[k & 1], c->Q[(k + 1) & 1], c->p.nx, c->p.ny, base.dtd, c->p.cell_lx,
                                c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d);
             HIP_TRY(c, hipGetLastError());
         }
+        HIP_TRY(c, hipEventRecord(c->lf_done[r], c->lf_stream));
+        c->lf_used[r] = true;
+        c->lf_last = r;
     }
+    c->blk_parity = r ^ 1;
     c->kstep += K;
     c->steps += K;
     c->blk_steps += K;
@@ -792,6 +832,12 @@ void sp_destroy(sp_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->lf_stream) (void)hipStreamSynchronize(c->lf_stream);
+    for (int i = 0; i < 2; ++i) {
+        if (c->dem_done[i]) (void)hipEventDestroy(c->dem_done[i]);
+        if (c->lf_done[i]) (void)hipEventDestroy(c->lf_done[i]);
+    }
+    if (c->lf_stream) (void)hipStreamDestroy(c->lf_stream);
     free_all(c);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -898,9 +944,12 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     hybrid_free(c);   // its cell lists follow the floes
     coupling_free(c);   // so do the coupled cadence's
     c->cpl_nudges = 0;
+    SP_TRY(join_block_lf(c));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->blk_ring) (void)hipFree(c->blk_ring);   // and the blocked steps' statistics
     c->blk_ring = nullptr;
     c->blk_ring_slots = 0;
+    c->lf_used[0] = c->lf_used[1] = false;
     c->have_floes = false;
     if (c->desc) (void)hipFree(c->desc);   // descriptors follow the floes
     if (c->mf) (void)hipFree(c->mf);
@@ -1009,6 +1058,7 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
             SP_TRY(block_chunk(c, base));
             left -= c->block_k;
         }
+        SP_TRY(join_block_lf(c));   // later work on the stream sees the continuum
     }
     while (left > 0) {
         const bool steady = (c->kstep % 2 == 0) && (c->lf_pending == cont);
@@ -1049,6 +1099,7 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
         sp_status st = SP_OK;
         HIP_TRY(c, hipEventRecord(ev[2 * chunks], c->stream));
         for (int64_t q = 0; q < chunks && !st; ++q) st = block_chunk(c, base, true, ev[2 * q], ev[2 * q + 1]);
+        if (!st) st = join_block_lf(c);
         HIP_TRY(c, hipEventRecord(ev[2 * chunks + 1], c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         double sd = 0.0;
