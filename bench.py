@@ -110,12 +110,12 @@ def measured_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=512)      # 16 blocks of 32 steps
+    ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--config", default="plain64")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--profile-steps", type=int, default=64)
     ap.add_argument("--no-hybrid", action="store_true",
                     help="skip training the closure and the DEM + closure run on the 512 x 512 grid")
     ap.add_argument("--hybrid-steps", type=int, default=2000)
@@ -174,7 +174,7 @@ def main():
     # events around every block's DEM launch); its work counted over the same steps
     k_block, blocked = sim.step_block()
     st0, wk0 = sim.stats(), sim.work()
-    dem_ms, lf_ms = sim.profile_steps(w.dt, args.profile_steps)
+    dem_ms, lf_ms = sim.profile_steps(w.dt, args.profile_steps)   # whole blocks when blocked
     st1, wk1 = sim.stats(), sim.work()
     stats = st1
     dsteps = st1["steps"] - st0["steps"]

@@ -560,13 +560,10 @@ sp_status join_block_lf(sp_ctx* c)
     return SP_OK;
 }
 
-// One blocked launch per bucket: K steps of the plain path from level kstep,
-// statistics of step t into slot t of one half of the ring; then the K
-// continuum updates on the update stream, which overlap the next block's DEM
-// launch (that launch writes the other half; a half is written again only
-// after its updates are done).
-sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr)
+// Statistics ring (two halves of block_k slots, zero rows for cells without
+// floes), update stream and events of blocked steps; allocated before the
+// first block (sp_set_floes, sp_set_step_block), so that no timed step pays it.
+sp_status block_prepare(sp_ctx* c)
 {
     const int K = c->block_k;
     const size_t slot = (size_t)c->ncells * kMomStride;
@@ -574,7 +571,7 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hi
         SP_TRY(join_block_lf(c));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         SP_TRY(dalloc(c, &c->blk_ring, 2 * slot * (size_t)K));
-        HIP_TRY(c, hipMemsetAsync(c->blk_ring, 0, 2 * slot * (size_t)K * 8, c->stream));   // cells without floes
+        HIP_TRY(c, hipMemsetAsync(c->blk_ring, 0, 2 * slot * (size_t)K * 8, c->stream));
         c->blk_ring_slots = K;
         c->lf_used[0] = c->lf_used[1] = false;
     }
@@ -585,6 +582,20 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hi
             HIP_TRY(c, hipEventCreateWithFlags(&c->lf_done[i], hipEventDisableTiming));
         }
     }
+    return SP_OK;
+}
+
+// One blocked launch per bucket: K steps of the plain path from level kstep,
+// statistics of step t into slot t of one half of the ring; then the K
+// continuum updates on the update stream, which overlap the next block's DEM
+// launch (that launch writes the other half; a half is written again only
+// after its updates are done).
+sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr)
+{
+    const int K = c->block_k;
+    const size_t slot = (size_t)c->ncells * kMomStride;
+    SP_TRY(block_prepare(c));
     SP_TRY(flush_lf(c));
     const int r = c->blk_parity;
     double* const ring = c->blk_ring + (size_t)r * K * slot;
@@ -1010,6 +1021,7 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     c->n = n;
     SP_TRY(build_buckets(c, counts));
     SP_TRY(prepare_buckets(c));
+    if (block_eligible(c)) SP_TRY(block_prepare(c));
     HIP_TRY(c, hipMemsetAsync(c->err_d, 0, 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->contacts_d, 0, (size_t)c->ncells * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->cands_d, 0, (size_t)c->ncells * 8, c->stream));
@@ -1306,6 +1318,7 @@ sp_status sp_set_step_block(sp_ctx* c, int32_t k)
     SP_TRY(flush_lf(c));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->block_k = k;
+    if (c->have_floes && block_eligible(c)) SP_TRY(block_prepare(c));
     return SP_OK;
 }
 
