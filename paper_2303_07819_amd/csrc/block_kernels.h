@@ -17,11 +17,54 @@
 
 namespace spdem {
 
-template <int SCHED, int W>
+// Coarse-to-fine update at the end of a block (two-way coupling, Sec. 3.3):
+// every cell of the launch is re-synchronised to X0 + frac (Q - X0) exactly as
+// resync_kernel does (radii scaled by one factor up to r_lim, then uniform
+// velocity and spin shifts), its floes still in LDS.  Inactive: x0m == null.
+struct BlockNudge {
+    const double* x0m;                 // [ncells][kMomStride] statistics at the coarse-step start
+    const double* Q;                   // [4][ncells] coarse state
+    double frac;
+    double area;
+    float r_lim;
+    float* r;                          // radii (the launch's floes are rescaled in place)
+    unsigned long long* counters;      // clamped, invalid cell updates
+};
+
+// Sum of one value per lane over a group of W wavefronts: DPP row sums, then
+// the 4 W row totals in a fixed order (every lane gets the same value).  Every
+// thread of the workgroup calls it.
+template <int W>
+__device__ __forceinline__ double group_sum_rows(double x, double* rows_g, int gt)
+{
+    x = row_sum(x);
+    if ((gt & 15) == 15) rows_g[gt >> 4] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4 * W; ++q) t += rows_g[q];
+    __syncthreads();
+    return t;
+}
+
+template <int W>
+__device__ __forceinline__ float group_max(float x, float* wmax_g, int gt)
+{
+    x = wave_max_f32(x);
+    if ((gt & 63) == 0) wmax_g[gt >> 6] = x;
+    __syncthreads();
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < W; ++q) t = fmaxf(t, wmax_g[q]);
+    __syncthreads();
+    return t;
+}
+
 // Five waves per SIMD: the step loop keeps more state live than one step does,
 // and five resident waves with a few spilled registers beat three without.
+template <int SCHED, int W>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) __attribute__((amdgpu_waves_per_eu(5)))
-void dem_block_kernel(StepArgs a, int K)
+void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 {
     constexpr int G = 64 * W;                  // threads per group (one floe per lane)
     constexpr int BT = G >= 256 ? G : 256;
@@ -339,6 +382,55 @@ void dem_block_kernel(StepArgs a, int K)
         rebuilt = rebuilt || build;
         __syncthreads();
         vd = valid ? vds[g] : 0.0f;
+    }
+
+    // ---- coarse-to-fine update of the cell (coupled cadence)
+    if (nd.x0m) {
+        double tg[4] = {0.0, 0.0, 0.0, 0.0};
+        if (valid) {
+            const double* st = nd.x0m + (size_t)c * kMomStride;
+            const double inv_area = 1.0 / nd.area;
+            const double x0[4] = {st[M_MASS] * inv_area, st[M_PX] * inv_area, st[M_PY] * inv_area,
+                                  st[M_L] * inv_area};
+#pragma unroll
+            for (int f = 0; f < 4; ++f) tg[f] = x0[f] + nd.frac * (nd.Q[(size_t)f * a.ncells + c] - x0[f]);
+        }
+        const bool ok = valid && n > 0 && isfinite(tg[0]) && isfinite(tg[1]) && isfinite(tg[2]) &&
+                        isfinite(tg[3]) && tg[0] > 0.0;
+        if (valid && !ok && gt == 0 && nd.counters) atomicAdd(&nd.counters[1], 1ull);
+        const uint4 p0 = has ? P[gt] : make_uint4(0, 0, 0, 0);
+        const float4 v0 = has ? V[gt] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float ro = __uint_as_float(p0.z);
+        const double rod = ro;
+        const double mass = group_sum_rows<W>(has ? a.rho_ice_d * (double)v0.w * kPi * rod * rod : 0.0,
+                                              rows[g][0], gt);
+        const float rmax = group_max<W>(has ? ro : 0.0f, wdisp + g * W, gt);
+        double sc = ok ? sqrt(tg[0] * nd.area / mass) : 1.0;
+        const bool clamped = ok && sc > (double)nd.r_lim / (double)rmax;
+        if (clamped) sc = (double)nd.r_lim / (double)rmax;
+        const float rn = (ok && has) ? fminf((float)(rod * sc), nd.r_lim) : ro;
+        const double rnd = rn;
+        const double m = has ? a.rho_ice_d * (double)v0.w * kPi * rnd * rnd : 0.0;
+        const double M = group_sum_rows<W>(m, rows[g][1], gt);
+        const double Px = group_sum_rows<W>(m * (double)v0.x, rows[g][2], gt);
+        const double Py = group_sum_rows<W>(m * (double)v0.y, rows[g][3], gt);
+        const double L = group_sum_rows<W>(m * rnd * rnd * (double)v0.z, rows[g][4], gt);
+        const double I = group_sum_rows<W>(m * rnd * rnd, rows[g][5], gt);
+        const float gmax = group_max<W>(has ? rn - ro : 0.0f, wdisp + g * W, gt);
+        if (ok && has) {
+            const double dvx = (tg[1] * nd.area - Px) / M;
+            const double dvy = (tg[2] * nd.area - Py) / M;
+            const double dw = (tg[3] * nd.area - L) / I;
+            P[gt].z = __float_as_uint(rn);
+            V[gt] = make_float4((float)((double)v0.x + dvx), (float)((double)v0.y + dvy),
+                                (float)((double)v0.z + dw), v0.w);
+            nd.r[s + gt] = rn;
+        }
+        if (ok && gt == 0) {
+            if (gmax > 0.0f) vd = (vd + gmax * (1.0f + 0x1p-22f)) * (1.0f + 0x1p-22f);
+            if (clamped && nd.counters) atomicAdd(&nd.counters[0], 1ull);
+        }
+        __syncthreads();
     }
 
     // ---- state, lists, bound and contact count back to HBM

@@ -181,11 +181,49 @@ sp_status nudge(sp_ctx* c, double frac)
 
 }  // namespace
 
-// Fine steps of the coupled cadence (declared before sp_step).
+// Fine steps of the coupled cadence (declared before sp_step).  Cells are
+// independent between coarse-to-fine updates, and an update needs only the
+// cell's own X0 and Q: with one floe per lane, each stretch up to the next
+// update or coarse step runs as one blocked launch per bucket (the floes
+// resident in LDS), the update done in the same launch.
 sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
 {
     SP_TRY(coupling_prepare(c));
     const size_t slot = (size_t)c->ncells * kMomStride;
+    if (c->block_k > 1 && buckets_one_per_lane(c)) {
+        int64_t left = nsteps;
+        while (left > 0) {
+            const int64_t r = c->cpl_j % c->N0;
+            const int64_t bound = std::min<int64_t>((r / c->n_t + 1) * c->n_t, c->N0);
+            const int64_t K = std::min<int64_t>(bound - r, left);
+            const int64_t jend = c->cpl_j + K;
+            const int64_t rend = jend % c->N0;
+            const bool update = rend != 0 && jend > c->N0 && rend % c->n_t == 0;
+            BlockNudge nd;
+            memset(&nd, 0, sizeof nd);
+            if (update && c->cpl_ncl > 0) {
+                nd.x0m = c->cpl_x0;
+                nd.Q = c->Q[0];
+                nd.frac = (double)rend / (double)c->N0;
+                nd.area = c->p.cell_lx * c->p.cell_ly;
+                nd.r_lim = c->r_bin;
+                nd.r = c->r;
+                nd.counters = c->cpl_count;
+            }
+            SP_TRY(launch_blocks(c, base, c->cpl_ring + (size_t)r * slot, (int)K, nd));
+            c->kstep += K;
+            c->steps += K;
+            c->blk_steps += K;
+            c->cpl_j = jend;
+            left -= K;
+            if (update && c->cpl_ncl > 0) {
+                c->cpl_nudges++;
+                c->desc_stale = true;
+            }
+            if (rend == 0) SP_TRY(coarse_step(c, base.dtd));
+        }
+        return SP_OK;
+    }
     for (int64_t it = 0; it < nsteps; ++it) {
         double* to = c->cpl_ring + (size_t)(c->cpl_j % c->N0) * slot;
         for (auto& b : c->bk) SP_TRY(launch_bucket(c, b, base, c->kstep, false, false, to));

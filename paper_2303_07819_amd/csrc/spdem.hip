@@ -444,25 +444,26 @@ sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads,
 }
 
 template <int SCHED, int W>
-sp_status launch_block_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K)
+sp_status launch_block_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K,
+                         const BlockNudge& nd)
 {
     if (lds > 65536)
         HIP_TRY(c, hipFuncSetAttribute((const void*)dem_block_kernel<SCHED, W>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((dem_block_kernel<SCHED, W>), dim3(grid), dim3(threads), lds, c->stream, a, K);
+    hipLaunchKernelGGL((dem_block_kernel<SCHED, W>), dim3(grid), dim3(threads), lds, c->stream, a, K, nd);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
 sp_status launch_block_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, int grid, int threads, size_t lds,
-                           int K)
+                           int K, const BlockNudge& nd)
 {
     const bool binned = sched == SP_SCHED_BINNED;
     switch (waves) {
-    case 1: return binned ? launch_block_t<2, 1>(c, a, grid, threads, lds, K) : launch_block_t<1, 1>(c, a, grid, threads, lds, K);
-    case 2: return binned ? launch_block_t<2, 2>(c, a, grid, threads, lds, K) : launch_block_t<1, 2>(c, a, grid, threads, lds, K);
-    case 4: return binned ? launch_block_t<2, 4>(c, a, grid, threads, lds, K) : launch_block_t<1, 4>(c, a, grid, threads, lds, K);
-    case 8: return binned ? launch_block_t<2, 8>(c, a, grid, threads, lds, K) : launch_block_t<1, 8>(c, a, grid, threads, lds, K);
+    case 1: return binned ? launch_block_t<2, 1>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 1>(c, a, grid, threads, lds, K, nd);
+    case 2: return binned ? launch_block_t<2, 2>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 2>(c, a, grid, threads, lds, K, nd);
+    case 4: return binned ? launch_block_t<2, 4>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 4>(c, a, grid, threads, lds, K, nd);
+    case 8: return binned ? launch_block_t<2, 8>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 8>(c, a, grid, threads, lds, K, nd);
     default: return fail(c, SP_EINVAL, "no blocked kernel for waves=%d", waves);
     }
 }
@@ -477,6 +478,35 @@ int bucket_gpb(const sp_ctx* c, const Bucket& b) { return groups_per_block(b.wav
 size_t bucket_lds(const sp_ctx* c, const Bucket& b) { return (size_t)bucket_gpb(c, b) * bucket_group_bytes(c, b); }
 
 int bucket_threads(const sp_ctx* c, const Bucket& b) { return bucket_gpb(c, b) * 64 * b.waves; }
+
+// One blocked launch per bucket of K steps from level kstep, the statistics of
+// step t into mom + t * (ncells x kMomStride); with an active nd, the
+// coarse-to-fine update of every launched cell at the end.
+sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd)
+{
+    for (const auto& b : c->bk) {
+        if (b.cells_h.empty()) continue;
+        StepArgs a = base;
+        a.work = b.work_d;
+        a.ncl = (int32_t)b.cells_h.size();
+        a.cap = b.cap;
+        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
+        a.mom = mom;
+        a.lf = 0;
+        const int gpb = bucket_gpb(c, b);
+        const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
+        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K, nd));
+    }
+    return SP_OK;
+}
+
+// Every count bucket holds cells of at most one floe per lane.
+bool buckets_one_per_lane(const sp_ctx* c)
+{
+    for (const auto& b : c->bk)
+        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
+    return true;
+}
 
 sp_status prepare_bucket(sp_ctx* c, Bucket& b)
 {
@@ -544,10 +574,7 @@ sp_status flush_lf(sp_ctx* c)
 // the cadence is the plain one and no hybrid is active.
 bool block_eligible(const sp_ctx* c)
 {
-    if (c->block_k <= 1 || c->N0 > 1 || c->hyb) return false;
-    for (const auto& b : c->bk)
-        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
-    return true;
+    return c->block_k > 1 && c->N0 == 1 && !c->hyb && buckets_one_per_lane(c);
 }
 
 // Make the library stream wait for the continuum updates of the last block
@@ -601,19 +628,9 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hi
     double* const ring = c->blk_ring + (size_t)r * K * slot;
     if (c->lf_used[r]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lf_done[r], 0));
     if (time_dem) HIP_TRY(c, hipEventRecord(e0, c->stream));
-    for (const auto& b : c->bk) {
-        if (b.cells_h.empty()) continue;
-        StepArgs a = base;
-        a.work = b.work_d;
-        a.ncl = (int32_t)b.cells_h.size();
-        a.cap = b.cap;
-        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
-        a.mom = ring;
-        a.lf = 0;
-        const int gpb = bucket_gpb(c, b);
-        const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K));
-    }
+    BlockNudge none;
+    memset(&none, 0, sizeof none);
+    SP_TRY(launch_blocks(c, base, ring, K, none));
     if (time_dem) HIP_TRY(c, hipEventRecord(e1, c->stream));
     if (!(c->p.flags & SP_NO_CONTINUUM)) {
         // everything enqueued on the library stream so far (this block's
