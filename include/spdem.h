@@ -235,8 +235,10 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * which every cell keeps its floes and candidate lists in LDS for the k steps
  * (the cell DEMs never read the continuum at this cadence), each step's
  * statistics going to a k-slot ring, followed by the k continuum updates;
- * steps left over run one by one.  Applies when every bucket's cells fit one
- * floe per lane, N0 = 1 and no hybrid is active.  The floe state is the same
+ * steps left over run one by one.  A bucket whose cells exceed one floe per
+ * lane (more than 64 W floes) takes k per-step launches inside the block,
+ * writing the same ring.  Applies when some bucket fits one floe per lane,
+ * N0 = 1 and no hybrid is active.  The floe state is the same
  * bit for bit as with k = 1; statistics are summed in another fixed order.
  * Ring: k x ncells x 128 B.  Default 32.  Errors: SP_EINVAL (k outside
  * [1, SP_MAX_STEP_BLOCK]). */

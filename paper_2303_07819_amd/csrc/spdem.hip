@@ -479,35 +479,6 @@ size_t bucket_lds(const sp_ctx* c, const Bucket& b) { return (size_t)bucket_gpb(
 
 int bucket_threads(const sp_ctx* c, const Bucket& b) { return bucket_gpb(c, b) * 64 * b.waves; }
 
-// One blocked launch per bucket of K steps from level kstep, the statistics of
-// step t into mom + t * (ncells x kMomStride); with an active nd, the
-// coarse-to-fine update of every launched cell at the end.
-sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd)
-{
-    for (const auto& b : c->bk) {
-        if (b.cells_h.empty()) continue;
-        StepArgs a = base;
-        a.work = b.work_d;
-        a.ncl = (int32_t)b.cells_h.size();
-        a.cap = b.cap;
-        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
-        a.mom = mom;
-        a.lf = 0;
-        const int gpb = bucket_gpb(c, b);
-        const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K, nd));
-    }
-    return SP_OK;
-}
-
-// Every count bucket holds cells of at most one floe per lane.
-bool buckets_one_per_lane(const sp_ctx* c)
-{
-    for (const auto& b : c->bk)
-        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
-    return true;
-}
-
 sp_status prepare_bucket(sp_ctx* c, Bucket& b)
 {
     return prepare_sel(c, c->sched, b.waves, b.persist, bucket_threads(c, b), bucket_lds(c, b), b.cap, &b.resident);
@@ -543,6 +514,43 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
+// K steps from level kstep as one blocked launch per bucket, the statistics of
+// step t into mom + t * (ncells x kMomStride); with an active nd, the
+// coarse-to-fine update of every launched cell at the end (every bucket must
+// then hold one floe per lane).  A bucket with more floes per cell than lanes
+// takes K per-step launches instead (plain cadence only).
+sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd)
+{
+    const size_t slot = (size_t)c->ncells * kMomStride;
+    for (const auto& b : c->bk) {
+        if (b.cells_h.empty()) continue;
+        if (b.cap > 64 * b.waves) {
+            if (nd.x0m) return fail(c, SP_EINVAL, "blocked update needs one floe per lane");
+            for (int t = 0; t < K; ++t) SP_TRY(launch_bucket(c, b, base, c->kstep + t, false, false, mom + t * slot));
+            continue;
+        }
+        StepArgs a = base;
+        a.work = b.work_d;
+        a.ncl = (int32_t)b.cells_h.size();
+        a.cap = b.cap;
+        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
+        a.mom = mom;
+        a.lf = 0;
+        const int gpb = bucket_gpb(c, b);
+        const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
+        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K, nd));
+    }
+    return SP_OK;
+}
+
+// Every count bucket holds cells of at most one floe per lane.
+bool buckets_one_per_lane(const sp_ctx* c)
+{
+    for (const auto& b : c->bk)
+        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
+    return true;
+}
+
 sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k);
 
 sp_status step_once(sp_ctx* c, const StepArgs& base)
@@ -574,7 +582,10 @@ sp_status flush_lf(sp_ctx* c)
 // the cadence is the plain one and no hybrid is active.
 bool block_eligible(const sp_ctx* c)
 {
-    return c->block_k > 1 && c->N0 == 1 && !c->hyb && buckets_one_per_lane(c);
+    if (c->block_k <= 1 || c->N0 != 1 || c->hyb) return false;
+    for (const auto& b : c->bk)   // some bucket gains from resident cells
+        if (!b.cells_h.empty() && b.cap <= 64 * b.waves) return true;
+    return false;
 }
 
 // Make the library stream wait for the continuum updates of the last block

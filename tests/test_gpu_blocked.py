@@ -12,7 +12,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import FLOOR, rel_err
-from workloads import dense_workload, ragged_workload
+from workloads import dense_workload, ragged_workload, uneven_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -74,16 +74,29 @@ def test_blocked_flags():
             assert np.array_equal(a["floes"][key], b["floes"][key]), (flags, key)
 
 
-def test_large_cells_keep_the_per_step_kernel():
-    """Cells above 64 W floes (the 1024-floe bucket) are not blocked; the
-    results stay those of the per-step path."""
+def test_mixed_buckets_step_large_cells_one_by_one_inside_a_block():
+    """Cells above 64 W floes (the 1024-floe bucket) take K per-step launches
+    inside a block while the others run blocked; the floe state stays that of
+    the per-step path bit for bit."""
     w = ragged_workload()
     a = _run(w, 1, 8)
     b = _run(w, 4, 8)
-    assert not b["active"]
+    assert b["active"]
     for key in a["floes"]:
         assert np.array_equal(a["floes"][key], b["floes"][key]), key
-    assert np.array_equal(a["q"], b["q"])
+    assert a["stats"]["contacts"] == b["stats"]["contacts"]
+    e = rel_err(b["q"], a["q"], floor=1e-6)
+    assert e.max() <= 1e-12, e.max()
+
+
+def test_uneven_workload_blocked_parity():
+    w = uneven_workload()
+    st, Q, mom, _ = oracle.run_plain(w, 8)
+    b = _run(w, 4, 8)
+    e_m, e_q = rel_err(b["mom"], mom).max(), rel_err(b["q"], Q).max()
+    _say(f"uneven: active {b['active']} moments {e_m:.2e} continuum {e_q:.2e}")
+    assert b["active"]
+    assert e_m <= TOL_CONTACT and e_q <= TOL_CONTACT
 
 
 def test_full_size_plain64_blocks():
