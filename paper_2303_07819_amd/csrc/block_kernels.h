@@ -9,10 +9,12 @@
 // list rebuild when the displacement bound passes half the skin (binned or
 // all-pairs search), the exact contact decision of every candidate, FP64 drag,
 // contact forces in ascending partner order, the update, the FP64 statistics
-// of the pre-step state.  Statistics are reduced by DPP row sums and four row
-// totals per wavefront (a fixed order).  One floe per lane: every cell of the
-// launch has at most 64 W floes.  Candidate tests (list entries examined) are
-// counted per cell, for the VALU accounting of the step.
+// of the pre-step state.  Statistics are reduced by a transposing DPP exchange
+// within rows of 16 lanes and the 4 W row totals per cell (a fixed order).  One
+// floe per lane: every cell of the launch has at most 64 W floes.  A floe's
+// inverse mass and inverse m r^2 are computed once per launch and kept in LDS.
+// Contacts and candidate tests (list entries examined, for the VALU accounting
+// of the step) are counted per lane over the block and reduced once.
 #pragma once
 
 namespace spdem {
@@ -91,7 +93,8 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 
     uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, theta bits
     float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, h
-    uint4* S = reinterpret_cast<uint4*>(V + cap);             // sorted copy (binned search)
+    double2* IM = reinterpret_cast<double2*>(V + cap);        // 1 / m, 1 / (m r^2)
+    uint4* S = reinterpret_cast<uint4*>(IM + cap);            // sorted copy (binned search)
     uint16_t* lst = reinterpret_cast<uint16_t*>(S + (SCHED == 2 ? cap : 0));
     int* cnt = reinterpret_cast<int*>(lst + (size_t)cap * kListCap);
     int* binof = reinterpret_cast<int*>(lst);                 // sort scratch inside the lists
@@ -117,6 +120,11 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     if (has) {
         P[gt] = make_uint4(a.xi[s + gt], a.yi[s + gt], __float_as_uint(a.r[s + gt]), __float_as_uint(a.th[s + gt]));
         V[gt] = make_float4(a.u[s + gt], a.v[s + gt], a.w[s + gt], a.h[s + gt]);
+        {
+            const double rld = (double)a.r[s + gt];
+            const double md = a.rho_ice_d * (double)a.h[s + gt] * kPi * rld * rld;
+            IM[gt] = make_double2(1.0 / md, 1.0 / (md * (rld * rld)));
+        }
         if (vd <= 0.5f * a.skin) {   // the kept lists are valid for the first step
             const int k = a.vcount[s + gt];
             cnt[gt] = k;
@@ -126,7 +134,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         }
     }
     bool rebuilt = false;
-    unsigned long long ctot = 0, ttot = 0;
+    uint32_t my_contacts = 0, my_tests = 0;    // this lane's counts over the block
 
     for (int step = 0; step < K; ++step) {
         const bool build = valid && !(vd <= 0.5f * a.skin);
@@ -207,7 +215,6 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         double acc[kDyn];
 #pragma unroll
         for (int k = 0; k < kDyn; ++k) acc[k] = 0.0;
-        unsigned long long ncontact = 0, ntest = 0;
         float maxdisp = 0.0f;
         uint4 pn = make_uint4(0, 0, 0, 0);
         float4 vn4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -226,7 +233,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
                 ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
-                const double sp = sqrt(du * du + dv * dv);
+                const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
                 fdx = alpha * du * sp;
                 fdy = alpha * dv * sp;
@@ -257,7 +264,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                     }
                 }
             }
-            ntest = (unsigned long long)k;
+            my_tests += (uint32_t)k;
             uint32_t cmask = 0;
             for (int q0 = 0; q0 < k; q0 += 8) {
                 const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
@@ -310,13 +317,14 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 Fx += Fn * nx + Ft * tx;
                 Fy += Fn * ny + Ft * ty;
                 T += rld * Ft;
-                ncontact += (l < j) ? 1ull : 0ull;
+                my_contacts += (l < j) ? 1u : 0u;
             }
-            const double inv_m = 1.0 / md;
+            const double2 im = IM[l];
+            const double inv_m = im.x, inv_i = im.y;
             const double dt = a.dtd;
             const double und = uld + dt * (Fx * inv_m);
             const double vnd = vld + dt * (Fy * inv_m);
-            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const double wnd = wld + dt * (T * inv_i);
             const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
             const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
             const int sx = __double2int_rn(dt * ux * a.inv_qxd);
@@ -340,19 +348,12 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
             acc[7] = tdr;
         }
         // ---- group reductions (the floe data is still read by nobody after this barrier)
-        const unsigned long long cs = wave_sum_u64(ncontact);
-        const unsigned long long ts = wave_sum_u64(ntest);
-        const float wd = wave_max_f32(maxdisp);
-#pragma unroll
-        for (int k = 0; k < kDyn; ++k) {
-            const double x = row_sum(acc[k]);
-            if ((gt & 15) == 15) rows[g][k][gt >> 4] = x;
+        const float wd = wave_max_nonneg(maxdisp);
+        {
+            const double x = row_sum8(acc, gt & 15);
+            if ((gt & 1) == 0) rows[g][(gt & 15) >> 1][gt >> 4] = x;
         }
-        if ((tid & 63) == 0) {
-            csum[tid >> 6] = cs;
-            tsum[tid >> 6] = ts;
-            wdisp[tid >> 6] = wd;
-        }
+        if ((tid & 63) == 0) wdisp[tid >> 6] = wd;
         __syncthreads();
         if (has) {                               // the new state, for the next step
             P[gt] = pn;
@@ -369,19 +370,28 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         }
         if (valid && gt == 0) {
             float d = 0.0f;
-            unsigned long long t = 0, tt = 0;
-            for (int q = 0; q < W; ++q) {
-                d = fmaxf(d, wdisp[g * W + q]);
-                t += csum[g * W + q];
-                tt += tsum[g * W + q];
-            }
-            ctot += t;
-            ttot += tt;
+            for (int q = 0; q < W; ++q) d = fmaxf(d, wdisp[g * W + q]);
             vds[g] = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
         }
         rebuilt = rebuilt || build;
         __syncthreads();
         vd = valid ? vds[g] : 0.0f;
+    }
+
+    unsigned long long ctot = 0, ttot = 0;
+    {
+        const unsigned long long cs = wave_sum_u64(my_contacts);
+        const unsigned long long ts = wave_sum_u64(my_tests);
+        if ((tid & 63) == 0) {
+            csum[tid >> 6] = cs;
+            tsum[tid >> 6] = ts;
+        }
+        __syncthreads();
+        if (valid && gt == 0)
+            for (int q = 0; q < W; ++q) {
+                ctot += csum[g * W + q];
+                ttot += tsum[g * W + q];
+            }
     }
 
     // ---- coarse-to-fine update of the cell (coupled cadence)

@@ -137,6 +137,44 @@ __device__ __forceinline__ float wave_max_f32(float x)
     return x;
 }
 
+// Maximum over the wavefront of x >= 0 by DPP: row scans (row_shr 1, 2, 4, 8,
+// zeros shifted in), then rows 1 and 3 take the last lane of rows 0 and 2
+// (row_bcast:15) and rows 2 and 3 that of row 1 (row_bcast:31); lane 63 holds
+// the maximum and every lane returns it.  No LDS traffic.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, CTRL < 0x140));
+}
+
+__device__ __forceinline__ float wave_max_nonneg(float x)
+{
+    x = fmaxf(x, dpp_f32<0x111, 0xf>(x));
+    x = fmaxf(x, dpp_f32<0x112, 0xf>(x));
+    x = fmaxf(x, dpp_f32<0x114, 0xf>(x));
+    x = fmaxf(x, dpp_f32<0x118, 0xf>(x));
+    x = fmaxf(x, dpp_f32<0x142, 0xa>(x));
+    x = fmaxf(x, dpp_f32<0x143, 0xc>(x));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Square root of a finite x >= 0 (the drag speed): the hardware reciprocal
+// square root y0, then Goldschmidt's coupled iteration for g ~ sqrt(x) and
+// h ~ 1 / (2 sqrt(x)) (g = x y0, h = y0 / 2, r = 1/2 - g h, g += g r,
+// h += h r) and one Newton correction g += (x - g^2) h; within an ulp of the
+// rounded root.  0 at x = 0 (where the reciprocal root is infinite).
+__device__ __forceinline__ double sqrt_nonneg(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 // FP64 contact predicate: (dx*dx + dy*dy) < R*R without contraction.
 __device__ __noinline__ bool exact_contact(int dxi, int dyi, float rl, float rj, double qxd,
                                            double qyd)
@@ -265,6 +303,35 @@ __device__ __forceinline__ double row_sum(double x)
     x += dpp_shr<0x114>(x);   // row_shr:4
     x += dpp_shr<0x118>(x);   // row_shr:8
     return x;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Row totals (16 lanes) of eight values per lane by a transposing exchange:
+// at each stage a lane keeps half of its values and adds its partner's copy of
+// that half (partners: lane i ^ 8 by row_ror:8, i ^ 7 by row_half_mirror,
+// i ^ 2 and i ^ 1 by quad permutes), so lane i of a row ends with the row
+// total of value i >> 1 (both lanes of a pair hold it).  About half the
+// instructions of eight row sums.  Every lane of the wavefront must be active.
+__device__ __forceinline__ double row_sum8(const double (&v)[8], int lane)
+{
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    double a4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        a4[j] = (b3 ? v[j + 4] : v[j]) + dpp_perm<0x128>(b3 ? v[j] : v[j + 4]);
+    double a2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        a2[j] = (b2 ? a4[j + 2] : a4[j]) + dpp_perm<0x141>(b2 ? a4[j] : a4[j + 2]);
+    const double a1 = (b1 ? a2[1] : a2[0]) + dpp_perm<0x4e>(b1 ? a2[0] : a2[1]);
+    return a1 + dpp_perm<0xb1>(a1);
 }
 
 // Exclusive scan of cnt[0..nb) into start[0..nb] by the G threads of a group
@@ -616,7 +683,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
                 ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
-                const double sp = sqrt(du * du + dv * dv);
+                const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
                 fdx = alpha * du * sp;
                 fdy = alpha * dv * sp;
@@ -722,7 +789,8 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             const double dt = a.dtd;
             const double und = uld + dt * (Fx * inv_m);
             const double vnd = vld + dt * (Fy * inv_m);
-            const double wnd = wld + dt * (T * inv_m / (rld * rld));
+            const double inv_i = 1.0 / (md * (rld * rld));
+            const double wnd = wld + dt * (T * inv_i);
             const bool fe = (a.flags & SP_FORWARD_EULER) != 0;
             const double ux = fe ? uld : und, vx = fe ? vld : vnd, wx = fe ? wld : wnd;
             const int sx = __double2int_rn(dt * ux * a.inv_qxd);
@@ -836,7 +904,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
             float uo = a.u0, vo = a.v0, zeta = 0.0f;
             ocean_modes(fx, fy, mode_k, mode_c, a.nmodes, a.modes.direct != 0, uo, vo, zeta);
             const double du = (double)uo - uld, dv = (double)vo - vld;
-            const double sp = sqrt(du * du + dv * dv);
+            const double sp = sqrt_nonneg(du * du + dv * dv);
             const double alpha = a.cdrho * kPi * rld * rld;
             fdx = alpha * du * sp;
             fdy = alpha * dv * sp;

@@ -529,16 +529,18 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
             for (int t = 0; t < K; ++t) SP_TRY(launch_bucket(c, b, base, c->kstep + t, false, false, mom + t * slot));
             continue;
         }
+        // the blocked kernel keeps 1 / m and 1 / (m r^2) per floe beside the state
+        const size_t gbytes = bucket_group_bytes(c, b) + (size_t)b.cap * 16;
+        const int gpb = groups_per_block(b.waves, gbytes);
         StepArgs a = base;
         a.work = b.work_d;
         a.ncl = (int32_t)b.cells_h.size();
         a.cap = b.cap;
-        a.group_bytes = (int32_t)bucket_group_bytes(c, b);
+        a.group_bytes = (int32_t)gbytes;
         a.mom = mom;
         a.lf = 0;
-        const int gpb = bucket_gpb(c, b);
         const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, bucket_threads(c, b), bucket_lds(c, b), K, nd));
+        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, gpb * 64 * b.waves, (size_t)gpb * gbytes, K, nd));
     }
     return SP_OK;
 }
