@@ -74,8 +74,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     const int gpb = blockDim.x / G;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float4 mode_k[SP_MAX_MODES];
-    __shared__ float4 mode_c[GPB][SP_MAX_MODES];
+    __shared__ float4 mode_c[GPB][2 * SP_MAX_MODES];   // per-cell mode constants (mode_consts)
     __shared__ int wsum[GPB][W];
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
@@ -87,9 +86,6 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     const int g = tid / G, gt = tid % G;
     unsigned char* gsm = smem + (size_t)g * a.group_bytes;
     const int cap = a.cap;
-
-    if (tid < a.nmodes)
-        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
 
     uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, theta bits
     float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, h
@@ -112,10 +108,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     const size_t slot_len = (size_t)a.ncells * kMomStride;
     uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
 
-    if (valid && gt < a.nmodes) {
-        const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
-        mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
-    }
+    if (valid && gt < a.nmodes) mode_consts(a.modes, gt, a.phase[(size_t)c * a.nmodes + gt], mode_c[g]);
     float vd = valid ? a.vdisp[c] : 0.0f;
     if (has) {
         P[gt] = make_uint4(a.xi[s + gt], a.yi[s + gt], __float_as_uint(a.r[s + gt]), __float_as_uint(a.th[s + gt]));
@@ -135,12 +128,22 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     }
     bool rebuilt = false;
     uint32_t my_contacts = 0, my_tests = 0;    // this lane's counts over the block
+    // whether some cell of the workgroup rebuilds its lists this step, from the
+    // displacement bounds in vds (the barrier also publishes the staged state)
+    if (valid && gt == 0) vds[g] = vd;
+    __syncthreads();
+    auto any_rebuild = [&]() {
+        bool any = false;
+        for (int q = 0; q < gpb; ++q)
+            any = any || (blockIdx.x * gpb + q < a.ncl && !(vds[q] <= 0.5f * a.skin));
+        return any;
+    };
+    bool any_build = any_rebuild();
 
     for (int step = 0; step < K; ++step) {
         const bool build = valid && !(vd <= 0.5f * a.skin);
         const int nb_build = build ? n : 0;
         if (build && has) cnt[gt] = 0;
-        const bool any_build = __syncthreads_or(build);
         if (SCHED == 2 && any_build) {
             const int nb = a.nbx * a.nby;
             for (int b = gt; b < nb; b += G) bcnt[b] = 0;
@@ -210,7 +213,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 }
             }
         }
-        __syncthreads();
+        if (any_build) __syncthreads();   // lists complete (sweeps append to partners' lists)
 
         double acc[kDyn];
 #pragma unroll
@@ -231,7 +234,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
                 const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
-                ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
+                ocean_modes(fx, fy, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
                 const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
@@ -331,7 +334,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
             const int sy = __double2int_rn(dt * vx * a.inv_qyd);
             {
                 const float ddx = (float)sx * a.qx, ddy = (float)sy * a.qy;
-                maxdisp = sqrtf(ddx * ddx + ddy * ddy);
+                maxdisp = ddx * ddx + ddy * ddy;   // squared: one root per cell below
             }
             const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
             pn = make_uint4(xl + (uint32_t)sx, yl + (uint32_t)sy, pl.z,
@@ -371,11 +374,12 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         if (valid && gt == 0) {
             float d = 0.0f;
             for (int q = 0; q < W; ++q) d = fmaxf(d, wdisp[g * W + q]);
-            vds[g] = (build ? 0.0f : vd) + d * 1.0001f + 1e-3f;
+            vds[g] = (build ? 0.0f : vd) + sqrtf(d) * 1.0001f + 1e-3f;
         }
         rebuilt = rebuilt || build;
         __syncthreads();
         vd = valid ? vds[g] : 0.0f;
+        any_build = any_rebuild();
     }
 
     unsigned long long ctot = 0, ttot = 0;

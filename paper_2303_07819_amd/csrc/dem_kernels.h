@@ -231,59 +231,67 @@ __device__ __forceinline__ void sincos_small(float x, float& s, float& c)
     c = ((q + 1) & 2) ? -c1 : c1;
 }
 
-// sin and cos of |x| <= 1.6 from their Taylor polynomials to degree 13 and
-// 14 (truncation below 1e-9 there), without range reduction.
+// sin and cos of |x| <= 1.62 from minimax polynomials (Remez exchange for the
+// absolute error on [-1.62, 1.62]): odd of degree 9 for sin (error 4.0e-8),
+// even of degree 10 for cos (3.5e-10).  Evaluated in FP32, FP32 rounding
+// included, they stay within 1.2e-7 and 1.6e-7 of sin and cos.
 __device__ __forceinline__ void sincos_direct(float x, float& s, float& c)
 {
     const float x2 = x * x;
-    float sp = fmaf(x2, 1.6059043837e-10f, -2.5052108385e-8f);   // 1/13!, -1/11!
-    sp = fmaf(x2, sp, 2.7557319224e-6f);                          // 1/9!
-    sp = fmaf(x2, sp, -1.9841269841e-4f);                         // -1/7!
-    sp = fmaf(x2, sp, 8.3333333333e-3f);                          // 1/5!
-    sp = fmaf(x2, sp, -1.6666666667e-1f);                         // -1/3!
+    float sp = fmaf(x2, 2.62724643e-06f, -0.000198211215f);
+    sp = fmaf(x2, sp, 0.0083332425f);
+    sp = fmaf(x2, sp, -0.166666657f);
     s = fmaf(x * x2, sp, x);
-    float cp = fmaf(x2, -1.1470745597e-11f, 2.0876756988e-9f);    // -1/14!, 1/12!
-    cp = fmaf(x2, cp, -2.7557319224e-7f);                         // -1/10!
-    cp = fmaf(x2, cp, 2.4801587302e-5f);                          // 1/8!
-    cp = fmaf(x2, cp, -1.3888888889e-3f);                         // -1/6!
-    cp = fmaf(x2, cp, 4.1666666667e-2f);                          // 1/4!
+    float cp = fmaf(x2, -2.59854716e-07f, 2.47567714e-05f);
+    cp = fmaf(x2, cp, -0.0013888306f);
+    cp = fmaf(x2, cp, 0.0416666344f);
     cp = fmaf(x2, cp, -0.5f);
     c = fmaf(x2, cp, 1.0f);
 }
 
+// Per-cell constants of ocean mode m (2 float4 at mc[2 m]): with a the mode's
+// velocity amplitudes (au, av), cz its curl coefficient and theta_c its phase
+// at the cell centre (S = sin theta_c, C = cos theta_c):
+// (au S, au C, av S, av C) and (cz C, -cz S, kx Lx, ky Ly).
+__device__ __forceinline__ void mode_consts(const Modes& md, int m, float2 sc, float4* mc)
+{
+    const float au = md.au[m], av = md.av[m], cz = md.cz[m];
+    mc[2 * m] = make_float4(au * sc.x, au * sc.y, av * sc.x, av * sc.y);
+    mc[2 * m + 1] = make_float4(cz * sc.y, -(cz * sc.x), md.kxL[m], md.kyL[m]);
+}
+
 // Ocean current (sum of a sin theta) and curl (sum of cz cos theta) at cell
 // fraction (fx, fy), by angle addition around the cell centre: theta = theta_c
-// + d with d = kxL fx + kyL fy.  mk[m] = (kxL, kyL, au, av); mc[m] = (cz,
-// sin theta_c, cos theta_c, -).  DIRECT: every |d| <= 1.6.
+// + d with d = kx Lx fx + ky Ly fy, sin theta = S cos d + C sin d and
+// cos theta = C cos d - S sin d, the amplitudes folded into the constants of
+// mode_consts.  DIRECT: every |d| <= 1.6.
 template <bool DIRECT>
-__device__ __forceinline__ void ocean_modes_t(float fx, float fy, const float4* mk, const float4* mc, int nmodes,
-                                              float& uo, float& vo, float& zeta)
+__device__ __forceinline__ void ocean_modes_t(float fx, float fy, const float4* mc, int nmodes, float& uo,
+                                              float& vo, float& zeta)
 {
 #pragma unroll 2
     for (int m = 0; m < nmodes; ++m) {
-        const float4 k = mk[m];
-        const float4 q = mc[m];
-        const float d = k.x * fx + k.y * fy;
+        const float4 p = mc[2 * m];
+        const float4 q = mc[2 * m + 1];
+        const float d = q.z * fx + q.w * fy;
         float sd, cd;
         if (DIRECT)
             sincos_direct(d, sd, cd);
         else
             sincos_small(d, sd, cd);
-        const float sn = q.y * cd + q.z * sd;    // sin and cos of the full phase
-        const float cn = q.z * cd - q.y * sd;
-        uo += k.z * sn;
-        vo += k.w * sn;
-        zeta += q.x * cn;
+        uo = fmaf(p.y, sd, fmaf(p.x, cd, uo));
+        vo = fmaf(p.w, sd, fmaf(p.z, cd, vo));
+        zeta = fmaf(q.y, sd, fmaf(q.x, cd, zeta));
     }
 }
 
-__device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mk, const float4* mc, int nmodes,
-                                            bool direct, float& uo, float& vo, float& zeta)
+__device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mc, int nmodes, bool direct,
+                                            float& uo, float& vo, float& zeta)
 {
     if (direct)
-        ocean_modes_t<true>(fx, fy, mk, mc, nmodes, uo, vo, zeta);
+        ocean_modes_t<true>(fx, fy, mc, nmodes, uo, vo, zeta);
     else
-        ocean_modes_t<false>(fx, fy, mk, mc, nmodes, uo, vo, zeta);
+        ocean_modes_t<false>(fx, fy, mc, nmodes, uo, vo, zeta);
 }
 
 // Sum over a row of 16 lanes with DPP row shifts (deterministic order); the
@@ -502,8 +510,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     const int gpb = blockDim.x / G;            // groups in this launch (LDS may allow fewer)
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float4 mode_k[SP_MAX_MODES];            // kx Lx, ky Ly, au, av
-    __shared__ float4 mode_c[GPB][SP_MAX_MODES];       // curl coefficient, sin, cos of centre phase
+    __shared__ float4 mode_c[GPB][2 * SP_MAX_MODES];   // per-cell mode constants (mode_consts)
     __shared__ int wsum[GPB][W];
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
@@ -513,9 +520,6 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     const int g = tid / G, gt = tid % G;
     unsigned char* gsm = smem + (size_t)g * a.group_bytes;
     const int cap = a.cap;
-
-    if (tid < a.nmodes)
-        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
 
     uint4* P = reinterpret_cast<uint4*>(gsm);                 // xi, yi, r bits, theta bits
     float4* V = reinterpret_cast<float4*>(P + cap);           // u, v, w, -
@@ -550,10 +554,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         const int nb_build = build ? n : 0;        // loop bound of the build work
         uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
 
-        if (valid && gt < a.nmodes) {
-            const float2 sc = a.phase[(size_t)c * a.nmodes + gt];
-            mode_c[g][gt] = make_float4(a.modes.cz[gt], sc.x, sc.y, 0.0f);
-        }
+        if (valid && gt < a.nmodes) mode_consts(a.modes, gt, a.phase[(size_t)c * a.nmodes + gt], mode_c[g]);
         for (int i = gt; i < n; i += G) {
             P[i] = make_uint4(a.xi[s + i], a.yi[s + i], __float_as_uint(a.r[s + i]), __float_as_uint(a.th[s + i]));
             V[i] = make_float4(a.u[s + i], a.v[s + i], a.w[s + i], a.h[s + i]);
@@ -681,7 +682,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
                 const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
-                ocean_modes(fx, fy, mode_k, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
+                ocean_modes(fx, fy, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
                 const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
@@ -879,17 +880,12 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* cells)
 {
     __shared__ double red11[SP_NMOM][16];
-    __shared__ float4 mode_k[SP_MAX_MODES];
-    __shared__ float4 mode_c[SP_MAX_MODES];
+    __shared__ float4 mode_c[2 * SP_MAX_MODES];
     const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
     const int s = a.cell_start[c];
     const int n = a.cell_start[c + 1] - s;
-    if (tid < a.nmodes) {
-        const float2 sc = a.phase[(size_t)c * a.nmodes + tid];
-        mode_k[tid] = make_float4(a.modes.kxL[tid], a.modes.kyL[tid], a.modes.au[tid], a.modes.av[tid]);
-        mode_c[tid] = make_float4(a.modes.cz[tid], sc.x, sc.y, 0.0f);
-    }
+    if (tid < a.nmodes) mode_consts(a.modes, tid, a.phase[(size_t)c * a.nmodes + tid], mode_c);
     __syncthreads();
     double acc[SP_NMOM];
 #pragma unroll
@@ -902,7 +898,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
             const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
             const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
             float uo = a.u0, vo = a.v0, zeta = 0.0f;
-            ocean_modes(fx, fy, mode_k, mode_c, a.nmodes, a.modes.direct != 0, uo, vo, zeta);
+            ocean_modes(fx, fy, mode_c, a.nmodes, a.modes.direct != 0, uo, vo, zeta);
             const double du = (double)uo - uld, dv = (double)vo - vld;
             const double sp = sqrt_nonneg(du * du + dv * dv);
             const double alpha = a.cdrho * kPi * rld * rld;

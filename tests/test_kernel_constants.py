@@ -1,0 +1,75 @@
+"""Constants written into the HIP kernels, checked against the mathematics
+they stand for (no GPU needed).
+
+The ocean current is a sum of Fourier modes evaluated in FP32 by angle
+addition around the cell centre; the phase offset d stays within |d| <= 1.6
+when the host selects the direct path, where sin d and cos d come from two
+fixed polynomials.  Their coefficients are read from the kernel source and
+the polynomials evaluated like the kernel does (FP32 fused multiply-adds),
+then compared with numpy's sin and cos in FP64.
+"""
+import os
+import re
+
+import numpy as np
+
+SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2303_07819_amd", "csrc", "dem_kernels.h")
+
+
+def _coefficients():
+    text = open(SRC).read()
+    body = text[text.index("void sincos_direct("):]
+    body = body[:body.index("\n}\n")]
+    lits = [float(x) for x in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
+    # sin: c9, c7 | c5 | c3 ; cos: c10, c8 | c6 | c4 | c2 (-0.5) | 1.0
+    sin_c = [lits[0], lits[1], lits[2], lits[3]]
+    cos_c = [lits[4], lits[5], lits[6], lits[7], lits[8]]
+    assert lits[9] == 1.0
+    return np.float32(sin_c), np.float32(cos_c)
+
+
+def _fma32(a, b, c):
+    return np.float32(a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64))
+
+
+def _eval32(x):
+    s_c, c_c = _coefficients()
+    x2 = np.float32(x * x)
+    sp = _fma32(x2, np.full_like(x2, s_c[0]), np.full_like(x2, s_c[1]))
+    sp = _fma32(x2, sp, np.full_like(x2, s_c[2]))
+    sp = _fma32(x2, sp, np.full_like(x2, s_c[3]))
+    s = _fma32(np.float32(x * x2), sp, x)
+    cp = _fma32(x2, np.full_like(x2, c_c[0]), np.full_like(x2, c_c[1]))
+    for k in (2, 3, 4):
+        cp = _fma32(x2, cp, np.full_like(x2, c_c[k]))
+    c = _fma32(x2, cp, np.ones_like(x2))
+    return s, c
+
+
+def test_direct_sincos_polynomials_are_accurate():
+    x = np.linspace(-1.62, 1.62, 400001).astype(np.float32)
+    s, c = _eval32(x)
+    xd = x.astype(np.float64)
+    es = np.max(np.abs(s.astype(np.float64) - np.sin(xd)))
+    ec = np.max(np.abs(c.astype(np.float64) - np.cos(xd)))
+    # FP32 evaluation: about one FP32 ulp of values near 1
+    assert es < 1.3e-7, es
+    assert ec < 1.7e-7, ec
+
+
+def test_direct_sincos_approximation_error_in_fp64():
+    """The polynomials themselves (FP32 coefficients, FP64 evaluation): the
+    minimax errors stated in the kernel source.  A wrong or transposed
+    coefficient moves them by orders of magnitude."""
+    s_c, c_c = _coefficients()
+    x = np.linspace(-1.62, 1.62, 400001)
+    x2 = x * x
+    sp = ((s_c[0] * x2 + s_c[1]) * x2 + s_c[2]) * x2 + s_c[3]
+    s = x + x * x2 * sp
+    cp = (((c_c[0] * x2 + c_c[1]) * x2 + c_c[2]) * x2 + c_c[3]) * x2 + c_c[4]
+    c = 1.0 + x2 * cp
+    assert np.max(np.abs(s - np.sin(x))) < 4.5e-8
+    assert np.max(np.abs(c - np.cos(x))) < 1.5e-8
+    # the sin error equioscillates (a minimax polynomial): extrema of both signs
+    e = s - np.sin(x)
+    assert e.max() > 3e-8 and e.min() < -3e-8
