@@ -221,18 +221,20 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         float maxdisp = 0.0f;
         uint4 pn = make_uint4(0, 0, 0, 0);
         float4 vn4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        // ---- per floe: drag, decisions of the listed candidates (contacts as a
+        // bit mask over the ascending list)
+        const uint4 pl = has ? P[gt] : make_uint4(0, 0, 0, 0);
+        const float4 vv = has ? V[gt] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const double rld = (double)__uint_as_float(pl.z), uld = (double)vv.x, vld = (double)vv.y,
+                     wld = (double)vv.z;
+        double fdx = 0.0, fdy = 0.0, tdr = 0.0;
+        uint16_t* const my = lst + (size_t)gt * kListCap;
+        uint32_t cmask = 0;
         if (has) {
             const int l = gt;
-            const uint4 pl = P[l];
-            const float4 vv = V[l];
-            const uint32_t xl = pl.x, yl = pl.y;
-            const float rl = __uint_as_float(pl.z);
-            const float ul = vv.x, vl = vv.y, wl = vv.z;
-            const double rld = (double)rl, uld = (double)ul, vld = (double)vl, wld = (double)wl;
-            double fdx = 0.0, fdy = 0.0, tdr = 0.0;
             if (!(a.flags & SP_OCEAN_OFF)) {
-                const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
-                const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
+                const float fx = (float)(int)(pl.x - 0x80000000u) * 2.3283064365386963e-10f;
+                const float fy = (float)(int)(pl.y - 0x80000000u) * 2.3283064365386963e-10f;
                 float uo = a.u0, vo = a.v0, zeta = 0.0f;
                 ocean_modes(fx, fy, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
                 const double du = (double)uo - uld, dv = (double)vo - vld;
@@ -245,9 +247,6 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 const double beta = a.cdrho * kPi * r2 * r2 * rld;
                 tdr = beta * dW * fabs(dW);
             }
-            const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
-
-            uint16_t* my = lst + (size_t)l * kListCap;
             int k = cnt[l];
             if (build) {
                 if (k > kListCap) {
@@ -268,7 +267,6 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 }
             }
             my_tests += (uint32_t)k;
-            uint32_t cmask = 0;
             for (int q0 = 0; q0 < k; q0 += 8) {
                 const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
                 const int qe = min(8, k - q0);
@@ -277,53 +275,29 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                     const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
                     if (j == l) continue;
                     const uint4 pj = P[j];
-                    if (decide((int)(pj.x - xl), (int)(pj.y - yl), rl, __uint_as_float(pj.z), a))
+                    if (decide((int)(pj.x - pl.x), (int)(pj.y - pl.y), __uint_as_float(pl.z), __uint_as_float(pj.z), a))
                         cmask |= 1u << (q0 + t);
                 }
             }
+            // ---- contact forces and torques in ascending partner order (FP64)
             double Fx = fdx, Fy = fdy, T = tdr;
             while (cmask) {
                 const int q = __builtin_ctz(cmask);
                 cmask &= cmask - 1u;
                 const int j = my[q];
                 const uint4 pj = P[j];
-                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
-                const float rj = __uint_as_float(pj.z);
-                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
-                const double d2 = dx * dx + dy * dy;
-                if (!(d2 > 0.0)) {
+                double cx, cy, ct;
+                if (!contact_terms((int)(pj.x - pl.x), (int)(pj.y - pl.y), rld, uld, vld, wld, __uint_as_float(pj.z),
+                                   V[j], l < j, a, cx, cy, ct)) {
                     atomicOr(a.err, kErrOverlap);
                     continue;
                 }
-                const double rjd = (double)rj;
-                const double d = sqrt(d2);
-                const double inv_d = 1.0 / d;
-                const double nx = dx * inv_d, ny = dy * inv_d;
-                const double tx = -ny, ty = nx;
-                const double R = rld + rjd;
-                const double delta = d - R;
-                const double dr = fabs(rld - rjd);
-                double cc;
-                if (d <= dr) {
-                    cc = 2.0 * fmin(rld, rjd);
-                } else {
-                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
-                    cc = sqrt(fmax(p, 0.0)) * inv_d;
-                }
-                const double Fn = cc * a.Ed * delta;
-                const float4 vj = V[j];
-                const double wjd = (double)vj.z;
-                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
-                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
-                const double capf = a.mud * fabs(Fn);
-                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
-                Fx += Fn * nx + Ft * tx;
-                Fy += Fn * ny + Ft * ty;
-                T += rld * Ft;
+                add_terms(Fx, Fy, T, cx, cy, ct);
                 my_contacts += (l < j) ? 1u : 0u;
             }
             const double2 im = IM[l];
             const double inv_m = im.x, inv_i = im.y;
+            const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
             const double dt = a.dtd;
             const double und = uld + dt * (Fx * inv_m);
             const double vnd = vld + dt * (Fy * inv_m);
@@ -337,7 +311,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 maxdisp = ddx * ddx + ddy * ddy;   // squared: one root per cell below
             }
             const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
-            pn = make_uint4(xl + (uint32_t)sx, yl + (uint32_t)sy, pl.z,
+            pn = make_uint4(pl.x + (uint32_t)sx, pl.y + (uint32_t)sy, pl.z,
                             __float_as_uint((float)((double)__uint_as_float(pl.w) + dt * wx)));
             vn4 = make_float4(un, vn, wn, vv.w);
             if (!(isfinite(un) && isfinite(vn) && isfinite(wn))) atomicOr(a.err, kErrNaN);

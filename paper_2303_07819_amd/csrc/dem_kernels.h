@@ -25,8 +25,8 @@
 //      FP64 expression (dx dx + dy dy) < R R without contraction, outside it by
 //      the FP32 screen, so the contact set is the one that expression defines;
 //   3. per floe: ocean current and curl (angle addition around the cell centre,
-//      Taylor sincos), FP64 drag and drag torque, contacts in ascending partner
-//      index (FP64), semi-implicit update, FP32 / fixed-point store;
+//      minimax sincos), FP64 drag and drag torque, contacts in ascending
+//      partner index (FP64), semi-implicit update, FP32 / fixed-point store;
 //   4. reduces the FP64 statistics of the pre-step state (LDS + DPP, fixed
 //      order, deterministic);
 //   5. (optionally) advances the continuum of its cell by one LF step from the
@@ -292,6 +292,62 @@ __device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mc
         ocean_modes_t<true>(fx, fy, mc, nmodes, uo, vo, zeta);
     else
         ocean_modes_t<false>(fx, fy, mc, nmodes, uo, vo, zeta);
+}
+
+// Contact of floe l (radius rld, velocity (uld, vld), spin wld) with floe j at
+// fixed-point offset (dxi, dyi), radius rj, velocity and spin vj (Sec. 2.1),
+// FP64: with d the centre distance, n the unit normal and t = (-n_y, n_x), the
+// overlap delta = d - (r_l + r_j) < 0 and the contact chord c (the full chord
+// of the overlapping disks, the smaller diameter once one disk lies within the
+// other), the normal force E c delta n and the tangential force
+// G c v_t t capped at mu |F_n|, v_t the relative tangential velocity with the
+// spins' surface speeds; the torque is r_l F_t.  The spin sum takes its
+// operands in a fixed order (lower floe index first) so that the two floes of
+// a pair see the same value.  The contributions are returned, not summed, so
+// that any lane can evaluate a pair; false for coincident centres (no force).
+__device__ __forceinline__ bool contact_terms(int dxi, int dyi, double rld, double uld, double vld, double wld,
+                                              float rj, float4 vj, bool lower, const StepArgs& a, double& cx,
+                                              double& cy, double& ct)
+{
+    const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
+    const double d2 = dx * dx + dy * dy;
+    if (!(d2 > 0.0)) return false;
+    const double rjd = (double)rj;
+    const double d = sqrt_nonneg(d2);
+    const double inv_d = 1.0 / d;
+    const double nx = dx * inv_d, ny = dy * inv_d;
+    const double tx = -ny, ty = nx;
+    const double R = rld + rjd;
+    const double delta = d - R;
+    const double dr = fabs(rld - rjd);
+    double cc;
+    if (d <= dr) {
+        cc = 2.0 * fmin(rld, rjd);
+    } else {
+        const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
+        cc = sqrt_nonneg(fmax(p, 0.0)) * inv_d;
+    }
+    const double Fn = cc * a.Ed * delta;
+    const double wjd = (double)vj.z;
+    const double spin = lower ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
+    const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
+    const double capf = a.mud * fabs(Fn);
+    const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+    cx = fma(Fn, nx, Ft * tx);
+    cy = fma(Fn, ny, Ft * ty);
+    ct = rld * Ft;
+    return true;
+}
+
+// Add one contact's contributions to a floe's sums.  The operands pass
+// through an empty asm so that no product feeding them is fused into the
+// sums: the result is the same whichever lane computed the contributions.
+__device__ __forceinline__ void add_terms(double& Fx, double& Fy, double& T, double cx, double cy, double ct)
+{
+    asm volatile("" : "+v"(cx), "+v"(cy), "+v"(ct));
+    Fx += cx;
+    Fy += cy;
+    T += ct;
 }
 
 // Sum over a row of 16 lanes with DPP row shifts (deterministic order); the
@@ -746,41 +802,13 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 cmask &= cmask - 1u;
                 const int j = my[q];
                 const uint4 pj = P[j];
-                const int dxi = (int)(pj.x - xl), dyi = (int)(pj.y - yl);
-                const float rj = __uint_as_float(pj.z);
-                const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
-                const double d2 = dx * dx + dy * dy;
-                if (!(d2 > 0.0)) {
+                double cx, cy, ct;
+                if (!contact_terms((int)(pj.x - xl), (int)(pj.y - yl), rld, uld, vld, wld, __uint_as_float(pj.z),
+                                   V[j], l < j, a, cx, cy, ct)) {
                     atomicOr(a.err, kErrOverlap);
                     continue;
                 }
-                const double rjd = (double)rj;
-                const double d = sqrt(d2);
-                const double inv_d = 1.0 / d;
-                const double nx = dx * inv_d, ny = dy * inv_d;
-                const double tx = -ny, ty = nx;
-                const double R = rld + rjd;
-                const double delta = d - R;
-                const double dr = fabs(rld - rjd);
-                double cc;
-                if (d <= dr) {
-                    cc = 2.0 * fmin(rld, rjd);
-                } else {
-                    const double p = (((-delta) * (d + R)) * (d - dr)) * (d + dr);
-                    cc = sqrt(fmax(p, 0.0)) * inv_d;
-                }
-                const double Fn = cc * a.Ed * delta;
-                const float4 vj = V[j];
-                const double wjd = (double)vj.z;
-                // spin sum in a fixed operand order (lower floe index first) so that
-                // the pair forces are exactly antisymmetric
-                const double spin = (l < j) ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
-                const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
-                const double capf = a.mud * fabs(Fn);
-                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
-                Fx += Fn * nx + Ft * tx;
-                Fy += Fn * ny + Ft * ty;
-                T += rld * Ft;
+                add_terms(Fx, Fy, T, cx, cy, ct);
                 ncontact += (l < j) ? 1ull : 0ull;
             }
 
