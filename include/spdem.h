@@ -155,7 +155,10 @@ sp_status sp_step(sp_ctx* ctx, double dt, int64_t nsteps);
  * stream once (a 4-byte read of that radius).  dt is the dt of each sp_step
  * call; a coarse step uses N0 times the dt of the call that completes it.
  * N0 = N1 = n_t = 1 is the plain step.  Between coarse steps
- * SP_MOMENTS_CONTINUUM reads the latest coarse state.  Cadence state lives in
+ * SP_MOMENTS_CONTINUUM reads the latest coarse state.  With a step block
+ * k > 1 (sp_set_step_block) and every count bucket within one floe per lane,
+ * the fine steps up to each update run as blocked launches of at most k steps,
+ * the update done inside the launch that ends at it.  Cadence state lives in
  * the context: a ring of N0 x ncells x 128 B statistics.
  * Errors: SP_EINVAL (a value < 1, N0 or N1 > SP_MAX_COUPLING), SP_ESTATE
  * (N0 > 1 with SP_NO_CONTINUUM or an active hybrid), SP_ENOMEM at the first
@@ -237,8 +240,10 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * statistics going to a k-slot ring, followed by the k continuum updates;
  * steps left over run one by one.  A bucket whose cells exceed one floe per
  * lane (more than 64 W floes) takes k per-step launches inside the block,
- * writing the same ring.  Applies when some bucket fits one floe per lane,
- * N0 = 1 and no hybrid is active.  The floe state is the same
+ * writing the same ring.  Applies to sp_step when some bucket fits one floe
+ * per lane and N0 = 1 (the coupled cadence blocks its stretches between
+ * coarse-to-fine updates, the hybrid its DEM cells between checks: see
+ * sp_set_coupling and sp_step_hybrid).  The floe state is the same
  * bit for bit as with k = 1; statistics are summed in another fixed order.
  * Ring: k x ncells x 128 B.  Default 32.  Errors: SP_EINVAL (k outside
  * [1, SP_MAX_STEP_BLOCK]). */
@@ -384,7 +389,10 @@ sp_status sp_resync_cells(sp_ctx* ctx, int32_t ncl, const int32_t* cells, const 
 sp_status sp_hybrid_set(sp_ctx* ctx, sp_mlp* net, const uint8_t* closure_cells, int32_t check_every,
                         int32_t check_cells, double tol, int32_t fallback_steps, double net_window);
 /* nsteps hybrid steps of size dt (asynchronous except at checks and mode
- * changes).
+ * changes).  With a step block k > 1 (sp_set_step_block) the DEM-mode cells'
+ * steps up to the next check or the end of a fallback window run as blocked
+ * launches of at most k steps, followed by each step's closure and continuum
+ * work in order; the floe state is the same bit for bit as with k = 1.
  * Errors: SP_EINVAL, SP_ESTATE (no hybrid), SP_EDEVICE. */
 sp_status sp_step_hybrid(sp_ctx* ctx, double dt, int64_t nsteps);
 /* current DEM-mode and closure-mode cell counts, checks made, fallbacks

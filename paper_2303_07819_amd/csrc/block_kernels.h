@@ -341,7 +341,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 #pragma unroll
             for (int q = 0; q < 4 * W; ++q) x += rows[g][gt][q];
             const int slot = dyn_slot(gt);
-            double* const mo = a.mom + (size_t)step * slot_len + (size_t)c * kMomStride;
+            double* const mo = (wk.w ? a.mom_alt : a.mom + (size_t)step * slot_len) + (size_t)c * kMomStride;
             mo[slot] = x;
             if (slot == M_UX || slot == M_UY) mo[slot == M_UX ? M_UBAR : M_VBAR] = n > 0 ? x / (double)n : 0.0;
         }

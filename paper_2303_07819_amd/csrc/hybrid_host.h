@@ -218,6 +218,7 @@ struct HybridState {
     double tol = 0.2;
     double net_window = 0.0;              // seconds after a reduced DEM's start the network acts (<= 0: always)
     int64_t checks = 0, fallbacks = 0, cursor = 0, hsteps = 0;
+    const double* last_mom = nullptr;     // statistics of the step just taken (the block ring, or momb)
     Bucket bk[kNumBuckets];               // DEM-mode cells, and the pool's closure-mode cells (shadow DEM:
                                           // their statistics go to scratch)
     std::vector<int32_t> clos_h;          // closure-mode cells
@@ -367,7 +368,7 @@ sp_status hybrid_check(sp_ctx* c, double dt)
                        h->Qs, ca, dt);
     HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(check_tendency_kernel, dim3((nk + 63) / 64), dim3(64), 0, c->stream, h->chk_d, nk, c->mom2,
-                       c->momb[k & 1], c->Q[c->kstep & 1], h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
+                       h->last_mom ? h->last_mom : c->momb[k & 1], c->Q[c->kstep & 1], h->Qs, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly,
                        inv_area, h->Tdem);
     HIP_TRY(c, hipGetLastError());
     // 3. the closure's residual for the same cells
@@ -554,60 +555,91 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     StepArgs base = make_args(c, dt);
     base.mom_alt = c->mom2;
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);
-    for (int64_t it = 0; it < nsteps; ++it) {
-        const int64_t k = c->kstep;
-        const int nclos = (int)h->clos_h.size();
-        if (nclos > 0) {
-            // base-updated level-k state, the network's residual for its
-            // features, the closure cells' coefficients from their reduced DEMs
-            ClosureArgs ca = closure_args(c, c->t_now);
-            hipLaunchKernelGGL(reduced_stats_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, ca,
-                               h->rs);
-            HIP_TRY(c, hipGetLastError());
-            ca.rs = h->rs;   // every cell's reduced statistics once, read by the stencils below
-            hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
-                               h->Qs, ca, dt);
-            HIP_TRY(c, hipGetLastError());
-            hipLaunchKernelGGL(features_kernel, dim3((nclos + 127) / 128), dim3(128), 0, c->stream, h->clos_d, nclos,
-                               h->Qs, ca, c->desc, h->X);
-            HIP_TRY(c, hipGetLastError());
-            SP_TRY(net_forward_on(c, h->net, h->X, nclos, h->T));
-            hipLaunchKernelGGL(reduced_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream, h->clos_d,
-                               nclos, ca, c->momb[k & 1]);
-            HIP_TRY(c, hipGetLastError());
+    const size_t slot = (size_t)c->ncells * kMomStride;
+    // The DEM cells never read the continuum between checks (no coarse-to-fine
+    // update at this cadence), so their steps up to the next check or the end
+    // of a fallback window run as blocked launches (statistics of step t into
+    // slot t of the block ring), followed by the closure and continuum work of
+    // each step in order, on the library stream.
+    const bool can_block = c->block_k > 1 && std::any_of(h->bk, h->bk + kNumBuckets, [](const Bucket& b) {
+        return !b.cells_h.empty() && b.cap <= 64 * b.waves;
+    });
+    if (can_block) SP_TRY(block_prepare(c));
+    for (int64_t it = 0; it < nsteps;) {
+        int64_t K = 1;
+        if (can_block) {
+            K = std::min<int64_t>(c->block_k, nsteps - it);
+            K = std::min<int64_t>(K, h->check_every - h->hsteps % h->check_every);
+            for (int32_t cell : h->fallback_cells) K = std::min<int64_t>(K, h->fallback_left[cell]);
         }
-        // DEM step of the other cells (statistics of level k), and of the check
-        // pool's closure cells (statistics into scratch: the closure drives them)
-        for (auto& b : h->bk) SP_TRY(launch_bucket(c, b, base, k, false));
-        hipLaunchKernelGGL(hybrid_continuum_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream,
-                           c->momb[k & 1], c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->red, c->t_now,
-                           h->net_window, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly, inv_area, c->cfl_bits_d,
-                           c->err_d);
-        HIP_TRY(c, hipGetLastError());
-        c->kstep++;
-        c->steps++;
-        c->t_now += dt;
-        h->hsteps++;
-        // fallback windows that end with this step: those cells' reduced DEMs
-        // restart from their floes
-        std::vector<int32_t> back;
-        size_t keep = 0;
-        for (size_t i = 0; i < h->fallback_cells.size(); ++i) {
-            const int32_t cell = h->fallback_cells[i];
-            if (--h->fallback_left[cell] == 0) {
-                if (h->closure[cell]) back.push_back(cell);
-            } else {
-                h->fallback_cells[keep++] = cell;
+        double* ring = nullptr;
+        if (K > 1) {
+            SP_TRY(join_block_lf(c));
+            BlockNudge none;
+            memset(&none, 0, sizeof none);
+            ring = c->blk_ring;
+            SP_TRY(launch_blocks(c, base, ring, (int)K, none, h->bk));
+            c->blk_steps += K;
+        }
+        for (int64_t t = 0; t < K; ++t, ++it) {
+            const int64_t k = c->kstep;
+            double* const mom = ring ? ring + (size_t)t * slot : c->momb[k & 1];
+            const int nclos = (int)h->clos_h.size();
+            if (nclos > 0) {
+                // base-updated level-k state, the network's residual for its
+                // features, the closure cells' coefficients from their reduced DEMs
+                ClosureArgs ca = closure_args(c, c->t_now);
+                hipLaunchKernelGGL(reduced_stats_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, ca,
+                                   h->rs);
+                HIP_TRY(c, hipGetLastError());
+                ca.rs = h->rs;   // every cell's reduced statistics once, read by the stencils below
+                hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
+                                   h->Qs, ca, dt);
+                HIP_TRY(c, hipGetLastError());
+                hipLaunchKernelGGL(features_kernel, dim3((nclos + 127) / 128), dim3(128), 0, c->stream, h->clos_d,
+                                   nclos, h->Qs, ca, c->desc, h->X);
+                HIP_TRY(c, hipGetLastError());
+                SP_TRY(net_forward_on(c, h->net, h->X, nclos, h->T));
+                hipLaunchKernelGGL(reduced_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream,
+                                   h->clos_d, nclos, ca, mom);
+                HIP_TRY(c, hipGetLastError());
             }
+            // DEM step of the other cells (statistics of level k), and of the
+            // check pool's closure cells (statistics into scratch: the closure
+            // drives them); in a block, already done
+            if (!ring)
+                for (auto& b : h->bk) SP_TRY(launch_bucket(c, b, base, k, false));
+            hipLaunchKernelGGL(hybrid_continuum_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, mom,
+                               c->Q[k & 1], h->Qs, c->Q[(k + 1) & 1], h->row_d, h->T, c->red, c->t_now,
+                               h->net_window, c->p.nx, c->p.ny, dt, c->p.cell_lx, c->p.cell_ly, inv_area,
+                               c->cfl_bits_d, c->err_d);
+            HIP_TRY(c, hipGetLastError());
+            h->last_mom = mom;
+            c->kstep++;
+            c->steps++;
+            c->t_now += dt;
+            h->hsteps++;
+            // fallback windows that end with this step (in a block, only its
+            // last step): those cells' reduced DEMs restart from their floes
+            std::vector<int32_t> back;
+            size_t keep = 0;
+            for (size_t i = 0; i < h->fallback_cells.size(); ++i) {
+                const int32_t cell = h->fallback_cells[i];
+                if (--h->fallback_left[cell] == 0) {
+                    if (h->closure[cell]) back.push_back(cell);
+                } else {
+                    h->fallback_cells[keep++] = cell;
+                }
+            }
+            h->fallback_cells.resize(keep);
+            if (!back.empty()) {
+                HIP_TRY(c, hipMemcpyAsync(h->back_d, back.data(), back.size() * 4, hipMemcpyHostToDevice, c->stream));
+                SP_TRY(restart_reduced(c, h->back_d, (int)back.size(), nullptr));
+                for (int32_t cell : back) h->red_t0[cell] = c->t_now;
+                SP_TRY(hybrid_rebuild(c));   // synchronises: `back` may go
+            }
+            if (h->hsteps % h->check_every == 0) SP_TRY(hybrid_check(c, dt));
         }
-        h->fallback_cells.resize(keep);
-        if (!back.empty()) {
-            HIP_TRY(c, hipMemcpyAsync(h->back_d, back.data(), back.size() * 4, hipMemcpyHostToDevice, c->stream));
-            SP_TRY(restart_reduced(c, h->back_d, (int)back.size(), nullptr));
-            for (int32_t cell : back) h->red_t0[cell] = c->t_now;
-            SP_TRY(hybrid_rebuild(c));   // synchronises: `back` may go
-        }
-        if (h->hsteps % h->check_every == 0) SP_TRY(hybrid_check(c, dt));
     }
     return SP_OK;
 }

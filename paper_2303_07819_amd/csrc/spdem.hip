@@ -514,15 +514,19 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
-// K steps from level kstep as one blocked launch per bucket, the statistics of
-// step t into mom + t * (ncells x kMomStride); with an active nd, the
+// K steps from level kstep as one blocked launch per bucket (of bk, default the
+// context's buckets), the statistics of step t into mom + t * (ncells x
+// kMomStride) (work entries flagged for mom_alt: there); with an active nd, the
 // coarse-to-fine update of every launched cell at the end (every bucket must
 // then hold one floe per lane).  A bucket with more floes per cell than lanes
 // takes K per-step launches instead (plain cadence only).
-sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd)
+sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd,
+                        const Bucket* bk = nullptr)
 {
     const size_t slot = (size_t)c->ncells * kMomStride;
-    for (const auto& b : c->bk) {
+    if (!bk) bk = c->bk;
+    for (int q = 0; q < kNumBuckets; ++q) {
+        const Bucket& b = bk[q];
         if (b.cells_h.empty()) continue;
         if (b.cap > 64 * b.waves) {
             if (nd.x0m) return fail(c, SP_EINVAL, "blocked update needs one floe per lane");

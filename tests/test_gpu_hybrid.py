@@ -325,6 +325,40 @@ def test_hybrid_checks_and_fallback():
     net.close()
 
 
+@pytest.mark.parametrize("tol", [1e-30, 1e30])
+def test_hybrid_blocked_equals_per_step(tol):
+    """The hybrid's DEM cells run as blocked launches between checks and the
+    ends of fallback windows: the same floes bit for bit as one launch per
+    step, the same checks and fallbacks, the continuum within 1e-12 (the DEM
+    statistics are summed in another fixed order)."""
+    w = fixtures.custom(6, 4, 25e3, 40, seed=45, r_scale=fixtures.radius_scale(40, 25e3 ** 2, phi=0.3))
+    rng = np.random.default_rng(45)
+    w.u[:] = rng.normal(0, 0.1, w.nfloes)
+    w.v[:] = rng.normal(0, 0.1, w.nfloes)
+    closure = np.zeros(w.ncells, bool)
+    closure[1::2] = True
+    norm = list(_norm_for(w))
+    out = []
+    for k in (1, 8):
+        net, _ = _net(7, *norm)
+        with sp.Sim.from_workload(w) as s:
+            s.set_step_block(k)
+            s.hybrid_set(net, closure, check_every=5, check_cells=3, tol=tol, fallback_steps=4)
+            s.step_hybrid(w.dt, 13)
+            s.step_hybrid(w.dt, 9)
+            out.append(dict(f=s.read_floes(), q=s.read_moments(sp.MOMENTS_CONTINUUM), hs=s.hybrid_stats(),
+                            work=s.work()))
+        net.close()
+    a, b = out
+    _say(f"tol {tol:g}: {b['hs']}, blocked steps {b['work']['blocked_steps']}")
+    assert a["hs"] == b["hs"]
+    assert b["work"]["blocked_steps"] > 0 and a["work"]["blocked_steps"] == 0
+    for q in a["f"]:
+        assert np.array_equal(a["f"][q], b["f"][q]), q
+    e = rel_err(b["q"], a["q"], floor=1e-6)
+    assert e.max() <= 1e-12, e.max()
+
+
 def test_trained_closure_gains_over_the_reduced_dem_alone():
     """A network trained here on the method's own DEM runs (three 64 x 64
     windows, six epochs) lowers the momentum error of the hybrid against full
