@@ -156,8 +156,8 @@ sp_status sp_step(sp_ctx* ctx, double dt, int64_t nsteps);
  * call; a coarse step uses N0 times the dt of the call that completes it.
  * N0 = N1 = n_t = 1 is the plain step.  Between coarse steps
  * SP_MOMENTS_CONTINUUM reads the latest coarse state.  With a step block
- * k > 1 (sp_set_step_block) and every count bucket within one floe per lane,
- * the fine steps up to each update run as blocked launches of at most k steps,
+ * k > 1 (sp_set_step_block) the fine steps up to each update run as blocked
+ * launches of at most k steps,
  * the update done inside the launch that ends at it.  Cadence state lives in
  * the context: a ring of N0 x ncells x 128 B statistics.
  * Errors: SP_EINVAL (a value < 1, N0 or N1 > SP_MAX_COUPLING), SP_ESTATE
@@ -238,10 +238,10 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * which every cell keeps its floes and candidate lists in LDS for the k steps
  * (the cell DEMs never read the continuum at this cadence), each step's
  * statistics going to a k-slot ring, followed by the k continuum updates;
- * steps left over run one by one.  A bucket whose cells exceed one floe per
- * lane (more than 64 W floes) takes k per-step launches inside the block,
- * writing the same ring.  Applies to sp_step when some bucket fits one floe
- * per lane and N0 = 1 (the coupled cadence blocks its stretches between
+ * steps left over run one by one.  Blocked launches hold one floe per lane: a
+ * bucket whose cells exceed 64 W floes runs them with W = 16 (up to
+ * SP_MAX_CELL_FLOES).  Applies to sp_step with N0 = 1 (the coupled cadence
+ * blocks its stretches between
  * coarse-to-fine updates, the hybrid its DEM cells between checks: see
  * sp_set_coupling and sp_step_hybrid).  The floe state is the same
  * bit for bit as with k = 1; statistics are summed in another fixed order.

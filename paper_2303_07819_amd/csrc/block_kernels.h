@@ -43,7 +43,7 @@ __device__ __forceinline__ double group_sum_rows(double x, double* rows_g, int g
     if ((gt & 15) == 15) rows_g[gt >> 4] = x;
     __syncthreads();
     double t = 0.0;
-#pragma unroll
+#pragma unroll 8
     for (int q = 0; q < 4 * W; ++q) t += rows_g[q];
     __syncthreads();
     return t;
@@ -64,8 +64,10 @@ __device__ __forceinline__ float group_max(float x, float* wmax_g, int gt)
 
 // Five waves per SIMD: the step loop keeps more state live than one step does,
 // and five resident waves with a few spilled registers beat three without.
+// W = 16 (cells of up to 1024 floes) fills a compute unit's LDS with one cell:
+// four waves per SIMD, the register file without spills.
 template <int SCHED, int W>
-__global__ __launch_bounds__(W >= 4 ? 64 * W : 256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(W >= 4 ? 64 * W : 256) __attribute__((amdgpu_waves_per_eu(W >= 16 ? 4 : 5)))
 void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 {
     constexpr int G = 64 * W;                  // threads per group (one floe per lane)
@@ -338,7 +340,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         }
         if (valid && gt < kDyn) {
             double x = 0.0;
-#pragma unroll
+#pragma unroll 8
             for (int q = 0; q < 4 * W; ++q) x += rows[g][gt][q];
             const int slot = dyn_slot(gt);
             double* const mo = (wk.w ? a.mom_alt : a.mom + (size_t)step * slot_len) + (size_t)c * kMomStride;

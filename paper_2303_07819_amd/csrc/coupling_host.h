@@ -183,14 +183,14 @@ sp_status nudge(sp_ctx* c, double frac)
 
 // Fine steps of the coupled cadence (declared before sp_step).  Cells are
 // independent between coarse-to-fine updates, and an update needs only the
-// cell's own X0 and Q: with one floe per lane, each stretch up to the next
-// update or coarse step runs as one blocked launch per bucket (the floes
-// resident in LDS), the update done in the same launch.
+// cell's own X0 and Q: with a step block above one, each stretch up to the
+// next update or coarse step runs as one blocked launch per bucket (the floes
+// resident in LDS, one per lane), the update done in the same launch.
 sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
 {
     SP_TRY(coupling_prepare(c));
     const size_t slot = (size_t)c->ncells * kMomStride;
-    if (c->block_k > 1 && buckets_one_per_lane(c)) {
+    if (c->block_k > 1) {
         int64_t left = nsteps;
         while (left > 0) {
             const int64_t r = c->cpl_j % c->N0;

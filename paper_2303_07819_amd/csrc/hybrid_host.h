@@ -561,9 +561,7 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     // of a fallback window run as blocked launches (statistics of step t into
     // slot t of the block ring), followed by the closure and continuum work of
     // each step in order, on the library stream.
-    const bool can_block = c->block_k > 1 && std::any_of(h->bk, h->bk + kNumBuckets, [](const Bucket& b) {
-        return !b.cells_h.empty() && b.cap <= 64 * b.waves;
-    });
+    const bool can_block = c->block_k > 1;
     if (can_block) SP_TRY(block_prepare(c));
     for (int64_t it = 0; it < nsteps;) {
         int64_t K = 1;

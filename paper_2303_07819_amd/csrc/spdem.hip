@@ -464,6 +464,7 @@ sp_status launch_block_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, i
     case 2: return binned ? launch_block_t<2, 2>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 2>(c, a, grid, threads, lds, K, nd);
     case 4: return binned ? launch_block_t<2, 4>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 4>(c, a, grid, threads, lds, K, nd);
     case 8: return binned ? launch_block_t<2, 8>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 8>(c, a, grid, threads, lds, K, nd);
+    case 16: return binned ? launch_block_t<2, 16>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 16>(c, a, grid, threads, lds, K, nd);
     default: return fail(c, SP_EINVAL, "no blocked kernel for waves=%d", waves);
     }
 }
@@ -514,28 +515,27 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
+// Wavefronts per cell of a bucket's blocked launches: the bucket's own W when
+// its cells have at most 64 W floes, else 16 (one floe per lane up to the
+// 1024-floe cell limit).
+int block_waves(const Bucket& b) { return b.cap <= 64 * b.waves ? b.waves : 16; }
+
 // K steps from level kstep as one blocked launch per bucket (of bk, default the
 // context's buckets), the statistics of step t into mom + t * (ncells x
 // kMomStride) (work entries flagged for mom_alt: there); with an active nd, the
-// coarse-to-fine update of every launched cell at the end (every bucket must
-// then hold one floe per lane).  A bucket with more floes per cell than lanes
-// takes K per-step launches instead (plain cadence only).
+// coarse-to-fine update of every launched cell at the end.
 sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd,
                         const Bucket* bk = nullptr)
 {
-    const size_t slot = (size_t)c->ncells * kMomStride;
     if (!bk) bk = c->bk;
     for (int q = 0; q < kNumBuckets; ++q) {
         const Bucket& b = bk[q];
         if (b.cells_h.empty()) continue;
-        if (b.cap > 64 * b.waves) {
-            if (nd.x0m) return fail(c, SP_EINVAL, "blocked update needs one floe per lane");
-            for (int t = 0; t < K; ++t) SP_TRY(launch_bucket(c, b, base, c->kstep + t, false, false, mom + t * slot));
-            continue;
-        }
+        const int w = block_waves(b);
+        if (b.cap > 64 * w) return fail(c, SP_EINVAL, "%d floes per cell exceed a blocked launch", b.cap);
         // the blocked kernel keeps 1 / m and 1 / (m r^2) per floe beside the state
-        const size_t gbytes = bucket_group_bytes(c, b) + (size_t)b.cap * 16;
-        const int gpb = groups_per_block(b.waves, gbytes);
+        const size_t gbytes = group_bytes(c->sched, b.cap, c->nbx * c->nby, w) + (size_t)b.cap * 16;
+        const int gpb = groups_per_block(w, gbytes);
         StepArgs a = base;
         a.work = b.work_d;
         a.ncl = (int32_t)b.cells_h.size();
@@ -544,17 +544,9 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
         a.mom = mom;
         a.lf = 0;
         const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, c->sched, b.waves, a, grid, gpb * 64 * b.waves, (size_t)gpb * gbytes, K, nd));
+        SP_TRY(launch_block_sel(c, c->sched, w, a, grid, gpb * 64 * w, (size_t)gpb * gbytes, K, nd));
     }
     return SP_OK;
-}
-
-// Every count bucket holds cells of at most one floe per lane.
-bool buckets_one_per_lane(const sp_ctx* c)
-{
-    for (const auto& b : c->bk)
-        if (!b.cells_h.empty() && b.cap > 64 * b.waves) return false;
-    return true;
 }
 
 sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k);
@@ -584,14 +576,11 @@ sp_status flush_lf(sp_ctx* c)
     return SP_OK;
 }
 
-// Blocked steps apply when every cell of every bucket has one floe per lane,
-// the cadence is the plain one and no hybrid is active.
+// Blocked plain steps apply with a block length above one, the plain cadence
+// and no hybrid (the coupled cadence and the hybrid block on their own terms).
 bool block_eligible(const sp_ctx* c)
 {
-    if (c->block_k <= 1 || c->N0 != 1 || c->hyb) return false;
-    for (const auto& b : c->bk)   // some bucket gains from resident cells
-        if (!b.cells_h.empty() && b.cap <= 64 * b.waves) return true;
-    return false;
+    return c->block_k > 1 && c->N0 == 1 && !c->hyb;
 }
 
 // Make the library stream wait for the continuum updates of the last block

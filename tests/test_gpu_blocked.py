@@ -74,10 +74,10 @@ def test_blocked_flags():
             assert np.array_equal(a["floes"][key], b["floes"][key]), (flags, key)
 
 
-def test_mixed_buckets_step_large_cells_one_by_one_inside_a_block():
-    """Cells above 64 W floes (the 1024-floe bucket) take K per-step launches
-    inside a block while the others run blocked; the floe state stays that of
-    the per-step path bit for bit."""
+def test_large_cells_block_with_sixteen_wavefronts():
+    """Cells above 64 W floes (the 1024-floe bucket at W = 8, two floes per
+    lane in the per-step kernel) run blocked with 16 wavefronts, one floe per
+    lane; the floe state stays that of the per-step path bit for bit."""
     w = ragged_workload()
     a = _run(w, 1, 8)
     b = _run(w, 4, 8)
