@@ -26,6 +26,8 @@ _lib = None
 OCEAN_OFF = 1
 FORWARD_EULER = 2
 BINNED = 4
+SPRING = 8          # tangential force as an incremental spring with contact history
+HCAP = 16           # contacts remembered per floe (SPRING)
 NMOM = 11
 MOMENT_NAMES = ["n", "M", "Px", "Py", "L", "Ux", "Uy", "Svx", "Svy", "Sw", "Aice"]
 Q_NAMES = ["rho", "Px", "Py", "Pw"]
@@ -68,7 +70,7 @@ def _load():
         lib.orc_chord.argtypes = [D, D, D]
         lib.orc_chord.restype = D
         lib.orc_moments.argtypes = [MP, P, P, P, P, P, P, P, P, P]
-        lib.orc_dem_steps.argtypes = [MP, P, P, I32, P, P, P, P, P, P, P, P, D, I64, P, P]
+        lib.orc_dem_steps.argtypes = [MP, P, P, I32, P, P, P, P, P, P, P, P, D, I64, P, P, P, P]
         lib.orc_dem_steps.restype = ctypes.c_int
         lib.orc_q_from_moments.argtypes = [MP, P, P]
         lib.orc_lf_step.argtypes = [MP, P, P, D, P]
@@ -95,6 +97,7 @@ class Model:
         self._keep = [_f64(oc.kx), _f64(oc.ky), _f64(oc.au), _f64(oc.av), _f64(oc.phase)]
         self.c = _Model(w.nx, w.ny, w.Lx, w.Ly, w.rho_ice, w.rho_ocean, w.cd, w.E, w.G, w.mu,
                         flags, oc.u0, oc.v0, oc.nmodes, *[_p(a) for a in self._keep])
+        self.flags = flags
         self.nx, self.ny, self.Lx, self.Ly = w.nx, w.ny, w.Lx, w.Ly
         self.ncells = w.nx * w.ny
         self.start = np.ascontiguousarray(w.start, np.int64)
@@ -110,6 +113,11 @@ class State:
     def __init__(self, xs, ys, u, v, w, th, r, h):
         self.xs, self.ys, self.u, self.v, self.w, self.th, self.r, self.h = (
             _f64(a).copy() for a in (xs, ys, u, v, w, th, r, h))
+        # contact history of the tangential spring (SPRING), made by the first
+        # such step: per floe HCAP partners (cell-local index, -1 none) and
+        # tangential displacements
+        self.hj = None
+        self.hx = None
 
     @staticmethod
     def from_fixed(xi, yi, u, v, omega, theta, r, h) -> "State":
@@ -122,7 +130,10 @@ class State:
         return State.from_fixed(w.xi, w.yi, w.u, w.v, w.omega, w.theta, w.r, w.h)
 
     def copy(self) -> "State":
-        return State(self.xs, self.ys, self.u, self.v, self.w, self.th, self.r, self.h)
+        st = State(self.xs, self.ys, self.u, self.v, self.w, self.th, self.r, self.h)
+        if self.hj is not None:
+            st.hj, st.hx = self.hj.copy(), self.hx.copy()
+        return st
 
     def arrays(self):
         return [self.xs, self.ys, self.u, self.v, self.w, self.th, self.r, self.h]
@@ -173,12 +184,19 @@ def dem_steps(model: Model, state: State, dt: float, nsteps: int, cells=None,
     ncl = model.ncells if cl is None else int(cl.size)
     mom = np.zeros((nsteps, ncl, NMOM)) if record else None
     stats = np.zeros(2, np.int64)
+    spring = (model.flags & SPRING) != 0
+    if spring and state.hj is None:
+        state.hj = np.full((state.xs.size, HCAP), -1, np.int32)
+        state.hx = np.zeros((state.xs.size, HCAP))
     rc = lib.orc_dem_steps(model.ref, _p(model.start), _p(cl), ncl, *[_p(a) for a in state.arrays()],
-                           dt, nsteps, _p(mom), _p(stats))
+                           dt, nsteps, _p(mom), _p(stats), _p(state.hj) if spring else None,
+                           _p(state.hx) if spring else None)
     if rc == -1:
         raise FloatingPointError("coincident floe centres")
     if rc == -2:
         raise FloatingPointError("non-finite floe state")
+    if rc == -3:
+        raise OverflowError(f"a floe in more than {HCAP} contacts")
     return mom, stats
 
 

@@ -40,6 +40,8 @@
 #define ORC_OCEAN_OFF 1
 #define ORC_FORWARD_EULER 2
 #define ORC_BINNED 4
+#define ORC_TSPRING 8   /* tangential force as an incremental spring with contact history */
+#define ORC_HCAP 16     /* contacts remembered per floe */
 
 #define NMOM 11
 enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE };
@@ -195,10 +197,17 @@ double orc_chord(double rl, double rj, double d)
 
 /* Force f^{lj} on floe l from floe j and the spin torque on l (contact law of
  * Sec. 2.1): f_n = c E delta n, f_t = c G v_t t with |f_t| <= mu |f_n|.
- * Returns 0, or -1 if the centres coincide. */
+ * With ORC_TSPRING the tangential force is the incremental spring that the
+ * cited Cundall-Strack model uses instead: the pair's tangential displacement
+ * xi (zero when the contact begins) grows by v_t dt each step, f_t = c G xi t
+ * with G a shear modulus, and where |f_t| would pass mu |f_n| the contact
+ * slips: f_t takes the Coulomb limit and xi the displacement that gives it.
+ * xi_old is the pair's displacement after the previous step (0 for a new
+ * contact); *xi receives the new one.  Returns 0, or -1 if the centres
+ * coincide. */
 static int contact_force(const orc_model* m, const double* xs, const double* ys, const double* u,
                          const double* v, const double* w, const double* r, int64_t l, int64_t j,
-                         double* fx, double* fy, double* tq)
+                         double dt, double xi_old, double* xi, double* fx, double* fy, double* tq)
 {
     double dx = min_image(xs[j] - xs[l]) * m->Lx;
     double dy = min_image(ys[j] - ys[l]) * m->Ly;
@@ -211,10 +220,23 @@ static int contact_force(const orc_model* m, const double* xs, const double* ys,
     double Fn = c * m->E * delta;
     /* relative tangential velocity of the contact point of j seen from l */
     double vt = (u[j] - u[l]) * tx + (v[j] - v[l]) * ty - w[j] * r[j] - w[l] * r[l];
-    double Ft = c * m->G * vt;
     double cap = m->mu * fabs(Fn);
-    if (Ft > cap) Ft = cap;
-    if (Ft < -cap) Ft = -cap;
+    double Ft;
+    if (m->flags & ORC_TSPRING) {
+        double k = c * m->G;               /* tangential stiffness of the contact */
+        double x = xi_old + vt * dt;
+        Ft = k * x;
+        if (Ft > cap || Ft < -cap) {       /* slip: the spring stretches no further */
+            Ft = Ft > cap ? cap : -cap;
+            x = k > 0.0 ? Ft / k : 0.0;
+        }
+        *xi = x;
+    } else {
+        Ft = c * m->G * vt;
+        if (Ft > cap) Ft = cap;
+        if (Ft < -cap) Ft = -cap;
+        *xi = 0.0;
+    }
     *fx = Fn * nx + Ft * tx;
     *fy = Fn * ny + Ft * ty;
     *tq = r[l] * Ft;
@@ -310,13 +332,19 @@ static int cmp_i32(const void* a, const void* b)
     return (p > q) - (p < q);
 }
 
-/* One fine step of one cell.  Returns 0, -1 (coincident centres) or -2 (NaN).
+/* One fine step of one cell.  Returns 0, -1 (coincident centres), -2 (NaN) or
+ * -3 (a floe in more than ORC_HCAP contacts with ORC_TSPRING).
  * mom (may be NULL) receives the statistics of the state before the step.
- * stats[0] += contacts, stats[1] += candidate pairs considered. */
+ * stats[0] += contacts, stats[1] += candidate pairs considered.
+ * hj, hx (ORC_TSPRING only): each floe's contact history, ORC_HCAP partner
+ * indices (-1: none) and their tangential displacements; a floe's entries are
+ * replaced by its contacts of this step, so a contact that ends is forgotten. */
 static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, double* ys,
                      double* u, double* v, double* w, double* th, const double* r,
-                     const double* h, double dt, double* mom, int64_t* stats)
+                     const double* h, double dt, double* mom, int64_t* stats, int32_t* hj,
+                     double* hx)
 {
+    const int spring = (m->flags & ORC_TSPRING) != 0;
     if (n == 0) {
         if (mom) memset(mom, 0, sizeof(double) * NMOM);
         return 0;
@@ -365,16 +393,35 @@ static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, 
     for (int64_t l = 0; l < n && !rc; ++l) {
         floe_terms t = drag_terms(m, ix, iy, xs[l], ys[l], u[l], v[l], w[l], r[l], h[l]);
         double Fx = t.Fdx, Fy = t.Fdy, T = t.Td;
+        int32_t nj[ORC_HCAP];
+        double nxi[ORC_HCAP];
+        int nh = 0;
         for (int64_t k = deg[l]; k < deg[l + 1]; ++k) {
-            double fx, fy, tq;
-            if (contact_force(m, xs, ys, u, v, w, r, l, adj[k], &fx, &fy, &tq)) {
+            double fx, fy, tq, xi, xi_old = 0.0;
+            if (spring)
+                for (int q = 0; q < ORC_HCAP; ++q)
+                    if (hj[l * ORC_HCAP + q] == adj[k]) xi_old = hx[l * ORC_HCAP + q];
+            if (contact_force(m, xs, ys, u, v, w, r, l, adj[k], dt, xi_old, &xi, &fx, &fy, &tq)) {
                 rc = -1;
                 break;
+            }
+            if (spring) {
+                if (nh == ORC_HCAP) {
+                    rc = -3;
+                    break;
+                }
+                nj[nh] = adj[k];
+                nxi[nh++] = xi;
             }
             Fx += fx;
             Fy += fy;
             T += tq;
         }
+        if (spring && !rc)
+            for (int q = 0; q < ORC_HCAP; ++q) {
+                hj[l * ORC_HCAP + q] = q < nh ? nj[q] : -1;
+                hx[l * ORC_HCAP + q] = q < nh ? nxi[q] : 0.0;
+            }
         ax[l] = Fx / t.m;
         ay[l] = Fy / t.m;
         aw[l] = T / t.I;
@@ -404,15 +451,17 @@ static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, 
 }
 
 /* nsteps fine steps of the listed cells (all cells if cells == NULL).
- * mom (may be NULL): [nsteps][ncl][NMOM], statistics of each pre-step state. */
+ * mom (may be NULL): [nsteps][ncl][NMOM], statistics of each pre-step state.
+ * hj, hx: contact histories [N][ORC_HCAP] (ORC_TSPRING only, else NULL). */
 int orc_dem_steps(const orc_model* m, const int64_t* start, const int32_t* cells, int32_t ncl,
                   double* xs, double* ys, double* u, double* v, double* w, double* th,
                   const double* r, const double* h, double dt, int64_t nsteps, double* mom,
-                  int64_t* stats)
+                  int64_t* stats, int32_t* hj, double* hx)
 {
     int32_t nc = cells ? ncl : m->nx * m->ny;
     int rc = 0;
     int64_t st0 = 0, st1 = 0;
+    if ((m->flags & ORC_TSPRING) && !(hj && hx)) return -4;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : st0, st1)
     for (int32_t k = 0; k < nc; ++k) {
         int32_t c = cells ? cells[k] : k;
@@ -421,7 +470,8 @@ int orc_dem_steps(const orc_model* m, const int64_t* start, const int32_t* cells
         for (int64_t it = 0; it < nsteps; ++it) {
             double* mo = mom ? mom + ((size_t)it * nc + k) * NMOM : NULL;
             int e = cell_step(m, c % m->nx, c / m->nx, n, xs + s, ys + s, u + s, v + s, w + s,
-                              th + s, r + s, h + s, dt, mo, loc);
+                              th + s, r + s, h + s, dt, mo, loc, hj ? hj + s * ORC_HCAP : NULL,
+                              hx ? hx + s * ORC_HCAP : NULL);
             if (e) {
 #pragma omp critical
                 { if (!rc) rc = e; }
