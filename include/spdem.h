@@ -54,6 +54,18 @@ typedef enum {
 #define SP_OCEAN_OFF 1u       /* no drag, no drag torque */
 #define SP_FORWARD_EULER 2u   /* positions advance with the old velocities */
 #define SP_NO_CONTINUUM 4u    /* skip the coarse Lax-Friedrichs update */
+/* Tangential contact force as the incremental spring of the Cundall-Strack
+ * model the paper cites for it (Sec. 2.1) instead of the printed viscous law:
+ * each contact keeps its tangential displacement xi (zero when the contact
+ * begins, forgotten when it ends), xi grows by v_t dt per step, the force is
+ * c G xi t with G read as a shear modulus (N/m^2), and where |c G xi| would
+ * pass mu |f_n| the contact slips: the force takes the Coulomb limit and xi
+ * the displacement that gives it.  History: SP_SPRING_CAP contacts per floe
+ * (SP_ECAPACITY beyond), kept in device memory.  Runs one DEM launch per
+ * step; not with N0 > 1, the hybrid, closure sampling or the autotuner
+ * (SP_ESTATE). */
+#define SP_TANGENTIAL_SPRING 8u
+#define SP_SPRING_CAP 8
 
 /* sp_params.schedule: how a cell's contact candidates are enumerated.
  * Every schedule yields the same contact set and, because each floe sums its
@@ -86,9 +98,11 @@ typedef struct {
     double rho_ocean;         /* ocean density (kg/m^3) */
     double cd;                /* ocean drag coefficient d_o */
     double E;                 /* normal stiffness per unit chord length (N/m^2) */
-    double G;                 /* tangential viscous coefficient per unit chord (N s/m^2) */
+    double G;                 /* tangential viscous coefficient per unit chord (N s/m^2);
+                                 with SP_TANGENTIAL_SPRING the shear modulus (N/m^2) */
     double mu;                /* Coulomb friction coefficient */
-    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER | SP_NO_CONTINUUM */
+    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER | SP_NO_CONTINUUM |
+                                 SP_TANGENTIAL_SPRING */
     int32_t schedule;         /* SP_SCHED_* */
 } sp_params;
 

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libspdem.so")
 SP_OCEAN_OFF = 1
 SP_FORWARD_EULER = 2
 SP_NO_CONTINUUM = 4
+SP_TANGENTIAL_SPRING = 8     # tangential force as an incremental spring with contact history
+SP_SPRING_CAP = 8            # contacts remembered per floe (SP_TANGENTIAL_SPRING)
 SP_MAX_COUPLING = 65536
 SP_MAX_STEP_BLOCK = 1024
 SCHED_AUTO, SCHED_ALLPAIRS, SCHED_BINNED = 0, 1, 2

@@ -249,6 +249,8 @@ sp_status sp_set_coupling(sp_ctx* c, int32_t N0, int32_t N1, int32_t n_t)
         return fail(c, SP_EINVAL, "N0, N1 and n_t must be >= 1 and N0, N1 <= %d", SP_MAX_COUPLING);
     if (N0 > 1 && (c->p.flags & SP_NO_CONTINUUM)) return fail(c, SP_ESTATE, "coupling needs the continuum update");
     if (N0 > 1 && c->hyb) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
+    if (N0 > 1 && (c->p.flags & SP_TANGENTIAL_SPRING))
+        return fail(c, SP_ESTATE, "the tangential spring runs with N0 = 1");
     SP_TRY(flush_lf(c));
     drop_graph(c);
     const bool was = c->N0 > 1;

@@ -82,7 +82,9 @@ struct StepArgs {
     double* mom_alt;           // where the statistics of work entries with w = 1 go instead
     uint32_t* err;
     unsigned long long* contacts;   // [ncells] contacts counted per cell since the floes were set
-    unsigned long long* cands;      // [ncells] candidate tests counted per cell by blocked steps
+    unsigned long long* cands;
+    uint4* tsp_j;              // tangential spring: per floe SP_SPRING_CAP partners (u16, 0xffff none)
+    double* tsp_x;             // and their tangential displacements [n][SP_SPRING_CAP]      // [ncells] candidate tests counted per cell by blocked steps
     // candidate lists kept between steps (Verlet lists with a skin): per cell,
     // from floe-index start * kListCap, [kListCap / 8][n][8] (groups of eight
     // entries per floe), partner indices in ascending order; per floe its
@@ -305,9 +307,14 @@ __device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mc
 // operands in a fixed order (lower floe index first) so that the two floes of
 // a pair see the same value.  The contributions are returned, not summed, so
 // that any lane can evaluate a pair; false for coincident centres (no force).
+// SPRING: the tangential force is the incremental spring (SP_TANGENTIAL_SPRING):
+// the pair's displacement xi_old (0 for a new contact) grows by v_t dt, the
+// force is c G xi, and past mu |F_n| the contact slips (the force at the
+// Coulomb limit, xi the displacement that gives it); xi receives the new value.
+template <bool SPRING = false>
 __device__ __forceinline__ bool contact_terms(int dxi, int dyi, double rld, double uld, double vld, double wld,
                                               float rj, float4 vj, bool lower, const StepArgs& a, double& cx,
-                                              double& cy, double& ct)
+                                              double& cy, double& ct, double xi_old = 0.0, double* xi = nullptr)
 {
     const double dx = (double)dxi * a.qxd, dy = (double)dyi * a.qyd;
     const double d2 = dx * dx + dy * dy;
@@ -332,7 +339,19 @@ __device__ __forceinline__ bool contact_terms(int dxi, int dyi, double rld, doub
     const double spin = lower ? (wld * rld + wjd * rjd) : (wjd * rjd + wld * rld);
     const double vt = (((double)vj.x - uld) * tx + ((double)vj.y - vld) * ty) - spin;
     const double capf = a.mud * fabs(Fn);
-    const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+    double Ft;
+    if (SPRING) {
+        const double k = cc * a.Gd;            // tangential stiffness of the contact
+        double x = xi_old + vt * a.dtd;
+        Ft = k * x;
+        if (Ft > capf || Ft < -capf) {         // slip: the spring stretches no further
+            Ft = Ft > capf ? capf : -capf;
+            x = k > 0.0 ? Ft / k : 0.0;
+        }
+        *xi = x;
+    } else {
+        Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+    }
     cx = fma(Fn, nx, Ft * tx);
     cy = fma(Fn, ny, Ft * ty);
     ct = rld * Ft;
@@ -557,7 +576,9 @@ __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* 
 // PERSIST: a grid of resident workgroups strides over the work list.
 // ONE: no cell has more floes than the group has lanes (one floe per lane:
 // the floe loop carries nothing, which frees registers for occupancy).
-template <int SCHED, int W, bool PERSIST, bool ONE>
+// TSP: the tangential spring (SP_TANGENTIAL_SPRING), each floe's contact
+// history read before its contacts and rewritten with them.
+template <int SCHED, int W, bool PERSIST, bool ONE, bool TSP = false>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArgs a)
 {
     constexpr int G = 64 * W;                  // threads per group
@@ -797,20 +818,53 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             // ---- contact forces and torques in ascending partner order (FP64);
             // a wave runs as many rounds as its lanes have contacts at most
             double Fx = fdx, Fy = fdy, T = tdr;
+            // the floe's contact history (TSP): partners and displacements
+            // after the previous step, rewritten below with this step's contacts
+            uint4 hj = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+            double hx[SP_SPRING_CAP];
+            uint16_t* const tj = TSP ? reinterpret_cast<uint16_t*>(a.tsp_j + s + l) : nullptr;
+            double* const tx = TSP ? a.tsp_x + (size_t)(s + l) * SP_SPRING_CAP : nullptr;
+            if (TSP) {
+                hj = a.tsp_j[s + l];
+#pragma unroll
+                for (int q = 0; q < SP_SPRING_CAP; ++q) hx[q] = tx[q];
+            }
+            int nh = 0;
             while (cmask) {
                 const int q = __builtin_ctz(cmask);
                 cmask &= cmask - 1u;
                 const int j = my[q];
                 const uint4 pj = P[j];
-                double cx, cy, ct;
-                if (!contact_terms((int)(pj.x - xl), (int)(pj.y - yl), rld, uld, vld, wld, __uint_as_float(pj.z),
-                                   V[j], l < j, a, cx, cy, ct)) {
+                double cx, cy, ct, xi = 0.0, xi_old = 0.0;
+                if (TSP) {
+#pragma unroll
+                    for (int e = 0; e < SP_SPRING_CAP; ++e) {
+                        const uint32_t wv = e < 2 ? hj.x : e < 4 ? hj.y : e < 6 ? hj.z : hj.w;
+                        if ((int)((wv >> (16 * (e & 1))) & 0xffffu) == j) xi_old = hx[e];
+                    }
+                }
+                if (!contact_terms<TSP>((int)(pj.x - xl), (int)(pj.y - yl), rld, uld, vld, wld,
+                                        __uint_as_float(pj.z), V[j], l < j, a, cx, cy, ct, xi_old, &xi)) {
                     atomicOr(a.err, kErrOverlap);
                     continue;
+                }
+                if (TSP) {
+                    if (nh < SP_SPRING_CAP) {
+                        tj[nh] = (uint16_t)j;
+                        tx[nh] = xi;
+                    } else {
+                        atomicOr(a.err, kErrCapacity);
+                    }
+                    ++nh;
                 }
                 add_terms(Fx, Fy, T, cx, cy, ct);
                 ncontact += (l < j) ? 1ull : 0ull;
             }
+            if (TSP)
+                for (int e = nh; e < SP_SPRING_CAP; ++e) {
+                    tj[e] = 0xffffu;
+                    tx[e] = 0.0;
+                }
 
             // ---- time update (semi-implicit Euler by default), FP64 arithmetic,
             // FP32 / fixed-point storage

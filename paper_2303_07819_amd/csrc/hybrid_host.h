@@ -486,6 +486,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
         return fail(c, SP_EINVAL, "check_every and fallback_steps must be >= 1, check_cells >= 0, tol > 0");
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "the hybrid needs the continuum update");
     if (c->N0 > 1) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
+    if (c->p.flags & SP_TANGENTIAL_SPRING) return fail(c, SP_ESTATE, "the hybrid runs the viscous contact law");
     HIP_TRY(c, hipStreamSynchronize(net->stream));   // parameters and normalisation in place
     SP_TRY(flush_lf(c));
     hybrid_free(c);

@@ -110,6 +110,8 @@ struct sp_ctx {
     double* qprev = nullptr;                // continuum snapshot for tendencies
     uint16_t* vlist = nullptr;              // candidate lists [n][kListCap], entry-major per cell
     uint8_t* vcount = nullptr;              // candidates per floe [n]
+    uint4* tsp_j = nullptr;                 // tangential spring history (SP_TANGENTIAL_SPRING): partners [n]
+    double* tsp_x = nullptr;                //   and displacements [n][SP_SPRING_CAP]
     float* vdisp = nullptr;                 // per-cell displacement bound since the lists were built
 
     // time stepping
@@ -224,7 +226,7 @@ void free_all(sp_ctx* c)
     void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
                   c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d,
-                  c->blk_ring, c->cands_d};
+                  c->blk_ring, c->cands_d, c->tsp_j, c->tsp_x};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     for (auto& b : c->bk) {
@@ -245,6 +247,8 @@ void free_all(sp_ctx* c)
     c->qprev = nullptr;
     c->vlist = nullptr;
     c->vcount = nullptr;
+    c->tsp_j = nullptr;
+    c->tsp_x = nullptr;
     c->vdisp = nullptr;
     c->empty_d = nullptr;
     c->nempty = 0;
@@ -289,6 +293,8 @@ StepArgs make_args(const sp_ctx* c, double dt)
     a.phase = c->phase;
     a.vlist = c->vlist;
     a.vcount = c->vcount;
+    a.tsp_j = c->tsp_j;
+    a.tsp_x = c->tsp_x;
     a.vdisp = c->vdisp;
     a.skin = c->skin;
     a.err = c->err_d;
@@ -389,7 +395,14 @@ sp_status check_device_err(sp_ctx* c)
 template <int SCHED, int W, bool PERSIST>
 sp_status launch_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds)
 {
-    if (a.cap <= 64 * W)   // one floe per lane
+    if (a.flags & SP_TANGENTIAL_SPRING) {   // one workgroup per cell group (launch_bucket's grid)
+        if (a.cap <= 64 * W)
+            hipLaunchKernelGGL((dem_step_kernel<SCHED, W, false, true, true>), dim3(grid), dim3(threads), lds,
+                               c->stream, a);
+        else
+            hipLaunchKernelGGL((dem_step_kernel<SCHED, W, false, false, true>), dim3(grid), dim3(threads), lds,
+                               c->stream, a);
+    } else if (a.cap <= 64 * W)   // one floe per lane
         hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST, true>), dim3(grid), dim3(threads), lds, c->stream, a);
     else
         hipLaunchKernelGGL((dem_step_kernel<SCHED, W, PERSIST, false>), dim3(grid), dim3(threads), lds, c->stream, a);
@@ -511,8 +524,10 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     }
     const int gpb = bucket_gpb(c, b);
     const int groups = (int)((b.cells_h.size() + gpb - 1) / gpb);
-    const int grid = b.persist ? std::min(groups, b.resident) : groups;
-    return launch_sel(c, c->sched, b.waves, b.persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
+    // the tangential spring's kernels take one workgroup per cell group
+    const bool persist = b.persist && !(c->p.flags & SP_TANGENTIAL_SPRING);
+    const int grid = persist ? std::min(groups, b.resident) : groups;
+    return launch_sel(c, c->sched, b.waves, persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
 // Wavefronts per cell of a bucket's blocked launches: the bucket's own W when
@@ -580,7 +595,7 @@ sp_status flush_lf(sp_ctx* c)
 // and no hybrid (the coupled cadence and the hybrid block on their own terms).
 bool block_eligible(const sp_ctx* c)
 {
-    return c->block_k > 1 && c->N0 == 1 && !c->hyb;
+    return c->block_k > 1 && c->N0 == 1 && !c->hyb && !(c->p.flags & SP_TANGENTIAL_SPRING);
 }
 
 // Make the library stream wait for the continuum updates of the last block
@@ -1002,6 +1017,12 @@ static sp_status set_floes_common(sp_ctx* c, int64_t n, const int32_t* counts, c
     SP_TRY(dalloc(c, &c->cell_start, (size_t)c->ncells + 1));
     SP_TRY(dalloc(c, &c->vlist, std::max<size_t>(1, N) * kListCap));
     SP_TRY(dalloc(c, &c->vcount, std::max<size_t>(1, N)));
+    if (c->p.flags & SP_TANGENTIAL_SPRING) {   // no contacts remembered yet
+        SP_TRY(dalloc(c, &c->tsp_j, std::max<size_t>(1, N)));
+        SP_TRY(dalloc(c, &c->tsp_x, std::max<size_t>(1, N) * SP_SPRING_CAP));
+        HIP_TRY(c, hipMemsetAsync(c->tsp_j, 0xff, std::max<size_t>(1, N) * sizeof(uint4), c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->tsp_x, 0, std::max<size_t>(1, N) * SP_SPRING_CAP * 8, c->stream));
+    }
     SP_TRY(dalloc(c, &c->vdisp, (size_t)c->ncells));
     void* dst[8] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h};
     if (n > 0) {
@@ -1382,6 +1403,7 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     if (!c) return SP_EINVAL;
     if (!c->have_floes) return fail(c, SP_ESTATE, "sp_autotune before sp_set_floes");
     if (!(dt > 0.0) || reps < 1) return fail(c, SP_EINVAL, "dt must be positive and reps >= 1");
+    if (c->p.flags & SP_TANGENTIAL_SPRING) return fail(c, SP_ESTATE, "the autotuner does not run the tangential spring");
     SP_TRY(upload_phase(c));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
