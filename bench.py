@@ -125,6 +125,8 @@ def main():
                     help="skip the error study of Sec. 4.1-4.3 against the global DEM")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the plain64 run under the two-way coupling (N0 = 100, n_t = 10)")
+    ap.add_argument("--no-spring", action="store_true",
+                    help="skip the plain64 run with the tangential spring (per-contact history)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--closure-probe", action="store_true",
@@ -229,6 +231,8 @@ def main():
         out["uneven"] = uneven_leg(stream)
     if not args.no_coupled:
         out["coupled"] = coupled_leg(stream)
+    if not args.no_spring:
+        out["spring"] = spring_leg(stream)
     if not args.no_scenarios:
         out["scenarios"] = scenario_leg(stream)
     if not args.no_hybrid:
@@ -295,6 +299,33 @@ def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):
     return {"workload": "plain64", "N0": N0, "N1": N1, "n_t": n_t, "steps": steps, "ms_per_step": ms,
             "floe_steps_per_s": w.nfloes / (ms * 1e-3), "nudge_passes": cp["nudges"],
             "clamped_cell_updates": cp["clamped"], "invalid_cell_updates": cp["invalid"], "max_cfl": cfl}
+
+
+def spring_leg(stream, steps=200, warmup=20, G_shear=80.0):
+    """plain64 with the tangential force as the incremental spring
+    (SP_TANGENTIAL_SPRING, G read as a shear modulus of 80 N/m^2): one DEM launch
+    per step reading and rewriting every floe's contact history, timed with HIP
+    events over `steps` steps after `warmup`; dem_ms from the library's own
+    events around the DEM launches."""
+    import torch
+    import fixtures
+    import paper_2303_07819_amd as sp
+    w = fixtures.make_config("plain64")
+    w.G = G_shear
+    with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, stream=stream.cuda_stream) as sim:
+        sim.step(w.dt, warmup)
+        sim.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(w.dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        dem_ms, _ = sim.profile_steps(w.dt, 32)
+        contacts = sim.stats()["contacts"]
+    return {"workload": "plain64", "G_shear": G_shear, "steps": steps, "ms_per_step": ms,
+            "dem_kernel_ms_per_step": dem_ms, "floe_steps_per_s": w.nfloes / (ms * 1e-3),
+            "contacts_total": contacts}
 
 
 def scenario_leg(stream, ks=(1, 2, 3)):

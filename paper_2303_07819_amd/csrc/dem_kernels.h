@@ -824,10 +824,12 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             double hx[SP_SPRING_CAP];
             uint16_t* const tj = TSP ? reinterpret_cast<uint16_t*>(a.tsp_j + s + l) : nullptr;
             double* const tx = TSP ? a.tsp_x + (size_t)(s + l) * SP_SPRING_CAP : nullptr;
+            bool had = false;   // the floe was in contact after the previous step
             if (TSP) {
                 hj = a.tsp_j[s + l];
+                had = (hj.x & hj.y & hj.z & hj.w) != 0xffffffffu;
 #pragma unroll
-                for (int q = 0; q < SP_SPRING_CAP; ++q) hx[q] = tx[q];
+                for (int q = 0; q < SP_SPRING_CAP; ++q) hx[q] = had ? tx[q] : 0.0;
             }
             int nh = 0;
             while (cmask) {
@@ -860,7 +862,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
                 add_terms(Fx, Fy, T, cx, cy, ct);
                 ncontact += (l < j) ? 1ull : 0ull;
             }
-            if (TSP)
+            if (TSP && (had || nh > 0))   // a floe out of contact before and now keeps its empty table
                 for (int e = nh; e < SP_SPRING_CAP; ++e) {
                     tj[e] = 0xffffu;
                     tx[e] = 0.0;
