@@ -531,9 +531,13 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
 }
 
 // Wavefronts per cell of a bucket's blocked launches: the bucket's own W when
-// its cells have at most 64 W floes, else 16 (one floe per lane up to the
-// 1024-floe cell limit).
-int block_waves(const Bucket& b) { return b.cap <= 64 * b.waves ? b.waves : 16; }
+// its cells have at most 64 W floes, else the smallest of 8 and 16 that holds
+// one floe per lane (up to the 1024-floe cell limit).
+int block_waves(const Bucket& b)
+{
+    if (b.cap <= 64 * b.waves) return b.waves;
+    return b.cap <= 512 ? 8 : 16;
+}
 
 // K steps from level kstep as one blocked launch per bucket (of bk, default the
 // context's buckets), the statistics of step t into mom + t * (ncells x
