@@ -253,8 +253,8 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * (the cell DEMs never read the continuum at this cadence), each step's
  * statistics going to a k-slot ring, followed by the k continuum updates;
  * steps left over run one by one.  Blocked launches hold one floe per lane: a
- * bucket whose cells exceed 64 W floes runs them with W = 16 (up to
- * SP_MAX_CELL_FLOES).  Applies to sp_step with N0 = 1 (the coupled cadence
+ * bucket whose cells exceed 64 W floes runs them with W = 8 (up to 512 floes)
+ * or 16 (up to SP_MAX_CELL_FLOES).  Applies to sp_step with N0 = 1 (the coupled cadence
  * blocks its stretches between
  * coarse-to-fine updates, the hybrid its DEM cells between checks: see
  * sp_set_coupling and sp_step_hybrid).  The floe state is the same
