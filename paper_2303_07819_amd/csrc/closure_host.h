@@ -189,7 +189,11 @@ __device__ __forceinline__ void base_cell(int C, const double* Q, const ClosureA
 
 // Base-updated state of every cell: Qb [4][nc].
 // The reduced DEM statistics of every cell at a.t (a.rs must be null).
-__global__ void reduced_stats_kernel(ClosureArgs a, double* rs)
+// Every cell's reduced statistics into rs; with row and mom, a closure cell
+// (row[C] >= 0) also writes its coefficient <v> into its statistics row of mom,
+// which its DEM neighbours' continuum stencils read.
+__global__ void reduced_stats_kernel(ClosureArgs a, double* rs, const int32_t* row = nullptr,
+                                     double* mom = nullptr)
 {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     if (C >= a.nx * a.ny) return;
@@ -197,6 +201,10 @@ __global__ void reduced_stats_kernel(ClosureArgs a, double* rs)
     reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, o);
 #pragma unroll
     for (int k = 0; k < 5; ++k) rs[(size_t)C * 5 + k] = o[k];
+    if (mom && row[C] >= 0) {
+        mom[(size_t)C * kMomStride + M_UBAR] = o[0];
+        mom[(size_t)C * kMomStride + M_VBAR] = o[1];
+    }
 }
 
 __global__ void base_kernel(const double* Q, double* Qb, ClosureArgs a, double dT)
@@ -231,19 +239,6 @@ __global__ void reduced_init_kernel(const int32_t* cells, int ncl, const int32_t
     q[1] = o.v - V;
     q[2] = 0.5 * o.zeta - Om;
     q[3] = a.t;
-}
-
-// Coefficient <v> of the listed (closure) cells' reduced DEM at time t, into
-// the statistics rows their neighbours' update reads.
-__global__ void reduced_coeff_kernel(const int32_t* cells, int ncl, ClosureArgs a, double* mom)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const int c = cells[i];
-    double st[5];
-    cell_rstats(c, a, st);
-    mom[(size_t)c * kMomStride + M_UBAR] = st[0];
-    mom[(size_t)c * kMomStride + M_VBAR] = st[1];
 }
 
 // The 45 closure inputs of cell C into o: the continuum state Q (rho, P_x, P_y,

@@ -588,8 +588,9 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
                 // base-updated level-k state, the network's residual for its
                 // features, the closure cells' coefficients from their reduced DEMs
                 ClosureArgs ca = closure_args(c, c->t_now);
+                // (the closure cells' <v> go into this step's statistics row as well)
                 hipLaunchKernelGGL(reduced_stats_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, ca,
-                                   h->rs);
+                                   h->rs, h->row_d, mom);
                 HIP_TRY(c, hipGetLastError());
                 ca.rs = h->rs;   // every cell's reduced statistics once, read by the stencils below
                 hipLaunchKernelGGL(base_kernel, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->Q[k & 1],
@@ -599,9 +600,6 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
                                    nclos, h->Qs, ca, c->desc, h->X);
                 HIP_TRY(c, hipGetLastError());
                 SP_TRY(net_forward_on(c, h->net, h->X, nclos, h->T));
-                hipLaunchKernelGGL(reduced_coeff_kernel, dim3((nclos + 255) / 256), dim3(256), 0, c->stream,
-                                   h->clos_d, nclos, ca, mom);
-                HIP_TRY(c, hipGetLastError());
             }
             // DEM step of the other cells (statistics of level k), and of the
             // check pool's closure cells (statistics into scratch: the closure
