@@ -9,7 +9,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import rel_err
-import closure_ref as cref
+from oracle import closure as cref
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
