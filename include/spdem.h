@@ -106,9 +106,12 @@ typedef struct {
     int32_t schedule;         /* SP_SCHED_* */
 } sp_params;
 
-/* Create a context on the current HIP device.  `stream` is a hipStream_t the
- * caller owns (e.g. torch.cuda.current_stream().cuda_stream) or NULL, in which
- * case the context creates its own default-priority stream.
+/* Create a context on the current HIP device: the coarse grid of one DEM per
+ * cell and the constants of the floe system (Algorithm 1, initialisation of
+ * the time-marching parameters; Sec. 2.1 constants; Sec. 3.1 one periodic DEM
+ * per coarse cell).  `stream` is a hipStream_t the caller owns (e.g.
+ * torch.cuda.current_stream().cuda_stream) or NULL, in which case the context
+ * creates its own default-priority stream.
  * Errors: SP_EINVAL (null out, nx/ny < 1, non-positive sizes or constants),
  * SP_EDEVICE. */
 sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out);
@@ -125,7 +128,10 @@ const char* sp_last_error(const sp_ctx* ctx);
 sp_status sp_set_ocean(sp_ctx* ctx, double u0, double v0, int32_t nmodes, const double* kx,
                        const double* ky, const double* au, const double* av, const double* phase);
 
-/* Floe state from host arrays (copied).  counts[ncells] floes per cell,
+/* Floe state from host arrays (copied): Algorithm 1's initialisation of the N
+ * floes, each with the position, velocity, spin, angle, radius and thickness
+ * of Sec. 2.1, assigned to the coarse cell that holds it (Sec. 3.1).
+ * counts[ncells] floes per cell,
  * sum(counts) = n; per-floe arrays of length n sorted by cell.  omega and theta
  * may be NULL (zero).  Resets the continuum to the statistics of this state.
  * Errors: SP_EINVAL (sizes, r <= 0, h <= 0, r_max >= min(cell_lx, cell_ly)/4),
@@ -187,15 +193,44 @@ sp_status sp_set_coupling(sp_ctx* ctx, int32_t N0, int32_t N1, int32_t n_t);
 sp_status sp_get_coupling(sp_ctx* ctx, int32_t* N0, int32_t* N1, int32_t* n_t, int64_t* nudges,
                           int64_t* replans, int64_t* clamped, int64_t* invalid);
 
+/* Save and restore a simulation (Algorithm 1 ends by saving the data of the
+ * run).  sp_save writes to the file at `path` everything a later sp_step reads:
+ * the floe state (all eight per-floe arrays, counts per cell), the continuum
+ * state of the current level, the step counters, the candidate lists and
+ * their displacement bounds, the contact and candidate counters, the largest
+ * CFL number, the ocean, every cell's reduced DEM and, with
+ * SP_TANGENTIAL_SPRING, the contact history; a continuum update still
+ * pending from the last step is saved as pending, with its operands.  It
+ * waits for the stream and does not change the simulation.  sp_load reads such a file into a
+ * context created with the same sp_params (grid, constants, flags, schedule):
+ * it sets the ocean and the floes as sp_set_ocean and sp_set_floes do (which
+ * removes a hybrid and restarts the coupling cadence), then restores the rest,
+ * so that the steps that follow give the same floe state and continuum bit for
+ * bit as the saved context would have.  The loading context keeps its own
+ * batching, step block and cadence settings.  Host byte order; the file is
+ * not portable across library versions.  Both synchronise.
+ * Errors: SP_EINVAL (null path, unreadable, truncated or foreign file, other
+ * parameters), SP_ESTATE (sp_save before sp_set_floes, with an active hybrid,
+ * or with N0 > 1), SP_EDEVICE (a write failed), the errors of sp_set_floes,
+ * and a latched device fault (sp_save). */
+sp_status sp_save(sp_ctx* ctx, const char* path);
+sp_status sp_load(sp_ctx* ctx, const char* path);
+/* Number of floes of the current state and of cells (either may be NULL). */
+sp_status sp_get_size(sp_ctx* ctx, int64_t* nfloes, int32_t* ncells);
+
 /* Block until the stream is idle; returns the first latched device fault. */
 sp_status sp_synchronize(sp_ctx* ctx);
 
-/* Copy moments to a caller-owned host array: [ncells][SP_NMOM] for
+/* The cell averages the coarse model consumes (eq. meang and Sec. 2.3 for the
+ * DEM statistics; Sec. 3.2 for the coarse state rho, rho v, P_w).
+ * Copy moments to a caller-owned host array: [ncells][SP_NMOM] for
  * SP_MOMENTS_DEM (statistics of the current state, drag at the current
  * state) or [ncells][4] for SP_MOMENTS_CONTINUUM.  Synchronises. */
 sp_status sp_read_moments(sp_ctx* ctx, int32_t which, double* out);
 
-/* Copy the floe state to caller-owned host arrays of length n (any may be NULL).
+/* The fine-scale state of Sec. 2.1 (positions, velocities, spins, angles,
+ * radii of every floe, in the cell-sorted order of sp_set_floes).
+ * Copy the floe state to caller-owned host arrays of length n (any may be NULL).
  * Synchronises. */
 sp_status sp_read_floes(sp_ctx* ctx, uint32_t* xi, uint32_t* yi, float* u, float* v,
                         float* omega, float* theta, float* r);
@@ -252,7 +287,8 @@ sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
  * which every cell keeps its floes and candidate lists in LDS for the k steps
  * (the cell DEMs never read the continuum at this cadence), each step's
  * statistics going to a k-slot ring, followed by the k continuum updates;
- * steps left over run one by one.  Blocked launches hold one floe per lane: a
+ * a call's remaining steps (fewer than k) run as one block of their own
+ * length, so every step of sp_step is blocked and none captures a graph.  Blocked launches hold one floe per lane: a
  * bucket whose cells exceed 64 W floes runs them with W = 8 (up to 512 floes)
  * or 16 (up to SP_MAX_CELL_FLOES).  Applies to sp_step with N0 = 1 (the coupled cadence
  * blocks its stretches between

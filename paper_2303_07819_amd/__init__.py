@@ -43,7 +43,7 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
-            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work"]
+            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -103,6 +103,9 @@ def load_library(path: str = LIB_PATH):
     lib.sp_get_step_block.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.sp_get_work.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.sp_set_coupling.argtypes = [P, I32, I32, I32]
+    lib.sp_save.argtypes = [P, ctypes.c_char_p]
+    lib.sp_load.argtypes = [P, ctypes.c_char_p]
+    lib.sp_get_size.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32)]
     PI32, PI64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
     lib.sp_get_coupling.argtypes = [P, PI32, PI32, PI32, PI64, PI64, PI64, PI64]
     F = ctypes.POINTER(ctypes.c_float)
@@ -231,6 +234,17 @@ class Sim:
 
     def step(self, dt: float, nsteps: int = 1):
         self._check(self._lib.sp_step(self._h, float(dt), int(nsteps)))
+
+    def save(self, path: str):
+        """Write the simulation to a file (sp_save)."""
+        self._check(self._lib.sp_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Restore a simulation saved by save() with the same parameters (sp_load)."""
+        self._check(self._lib.sp_load(self._h, os.fsencode(path)))
+        n = ctypes.c_int64()
+        self._check(self._lib.sp_get_size(self._h, ctypes.byref(n), None))
+        self.n = int(n.value)
 
     def synchronize(self):
         self._check(self._lib.sp_synchronize(self._h))
