@@ -94,7 +94,7 @@ struct sp_ctx {
     uint32_t *xi = nullptr, *yi = nullptr;
     float *u = nullptr, *v = nullptr, *w = nullptr, *th = nullptr, *r = nullptr, *h = nullptr;
     int32_t* cell_start = nullptr;
-    float2* phase = nullptr;
+    double2* phase = nullptr;
     double* momb[2] = {nullptr, nullptr};   // statistics of time level k in momb[k & 1]
     double* mom2 = nullptr;                 // statistics of the current state (read_moments)
     double* Q[2] = {nullptr, nullptr};      // continuum of time level k in Q[k & 1]
@@ -323,14 +323,14 @@ StepArgs make_args(const sp_ctx* c, double dt)
     a.mud = c->p.mu;
     a.rho_ice_d = c->p.rho_ice;
     a.cdrho = c->p.cd * c->p.rho_ocean;
-    a.u0 = (float)c->u0;
-    a.v0 = (float)c->v0;
+    a.u0 = c->u0;
+    a.v0 = c->v0;
     for (int m = 0; m < c->nmodes; ++m) {
         a.modes.kxL[m] = (float)(c->kx[m] * c->p.cell_lx);
         a.modes.kyL[m] = (float)(c->ky[m] * c->p.cell_ly);
-        a.modes.au[m] = (float)c->au[m];
-        a.modes.av[m] = (float)c->av[m];
-        a.modes.cz[m] = (float)(c->av[m] * c->kx[m] - c->au[m] * c->ky[m]);
+        a.modes.au[m] = c->au[m];
+        a.modes.av[m] = c->av[m];
+        a.modes.cz[m] = c->av[m] * c->kx[m] - c->au[m] * c->ky[m];
     }
     // phase offsets within a cell stay inside [-1.6, 1.6]: sin and cos
     // straight from their polynomials (no range reduction)
@@ -345,17 +345,17 @@ sp_status upload_phase(sp_ctx* c)
 {
     if (!c->phase_dirty || c->ncells == 0) return SP_OK;
     const int nm = c->nmodes > 0 ? c->nmodes : 1;
-    std::vector<float2> tab((size_t)c->ncells * nm, make_float2(0.0f, 1.0f));
+    std::vector<double2> tab((size_t)c->ncells * nm, make_double2(0.0, 1.0));
     for (int cell = 0; cell < c->ncells; ++cell) {
         const double Xc = ((double)(cell % c->p.nx) + 0.5) * c->p.cell_lx;
         const double Yc = ((double)(cell / c->p.nx) + 0.5) * c->p.cell_ly;
         for (int m = 0; m < c->nmodes; ++m) {
             const double t = c->kx[m] * Xc + c->ky[m] * Yc + c->ph[m];
-            tab[(size_t)cell * nm + m] = make_float2((float)sin(t), (float)cos(t));
+            tab[(size_t)cell * nm + m] = make_double2(sin(t), cos(t));
         }
     }
     SP_TRY(dalloc(c, &c->phase, tab.size()));
-    HIP_TRY(c, hipMemcpyAsync(c->phase, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice,
+    HIP_TRY(c, hipMemcpyAsync(c->phase, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice,
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->phase_dirty = false;
@@ -637,20 +637,22 @@ sp_status block_prepare(sp_ctx* c)
     return SP_OK;
 }
 
-// One blocked launch per bucket: K steps of the plain path from level kstep,
-// statistics of step t into slot t of one half of the ring; then the K
-// continuum updates on the update stream, which overlap the next block's DEM
-// launch (that launch writes the other half; a half is written again only
-// after its updates are done).
-sp_status block_chunk(sp_ctx* c, const StepArgs& base, bool time_dem = false, hipEvent_t e0 = nullptr,
+// One blocked launch per bucket: K steps (1 <= K <= block_k) of the plain
+// path from level kstep, statistics of step t into slot t of one half of the
+// ring; then the K continuum updates on the update stream, which overlap the
+// next block's DEM launch (that launch writes the other half; a half is
+// written again only after its updates are done).  A run shorter than a block
+// is one launch of its own length, so every plain step of an eligible context
+// is blocked.
+sp_status block_chunk(sp_ctx* c, const StepArgs& base, int K, bool time_dem = false, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr)
 {
-    const int K = c->block_k;
     const size_t slot = (size_t)c->ncells * kMomStride;
     SP_TRY(block_prepare(c));
+    if (K < 1 || K > c->blk_ring_slots) return fail(c, SP_EINVAL, "block of %d steps outside [1, %d]", K, c->blk_ring_slots);
     SP_TRY(flush_lf(c));
     const int r = c->blk_parity;
-    double* const ring = c->blk_ring + (size_t)r * K * slot;
+    double* const ring = c->blk_ring + (size_t)r * c->blk_ring_slots * slot;
     if (c->lf_used[r]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lf_done[r], 0));
     if (time_dem) HIP_TRY(c, hipEventRecord(e0, c->stream));
     BlockNudge none;
@@ -1114,11 +1116,15 @@ sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
     if (c->N0 > 1) return coupled_steps(c, base, nsteps);
     int64_t left = nsteps;
     if (block_eligible(c)) {
-        while (left >= c->block_k) {
-            SP_TRY(block_chunk(c, base));
-            left -= c->block_k;
+        // whole blocks, then the remainder as one shorter block: no step of
+        // this path runs the per-step kernel or captures a graph
+        while (left > 0) {
+            const int K = (int)std::min<int64_t>(left, c->block_k);
+            SP_TRY(block_chunk(c, base, K));
+            left -= K;
         }
         SP_TRY(join_block_lf(c));   // later work on the stream sees the continuum
+        return SP_OK;
     }
     while (left > 0) {
         const bool steady = (c->kstep % 2 == 0) && (c->lf_pending == cont);
@@ -1158,7 +1164,7 @@ sp_status sp_profile_steps(sp_ctx* c, double dt, int64_t nsteps, double* dem_ms,
         c->t_now += dt * (double)(chunks * c->block_k);
         sp_status st = SP_OK;
         HIP_TRY(c, hipEventRecord(ev[2 * chunks], c->stream));
-        for (int64_t q = 0; q < chunks && !st; ++q) st = block_chunk(c, base, true, ev[2 * q], ev[2 * q + 1]);
+        for (int64_t q = 0; q < chunks && !st; ++q) st = block_chunk(c, base, c->block_k, true, ev[2 * q], ev[2 * q + 1]);
         if (!st) st = join_block_lf(c);
         HIP_TRY(c, hipEventRecord(ev[2 * chunks + 1], c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1510,3 +1516,4 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
 #include "hybrid_host.h"
 #include "coupling_host.h"
 #include "global_dem.h"
+#include "checkpoint_host.h"
