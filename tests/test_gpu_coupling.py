@@ -2,9 +2,12 @@
 oracle's run_coupled on identical seeded inputs (needs an MI355X).
 
 Bars as in test_gpu_parity: per-cell DEM statistics and continuum state
-within 1e-5 relative (field-rms floor), or within five times the storage floor
-of the case where that is larger (contact-dominated workloads, coarse-to-fine
-updates every fine step: tests/storage.py); radii after
+within 1e-5 relative, against floors of 1e-3 of each component's rms raised
+only where the storage of the state in the GPU's formats alone (the oracle's
+schedule rerun with its state rounded after every step and update,
+tests/storage.py) would use a fifth of the allowance: coarse-to-fine updates
+set a cell's momentum to a target close to its current value, so the FP32
+rounding of the shifted velocities is amplified in the next window; radii after
 re-synchronisation within FP32 rounding of the oracle's; no clamped or
 invalid cell updates where the oracle has none (it never clamps; the HIP
 path clamps only radii past a quarter of the cell).
@@ -14,14 +17,12 @@ import pytest
 
 import fixtures
 import oracle
-from metrics import FLOOR, rel_err
-from storage import coupled_floor
+from metrics import FLOOR, TOL, rel_err, storage_floors
+from storage import fp32_storage_bound, run_coupled_stored
 from workloads import lattice_workload, ragged_workload
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
-TOL_CONTACT = 5e-5
 
 sp = pytest.importorskip("paper_2303_07819_amd")
 
@@ -33,7 +34,8 @@ def _say(*a):
 def compare(w, nsteps, N0, N1, n_t, flags=0, oflags=0, tol=TOL):
     _say(f"coupled {w.name} ncells={w.ncells} n={w.nfloes} steps={nsteps} N0={N0} N1={N1} n_t={n_t}")
     st, Q, mom, cfl = oracle.run_coupled(w, nsteps, N0, N1, n_t, flags=oflags)
-    tol = max(tol, 5.0 * coupled_floor(w, nsteps, N0, N1, n_t, flags=oflags))
+    Qs, moms = run_coupled_stored(w, nsteps, N0, N1, n_t, flags=oflags)
+    fm, fq = storage_floors(mom, moms), storage_floors(Q, Qs)
     with sp.Sim.from_workload(w, flags=flags) as s:
         s.set_coupling(N0, N1, n_t)
         s.step(w.dt, nsteps)
@@ -42,11 +44,11 @@ def compare(w, nsteps, N0, N1, n_t, flags=0, oflags=0, tol=TOL):
         gf = s.read_floes()
         cp = s.coupling()
         stats = s.stats()
-    e_m = rel_err(gm, mom)
-    e_q = rel_err(gq, Q)
+    e_m = rel_err(gm, mom, fm)
+    e_q = rel_err(gq, Q, fq)
     e_r = np.abs(gf["r"] - st.r) / st.r
     _say(f"  max rel err moments {e_m.max():.2e} continuum {e_q.max():.2e} radii {e_r.max():.2e} "
-         f"(bar {tol:.1e}) {cp}")
+         f"(floors {fm.max():.1e} {fq.max():.1e}) {cp}")
     assert cp["clamped"] == 0 and cp["invalid"] == 0
     assert np.array_equal(gm[:, 0], mom[:, 0])
     assert e_r.max() <= 4e-7 * max(1, cp["nudges"])
@@ -86,7 +88,7 @@ def test_ragged_and_empty_cells_first_coarse_step():
     """Empty, single-floe and 700-floe cells: window statistics and two coarse
     steps; n_t = N0 takes no coarse-to-fine update (they would clamp here, see
     the next test)."""
-    cp = compare(ragged_workload(), 7, 3, 2, 3, tol=TOL_CONTACT)
+    cp = compare(ragged_workload(), 7, 3, 2, 3)
     assert cp["nudges"] == 0
 
 
@@ -102,9 +104,22 @@ def _first_update(w, N0):
         q = s.read_moments(sp.MOMENTS_CONTINUUM)
         s.step(w.dt, 1)
         after = oracle.q_from_moments(m, s.read_moments(sp.MOMENTS_DEM))
-        r = s.read_floes()["r"]
+        f = s.read_floes()
         cp = s.coupling()
-    return x0 + (1.0 / N0) * (q - x0), after, r, cp
+    return x0 + (1.0 / N0) * (q - x0), after, f, cp
+
+
+def _on_target(w, after, target, floes, cells):
+    """|after - target| <= 1e-5 max(|target|, 1e-3 rms) plus what storing the
+    updated floes in FP32 alone can move the cell values (the update computes
+    its shifts in FP64 and rounds the new velocities and spins once)."""
+    rms = np.sqrt(np.mean(target[cells] ** 2, axis=0))
+    allow = TOL * np.maximum(np.abs(target[cells]), FLOOR * rms) + fp32_storage_bound(w, floes)[cells]
+    err = np.abs(after[cells] - target[cells])
+    ratio = np.where(allow > 0, err / np.where(allow > 0, allow, 1.0), np.where(err > 0, np.inf, 0.0))
+    _say(f"  largest error / allowance {ratio.max():.2f}; relative at the 1e-3 floor "
+         f"{rel_err(after[cells], target[cells]).max():.2e}")
+    return ratio.max()
 
 
 def test_ragged_updates_land_on_targets_after_a_replan():
@@ -112,14 +127,13 @@ def test_ragged_updates_land_on_targets_after_a_replan():
     the coarse step re-plans the contact search for the radii they need, and
     every cell with floes lands on its target."""
     w = ragged_workload()
-    target, after, r, cp = _first_update(w, 3)
+    target, after, f, cp = _first_update(w, 3)
+    r = f["r"]
     has = np.diff(w.start) > 0
     _say(f"  counters {cp}, largest radius {r.max():.1f} (initially {w.r.max():.1f})")
     assert cp["nudges"] == 1 and cp["replans"] == 1 and cp["clamped"] == 0 and cp["invalid"] == 0
     assert r.max() > 1.5 * w.r.max()
-    e = rel_err(after[has], target[has])
-    _say(f"  max rel err {e.max():.2e}")
-    assert e.max() <= TOL
+    assert _on_target(w, after, target, f, has) <= 1.0
 
 
 def test_clamp_only_past_a_quarter_cell():
@@ -133,15 +147,14 @@ def test_clamp_only_past_a_quarter_cell():
     w = lattice_workload(counts, nx, ny, r=2000.0, seed=3, big_radius=0.0)
     w.h[w.start[5]] = 0.02
     r_lim = np.float32(0.25 * w.Lx * (1.0 - 1e-6))
-    target, after, r, cp = _first_update(w, 3)
+    target, after, f, cp = _first_update(w, 3)
+    r = f["r"]
     rmax_cell = np.array([r[w.start[c]:w.start[c + 1]].max() for c in range(w.ncells)])
     clamped = rmax_cell == r_lim
     _say(f"  clamped cells {np.flatnonzero(clamped).tolist()} counters {cp}")
     assert np.flatnonzero(clamped).tolist() == [5] and cp["clamped"] == 1 and cp["invalid"] == 0
     assert after[5, 0] < target[5, 0]
-    e = rel_err(after[~clamped], target[~clamped])
-    _say(f"  other cells max rel err {e.max():.2e}")
-    assert e.max() <= TOL
+    assert _on_target(w, after, target, f, ~clamped) <= 1.0
 
 
 def test_unit_cadence_is_the_plain_step_and_cadence_changes_mid_run():
@@ -200,14 +213,13 @@ def test_full_size_plain64_first_coarse_step_and_nudge():
         s.step(w.dt, n_t)
         after = oracle.q_from_moments(oracle.Model(w), s.read_moments(sp.MOMENTS_DEM))
         gq2 = s.read_moments(sp.MOMENTS_CONTINUUM)
+        floes = s.read_floes()
         cp = s.coupling()
     assert cp["nudges"] == 1 and cp["clamped"] == 0 and cp["invalid"] == 0
     np.testing.assert_array_equal(gq2, gq)
     assert abs(gq[:, 0].sum() - q0[:, 0].sum()) <= 1e-12 * abs(q0[:, 0].sum())
     target = x0 + 0.5 * (gq - x0)
-    e = rel_err(after, target)
-    _say(f"  nudge targets max rel err {e.max():.2e}")
-    assert e.max() <= TOL
+    assert _on_target(w, after, target, floes, np.ones(w.ncells, bool)) <= 1.0
     m = oracle.Model(w)
     k = N1
     for (cx, cy) in ((0, 0), (41, 17), (63, 63)):
