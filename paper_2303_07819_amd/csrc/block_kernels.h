@@ -76,7 +76,7 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     const int gpb = blockDim.x / G;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float4 mode_c[GPB][2 * SP_MAX_MODES];   // per-cell mode constants (mode_consts)
+    __shared__ ModeC mode_c[GPB][SP_MAX_MODES];        // per-cell mode constants (mode_consts)
     __shared__ int wsum[GPB][W];
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
@@ -237,14 +237,14 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
             if (!(a.flags & SP_OCEAN_OFF)) {
                 const float fx = (float)(int)(pl.x - 0x80000000u) * 2.3283064365386963e-10f;
                 const float fy = (float)(int)(pl.y - 0x80000000u) * 2.3283064365386963e-10f;
-                float uo = a.u0, vo = a.v0, zeta = 0.0f;
+                double uo = a.u0, vo = a.v0, zeta = 0.0;
                 ocean_modes(fx, fy, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
-                const double du = (double)uo - uld, dv = (double)vo - vld;
+                const double du = uo - uld, dv = vo - vld;
                 const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
                 fdx = alpha * du * sp;
                 fdy = alpha * dv * sp;
-                const double dW = 0.5 * (double)zeta - wld;
+                const double dW = 0.5 * zeta - wld;
                 const double r2 = rld * rld;
                 const double beta = a.cdrho * kPi * r2 * r2 * rld;
                 tdr = beta * dW * fabs(dW);

@@ -90,15 +90,15 @@ struct CellOcean {
 };
 
 // Ocean current and curl at the centre of cell C (from its phase table).
-__device__ __forceinline__ CellOcean ocean_centre(int C, const float2* phase, int nmodes, const Modes& modes,
-                                                  float u0, float v0)
+__device__ __forceinline__ CellOcean ocean_centre(int C, const double2* phase, int nmodes, const Modes& modes,
+                                                  double u0, double v0)
 {
-    CellOcean o{(double)u0, (double)v0, 0.0};
+    CellOcean o{u0, v0, 0.0};
     for (int m = 0; m < nmodes; ++m) {
-        const float2 sc = phase[(size_t)C * nmodes + m];
-        o.u += (double)modes.au[m] * (double)sc.x;
-        o.v += (double)modes.av[m] * (double)sc.x;
-        o.zeta += (double)modes.cz[m] * (double)sc.y;
+        const double2 sc = phase[(size_t)C * nmodes + m];
+        o.u += modes.au[m] * sc.x;
+        o.v += modes.av[m] * sc.x;
+        o.zeta += modes.cz[m] * sc.y;
     }
     return o;
 }
@@ -119,8 +119,8 @@ __device__ __forceinline__ void reduced_rel(int C, const double* red, const doub
 
 // Statistics of cell C's reduced DEM at time t: coefficient (u, v), sources
 // per unit area (s_x, s_y, s_w).
-__device__ __forceinline__ void reduced_stats(int C, const double* red, const double* mf, const float2* phase,
-                                              int nmodes, const Modes& modes, float u0, float v0, double t,
+__device__ __forceinline__ void reduced_stats(int C, const double* red, const double* mf, const double2* phase,
+                                              int nmodes, const Modes& modes, double u0, double v0, double t,
                                               double out[5])
 {
     const CellOcean o = ocean_centre(C, phase, nmodes, modes, u0, v0);
@@ -138,10 +138,10 @@ __device__ __forceinline__ void reduced_stats(int C, const double* red, const do
 struct ClosureArgs {
     const double* red;
     const double* mf;
-    const float2* phase;
+    const double2* phase;
     int nmodes;
     Modes modes;
-    float u0, v0;
+    double u0, v0;
     int nx, ny;
     double dX, dY;
     double t;       // time of the pre-step state

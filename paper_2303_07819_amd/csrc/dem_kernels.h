@@ -60,9 +60,9 @@ enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE,
 struct Modes {
     float kxL[SP_MAX_MODES];  // kx * Lx: phase per cell fraction
     float kyL[SP_MAX_MODES];
-    float au[SP_MAX_MODES];
-    float av[SP_MAX_MODES];
-    float cz[SP_MAX_MODES];   // curl coefficient av kx - au ky
+    double au[SP_MAX_MODES];
+    double av[SP_MAX_MODES];
+    double cz[SP_MAX_MODES];  // curl coefficient av kx - au ky
     int direct;               // every phase offset |kxL fx + kyL fy| (|fx|, |fy| <= 1/2) is <= 1.6
 };
 
@@ -77,7 +77,7 @@ struct StepArgs {
     const float* r;
     const float* h;
     const int32_t* cell_start;
-    const float2* phase;       // [ncells][nmodes]: (sin, cos) of the phase at the cell centre
+    const double2* phase;      // [ncells][nmodes]: (sin, cos) of the phase at the cell centre
     double* mom;               // statistics written by this step [ncells][kMomStride]
     double* mom_alt;           // where the statistics of work entries with w = 1 go instead
     uint32_t* err;
@@ -120,7 +120,7 @@ struct StepArgs {
     double Ed, Gd, mud;
     double cdrho;              // Cd rho_o
     double rho_ice_d;
-    float u0, v0;
+    double u0, v0;
     Modes modes;
 };
 
@@ -251,44 +251,63 @@ __device__ __forceinline__ void sincos_direct(float x, float& s, float& c)
     c = fmaf(x2, cp, 1.0f);
 }
 
-// Per-cell constants of ocean mode m (2 float4 at mc[2 m]): with a the mode's
-// velocity amplitudes (au, av), cz its curl coefficient and theta_c its phase
-// at the cell centre (S = sin theta_c, C = cos theta_c):
-// (au S, au C, av S, av C) and (cz C, -cz S, kx Lx, ky Ly).
-__device__ __forceinline__ void mode_consts(const Modes& md, int m, float2 sc, float4* mc)
+// Per-cell constants of ocean mode m: with a the mode's velocity amplitudes
+// (au, av), cz its curl coefficient and theta_c its phase at the cell centre
+// (S = sin theta_c, C = cos theta_c): the products au S, au C, av S, av C,
+// cz C, -cz S in FP64, and the mode's phase per cell fraction kx Lx, ky Ly.
+struct ModeC {
+    double aS, aC, bS, bC, zC, zS;
+    float kxL, kyL;
+};
+
+__device__ __forceinline__ void mode_consts(const Modes& md, int m, double2 sc, ModeC* mc)
 {
-    const float au = md.au[m], av = md.av[m], cz = md.cz[m];
-    mc[2 * m] = make_float4(au * sc.x, au * sc.y, av * sc.x, av * sc.y);
-    mc[2 * m + 1] = make_float4(cz * sc.y, -(cz * sc.x), md.kxL[m], md.kyL[m]);
+    const double au = md.au[m], av = md.av[m], cz = md.cz[m];
+    ModeC q;
+    q.aS = au * sc.x;
+    q.aC = au * sc.y;
+    q.bS = av * sc.x;
+    q.bC = av * sc.y;
+    q.zC = cz * sc.y;
+    q.zS = -(cz * sc.x);
+    q.kxL = md.kxL[m];
+    q.kyL = md.kyL[m];
+    mc[m] = q;
 }
 
 // Ocean current (sum of a sin theta) and curl (sum of cz cos theta) at cell
 // fraction (fx, fy), by angle addition around the cell centre: theta = theta_c
 // + d with d = kx Lx fx + ky Ly fy, sin theta = S cos d + C sin d and
 // cos theta = C cos d - S sin d, the amplitudes folded into the constants of
-// mode_consts.  DIRECT: every |d| <= 1.6.
+// mode_consts.  sin d and cos d are FP32 polynomials of the FP32 offset
+// (within 2e-7 of the exact values); the products with the cell constants and
+// the sum over modes are FP64: the drag depends on the current minus the floe
+// velocity, a small difference of nearly equal values, and FP32 constants and
+// sums (relative error about 3e-7 of the current) moved cell drag sums by up
+// to 3e-7 of their scale, ten times what the FP32 storage of the state does.
+// DIRECT: every |d| <= 1.6.
 template <bool DIRECT>
-__device__ __forceinline__ void ocean_modes_t(float fx, float fy, const float4* mc, int nmodes, float& uo,
-                                              float& vo, float& zeta)
+__device__ __forceinline__ void ocean_modes_t(float fx, float fy, const ModeC* mc, int nmodes, double& uo,
+                                              double& vo, double& zeta)
 {
 #pragma unroll 2
     for (int m = 0; m < nmodes; ++m) {
-        const float4 p = mc[2 * m];
-        const float4 q = mc[2 * m + 1];
-        const float d = q.z * fx + q.w * fy;
-        float sd, cd;
+        const ModeC q = mc[m];
+        const float d = q.kxL * fx + q.kyL * fy;
+        float sdf, cdf;
         if (DIRECT)
-            sincos_direct(d, sd, cd);
+            sincos_direct(d, sdf, cdf);
         else
-            sincos_small(d, sd, cd);
-        uo = fmaf(p.y, sd, fmaf(p.x, cd, uo));
-        vo = fmaf(p.w, sd, fmaf(p.z, cd, vo));
-        zeta = fmaf(q.y, sd, fmaf(q.x, cd, zeta));
+            sincos_small(d, sdf, cdf);
+        const double sd = sdf, cd = cdf;
+        uo = fma(q.aC, sd, fma(q.aS, cd, uo));
+        vo = fma(q.bC, sd, fma(q.bS, cd, vo));
+        zeta = fma(q.zS, sd, fma(q.zC, cd, zeta));
     }
 }
 
-__device__ __forceinline__ void ocean_modes(float fx, float fy, const float4* mc, int nmodes, bool direct,
-                                            float& uo, float& vo, float& zeta)
+__device__ __forceinline__ void ocean_modes(float fx, float fy, const ModeC* mc, int nmodes, bool direct,
+                                            double& uo, double& vo, double& zeta)
 {
     if (direct)
         ocean_modes_t<true>(fx, fy, mc, nmodes, uo, vo, zeta);
@@ -587,7 +606,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
     const int gpb = blockDim.x / G;            // groups in this launch (LDS may allow fewer)
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float4 mode_c[GPB][2 * SP_MAX_MODES];   // per-cell mode constants (mode_consts)
+    __shared__ ModeC mode_c[GPB][SP_MAX_MODES];        // per-cell mode constants (mode_consts)
     __shared__ int wsum[GPB][W];
     __shared__ float wdisp[BT / 64];
     __shared__ unsigned long long csum[BT / 64];
@@ -758,14 +777,14 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
             if (!(a.flags & SP_OCEAN_OFF)) {
                 const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
                 const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
-                float uo = a.u0, vo = a.v0, zeta = 0.0f;
+                double uo = a.u0, vo = a.v0, zeta = 0.0;
                 ocean_modes(fx, fy, mode_c[g], a.nmodes, a.modes.direct != 0, uo, vo, zeta);
-                const double du = (double)uo - uld, dv = (double)vo - vld;
+                const double du = uo - uld, dv = vo - vld;
                 const double sp = sqrt_nonneg(du * du + dv * dv);
                 const double alpha = a.cdrho * kPi * rld * rld;
                 fdx = alpha * du * sp;
                 fdy = alpha * dv * sp;
-                const double dW = 0.5 * (double)zeta - wld;
+                const double dW = 0.5 * zeta - wld;
                 const double r2 = rld * rld;
                 const double beta = a.cdrho * kPi * r2 * r2 * rld;
                 tdr = beta * dW * fabs(dW);
@@ -964,7 +983,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* cells)
 {
     __shared__ double red11[SP_NMOM][16];
-    __shared__ float4 mode_c[2 * SP_MAX_MODES];
+    __shared__ ModeC mode_c[SP_MAX_MODES];
     const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
     const int s = a.cell_start[c];
@@ -981,14 +1000,14 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
         if (!(a.flags & SP_OCEAN_OFF)) {
             const float fx = (float)(int)(xl - 0x80000000u) * 2.3283064365386963e-10f;
             const float fy = (float)(int)(yl - 0x80000000u) * 2.3283064365386963e-10f;
-            float uo = a.u0, vo = a.v0, zeta = 0.0f;
+            double uo = a.u0, vo = a.v0, zeta = 0.0;
             ocean_modes(fx, fy, mode_c, a.nmodes, a.modes.direct != 0, uo, vo, zeta);
-            const double du = (double)uo - uld, dv = (double)vo - vld;
+            const double du = uo - uld, dv = vo - vld;
             const double sp = sqrt_nonneg(du * du + dv * dv);
             const double alpha = a.cdrho * kPi * rld * rld;
             fdx = alpha * du * sp;
             fdy = alpha * dv * sp;
-            const double dW = 0.5 * (double)zeta - wld;
+            const double dW = 0.5 * zeta - wld;
             const double r2 = rld * rld;
             tdr = a.cdrho * kPi * r2 * r2 * rld * dW * fabs(dW);
         }

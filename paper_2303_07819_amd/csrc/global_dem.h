@@ -50,7 +50,7 @@ struct sp_gdem {
     size_t cstart_cap = 0;
     double* cmom = nullptr;            // coarse statistics (read-out)
     size_t cmom_cap = 0;
-    float2* phase = nullptr;           // (sin, cos) of every mode's phase at each sub-bin centre
+    double2* phase = nullptr;          // (sin, cos) of every mode's phase at each sub-bin centre
     uint32_t* err_d = nullptr;
     unsigned long long* contacts_d = nullptr;
     int64_t steps = 0;
@@ -80,10 +80,11 @@ struct GArgs {
     float* ho;
     int32_t* ido;
     const int32_t* bstart;
-    const float2* phase;
+    const double2* phase;
     int n, nbx, nby, nmodes;
     uint32_t flags;
-    float qx, qy, u0, v0;
+    float qx, qy;
+    double u0, v0;
     double qxd, qyd, inv_qxd, inv_qyd;
     double dtd, Ed, Gd, mud, cdrho, rho_ice_d;
     Modes modes;                       // kxL, kyL per sub-bin side
@@ -147,29 +148,32 @@ __global__ __launch_bounds__(256) void gstart_kernel(const uint32_t* keys, int n
     start[b] = lo;
 }
 
-// Ocean current and curl at a floe from the phase table of its sub-bin.
-__device__ __forceinline__ void gocean(const GArgs& a, uint32_t x, uint32_t y, float& uo, float& vo, float& zeta)
+// Ocean current and curl at a floe from the phase table of its sub-bin: the
+// offset's sin and cos in FP32, the angle addition and the sum over modes in
+// FP64 (as the cell kernels).
+__device__ __forceinline__ void gocean(const GArgs& a, uint32_t x, uint32_t y, double& uo, double& vo, double& zeta)
 {
     uo = a.u0;
     vo = a.v0;
-    zeta = 0.0f;
+    zeta = 0.0;
     if (a.nmodes == 0) return;
     const int b = (int)(gbin_axis(y, a.nby) * (uint32_t)a.nbx + gbin_axis(x, a.nbx));
     const float fx = gbin_offset(x, a.nbx), fy = gbin_offset(y, a.nby);
-    const float2* ph = a.phase + (size_t)b * a.nmodes;
+    const double2* ph = a.phase + (size_t)b * a.nmodes;
     for (int m = 0; m < a.nmodes; ++m) {
         const float d = a.modes.kxL[m] * fx + a.modes.kyL[m] * fy;
-        float sd, cd;
+        float sdf, cdf;
         if (a.modes.direct)
-            sincos_direct(d, sd, cd);
+            sincos_direct(d, sdf, cdf);
         else
-            sincos_small(d, sd, cd);
-        const float2 q = ph[m];
-        const float sn = q.x * cd + q.y * sd;
-        const float cn = q.y * cd - q.x * sd;
-        uo += a.modes.au[m] * sn;
-        vo += a.modes.av[m] * sn;
-        zeta += a.modes.cz[m] * cn;
+            sincos_small(d, sdf, cdf);
+        const double sd = sdf, cd = cdf;
+        const double2 q = ph[m];
+        const double sn = fma(q.x, cd, q.y * sd);
+        const double cn = fma(q.y, cd, -(q.x * sd));
+        uo = fma(a.modes.au[m], sn, uo);
+        vo = fma(a.modes.av[m], sn, vo);
+        zeta = fma(a.modes.cz[m], cn, zeta);
     }
 }
 
@@ -179,14 +183,14 @@ __device__ __forceinline__ void gdrag(const GArgs& a, uint32_t x, uint32_t y, do
 {
     fdx = fdy = tdr = 0.0;
     if (a.flags & SP_OCEAN_OFF) return;
-    float uo, vo, zeta;
+    double uo, vo, zeta;
     gocean(a, x, y, uo, vo, zeta);
-    const double du = (double)uo - uld, dv = (double)vo - vld;
+    const double du = uo - uld, dv = vo - vld;
     const double sp = sqrt(du * du + dv * dv);
     const double alpha = a.cdrho * kPi * rld * rld;
     fdx = alpha * du * sp;
     fdy = alpha * dv * sp;
-    const double dW = 0.5 * (double)zeta - wld;
+    const double dW = 0.5 * zeta - wld;
     const double r2 = rld * rld;
     const double beta = a.cdrho * kPi * r2 * r2 * rld;
     tdr = beta * dW * fabs(dW);
@@ -480,16 +484,16 @@ GArgs gargs(const sp_gdem* g, double dt, int from, int to)
     a.mud = g->p.mu;
     a.cdrho = g->p.cd * g->p.rho_ocean;
     a.rho_ice_d = g->p.rho_ice;
-    a.u0 = (float)g->u0;
-    a.v0 = (float)g->v0;
+    a.u0 = g->u0;
+    a.v0 = g->v0;
     const double bx = g->p.lx / g->nbx, by = g->p.ly / g->nby;
     float reach = 0.0f;
     for (int m = 0; m < g->nmodes; ++m) {
         a.modes.kxL[m] = (float)(g->kx[m] * bx);
         a.modes.kyL[m] = (float)(g->ky[m] * by);
-        a.modes.au[m] = (float)g->au[m];
-        a.modes.av[m] = (float)g->av[m];
-        a.modes.cz[m] = (float)(g->av[m] * g->kx[m] - g->au[m] * g->ky[m]);
+        a.modes.au[m] = g->au[m];
+        a.modes.av[m] = g->av[m];
+        a.modes.cz[m] = g->av[m] * g->kx[m] - g->au[m] * g->ky[m];
         reach = std::max(reach, 0.5f * (fabsf(a.modes.kxL[m]) + fabsf(a.modes.kyL[m])));
     }
     a.modes.direct = reach <= 1.6f ? 1 : 0;
@@ -503,17 +507,17 @@ sp_status gupload_phase(sp_gdem* g)
     if (!g->phase_dirty || !g->have_floes) return SP_OK;
     const int nm = std::max(1, g->nmodes);
     const size_t nb = (size_t)g->nbx * g->nby;
-    std::vector<float2> tab(nb * nm, make_float2(0.0f, 1.0f));
+    std::vector<double2> tab(nb * nm, make_double2(0.0, 1.0));
     for (size_t b = 0; b < nb; ++b) {
         const double Xc = ((double)(b % g->nbx) + 0.5) * g->p.lx / g->nbx;
         const double Yc = ((double)(b / g->nbx) + 0.5) * g->p.ly / g->nby;
         for (int m = 0; m < g->nmodes; ++m) {
             const double t = g->kx[m] * Xc + g->ky[m] * Yc + g->ph[m];
-            tab[b * nm + m] = make_float2((float)sin(t), (float)cos(t));
+            tab[b * nm + m] = make_double2(sin(t), cos(t));
         }
     }
     SP_TRY(galloc(g, &g->phase, tab.size()));
-    GD_TRY(g, hipMemcpyAsync(g->phase, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice, g->stream));
+    GD_TRY(g, hipMemcpyAsync(g->phase, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice, g->stream));
     GD_TRY(g, hipStreamSynchronize(g->stream));
     g->phase_dirty = false;
     return SP_OK;
