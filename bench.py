@@ -32,24 +32,165 @@ MLP_BWD_MACS = MLP_FWD_MACS + 2 * 128 * 128 + 128 * 4
 TRAIN_FLOPS_PER_SAMPLE = 2 * (MLP_FWD_MACS + MLP_BWD_MACS)
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The oracle as it stands, on this host's cores, over whole steps of the workload."""
-    import oracle
+def _cores():
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         cores = min(cores, int(omp))
+    return cores
+
+
+def _sample_cells(w, n, seed=7):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    has = np.flatnonzero(w.counts > 0)
+    return np.sort(rng.choice(has, min(n, has.size), replace=False)).astype(np.int32)
+
+
+def _oracle_cells(w, cells, nsteps, threads, state=None, binned=True):
+    """The oracle on the listed cells for nsteps from `state` (default the
+    workload's): (seconds, floe-steps, moments of the listed cells, contacts,
+    candidate pairs)."""
+    import oracle
+    oracle.set_threads(threads)
+    m = oracle.Model(w, oracle.BINNED if binned else 0)
+    st = (oracle.State.from_workload(w) if state is None else state.copy())
     t0 = time.perf_counter()
-    oracle.run_plain(w, 1)
-    t1 = time.perf_counter()
-    k = max(1, min(50, int(budget_s / max(t1 - t0, 1e-3))))
-    t2 = time.perf_counter()
-    oracle.run_plain(w, k)
-    t3 = time.perf_counter()
-    return {"value": w.nfloes * k / (t3 - t2), "unit": "floe-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{w.name}: all {w.ncells} cells, {w.nfloes} floes, {k} steps from t=0 "
-                      f"(brute-force contacts, FP64, OpenMP over cells)"}
+    _, stats = oracle.dem_steps(m, st, w.dt, nsteps, cells=cells)
+    sec = time.perf_counter() - t0
+    nfl = int(sum(int(w.counts[c]) for c in cells))
+    return sec, nfl * nsteps, oracle.moments(m, st)[cells], int(stats[0]), int(stats[1])
+
+
+STAT_NAMES = ["n", "M", "Px", "Py", "L", "Ux", "Uy", "Svx", "Svy", "Sw", "Aice"]
+
+
+def _oracle_cells_stored(w, cells, nsteps, state=None):
+    """The oracle on the listed cells with their floe state rounded after every
+    step to the formats the GPU stores (positions to 2^-32 of the cell,
+    velocities and spin to FP32): what the 32-bit storage alone changes.
+    Returns the moments of the listed cells."""
+    import numpy as np
+    import oracle
+    m = oracle.Model(w, oracle.BINNED)
+    st = (oracle.State.from_workload(w) if state is None else state.copy())
+    idx = np.concatenate([np.arange(w.start[c], w.start[c + 1]) for c in cells])
+    for _ in range(nsteps):
+        oracle.dem_steps(m, st, w.dt, 1, cells=cells)
+        for a in (st.u, st.v, st.w):
+            a[idx] = a[idx].astype(np.float32)
+        for a in (st.xs, st.ys):
+            a[idx] = np.round(a[idx] * 2.0 ** 32) / 2.0 ** 32 % 1.0
+    return oracle.moments(m, st)[cells]
+
+
+def _storage_floors(ref, stored, tol=1e-5, floor=1e-3, margin=5.0):
+    """Per-statistic floor of the relative error: 1e-3 of the statistic's rms,
+    raised where the storage-only deviation D would use more than 1 / margin of
+    the allowance (floor margin D / (tol rms))."""
+    import numpy as np
+    rms = np.sqrt(np.mean(ref * ref, axis=0))
+    dev = np.max(np.abs(stored - ref), axis=0)
+    need = np.where(rms > 0, margin * dev / (tol * np.where(rms > 0, rms, 1.0)), 0.0)
+    return np.maximum(floor, need)
+
+
+def _moment_error(gm, ref, stored):
+    """The GPU's per-cell statistics against the oracle's: the largest relative
+    error at a floor of 1e-3 of each statistic's rms over the compared cells,
+    the same per statistic, at the storage-derived floors (as the parity
+    tests), and the storage-only deviation in units of the rms."""
+    import numpy as np
+    e_rel, e_abs = _rel_err(gm, ref)
+    fl = _storage_floors(ref, stored)
+    rms = np.sqrt(np.mean(ref * ref, axis=0))
+    rmsd = np.where(rms > 0, rms, 1.0)
+    per = {}
+    for k, nm in enumerate(STAT_NAMES):
+        a, _ = _rel_err(gm[:, k:k + 1], ref[:, k:k + 1])
+        b, _ = _rel_err(gm[:, k:k + 1], ref[:, k:k + 1], fl[k])
+        per[nm] = {"rel_err_floor_1e-3": a, "rel_err_storage_floor": b, "storage_floor": float(fl[k]),
+                   "gpu_abs_err_per_rms": float(np.max(np.abs(gm[:, k] - ref[:, k])) / rmsd[k]),
+                   "storage_abs_dev_per_rms": float(np.max(np.abs(stored[:, k] - ref[:, k])) / rmsd[k])}
+    return {"max_rel_err": e_rel, "floor": 1e-3, "max_abs_err_per_rms": e_abs,
+            "max_rel_err_storage_floors": max(v["rel_err_storage_floor"] for v in per.values()),
+            "per_statistic": per}
+
+
+def _rel_err(a, b, floor=1e-3):
+    """Largest per-cell relative error with a floor of `floor` times the
+    component's rms over the compared cells, and the largest absolute error in
+    units of that rms."""
+    import numpy as np
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    rms = np.sqrt(np.mean(b * b, axis=0, keepdims=True))
+    den = np.maximum(np.abs(b), floor * rms)
+    den = np.where(den > 0, den, 1.0)
+    rmsd = np.where(rms > 0, rms, 1.0)
+    return float(np.max(np.abs(a - b) / den)), float(np.max(np.abs(a - b) / rmsd))
+
+
+def cpu_baseline(w, gm_after, nsteps, budget_s=10.0, dense=None, extra=None):
+    """The FP64 oracle as it stands, timed on this host's cores on bounded
+    samples of the workloads (cells are independent DEMs, so a sample of cells
+    is a smaller instance of the same work), binned contact search (its
+    sub-bin mode), OpenMP over cells.
+
+    value: plain64 from t = 0 over the same steps the GPU took before the
+    moments were read, on a sample of cells sized to about `budget_s` seconds
+    on all cores; the same oracle run gives the GPU's moment error on those
+    cells.  Also: one core, the brute-force search, the dense phase (from the
+    GPU state after 5000 steps), the 4 x 4 small workload in full, samples of
+    uneven128 and hybrid512."""
+    import numpy as np
+    import oracle
+    cores = _cores()
+    allc = oracle.set_threads(cores)
+    # calibrate: one step of 64 sampled cells
+    probe = _sample_cells(w, 64, seed=11)
+    sec, fs, _, _, _ = _oracle_cells(w, probe, 1, cores)
+    rate = fs / max(sec, 1e-4)
+    ncell = int(max(16, min(w.ncells, budget_s * rate / (nsteps * float(w.counts.mean())))))
+    cells = _sample_cells(w, ncell)
+    sec, fs, ref, contacts, cands = _oracle_cells(w, cells, nsteps, cores)
+    mcells = cells[: min(cells.size, 512)]
+    me = _moment_error(gm_after[mcells], ref[: mcells.size], _oracle_cells_stored(w, mcells, nsteps))
+    out = {"value": fs / sec, "unit": "floe-steps/s", "cores": allc, "kind": "oracle",
+           "sample": f"{w.name}: {cells.size} of {w.ncells} cells ({fs // nsteps} floes), {nsteps} steps from t=0, "
+                     f"binned contact search, FP64, OpenMP over cells on {allc} threads",
+           "seconds": sec}
+    moment_error = {"workload": w.name, "cells": int(mcells.size), "steps": nsteps,
+                    "reference": "FP64 oracle on the sampled cells from the same initial state",
+                    "statistics": "n, M, P, L, U, S_v, S_w, A_ice per cell (DEM moments)", **me}
+    # one core, fewer cells
+    c1 = cells[: max(8, cells.size // max(1, allc))]
+    s1, f1, _, _, _ = _oracle_cells(w, c1, nsteps, 1)
+    out["one_core"] = {"value": f1 / s1, "cores": 1, "sample": f"{c1.size} cells, {nsteps} steps"}
+    # the oracle's brute-force search (every pair of a cell), all cores
+    cb = cells[: max(8, cells.size // 8)]
+    kb = max(1, min(nsteps, 5))
+    sb, fb, _, _, _ = _oracle_cells(w, cb, kb, cores, binned=False)
+    out["brute_force"] = {"value": fb / sb, "cores": allc, "sample": f"{cb.size} cells, {kb} steps"}
+    legs = {}
+    if dense is not None:
+        dw, dfl, dsteps, dgm = dense
+        dstate = oracle.State.from_fixed(dfl["xi"], dfl["yi"], dfl["u"], dfl["v"], dfl["omega"], dfl["theta"],
+                                         dfl["r"], dw.h)
+        dc = _sample_cells(dw, max(16, min(dw.ncells, cells.size)), seed=13)
+        ds, dfs, dref, dcont, dcand = _oracle_cells(dw, dc, dsteps, cores, state=dstate)
+        mc = dc[: min(dc.size, 512)]
+        dme = _moment_error(dgm[mc], dref[: mc.size], _oracle_cells_stored(dw, mc, dsteps, state=dstate))
+        legs["plain64_dense"] = {"value": dfs / ds, "cores": allc, "steps": dsteps,
+                                 "sample": f"{dc.size} cells from the GPU state after 5000 steps",
+                                 "contacts_per_floe_step": 2.0 * dcont / max(1, dfs),
+                                 "moment_error": {"cells": int(mc.size), "steps": dsteps, **dme}}
+    for name, ew, k, ncl in (extra or []):
+        ec = _sample_cells(ew, ncl, seed=17)
+        es, efs, _, _, _ = _oracle_cells(ew, ec, k, cores)
+        legs[name] = {"value": efs / es, "cores": allc, "sample": f"{ec.size} of {ew.ncells} cells, {k} steps"}
+    out["legs"] = legs
+    oracle.set_threads(cores)
+    return out, moment_error
 
 
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "dem_block_kernel_plain64.md")
@@ -125,6 +266,10 @@ def main():
                     help="skip the error study of Sec. 4.1-4.3 against the global DEM")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the plain64 run under the two-way coupling (N0 = 100, n_t = 10)")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the plain64 dense-phase run restored from a state saved after 5000 steps")
+    ap.add_argument("--no-inference", action="store_true",
+                    help="skip the closure inference timing on the 256 x 256 grid")
     ap.add_argument("--no-spring", action="store_true",
                     help="skip the plain64 run with the tangential spring (per-contact history)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -171,19 +316,75 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
     value = w.nfloes * args.steps / (ms / 1e3)
+    gm_after = sim.read_moments(sp.MOMENTS_DEM)       # judged against the oracle by the CPU leg
+    work_timed = sim.work()
+    roofline, contacts_per_floe_step = dem_roofline(sim, w, args.profile_steps)
+    sim.close()
 
-    # dominant kernel, timed live with HIP events on its stream (blocked steps:
-    # events around every block's DEM launch); its work counted over the same steps
+    out = {
+        "metric": "floe-steps/sec at 1 GPU (plain DEM vs DEM+closure) at stated moment error",
+        "value": value,
+        "unit": "floe-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state (u32 fixed-point positions), f64 contact geometry and moment sums",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": [w.nx, w.ny], "cell_km": w.Lx / 1e3,
+                   "floes": w.nfloes, "floes_per_cell": float(w.nfloes) / w.ncells, "dt_s": w.dt,
+                   "schedule": ["auto", "allpairs", "binned"][sched[0]], "sub_bins": [sched[1], sched[2]],
+                   "continuum": "lax-friedrichs every step", "step_block": roofline.get("steps_per_launch", 1),
+                   "blocked_steps_timed": work_timed["blocked_steps"]},
+        "roofline": roofline,
+        "moment_error": None,
+        "contacts_per_floe_step": contacts_per_floe_step,
+        "wall_s_timed": wall,
+    }
+    built = {}
+    dense = None
+    if not args.no_dense:
+        out["dense"], dense = dense_leg(stream, w, args.profile_steps)
+    if not args.no_uneven:
+        out["uneven"], built["uneven128"] = uneven_leg(stream)
+    if not args.no_inference:
+        out["inference"] = inference_leg(stream)
+    if not args.no_coupled:
+        out["coupled"] = coupled_leg(stream)
+    if not args.no_spring:
+        out["spring"] = spring_leg(stream)
+    if not args.no_scenarios:
+        out["scenarios"] = scenario_leg(stream)
+    if not args.no_hybrid:
+        out["hybrid"], built["hybrid512"] = hybrid_leg(args, stream)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        extra = [("small", fixtures.make_config(0), 1000, 16)]
+        if "uneven128" in built:
+            extra.append(("uneven128", built["uneven128"], 10, 256))
+        if "hybrid512" in built:
+            extra.append(("hybrid512", built["hybrid512"], 10, 1024))
+        out["cpu_baseline"], out["moment_error"] = cpu_baseline(w, gm_after, args.warmup + args.steps, dense=dense,
+                                                                extra=extra)
+    print(json.dumps(out), flush=True)
+
+
+def dem_roofline(sim, w, profile_steps):
+    """The dominant kernel timed live with HIP events on its stream (blocked
+    steps: events around every block's DEM launch) over `profile_steps` more
+    steps, its work counted over the same steps: (roofline object, contacts
+    per floe-step)."""
     k_block, blocked = sim.step_block()
     st0, wk0 = sim.stats(), sim.work()
-    dem_ms, lf_ms = sim.profile_steps(w.dt, args.profile_steps)   # whole blocks when blocked
+    dem_ms, lf_ms = sim.profile_steps(w.dt, profile_steps)   # whole blocks when blocked
     st1, wk1 = sim.stats(), sim.work()
-    stats = st1
     dsteps = st1["steps"] - st0["steps"]
     contacts_per_floe_step = (st1["contacts"] - st0["contacts"]) * 2.0 / max(1, w.nfloes * dsteps)
     candidates_per_floe_step = (wk1["candidate_tests"] - wk0["candidate_tests"]) / max(
         1, w.nfloes * (wk1["blocked_steps"] - wk0["blocked_steps"]))
-    sim.close()
     if blocked:
         # floes resident in LDS for k_block steps: VALU binds (state read and
         # written once per launch, statistics every step)
@@ -202,45 +403,88 @@ def main():
     else:
         bytes_launch = BYTES_PER_FLOE_STEP * w.nfloes + BYTES_PER_CELL_STEP * w.ncells
         achieved = bytes_launch / (dem_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "dem_cell_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        roofline = {"bound": "hbm", "kernel": "dem_step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dem_ms,
                     "lf_kernel_ms": lf_ms, "algorithmic_bytes_per_launch": bytes_launch}
+    return roofline, contacts_per_floe_step
 
-    out = {
-        "metric": "floe-steps/sec at 1 GPU (plain DEM vs DEM+closure) at stated moment error",
-        "value": value,
-        "unit": "floe-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 state (u32 fixed-point positions), f64 contact geometry and moment sums",
-        "data": "synthetic",
-        "config": {"workload": w.name, "cells": [w.nx, w.ny], "cell_km": w.Lx / 1e3,
-                   "floes": w.nfloes, "floes_per_cell": float(w.nfloes) / w.ncells, "dt_s": w.dt,
-                   "schedule": ["auto", "allpairs", "binned"][sched[0]], "sub_bins": [sched[1], sched[2]],
-                   "continuum": "lax-friedrichs every step"},
-        "roofline": roofline,
-        "contacts_per_floe_step": contacts_per_floe_step,
-        "wall_s_timed": wall,
-    }
-    if not args.no_uneven:
-        out["uneven"] = uneven_leg(stream)
-    if not args.no_coupled:
-        out["coupled"] = coupled_leg(stream)
-    if not args.no_spring:
-        out["spring"] = spring_leg(stream)
-    if not args.no_scenarios:
-        out["scenarios"] = scenario_leg(stream)
-    if not args.no_hybrid:
-        out["hybrid"] = hybrid_leg(args, stream)
-    if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(out), flush=True)
+
+def dense_leg(stream, w, profile_steps, pre=5000, steps=512, check_steps=10):
+    """plain64 in its dense-contact phase: `pre` steps from t = 0, saved with
+    sp_save; a fresh context restored from the file (sp_load) is timed over
+    `steps` steps with HIP events and profiled like the headline; another
+    restored context steps `check_steps` for the CPU leg's moment check
+    (returned with the floes at the restored state)."""
+    import tempfile
+    import torch
+    import paper_2303_07819_amd as sp
+    path = os.path.join(tempfile.mkdtemp(prefix="spdem_"), "plain64_dense.spdem")
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        sim.step(w.dt, pre)
+        sim.save(path)
+        cont0 = sim.stats()["contacts"]
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        sim.load(path)
+        floes = sim.read_floes()
+        sim.step(w.dt, check_steps)
+        gm = sim.read_moments(sp.MOMENTS_DEM)
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        sim.load(path)
+        sim.step(w.dt, 32)
+        sim.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(w.dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        roofline, cpf = dem_roofline(sim, w, profile_steps)
+    os.remove(path)
+    res = {"workload": w.name, "restored_from_step": pre, "steps": steps, "ms_per_step": ms,
+           "floe_steps_per_s": w.nfloes / (ms * 1e-3), "contacts_per_floe_step": cpf,
+           "candidates_per_floe_step": roofline.get("candidates_per_floe_step"),
+           "contacts_first_5000_steps": cont0, "roofline": roofline}
+    return res, (w, floes, check_steps, gm)
+
+
+def inference_leg(stream, reps=20):
+    """Closure inference on the 256 x 256 grid (65,536 cells, 256 floes per
+    cell): the 45 inputs of every cell (sp_closure_features) and the fused
+    bfloat16 MFMA forward (sp_mlp_forward), timed with HIP events over `reps`
+    repetitions; the network has its initial (Kaiming-uniform) weights, which
+    do not change the work."""
+    import numpy as np
+    import torch
+    import fixtures
+    import paper_2303_07819_amd as sp
+    w = fixtures.make_config("closure256")
+    with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim, sp.MLP(stream=stream.cuda_stream) as net:
+        net.set_params(fixtures.mlp_init(230307904))
+        net.set_norm(np.zeros(45, np.float32), np.ones(45, np.float32), np.zeros(4, np.float32),
+                     np.ones(4, np.float32))
+        with torch.cuda.stream(stream):
+            X = torch.empty((w.ncells, 45), device="cuda", dtype=torch.float32)
+            y = torch.empty((w.ncells, 4), device="cuda", dtype=torch.float32)
+        sim.closure_features(X)
+        net.forward(X, y)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            sim.closure_features(X)
+        ev[1].record(stream)
+        for _ in range(reps):
+            net.forward(X, y)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        feat_us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        fwd_us = ev[1].elapsed_time(ev[2]) * 1e3 / reps
+    flops = 2 * MLP_FWD_MACS * w.ncells
+    return {"workload": "closure256", "cells": w.ncells, "features_us": feat_us, "forward_us": fwd_us,
+            "cells_per_s": w.ncells / ((feat_us + fwd_us) * 1e-6),
+            "mfma_roofline": {"bound": "mfma", "kernel": "mlp_forward_kernel", "achieved": flops / fwd_us / 1e6,
+                              "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": flops / fwd_us / 1e6 / MFMA_BF16_PEAK_TFLOPS}}
 
 
 def uneven_leg(stream, steps=500, warmup=20):
@@ -271,7 +515,7 @@ def uneven_leg(stream, steps=500, warmup=20):
     return {"workload": "uneven128", "cells": [w.nx, w.ny], "floes": w.nfloes, "steps": steps,
             "bucket_cells": cells.tolist(), "default_waves": waves0.tolist(), "default_ms_per_step": ms_default,
             "tuned_waves": waves.tolist(), "tuned_persistent": persist.tolist(), "tuned_ms_per_step": ms_tuned,
-            "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}
+            "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}, w
 
 
 def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):
@@ -408,7 +652,7 @@ def hybrid_leg(args, stream):
                        "mfma_roofline": training_rate(hist)}
     res["workload"] = "hybrid512"
     res["metric"] = "floe-steps/s, plain DEM vs DEM + closure, relative L2 moment error vs full DEM"
-    return res
+    return res, w
 
 
 if __name__ == "__main__":

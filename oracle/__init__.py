@@ -77,6 +77,8 @@ def _load():
         lib.orc_lf_step.restype = D
         lib.orc_resync_cell.argtypes = [MP, I64, P, P, P, P, P, P]
         lib.orc_resync_cell.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -137,6 +139,12 @@ class State:
 
     def arrays(self):
         return [self.xs, self.ys, self.u, self.v, self.w, self.th, self.r, self.h]
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's loops over cells (0: leave as is); returns the
+    count in effect.  Timing only: results do not depend on it."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def ocean_at(model: Model, X: float, Y: float):

@@ -33,6 +33,7 @@
  *   (semi-implicit Euler; the literal forward Euler is a flag).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -486,6 +487,14 @@ int orc_dem_steps(const orc_model* m, const int64_t* start, const int32_t* cells
         stats[1] += st1;
     }
     return rc;
+}
+
+/* Threads of the parallel loops over cells (timing only; results do not
+ * depend on it).  Returns the number now in effect. */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 /* ----------------------------------------------------------- continuum --- */
