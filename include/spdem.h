@@ -228,6 +228,19 @@ sp_status sp_synchronize(sp_ctx* ctx);
  * state) or [ncells][4] for SP_MOMENTS_CONTINUUM.  Synchronises. */
 sp_status sp_read_moments(sp_ctx* ctx, int32_t which, double* out);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses
+ * that forbid hipMalloc): sp_read_moments without any allocation.  The same
+ * values as sp_read_moments bit for bit, into the same caller-owned host
+ * array out ([ncells][SP_NMOM] or [ncells][4]); the rows are staged in a
+ * static device array of the library (8 MiB per device, held until the
+ * process ends) instead of buffers it allocates, so it serves contexts of at
+ * most 65,536 cells.  Every call on a device uses that device's one array:
+ * calls that overlap on one device (from several threads) race; each call
+ * writes every row it reads, so nothing carries over between calls.
+ * Synchronises.  Errors: those of sp_read_moments, SP_ECAPACITY (more than
+ * 65,536 cells), SP_EDEVICE (the array's address could not be taken). */
+sp_status sp_read_moments_noalloc(sp_ctx* ctx, int32_t which, double* out);
+
 /* The fine-scale state of Sec. 2.1 (positions, velocities, spins, angles,
  * radii of every floe, in the cell-sorted order of sp_set_floes).
  * Copy the floe state to caller-owned host arrays of length n (any may be NULL).

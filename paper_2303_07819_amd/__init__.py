@@ -43,7 +43,7 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
-            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size"]
+            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size", "sp_read_moments_noalloc"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.sp_step.argtypes = [P, D, I64]
     lib.sp_synchronize.argtypes = [P]
     lib.sp_read_moments.argtypes = [P, I32, P]
+    lib.sp_read_moments_noalloc.argtypes = [P, I32, P]
     lib.sp_read_floes.argtypes = [P, P, P, P, P, P, P, P]
     lib.sp_read_pairs.argtypes = [P, I64, P, P, ctypes.POINTER(I64)]
     lib.sp_get_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(D)]
@@ -253,6 +254,13 @@ class Sim:
         k = NMOM if which == MOMENTS_DEM else 4
         out = np.zeros((self.ncells, k), np.float64)
         self._check(self._lib.sp_read_moments(self._h, int(which), _p(out)))
+        return out
+
+    def read_moments_noalloc(self, which: int = MOMENTS_DEM) -> np.ndarray:
+        """read_moments through the entry point that allocates no device memory."""
+        k = NMOM if which == MOMENTS_DEM else 4
+        out = np.zeros((self.ncells, k), np.float64)
+        self._check(self._lib.sp_read_moments_noalloc(self._h, int(which), _p(out)))
         return out
 
     def read_floes(self) -> dict:

@@ -883,7 +883,7 @@ sp_status refresh_reduced_all(sp_ctx* c)
 {
     StepArgs a = make_args(c, 0.0);
     a.mom = c->mom2;
-    hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
+    hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr, 0);
     HIP_TRY(c, hipGetLastError());
     return init_reduced_all(c, c->mom2);
 }

@@ -149,7 +149,7 @@ sp_status coarse_step(sp_ctx* c, double dt)
                               hipMemcpyDeviceToDevice, c->stream));
     StepArgs a = make_args(c, 0.0);
     a.mom = c->cpl_x0;
-    hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
+    hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr, 0);
     HIP_TRY(c, hipGetLastError());
     if (c->cpl_ncl == 0 || c->N0 <= c->n_t) return SP_OK;   // no update in the next coarse step
     HIP_TRY(c, hipMemsetAsync(c->cpl_rreq, 0, sizeof(unsigned int), c->stream));

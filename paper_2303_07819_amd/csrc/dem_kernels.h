@@ -979,12 +979,13 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
 
 // ------------------------------------------------------- cell statistics
 // All 11 statistics of the current state, one 256-thread workgroup per cell
-// (cell blockIdx.x, or cells[blockIdx.x] with a cell list).
-__global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* cells)
+// (cell c0 + blockIdx.x, or cells[blockIdx.x] with a cell list), written to
+// row c - c0 of a.mom.
+__global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* cells, int c0)
 {
     __shared__ double red11[SP_NMOM][16];
     __shared__ ModeC mode_c[SP_MAX_MODES];
-    const int c = cells ? cells[blockIdx.x] : (int)blockIdx.x;
+    const int c = cells ? cells[blockIdx.x] : c0 + (int)blockIdx.x;
     const int tid = threadIdx.x;
     const int s = a.cell_start[c];
     const int n = a.cell_start[c + 1] - s;
@@ -1035,9 +1036,9 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
         double x = red11[tid][0];
 #pragma unroll
         for (int q = 1; q < 16; ++q) x += red11[tid][q];
-        a.mom[(size_t)c * kMomStride + tid] = x;
-        if (tid == M_UX || tid == M_UY)
-            a.mom[(size_t)c * kMomStride + (tid == M_UX ? M_UBAR : M_VBAR)] = n > 0 ? x / (double)n : 0.0;
+        double* const row = a.mom + (size_t)(c - c0) * kMomStride;
+        row[tid] = x;
+        if (tid == M_UX || tid == M_UY) row[tid == M_UX ? M_UBAR : M_VBAR] = n > 0 ? x / (double)n : 0.0;
     }
 }
 

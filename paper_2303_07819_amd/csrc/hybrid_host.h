@@ -308,7 +308,7 @@ sp_status restart_reduced(sp_ctx* c, const int32_t* cells_d, int ncl, const int3
     if (ncl <= 0) return SP_OK;
     StepArgs a = make_args(c, 0.0);
     a.mom = c->mom2;
-    hipLaunchKernelGGL(stats_kernel, dim3(ncl), dim3(256), 0, c->stream, a, cells_d);
+    hipLaunchKernelGGL(stats_kernel, dim3(ncl), dim3(256), 0, c->stream, a, cells_d, 0);
     HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(reduced_init_kernel, dim3((ncl + 255) / 256), dim3(256), 0, c->stream, cells_d, ncl, status_d,
                        c->mom2, closure_args(c, c->t_now), c->red);
@@ -359,7 +359,7 @@ sp_status hybrid_check(sp_ctx* c, double dt)
     //    neighbours' coefficients are those of the step just taken
     StepArgs a = make_args(c, dt);
     a.mom = c->mom2;
-    hipLaunchKernelGGL(stats_kernel, dim3(nk), dim3(256), 0, c->stream, a, h->chk_d);
+    hipLaunchKernelGGL(stats_kernel, dim3(nk), dim3(256), 0, c->stream, a, h->chk_d, 0);
     HIP_TRY(c, hipGetLastError());
     const int64_t k = c->kstep - 1;
     const double inv_area = 1.0 / (c->p.cell_lx * c->p.cell_ly);

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -154,6 +155,47 @@ struct sp_ctx {
     hipGraphExec_t gexec = nullptr;
     double graph_dt = 0.0;
 };
+
+// Scratch of sp_read_moments_noalloc: the statistics rows of up to
+// kNoAllocMaxCells cells (8 MiB), one copy per device for the life of the
+// process.  Host code never names it: it uses the device address taken by
+// hipGetSymbolAddress when a context is created on that device.
+constexpr int kNoAllocMaxCells = 65536;
+static __device__ __align__(256) double scratch[(size_t)kNoAllocMaxCells * kMomStride];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, the current device (taken once
+// per device).
+hipError_t scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+double* scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+// Continuum rows: out[c][f] = Q[f][c].
+__global__ __launch_bounds__(256) void q_rows_kernel(const double* Q, int nc, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc * 4) out[i] = Q[(size_t)(i & 3) * nc + (i >> 2)];
+}
+}  // namespace
 
 void hybrid_free(sp_ctx* c);   // hybrid_host.h
 sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps);   // coupling_host.h
@@ -763,7 +805,7 @@ sp_status reset_continuum(sp_ctx* c)
     StepArgs a = make_args(c, 0.0);
     a.mom = c->momb[0];
     if (c->ncells > 0) {
-        hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr);
+        hipLaunchKernelGGL(stats_kernel, dim3(c->ncells), dim3(256), 0, c->stream, a, nullptr, 0);
         HIP_TRY(c, hipGetLastError());
         // the static statistics (n, M, A_ice) must be present at both levels
         HIP_TRY(c, hipMemcpyAsync(c->momb[1], c->momb[0], (size_t)c->ncells * kMomStride * 8,
@@ -849,6 +891,14 @@ sp_status sp_create(const sp_params* params, void* stream, sp_ctx** out)
     c->ncells = p.nx * p.ny;
     for (int q = 0; q < kNumBuckets; ++q) c->bk[q].waves = kDefaultWaves[q];
     (void)hipGetDevice(&c->device);
+    {
+        const hipError_t e = scratch_setup(c->device);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            return SP_EDEVICE;
+        }
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
         c->num_cus = cus;
@@ -1224,7 +1274,7 @@ sp_status sp_read_moments(sp_ctx* c, int32_t which, double* out)
         StepArgs a = make_args(c, 0.0);
         a.mom = c->mom2;
         if (nc > 0) {
-            hipLaunchKernelGGL(stats_kernel, dim3(nc), dim3(256), 0, c->stream, a, nullptr);
+            hipLaunchKernelGGL(stats_kernel, dim3(nc), dim3(256), 0, c->stream, a, nullptr, 0);
             HIP_TRY(c, hipGetLastError());
         }
         std::vector<double> buf((size_t)nc * kMomStride);
@@ -1243,6 +1293,40 @@ sp_status sp_read_moments(sp_ctx* c, int32_t which, double* out)
     } else {
         return fail(c, SP_EINVAL, "unknown moments selector %d", which);
     }
+    return check_device_err(c);
+}
+
+sp_status sp_read_moments_noalloc(sp_ctx* c, int32_t which, double* out)
+{
+    if (!c || !out) return c ? fail(c, SP_EINVAL, "null output") : SP_EINVAL;
+    if (!c->have_floes) return fail(c, SP_ESTATE, "no floes");
+    if (which != SP_MOMENTS_DEM && which != SP_MOMENTS_CONTINUUM)
+        return fail(c, SP_EINVAL, "unknown moments selector %d", which);
+    if (c->ncells > kNoAllocMaxCells)
+        return fail(c, SP_ECAPACITY, "%d cells exceed the %d of sp_read_moments_noalloc's static scratch",
+                    c->ncells, kNoAllocMaxCells);
+    double* const sc = scratch_of(c->device);
+    if (!sc) return fail(c, SP_EDEVICE, "no static scratch on device %d", c->device);
+    const int nc = c->ncells;
+    if (which == SP_MOMENTS_DEM) {
+        StepArgs a = make_args(c, 0.0);
+        a.mom = sc;   // every row of the call is written before it is read
+        if (nc > 0) {
+            hipLaunchKernelGGL(stats_kernel, dim3(nc), dim3(256), 0, c->stream, a, nullptr, 0);
+            HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipMemcpy2DAsync(out, SP_NMOM * sizeof(double), sc, kMomStride * sizeof(double),
+                                        SP_NMOM * sizeof(double), (size_t)nc, hipMemcpyDeviceToHost, c->stream));
+        }
+    } else {
+        SP_TRY(flush_lf(c));
+        if (nc > 0) {
+            hipLaunchKernelGGL(q_rows_kernel, dim3((nc * 4 + 255) / 256), dim3(256), 0, c->stream, c->Q[c->kstep & 1],
+                               nc, sc);
+            HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipMemcpyAsync(out, sc, (size_t)nc * 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return check_device_err(c);
 }
 
