@@ -508,14 +508,16 @@ def uneven_leg(stream, steps=500, warmup=20):
 
     with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
         ms_default = timed(sim)
-        cells, waves0, _ = sim.batching()
-        sim.autotune(w.dt)
+        cells, _, _ = sim.batching()
+        bw0, k0 = sim.block_waves(), sim.step_block()[0]
+        best = sim.autotune(w.dt, 5)
         ms_tuned = timed(sim)
-        _, waves, persist = sim.batching()
+        bw, k = sim.block_waves(), sim.step_block()[0]
     return {"workload": "uneven128", "cells": [w.nx, w.ny], "floes": w.nfloes, "steps": steps,
-            "bucket_cells": cells.tolist(), "default_waves": waves0.tolist(), "default_ms_per_step": ms_default,
-            "tuned_waves": waves.tolist(), "tuned_persistent": persist.tolist(), "tuned_ms_per_step": ms_tuned,
-            "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}, w
+            "bucket_cells": cells.tolist(), "tuned": "blocked kernel: wavefronts per cell per bucket, block length",
+            "default_block_waves": bw0.tolist(), "default_step_block": k0, "default_ms_per_step": ms_default,
+            "tuned_block_waves": bw.tolist(), "tuned_step_block": k, "tuner_best_ms_per_step": best,
+            "tuned_ms_per_step": ms_tuned, "floe_steps_per_s": w.nfloes / (ms_tuned * 1e-3)}, w
 
 
 def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):

@@ -288,12 +288,22 @@ sp_status sp_profile_steps(sp_ctx* ctx, double dt, int64_t nsteps, double* dem_m
 sp_status sp_get_batching(sp_ctx* ctx, int32_t* cells, int32_t* waves, int32_t* persistent);
 sp_status sp_set_batching(sp_ctx* ctx, const int32_t* waves, const int32_t* persistent);
 
-/* Time every (waves, persistent) variant of every non-empty bucket on a scratch
- * copy of the floe state (reps timed repetitions of two steps each, minimum
- * kept) and keep the fastest.  The simulation state is not advanced.  *best_ms
- * (may be NULL) receives the summed best step time of the buckets.
- * Synchronises.  Errors: SP_EINVAL, SP_ESTATE, SP_ENOMEM, SP_EDEVICE. */
+/* Tune the batching of the launches sp_step runs, on a scratch copy of the
+ * floe state (the simulation is not advanced; candidate lists are rebuilt at
+ * the next step).  With blocked steps (block length > 1 at the plain cadence,
+ * see sp_set_step_block): every non-empty bucket alone over the wavefronts per
+ * cell of its blocked launches that hold one floe per lane (W = 1, 2, 4, 8,
+ * 16), then the block length (16, 32 or 64 steps) over the whole step; each
+ * variant one warm-up launch and the minimum of reps timed launches; *best_ms
+ * receives the best whole step's time per step.  Otherwise (per-step launches)
+ * every (waves, persistent) variant of every bucket's per-step kernel, reps
+ * repetitions of two steps each; *best_ms the summed best step time of the
+ * buckets.  *best_ms may be NULL.  Synchronises.
+ * Errors: SP_EINVAL, SP_ESTATE, SP_ENOMEM, SP_EDEVICE. */
 sp_status sp_autotune(sp_ctx* ctx, double dt, int32_t reps, double* best_ms);
+/* Wavefronts per cell of each bucket's blocked launches (0 for an empty
+ * bucket), as sp_autotune or the defaults set them. */
+sp_status sp_get_block_waves(sp_ctx* ctx, int32_t* waves);
 
 /* Temporal blocking of the plain step (coarse step = fine step): with k > 1,
  * sp_step runs whole blocks of k steps as one DEM launch per count bucket in

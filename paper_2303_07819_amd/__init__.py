@@ -43,7 +43,7 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
-            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size", "sp_read_moments_noalloc"]
+            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size", "sp_read_moments_noalloc", "sp_get_block_waves"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.sp_get_batching.argtypes = [P, P, P, P]
     lib.sp_set_batching.argtypes = [P, P, P]
     lib.sp_autotune.argtypes = [P, D, I32, ctypes.POINTER(D)]
+    lib.sp_get_block_waves.argtypes = [P, P]
     lib.sp_set_graph_chunk.argtypes = [P, I32]
     lib.sp_set_step_block.argtypes = [P, I32]
     lib.sp_get_step_block.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -310,6 +311,12 @@ class Sim:
         best = ctypes.c_double()
         self._check(self._lib.sp_autotune(self._h, float(dt), int(reps), ctypes.byref(best)))
         return float(best.value)
+
+    def block_waves(self):
+        """Wavefronts per cell of each bucket's blocked launches (0: empty bucket)."""
+        w = np.zeros(NUM_BUCKETS, np.int32)
+        self._check(self._lib.sp_get_block_waves(self._h, _p(w)))
+        return w
 
     def set_graph_chunk(self, chunk: int):
         self._check(self._lib.sp_set_graph_chunk(self._h, int(chunk)))

@@ -520,6 +520,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     for (int q = 0; q < kNumBuckets; ++q) {
         h->bk[q].waves = c->bk[q].waves;
         h->bk[q].persist = c->bk[q].persist;
+        h->bk[q].bwaves = c->bk[q].bwaves;
     }
     const size_t nk = (size_t)std::max(1, check_cells);
     SP_TRY(dalloc(c, &h->row_d, (size_t)c->ncells));

@@ -50,6 +50,7 @@ constexpr int kDefaultStepBlock = 32;   // steps per blocked DEM launch
 struct Bucket {
     int waves = 4;
     int persist = 0;                    // resident workgroups stride over the cells
+    int bwaves = 0;                     // wavefronts per cell of blocked launches (0: derived from waves)
     int cap = 0;                        // LDS floe capacity per group
     int resident = 1;                   // workgroups resident at once (persistent grid size)
     std::vector<int32_t> cells_h;       // costliest first
@@ -572,11 +573,13 @@ sp_status launch_bucket(sp_ctx* c, const Bucket& b, const StepArgs& base, int64_
     return launch_sel(c, c->sched, b.waves, persist, a, grid, bucket_threads(c, b), bucket_lds(c, b));
 }
 
-// Wavefronts per cell of a bucket's blocked launches: the bucket's own W when
-// its cells have at most 64 W floes, else the smallest of 8 and 16 that holds
-// one floe per lane (up to the 1024-floe cell limit).
+// Wavefronts per cell of a bucket's blocked launches: the autotuner's choice
+// where it made one, else the bucket's own W when its cells have at most 64 W
+// floes, else the smallest of 8 and 16 that holds one floe per lane (up to the
+// 1024-floe cell limit).
 int block_waves(const Bucket& b)
 {
+    if (b.bwaves > 0 && b.cap <= 64 * b.bwaves) return b.bwaves;
     if (b.cap <= 64 * b.waves) return b.waves;
     return b.cap <= 512 ? 8 : 16;
 }
@@ -869,6 +872,84 @@ sp_status capture_graph(sp_ctx* c, double dt)
     }
     c->graph = g;
     c->graph_dt = dt;
+    return SP_OK;
+}
+
+// Autotuning of blocked steps on a scratch copy of the state (`a` points at
+// it): every non-empty bucket alone, over the wavefronts per cell that hold one
+// floe per lane (W = 1 .. 16), then the block length over the whole step
+// (16, 32, 64 steps); each variant one warm-up launch and the minimum of reps
+// timed launches, per step.  Sets each bucket's bwaves and the block length.
+constexpr int kTuneBlocks[3] = {16, 32, 64};
+
+sp_status tune_blocked(sp_ctx* c, StepArgs a, int reps, hipEvent_t e0, hipEvent_t e1, double* total)
+{
+    double* smom = nullptr;
+    unsigned long long* scands = nullptr;
+    sp_status st = dalloc(c, &smom, (size_t)kTuneBlocks[2] * c->ncells * kMomStride);
+    if (!st) st = dalloc(c, &scands, std::max<size_t>(1, (size_t)c->ncells));
+    a.cands = scands;
+    BlockNudge none;
+    memset(&none, 0, sizeof none);
+    auto time_blocks = [&](const Bucket* bk, int K, double* per_step) -> sp_status {
+        SP_TRY(launch_blocks(c, a, smom, K, none, bk));   // warm-up (and list rebuilds)
+        double best = 1e30;
+        for (int r = 0; r < reps; ++r) {
+            HIP_TRY(c, hipEventRecord(e0, c->stream));
+            SP_TRY(launch_blocks(c, a, smom, K, none, bk));
+            HIP_TRY(c, hipEventRecord(e1, c->stream));
+            HIP_TRY(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, (double)ms / K);
+        }
+        *per_step = best;
+        return SP_OK;
+    };
+    const int wv[5] = {1, 2, 4, 8, 16};
+    double sum = 0.0;
+    for (int q = 0; q < kNumBuckets && !st; ++q) {
+        Bucket& b = c->bk[q];
+        if (b.cells_h.empty()) continue;
+        Bucket trial[kNumBuckets];
+        trial[q].cap = b.cap;
+        trial[q].waves = b.waves;
+        trial[q].cells_h = b.cells_h;
+        trial[q].work_d = b.work_d;
+        double best = 1e30;
+        int bw = block_waves(b);
+        for (int wi = 0; wi < 5 && !st; ++wi) {
+            if (b.cap > 64 * wv[wi]) continue;        // one floe per lane
+            trial[q].bwaves = wv[wi];
+            double t = 0.0;
+            st = time_blocks(trial, c->block_k, &t);
+            if (!st && t < best) {
+                best = t;
+                bw = wv[wi];
+            }
+        }
+        trial[q].work_d = nullptr;    // owned by the real bucket
+        if (!st) {
+            b.bwaves = bw;
+            sum += best;
+        }
+    }
+    int bestK = c->block_k;
+    double bestT = 1e30;
+    for (int i = 0; i < 3 && !st; ++i) {
+        double t = 0.0;
+        st = time_blocks(c->bk, kTuneBlocks[i], &t);
+        if (!st && t < bestT) {
+            bestT = t;
+            bestK = kTuneBlocks[i];
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    if (smom) (void)hipFree(smom);
+    if (scands) (void)hipFree(scands);
+    if (st) return st;
+    c->block_k = bestK;
+    *total = bestT < 1e30 ? bestT : sum;
     return SP_OK;
 }
 
@@ -1444,6 +1525,7 @@ sp_status sp_set_batching(sp_ctx* c, const int32_t* waves, const int32_t* persis
     for (int q = 0; q < kNumBuckets; ++q) {
         c->bk[q].waves = waves[q];
         c->bk[q].persist = persistent[q];
+        c->bk[q].bwaves = 0;   // blocked launches follow the new W
     }
     if (c->have_floes) SP_TRY(prepare_buckets(c));
     return SP_OK;
@@ -1545,8 +1627,10 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     a.mom = smom;
     a.lf = 0;
     double total = 0.0;
+    const bool blocked = block_eligible(c);
+    if (!st && blocked) st = tune_blocked(c, a, reps, e0, e1, &total);
     const int wv[4] = {1, 2, 4, 8};
-    for (int q = 0; q < kNumBuckets && !st; ++q) {
+    for (int q = 0; q < kNumBuckets && !st && !blocked; ++q) {
         Bucket& b = c->bk[q];
         if (b.cells_h.empty()) continue;
         Bucket trial;
@@ -1589,8 +1673,16 @@ sp_status sp_autotune(sp_ctx* c, double dt, int32_t reps, double* best_ms)
     if (st) return st == SP_EDEVICE ? fail(c, st, "autotune timing failed") : st;
     SP_TRY(prepare_buckets(c));
     SP_TRY(invalidate_lists(c, nullptr, c->ncells));   // the trials stepped a scratch state with them
+    if (blocked) SP_TRY(block_prepare(c));              // the ring for the chosen block length
     drop_graph(c);
     if (best_ms) *best_ms = total;
+    return SP_OK;
+}
+
+sp_status sp_get_block_waves(sp_ctx* c, int32_t* waves)
+{
+    if (!c || !waves) return c ? fail(c, SP_EINVAL, "null waves") : SP_EINVAL;
+    for (int q = 0; q < kNumBuckets; ++q) waves[q] = c->bk[q].cells_h.empty() ? 0 : block_waves(c->bk[q]);
     return SP_OK;
 }
 

@@ -23,8 +23,10 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def run(w, nsteps, waves=None, persistent=None, chunk=None, autotune=False):
+def run(w, nsteps, waves=None, persistent=None, chunk=None, autotune=False, block=None):
     s = sp.Sim.from_workload(w)
+    if block is not None:
+        s.set_step_block(block)
     if chunk is not None:
         s.set_graph_chunk(chunk)
     if waves is not None:
@@ -95,13 +97,48 @@ def test_graph_replay_equals_eager():
 
 
 def test_autotune_does_not_advance_the_state():
+    """Per-step launches (block length 1): the tuner picks (waves, persistent)
+    per bucket; the state it leaves is the untuned one's bit for bit."""
     w = uneven_workload(seed=5)
-    plain = run(w, 4, chunk=0)
-    tuned = run(w, 4, chunk=0, autotune=True)
+    plain = run(w, 4, chunk=0, block=1)
+    tuned = run(w, 4, chunk=0, autotune=True, block=1)
     _say(f"autotuned waves {tuned[3][1].tolist()} persistent {tuned[3][2].tolist()}")
     for k in plain[0]:
         assert np.array_equal(plain[0][k], tuned[0][k]), k
     np.testing.assert_allclose(tuned[2], plain[2], rtol=1e-12, atol=1e-300)
+
+
+def test_autotune_of_blocked_steps_keeps_the_state():
+    """Blocked steps (the default): the tuner times the blocked kernel per
+    bucket over its wavefronts per cell and the block length; steps after
+    tuning give the untuned floe state bit for bit (the per-floe arithmetic
+    does not depend on W or the block length) and its continuum to FP64
+    rounding."""
+    w = uneven_workload(seed=6)
+    rng = np.random.default_rng(1)
+    w.u[:] = rng.normal(0, 0.2, w.nfloes)
+    w.v[:] = rng.normal(0, 0.2, w.nfloes)
+    with sp.Sim.from_workload(w) as s:
+        s.step(w.dt, 37)
+        f0, q0 = s.read_floes(), s.read_moments(sp.MOMENTS_CONTINUUM)
+        bw0 = s.block_waves()
+    with sp.Sim.from_workload(w) as s:
+        best = s.autotune(w.dt, 2)
+        k, active = s.step_block()
+        bw = s.block_waves()
+        cells = s.batching()[0]
+        s.step(w.dt, 37)
+        f1, q1 = s.read_floes(), s.read_moments(sp.MOMENTS_CONTINUUM)
+        work = s.work()
+    _say(f"blocked autotune: block {k}, waves {bw.tolist()} (default {bw0.tolist()}), best {best:.4f} ms/step")
+    assert active and k in (16, 32, 64) and best > 0
+    assert work["blocked_steps"] == 37
+    for q in range(5):
+        if cells[q]:
+            assert bw[q] in (1, 2, 4, 8, 16)
+    for key in f0:
+        assert np.array_equal(f0[key], f1[key]), key
+    np.testing.assert_allclose(q1, q0, rtol=1e-12, atol=1e-300)
 
 
 def test_full_size_uneven128_sampled_cells():
