@@ -27,6 +27,8 @@ OCEAN_OFF = 1
 FORWARD_EULER = 2
 BINNED = 4
 SPRING = 8          # tangential force as an incremental spring with contact history
+WALLS_X = 16        # DEM: fixed walls at x = 0 and x = Lx, periodic in y only (Sec. 4.4)
+DIRICHLET_X = 32    # continuum: zero state and coefficients beyond the x edges (Sec. 4.4)
 HCAP = 16           # contacts remembered per floe (SPRING)
 NMOM = 11
 MOMENT_NAMES = ["n", "M", "Px", "Py", "L", "Ux", "Uy", "Svx", "Svy", "Sw", "Aice"]
@@ -205,6 +207,10 @@ def dem_steps(model: Model, state: State, dt: float, nsteps: int, cells=None,
         raise FloatingPointError("non-finite floe state")
     if rc == -3:
         raise OverflowError(f"a floe in more than {HCAP} contacts")
+    if rc == -5:
+        raise FloatingPointError("a floe crossed a wall")
+    if rc == -6:
+        raise ValueError("the tangential spring does not run between walls")
     return mom, stats
 
 

@@ -42,6 +42,8 @@
 #define ORC_FORWARD_EULER 2
 #define ORC_BINNED 4
 #define ORC_TSPRING 8   /* tangential force as an incremental spring with contact history */
+#define ORC_WALLS_X 16  /* fixed walls at x = 0 and x = Lx (the DEM is periodic in y only) */
+#define ORC_DIRICHLET_X 32  /* continuum: zero state beyond the x edges (Sec. 4.4) */
 #define ORC_HCAP 16     /* contacts remembered per floe */
 
 #define NMOM 11
@@ -92,7 +94,8 @@ static double min_image(double d)
 static int contact_pred(const orc_model* m, double xl, double yl, double rl,
                         double xj, double yj, double rj)
 {
-    double dx = min_image(xj - xl) * m->Lx;
+    /* between walls the x difference is the plain one (no periodic image) */
+    double dx = ((m->flags & ORC_WALLS_X) ? xj - xl : min_image(xj - xl)) * m->Lx;
     double dy = min_image(yj - yl) * m->Ly;
     double R = rl + rj;
     double d2 = dx * dx + dy * dy;
@@ -210,7 +213,7 @@ static int contact_force(const orc_model* m, const double* xs, const double* ys,
                          const double* v, const double* w, const double* r, int64_t l, int64_t j,
                          double dt, double xi_old, double* xi, double* fx, double* fy, double* tq)
 {
-    double dx = min_image(xs[j] - xs[l]) * m->Lx;
+    double dx = ((m->flags & ORC_WALLS_X) ? xs[j] - xs[l] : min_image(xs[j] - xs[l])) * m->Lx;
     double dy = min_image(ys[j] - ys[l]) * m->Ly;
     double d = sqrt(dx * dx + dy * dy);
     if (!(d > 0.0)) return -1;
@@ -242,6 +245,34 @@ static int contact_force(const orc_model* m, const double* xs, const double* ys,
     *fy = Fn * ny + Ft * ty;
     *tq = r[l] * Ft;
     return 0;
+}
+
+/* Contact of floe l with a fixed straight wall at distance d from its centre
+ * (the contact law of Sec. 2.1 with the wall as the other body: it does not
+ * move or spin).  nsx = +1 for a wall on the floe's +x side, -1 for -x; the
+ * normal n = (nsx, 0) points from the floe to the wall, t = (-n_y, n_x) =
+ * (0, nsx).  In contact iff d < r: overlap delta = d - r, contact chord
+ * c = 2 sqrt(r^2 - d^2) (the chord the wall line cuts from the disk: the
+ * common chord of two disks as the other radius grows without bound),
+ * f_n = c E delta n, v_t = -(v_l . t) - w_l r_l, f_t = c G v_t t capped at
+ * mu |f_n|; the spin torque on the floe is r_l f_t.  Returns 1 in contact. */
+static int wall_force(const orc_model* m, double d, double nsx, double u, double v, double w, double r,
+                      double* fx, double* fy, double* tq)
+{
+    if (!(d < r)) return 0;
+    double delta = d - r;
+    double c = 2.0 * sqrt(r * r - d * d);
+    double Fn = c * m->E * delta;
+    double tx = 0.0, ty = nsx;
+    double vt = -(u * tx + v * ty) - w * r;
+    double cap = m->mu * fabs(Fn);
+    double Ft = c * m->G * vt;
+    if (Ft > cap) Ft = cap;
+    if (Ft < -cap) Ft = -cap;
+    *fx = Fn * nsx + Ft * tx;
+    *fy = Ft * ty;
+    *tq = r * Ft;
+    return 1;
 }
 
 /* ---------------------------------------------------- compensated sums --- */
@@ -346,6 +377,8 @@ static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, 
                      double* hx)
 {
     const int spring = (m->flags & ORC_TSPRING) != 0;
+    int64_t nwall = 0;   /* floe-wall contacts of this step */
+    if (spring && (m->flags & ORC_WALLS_X)) return -6;
     if (n == 0) {
         if (mom) memset(mom, 0, sizeof(double) * NMOM);
         return 0;
@@ -418,6 +451,23 @@ static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, 
             Fy += fy;
             T += tq;
         }
+        if ((m->flags & ORC_WALLS_X) && !rc) {
+            /* the walls at x = 0 and x = Lx, after the floe contacts */
+            double fx, fy, tq;
+            double dl = xs[l] * m->Lx, dr = (1.0 - xs[l]) * m->Lx;
+            if (wall_force(m, dl, -1.0, u[l], v[l], w[l], r[l], &fx, &fy, &tq)) {
+                Fx += fx;
+                Fy += fy;
+                T += tq;
+                if (stats) nwall++;
+            }
+            if (wall_force(m, dr, 1.0, u[l], v[l], w[l], r[l], &fx, &fy, &tq)) {
+                Fx += fx;
+                Fy += fy;
+                T += tq;
+                if (stats) nwall++;
+            }
+        }
         if (spring && !rc)
             for (int q = 0; q < ORC_HCAP; ++q) {
                 hj[l * ORC_HCAP + q] = q < nh ? nj[q] : -1;
@@ -435,11 +485,17 @@ static int cell_step(const orc_model* m, int ix, int iy, int64_t n, double* xs, 
         w[l] += dt * aw[l];
         int fe = (m->flags & ORC_FORWARD_EULER) != 0;
         double uu = fe ? u_old : u[l], vv = fe ? v_old : v[l], ww = fe ? w_old : w[l];
-        xs[l] = wrap01(xs[l] + dt * uu / m->Lx);
+        if (m->flags & ORC_WALLS_X) {
+            xs[l] = xs[l] + dt * uu / m->Lx;     /* no periodic wrap between walls */
+            if (!(xs[l] >= 0.0 && xs[l] < 1.0)) rc = -5;
+        } else {
+            xs[l] = wrap01(xs[l] + dt * uu / m->Lx);
+        }
         ys[l] = wrap01(ys[l] + dt * vv / m->Ly);
         th[l] += dt * ww;
         if (!isfinite(u[l]) || !isfinite(v[l]) || !isfinite(w[l])) rc = -2;
     }
+    if (stats) stats[0] += nwall;
     free(ax);
     free(ay);
     free(aw);
@@ -529,9 +585,17 @@ double orc_lf_step(const orc_model* m, const double* Q, const double* mom, doubl
             int C = iy * nx + ix;
             int E = iy * nx + (ix + 1) % nx, W = iy * nx + (ix + nx - 1) % nx;
             int N = ((iy + 1) % ny) * nx + ix, S = ((iy + ny - 1) % ny) * nx + ix;
+            /* Dirichlet in x (Sec. 4.4): beyond the first and last column lies
+             * a ghost cell with zero state and zero coefficients (no ice, no
+             * drift); E or W = -1 marks it */
+            if (m->flags & ORC_DIRICHLET_X) {
+                if (ix == nx - 1) E = -1;
+                if (ix == 0) W = -1;
+            }
             const double* sC = mom + (size_t)C * NMOM;
-#define UBAR(K) (mom[(size_t)(K) * NMOM + M_N] > 0 ? mom[(size_t)(K) * NMOM + M_UX] / mom[(size_t)(K) * NMOM + M_N] : 0.0)
-#define VBAR(K) (mom[(size_t)(K) * NMOM + M_N] > 0 ? mom[(size_t)(K) * NMOM + M_UY] / mom[(size_t)(K) * NMOM + M_N] : 0.0)
+#define UBAR(K) ((K) >= 0 && mom[(size_t)(K) * NMOM + M_N] > 0 ? mom[(size_t)(K) * NMOM + M_UX] / mom[(size_t)(K) * NMOM + M_N] : 0.0)
+#define VBAR(K) ((K) >= 0 && mom[(size_t)(K) * NMOM + M_N] > 0 ? mom[(size_t)(K) * NMOM + M_UY] / mom[(size_t)(K) * NMOM + M_N] : 0.0)
+#define QV(K, F) ((K) >= 0 ? Q[4 * (K) + (F)] : 0.0)
             double uE = UBAR(E), uW = UBAR(W), vN = VBAR(N), vS = VBAR(S);
             double uC = UBAR(C), vC = VBAR(C);
 #undef UBAR
@@ -541,13 +605,13 @@ double orc_lf_step(const orc_model* m, const double* Q, const double* mom, doubl
             /* mass, conservative */
             {
                 int f = 0;
-                double qE = Q[4 * E + f], qW = Q[4 * W + f], qN = Q[4 * N + f], qS = Q[4 * S + f];
+                double qE = QV(E, f), qW = QV(W, f), qN = QV(N, f), qS = QV(S, f);
                 Qn[4 * C + f] = 0.25 * (qE + qW + qN + qS) - cx * (uE * qE - uW * qW) -
                                 cy * (vN * qN - vS * qS);
             }
             /* momentum, Oseen form, drag source */
             for (int f = 1; f <= 2; ++f) {
-                double qE = Q[4 * E + f], qW = Q[4 * W + f], qN = Q[4 * N + f], qS = Q[4 * S + f];
+                double qE = QV(E, f), qW = QV(W, f), qN = QV(N, f), qS = QV(S, f);
                 double src = sC[f == 1 ? M_SVX : M_SVY] / A;
                 Qn[4 * C + f] = 0.25 * (qE + qW + qN + qS) -
                                 dT * (uC * (qE - qW) / (2.0 * m->Lx) + vC * (qN - qS) / (2.0 * m->Ly)) +
@@ -556,10 +620,11 @@ double orc_lf_step(const orc_model* m, const double* Q, const double* mom, doubl
             /* spin angular momentum, conservative, drag-torque source */
             {
                 int f = 3;
-                double qE = Q[4 * E + f], qW = Q[4 * W + f], qN = Q[4 * N + f], qS = Q[4 * S + f];
+                double qE = QV(E, f), qW = QV(W, f), qN = QV(N, f), qS = QV(S, f);
                 Qn[4 * C + f] = 0.25 * (qE + qW + qN + qS) - cx * (uE * qE - uW * qW) -
                                 cy * (vN * qN - vS * qS) + dT * sC[M_SW] / A;
             }
+#undef QV
         }
     return cfl;
 }
