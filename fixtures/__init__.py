@@ -343,12 +343,12 @@ SCENARIO_CONSTANTS = dict(rho_ice=1.0, rho_ocean=1.0, cd=50.0, E=1.0e4, G=1.0, m
 
 
 def scenario_ocean(k: int) -> Ocean:
-    """Prescribed currents of Sec. 4.1 (uniform), 4.2 (0.3 - 0.1 cos(pi x), 0)
-    and 4.3 (0.3 - 0.1 sin(0.1 pi x) cos(pi y), 0.05 cos(0.1 pi x) sin(pi y)),
-    the last written as two plane modes."""
+    """Prescribed currents of Sec. 4.1 and 4.4 (uniform), 4.2
+    (0.3 - 0.1 cos(pi x), 0) and 4.3 (0.3 - 0.1 sin(0.1 pi x) cos(pi y),
+    0.05 cos(0.1 pi x) sin(pi y)), the last written as two plane modes."""
     p = math.pi
     u0 = float(np.float32(0.3))           # equal to the floes' stored velocity
-    if k == 1:
+    if k in (1, 4):
         return Ocean(u0, 0.0)
     if k == 2:
         return Ocean(u0, 0.0, np.array([p]), np.array([0.0]), np.array([-0.1]), np.array([0.0]),
@@ -361,8 +361,9 @@ def scenario_ocean(k: int) -> Ocean:
 
 def scenario_global(k: int, nfx: int = 480, nfy: int = 240, Lx: float = 4.0, Ly: float = 2.0,
                     dt: float = 1e-4) -> Workload:
-    """The initial state of scenario 4.k as one global periodic DEM (a single
-    cell spanning the domain; positions are fractions of the domain)."""
+    """The initial state of scenario 4.k as one global DEM (a single cell
+    spanning the domain; positions are fractions of the domain).  Scenario
+    4.4 starts as 4.1; its walls in x are a flag of the models that run it."""
     fx = (np.arange(nfx) + 0.5) / nfx
     fy = (np.arange(nfy) + 0.5) / nfy
     X, Y = np.meshgrid(fx, fy)

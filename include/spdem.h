@@ -47,7 +47,8 @@ typedef enum {
     SP_EOVERLAP = -5,   /* two floe centres coincide: contact normal undefined */
     SP_ENAN = -6,       /* non-finite floe state */
     SP_ESTATE = -7,     /* call out of order (e.g. step before set_floes) */
-    SP_ECAPACITY = -8   /* a cell exceeds the per-cell floe or contact capacity */
+    SP_ECAPACITY = -8,  /* a cell exceeds the per-cell floe or contact capacity */
+    SP_EWALL = -9       /* a floe crossed a wall (SP_WALL_X) */
 } sp_status;
 
 /* sp_params.flags */
@@ -66,6 +67,23 @@ typedef enum {
  * (SP_ESTATE). */
 #define SP_TANGENTIAL_SPRING 8u
 #define SP_SPRING_CAP 8
+/* Walls at x = 0 and at the far x edge, the boundary of the paper's
+ * scenario of floes driven into a fixed wall (Sec. 4.4); periodic in y.
+ * sp_ctx (sp_params.flags): the coarse model takes a zero (Dirichlet)
+ * boundary condition on the floe concentration in x: beyond the first and
+ * the last column of cells lies a ghost cell with zero state (rho, P_x, P_y,
+ * P_w) and zero coefficients <v> in every Lax-Friedrichs step, on every path
+ * (plain, blocked, coupled); the cell DEMs stay doubly periodic (Sec. 3.1).
+ * Not with the hybrid or closure sampling (SP_ESTATE).
+ * sp_gdem (sp_gdem_params.flags): the global DEM is periodic in y only, and a
+ * floe whose centre lies within its radius of a wall is in contact with it:
+ * the contact law of Sec. 2.1 with the wall as a fixed body, overlap
+ * delta = d - r (d the centre's distance to the wall), chord
+ * c = 2 sqrt(r^2 - d^2), normal force c E delta towards the floe, tangential
+ * force c G v_t capped at mu |f_n| with v_t the floe's contact-point velocity
+ * along the wall, spin torque r f_t; each wall contact counts as a contact.
+ * A floe whose centre passes a wall latches SP_EWALL. */
+#define SP_WALL_X 16u
 
 /* sp_params.schedule: how a cell's contact candidates are enumerated.
  * Every schedule yields the same contact set and, because each floe sums its
@@ -102,7 +120,7 @@ typedef struct {
                                  with SP_TANGENTIAL_SPRING the shear modulus (N/m^2) */
     double mu;                /* Coulomb friction coefficient */
     uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER | SP_NO_CONTINUUM |
-                                 SP_TANGENTIAL_SPRING */
+                                 SP_TANGENTIAL_SPRING | SP_WALL_X */
     int32_t schedule;         /* SP_SCHED_* */
 } sp_params;
 
@@ -492,7 +510,7 @@ typedef struct sp_gdem sp_gdem;
 typedef struct {
     double lx, ly;            /* domain size (length unit of the inputs) */
     double rho_ice, rho_ocean, cd, E, G, mu;   /* as sp_params */
-    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER */
+    uint32_t flags;           /* SP_OCEAN_OFF | SP_FORWARD_EULER | SP_WALL_X */
 } sp_gdem_params;
 
 /* Create a context on the current device (stream as sp_create).

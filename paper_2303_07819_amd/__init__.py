@@ -23,6 +23,7 @@ SP_OCEAN_OFF = 1
 SP_FORWARD_EULER = 2
 SP_NO_CONTINUUM = 4
 SP_TANGENTIAL_SPRING = 8     # tangential force as an incremental spring with contact history
+SP_WALL_X = 16               # walls in x: Dirichlet coarse boundary (Sim), floe-wall contact (GlobalDEM)
 SP_SPRING_CAP = 8            # contacts remembered per floe (SP_TANGENTIAL_SPRING)
 SP_MAX_COUPLING = 65536
 SP_MAX_STEP_BLOCK = 1024
@@ -31,7 +32,8 @@ MOMENTS_DEM, MOMENTS_CONTINUUM = 0, 1
 NMOM = 11
 TEND_FULL, TEND_RESIDUAL = 0, 1
 STATUS = {0: "SP_OK", -1: "SP_EINVAL", -2: "SP_ENOMEM", -3: "SP_EDEVICE", -4: "SP_ECFL",
-          -5: "SP_EOVERLAP", -6: "SP_ENAN", -7: "SP_ESTATE", -8: "SP_ECAPACITY"}
+          -5: "SP_EOVERLAP", -6: "SP_ENAN", -7: "SP_ESTATE", -8: "SP_ECAPACITY",
+          -9: "SP_EWALL"}
 
 EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_floes",
             "sp_set_floes_device", "sp_step", "sp_synchronize", "sp_read_moments", "sp_read_floes",

@@ -912,6 +912,7 @@ sp_status sp_closure_sample(sp_ctx* c, double dt, int32_t mode, float* x, float*
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SP_EINVAL, "dt must be positive");
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "sampling needs the continuum update");
     if (c->p.flags & SP_TANGENTIAL_SPRING) return fail(c, SP_ESTATE, "sampling runs the viscous contact law");
+    if (c->p.flags & SP_WALL_X) return fail(c, SP_ESTATE, "sampling runs on the periodic coarse grid");
     if (c->N0 > 1) return fail(c, SP_ESTATE, "sampling takes one-step tendencies (N0 = 1)");
     if (!c->have_floes) return fail(c, SP_ESTATE, "no floes");
     SP_TRY(flush_lf(c));

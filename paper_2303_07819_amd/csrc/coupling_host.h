@@ -142,7 +142,7 @@ sp_status coarse_step(sp_ctx* c, double dt)
     for (int i = 0; i < c->N1; ++i) {
         hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->cpl_mean, c->Q[i & 1],
                            c->Q[(i + 1) & 1], c->p.nx, c->p.ny, dTs, c->p.cell_lx, c->p.cell_ly, inv_area,
-                           c->cfl_bits_d, c->err_d);
+                           c->cfl_bits_d, c->err_d, wall_x(c));
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipMemcpyAsync(c->Q[(c->N1 + 1) & 1], c->Q[c->N1 & 1], (size_t)c->ncells * 4 * 8,

@@ -54,6 +54,7 @@ constexpr uint32_t kErrOverlap = 1u;
 constexpr uint32_t kErrNaN = 2u;
 constexpr uint32_t kErrCFL = 4u;
 constexpr uint32_t kErrCapacity = 8u;
+constexpr uint32_t kErrWall = 16u;
 
 enum { M_N = 0, M_MASS, M_PX, M_PY, M_L, M_UX, M_UY, M_SVX, M_SVY, M_SW, M_AICE, M_UBAR, M_VBAR };
 
@@ -512,12 +513,14 @@ struct LfNeighbours {
     int E, W, N, S;
 };
 
-__device__ __forceinline__ LfNeighbours lf_neighbours(int C, int nx, int ny)
+// With walls in x (SP_WALL_X, Sec. 4.4) the neighbour beyond the first or
+// last column is a ghost cell of zero state and zero coefficients (-1).
+__device__ __forceinline__ LfNeighbours lf_neighbours(int C, int nx, int ny, bool wall)
 {
     const int ix = C % nx, iy = C / nx;
     LfNeighbours b;
-    b.E = iy * nx + (ix + 1 == nx ? 0 : ix + 1);
-    b.W = iy * nx + (ix == 0 ? nx - 1 : ix - 1);
+    b.E = (wall && ix + 1 == nx) ? -1 : iy * nx + (ix + 1 == nx ? 0 : ix + 1);
+    b.W = (wall && ix == 0) ? -1 : iy * nx + (ix == 0 ? nx - 1 : ix - 1);
     b.N = (iy + 1 == ny ? 0 : iy + 1) * nx + ix;
     b.S = (iy == 0 ? ny - 1 : iy - 1) * nx + ix;
     return b;
@@ -527,14 +530,14 @@ __device__ __forceinline__ LfNeighbours lf_neighbours(int C, int nx, int ny)
 // 16..21 <u>_E, <u>_W, <v>_N, <v>_S, <u>_C, <v>_C; 22..24 the sources S_w,
 // S_vx, S_vy of C.
 __device__ __forceinline__ double lf_operand(int C, int t, const double* mom, const double* Q, int nx,
-                                            int ny)
+                                            int ny, bool wall)
 {
-    const LfNeighbours b = lf_neighbours(C, nx, ny);
+    const LfNeighbours b = lf_neighbours(C, nx, ny, wall);
     const int nc = nx * ny;
     if (t < 16) {
         const int k = t & 3;
         const int cell = k == 0 ? b.E : k == 1 ? b.W : k == 2 ? b.N : b.S;
-        return Q[(size_t)(t >> 2) * nc + cell];
+        return cell < 0 ? 0.0 : Q[(size_t)(t >> 2) * nc + cell];
     }
     int cell, slot;
     switch (t) {
@@ -548,7 +551,7 @@ __device__ __forceinline__ double lf_operand(int C, int t, const double* mom, co
     case 23: cell = C; slot = M_SVX; break;
     default: cell = C; slot = M_SVY; break;
     }
-    return mom[(size_t)cell * kMomStride + slot];
+    return cell < 0 ? 0.0 : mom[(size_t)cell * kMomStride + slot];
 }
 
 __device__ __forceinline__ void lf_from_ops(int C, const double* o, double* Qn, int nc, double dT, double dX,
@@ -582,11 +585,11 @@ __device__ __forceinline__ void lf_from_ops(int C, const double* o, double* Qn, 
 __device__ __forceinline__ void lf_cell(int C, const double* mom, const double* Q, double* Qn,
                                         int nx, int ny, double dT, double dX, double dY,
                                         double inv_area, unsigned long long* max_cfl_bits,
-                                        uint32_t* err)
+                                        uint32_t* err, bool wall)
 {
     double o[kLfOps];
 #pragma unroll
-    for (int t = 0; t < kLfOps; ++t) o[t] = lf_operand(C, t, mom, Q, nx, ny);
+    for (int t = 0; t < kLfOps; ++t) o[t] = lf_operand(C, t, mom, Q, nx, ny, wall);
     lf_from_ops(C, o, Qn, nx * ny, dT, dX, dY, inv_area, max_cfl_bits, err);
 }
 
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) void dem_step_kernel(StepArg
         // the continuum update of the previous level for this cell reads only
         // buffers this launch does not write: its operands are loaded now, one
         // per lane, and combined after the floes are done
-        const double lfo = (valid && a.lf && gt < kLfOps) ? lf_operand(c, gt, a.mom_prev, a.Qp, a.nx, a.ny) : 0.0;
+        const double lfo = (valid && a.lf && gt < kLfOps) ? lf_operand(c, gt, a.mom_prev, a.Qp, a.nx, a.ny, (a.flags & SP_WALL_X) != 0) : 0.0;
         // rebuild the cell's candidate lists when its floes may have moved by
         // skin / 2 since they were built (every pair then changed its distance
         // by less than the skin); the same for the whole group
@@ -1046,10 +1049,10 @@ __global__ __launch_bounds__(256) void stats_kernel(StepArgs a, const int32_t* c
 __global__ __launch_bounds__(64) void lf_kernel(const double* mom, const double* Q, double* Qn, int nx,
                                                 int ny, double dT, double dX, double dY,
                                                 double inv_area, unsigned long long* max_cfl_bits,
-                                                uint32_t* err)
+                                                uint32_t* err, int wall)
 {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
-    if (C < nx * ny) lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
+    if (C < nx * ny) lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err, wall != 0);
 }
 
 // The same update for the listed cells only (the cells without floes, which
@@ -1057,10 +1060,10 @@ __global__ __launch_bounds__(64) void lf_kernel(const double* mom, const double*
 __global__ __launch_bounds__(64) void lf_list_kernel(const int32_t* cells, int ncl, const double* mom, const double* Q,
                                                      double* Qn, int nx, int ny, double dT, double dX, double dY,
                                                      double inv_area, unsigned long long* max_cfl_bits,
-                                                     uint32_t* err)
+                                                     uint32_t* err, int wall)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ncl) lf_cell(cells[i], mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
+    if (i < ncl) lf_cell(cells[i], mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err, wall != 0);
 }
 
 __global__ void q_from_moments_kernel(const double* mom, double* Q, int nc, double inv_area)

@@ -85,6 +85,7 @@ struct GArgs {
     uint32_t flags;
     float qx, qy;
     double u0, v0;
+    double lxd;                        // domain length in x (position of the far wall with SP_WALL_X)
     double qxd, qyd, inv_qxd, inv_qyd;
     double dtd, Ed, Gd, mud, cdrho, rho_ice_d;
     Modes modes;                       // kxL, kyL per sub-bin side
@@ -211,14 +212,20 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
         const int bx = (int)gbin_axis(xl, a.nbx), by = (int)gbin_axis(yl, a.nby);
         const int oy0 = a.nby >= 3 ? -1 : 0, oy1 = a.nby >= 3 ? 1 : 0;
         const int ox0 = a.nbx >= 3 ? -1 : 0, ox1 = a.nbx >= 3 ? 1 : 0;
+        const bool wall = (a.flags & SP_WALL_X) != 0;
         for (int oy = oy0; oy <= oy1; ++oy) {
             const int byy = (by + oy + a.nby) % a.nby;
             for (int ox = ox0; ox <= ox1; ++ox) {
+                if (wall && (bx + ox < 0 || bx + ox >= a.nbx)) continue;   // no periodic image across a wall
                 const int b = byy * a.nbx + (bx + ox + a.nbx) % a.nbx;
                 const int j1 = a.bstart[b + 1];
                 for (int j = a.bstart[b]; j < j1; ++j) {
                     if (j == k) continue;
-                    const int dxi = (int)(a.xi[j] - xl), dyi = (int)(a.yi[j] - yl);
+                    // between walls the x difference is the plain one (pairs
+                    // more than half the domain apart are far from contact)
+                    const long long ddx = (long long)a.xi[j] - (long long)xl;
+                    if (wall && (ddx >= 0x80000000ll || ddx < -0x80000000ll)) continue;
+                    const int dxi = wall ? (int)ddx : (int)(a.xi[j] - xl), dyi = (int)(a.yi[j] - yl);
                     const float rj = a.r[j];
                     float diff, R2;
                     screen(dxi, dyi, rl, rj, a.qx, a.qy, diff, R2);
@@ -260,6 +267,27 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
                 }
             }
         }
+        if (wall) {
+            // the walls at x = 0 and x = lx, after the floe contacts: the
+            // contact law with a fixed body, in contact iff the centre's
+            // distance d to the wall is below r
+            const double dw[2] = {(double)xl * a.qxd, (double)(0x100000000ull - (unsigned long long)xl) * a.qxd};
+            const double sgn[2] = {-1.0, 1.0};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double d = dw[q];
+                if (!(d < rld)) continue;
+                const double cc = 2.0 * sqrt(fmax(rld * rld - d * d, 0.0));
+                const double Fn = cc * a.Ed * (d - rld);
+                const double vt = -(vld * sgn[q]) - wld * rld;     // t = (0, sgn): -v.t - w r
+                const double capf = a.mud * fabs(Fn);
+                const double Ft = fmin(fmax(cc * a.Gd * vt, -capf), capf);
+                Fx += Fn * sgn[q];
+                Fy += Ft * sgn[q];
+                T += rld * Ft;
+                ncontact += 1ull;
+            }
+        }
         // semi-implicit Euler (positions with the new velocities) unless forward Euler
         const double inv_m = 1.0 / md;
         const double dt = a.dtd;
@@ -271,6 +299,10 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
         const int sx = __double2int_rn(dt * ux * a.inv_qxd);
         const int sy = __double2int_rn(dt * vx * a.inv_qyd);
         const float un = (float)und, vn = (float)vnd, wn = (float)wnd;
+        if (wall) {
+            const long long xn = (long long)xl + sx;
+            if (xn < 0 || xn >= 0x100000000ll) atomicOr(a.err, kErrWall);
+        }
         a.xo[k] = xl + (uint32_t)sx;
         a.yo[k] = yl + (uint32_t)sy;
         a.uo[k] = un;
@@ -486,6 +518,7 @@ GArgs gargs(const sp_gdem* g, double dt, int from, int to)
     a.rho_ice_d = g->p.rho_ice;
     a.u0 = g->u0;
     a.v0 = g->v0;
+    a.lxd = g->p.lx;
     const double bx = g->p.lx / g->nbx, by = g->p.ly / g->nby;
     float reach = 0.0f;
     for (int m = 0; m < g->nmodes; ++m) {
@@ -530,6 +563,7 @@ sp_status gcheck(sp_gdem* g)
     GD_TRY(g, hipStreamSynchronize(g->stream));
     if (e & kErrOverlap) return gfail(g, SP_EOVERLAP, "two floe centres coincide");
     if (e & kErrNaN) return gfail(g, SP_ENAN, "non-finite floe state");
+    if (e & kErrWall) return gfail(g, SP_EWALL, "a floe crossed a wall");
     return SP_OK;
 }
 

@@ -161,7 +161,7 @@ __global__ void hybrid_continuum_kernel(const double* mom, const double* Q, cons
 #pragma unroll
         for (int f = 0; f < 4; ++f) Qn[(size_t)f * nc + C] = Qb[(size_t)f * nc + C] + w * (double)T[(size_t)q * 4 + f];
     } else {
-        lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err);
+        lf_cell(C, mom, Q, Qn, nx, ny, dT, dX, dY, inv_area, max_cfl_bits, err, false);   // the hybrid has no walls
     }
 }
 
@@ -487,6 +487,7 @@ sp_status sp_hybrid_set(sp_ctx* c, sp_mlp* net, const uint8_t* closure_cells, in
     if (c->p.flags & SP_NO_CONTINUUM) return fail(c, SP_ESTATE, "the hybrid needs the continuum update");
     if (c->N0 > 1) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
     if (c->p.flags & SP_TANGENTIAL_SPRING) return fail(c, SP_ESTATE, "the hybrid runs the viscous contact law");
+    if (c->p.flags & SP_WALL_X) return fail(c, SP_ESTATE, "the hybrid runs on the periodic coarse grid");
     HIP_TRY(c, hipStreamSynchronize(net->stream));   // parameters and normalisation in place
     SP_TRY(flush_lf(c));
     hybrid_free(c);

@@ -209,6 +209,9 @@ void coupling_free(sp_ctx* c);                              // coupling_host.h
 
 namespace {
 
+// Dirichlet boundary in x of the coarse model (SP_WALL_X).
+int wall_x(const sp_ctx* c) { return (c->p.flags & SP_WALL_X) ? 1 : 0; }
+
 sp_status fail(sp_ctx* ctx, sp_status st, const char* fmt, ...)
 {
     char buf[512];
@@ -431,6 +434,7 @@ sp_status check_device_err(sp_ctx* c)
     if (e & kErrOverlap) return fail(c, SP_EOVERLAP, "coincident floe centres in contact");
     if (e & kErrNaN) return fail(c, SP_ENAN, "non-finite floe state");
     if (e & kErrCapacity) return fail(c, SP_ECAPACITY, "more than %d contacts on one floe", kListCap);
+    if (e & kErrWall) return fail(c, SP_EWALL, "a floe crossed a wall");
     return fail(c, SP_ECFL, "continuum CFL number exceeded 1");
 }
 
@@ -634,7 +638,7 @@ sp_status flush_lf(sp_ctx* c)
     const int64_t k = c->kstep - 1;
     hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->momb[k & 1],
                        c->Q[k & 1], c->Q[(k + 1) & 1], c->p.nx, c->p.ny, c->lf_dt, c->p.cell_lx,
-                       c->p.cell_ly, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->cfl_bits_d, c->err_d);
+                       c->p.cell_ly, 1.0 / (c->p.cell_lx * c->p.cell_ly), c->cfl_bits_d, c->err_d, wall_x(c));
     HIP_TRY(c, hipGetLastError());
     c->lf_pending = false;
     return SP_OK;
@@ -713,7 +717,7 @@ sp_status block_chunk(sp_ctx* c, const StepArgs& base, int K, bool time_dem = fa
             const int64_t k = c->kstep + t;
             hipLaunchKernelGGL(lf_kernel, dim3((c->ncells + 63) / 64), dim3(64), 0, c->lf_stream, ring + t * slot,
                                c->Q[k & 1], c->Q[(k + 1) & 1], c->p.nx, c->p.ny, base.dtd, c->p.cell_lx,
-                               c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d);
+                               c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d, wall_x(c));
             HIP_TRY(c, hipGetLastError());
         }
         HIP_TRY(c, hipEventRecord(c->lf_done[r], c->lf_stream));
@@ -798,7 +802,7 @@ sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k)
     if (c->nempty == 0) return SP_OK;
     hipLaunchKernelGGL(lf_list_kernel, dim3((c->nempty + 63) / 64), dim3(64), 0, c->stream, c->empty_d, c->nempty,
                        c->momb[(k + 1) & 1], c->Q[(k + 1) & 1], c->Q[k & 1], c->p.nx, c->p.ny, base.dtd,
-                       c->p.cell_lx, c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d);
+                       c->p.cell_lx, c->p.cell_ly, base.inv_area, c->cfl_bits_d, c->err_d, wall_x(c));
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
