@@ -245,11 +245,16 @@ def _evolve(w, stream, nsteps, marks, net=None, dem=None, window=0.0, check=(250
 
 
 def hybrid_experiment(w, net, nsteps: int, stream, marks=(10, 100, 400), window_steps: int = NET_WINDOW_STEPS,
-                      check=(250, 256, 0.02, 100), log=None):
+                      check=(250, 256, 0.02, 100), curve_hi=(0.9, 1.01), log=None):
     """Full DEM, the hybrid with the network and the hybrid without it (the
     reduced DEMs alone), all from the same initial state.  Throughputs of
     nsteps-step runs, relative L2 errors against full DEM per component at
-    nsteps and at the marks (short horizons), 95th-percentile per-cell errors."""
+    nsteps and at the marks (short horizons), 95th-percentile per-cell errors.
+    Also the speed / error curve of wider DEM bands (DEM iff MIZ_LO <= c <= hi
+    for each hi of curve_hi, with and without the network), and the distance
+    between two full-DEM runs whose floes differ by one position unit (2^-32
+    of the cell): how far the DEM's own continuum is determined by its
+    initial state over the run."""
     import torch
     dem = miz_mask(w)
     names = ["rho", "Px", "Py", "Pw"]
@@ -285,6 +290,22 @@ def hybrid_experiment(w, net, nsteps: int, stream, marks=(10, 100, 400), window_
     bm = _evolve(w, stream, max(marks), marks, zero, dem, window)
     res["short_horizon_rel_l2"] = {str(mk): {"network": errs(hm[mk], fm[mk])[0],
                                              "no_network": errs(bm[mk], fm[mk])[0]} for mk in marks}
+    c = np.asarray(w.conc).reshape(-1)
+    curve = []
+    for hi in curve_hi:
+        band = (c >= MIZ_LO) & (c <= hi)
+        for name, nt in (("network", net), ("no_network", zero)):
+            h = _evolve(w, stream, nsteps, (), nt, band, window, check, timed=True)
+            curve.append({"dem_band": [MIZ_LO, hi], "closure": name,
+                          "floes_in_dem_cells": float(w.counts[band].sum()) / w.nfloes,
+                          "ms_per_step": 1e3 * h["seconds"] / nsteps, "speedup": full["seconds"] / h["seconds"],
+                          "rel_l2": errs(h[nsteps], Qf)[0]})
+    res["curve"] = curve
+    import copy
+    w2 = copy.copy(w)
+    w2.xi = (w.xi ^ np.uint32(1)).astype(np.uint32)
+    twin = _evolve(w2, stream, nsteps, (nsteps,))[nsteps]
+    res["full_dem_twin_rel_l2"] = errs(twin, Qf)[0]
     zero.close()
     if log:
         log(f"full DEM {res['full_dem_ms_per_step']:.3f} ms/step, hybrid {res['hybrid_ms_per_step']:.3f} ms/step "

@@ -372,30 +372,39 @@ def test_hybrid_blocked_equals_per_step(tol):
 
 
 def test_trained_closure_gains_over_the_reduced_dem_alone():
-    """A network trained here on the method's own DEM runs (three 64 x 64
-    windows, six epochs) lowers the momentum error of the hybrid against full
-    DEM on a held-out window, compared with the same hybrid without it (the
-    reduced DEMs alone), over the relaxation transient."""
+    """The network trained here as the benchmark trains it (samples of eight
+    64 x 64 windows of the method's own DEM runs, 20 epochs) lowers the error
+    of the hybrid against full DEM on a held-out window, compared with the same
+    hybrid without it (the reduced DEMs alone): the momentum error over the
+    relaxation transient (60 steps, by a factor 0.7 at least) and at the end
+    of the network's window (400 steps).  The spin error is reported and held
+    within 1.25 times the reduced DEMs' own at 400 steps: on this window the
+    network does not lower it (measured 3.5 % against 3.1 %; on the 512 x 512
+    grid it does, 8.9 % against 13.9 %)."""
     from paper_2303_07819_amd import closure as cl
     stream = torch.cuda.Stream()
-    X, T = cl.generate_samples([cl.training_workload(230307900 + k) for k in (1, 5, 7)], stream=stream.cuda_stream)
-    net, hist = cl.train(X, T, epochs=6, stream=stream.cuda_stream)
+    X, T = cl.training_set(stream=stream.cuda_stream)
+    net, hist = cl.train(X, T, stream=stream.cuda_stream)
     _say(f"training: {hist['samples']} samples, held-out loss {hist['val'][-1]:.3f}")
     assert hist["val"][-1] < 0.8
     del X, T
     w = cl.training_workload(230307993)      # held out; 3456 of 4096 cells in the ice edge band
     dem = cl.miz_mask(w)
     zero = cl.zero_network(stream.cuda_stream)
-    steps = 60
-    full = cl._evolve(w, stream, steps, (steps,))[steps]
-    with_net = cl._evolve(w, stream, steps, (steps,), net, dem, cl.NET_WINDOW_STEPS * w.dt)[steps]
-    without = cl._evolve(w, stream, steps, (steps,), zero, dem, cl.NET_WINDOW_STEPS * w.dt)[steps]
-    e_net = cl.rel_l2(with_net, full)
-    e_base = cl.rel_l2(without, full)
-    _say(f"rel L2 after {steps} steps: with network {e_net}, without {e_base}")
+    marks = (60, 400)
+    full = cl._evolve(w, stream, max(marks), marks)
+    with_net = cl._evolve(w, stream, max(marks), marks, net, dem, cl.NET_WINDOW_STEPS * w.dt)
+    without = cl._evolve(w, stream, max(marks), marks, zero, dem, cl.NET_WINDOW_STEPS * w.dt)
+    e = {mk: (cl.rel_l2(with_net[mk], full[mk]), cl.rel_l2(without[mk], full[mk])) for mk in marks}
+    for mk in marks:
+        _say(f"rel L2 after {mk} steps: with network {e[mk][0]}, without {e[mk][1]}")
+    e_net, e_base = e[60]
     # mass moves by transport alone; the closure cells' <v> differs from the
     # DEM's number average only slightly
     assert e_net[0] <= 1e-4 and e_base[0] <= 1e-4
     assert max(e_net[1], e_net[2]) < 0.7 * max(e_base[1], e_base[2])
+    e_net, e_base = e[400]
+    assert max(e_net[1], e_net[2]) < 0.7 * max(e_base[1], e_base[2])
+    assert e_net[3] <= 1.25 * e_base[3]
     net.close()
     zero.close()
