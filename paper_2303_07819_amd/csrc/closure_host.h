@@ -346,8 +346,8 @@ struct sp_mlp {
     std::string err;
     float* theta = nullptr;      // FP32 master parameters
     uint16_t* theta_h = nullptr; // bfloat16 copy read by the matrix products
-    spmlp::bf16x4* wsw = nullptr; // weight tiles of the fused forward (swizzled theta_h)
-    bool wsw_stale = true;       // theta_h changed since wsw was made
+    unsigned char* wsw = nullptr; // LDS image of the fused forward (kFwdLds bytes: weight tiles, biases, norm)
+    bool wsw_stale = true;        // parameters or normalisation changed since wsw was made
     float* m = nullptr;          // Adam moments
     float* v = nullptr;
     float* grad = nullptr;
@@ -536,15 +536,15 @@ sp_status mlp_infer(sp_mlp* mm, const float* x, int64_t M, float* y, hipStream_t
 {
     if (M <= 0) return SP_OK;
     if (mm->wsw_stale) {
-        hipLaunchKernelGGL(swizzle_weights_kernel, dim3(kFwdTiles * 64 / 256), dim3(256), 0, stream, mm->theta_h,
-                           mm->wsw);
+        hipLaunchKernelGGL(stage_forward_kernel, dim3((kFwdStageThreads + 255) / 256), dim3(256), 0, stream,
+                           mm->theta_h, mm->theta, mm->norm, mm->wsw);
         MLP_HIP(mm, hipGetLastError());
         mm->wsw_stale = false;
     }
     const int64_t per_block = (int64_t)kFwdWaves * 16;
     const int64_t blocks = std::min<int64_t>((M + per_block - 1) / per_block, 2 * (int64_t)mm->num_cus);
     hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(64 * kFwdWaves), kFwdLds, stream, x,
-                       (long)M, mm->wsw, mm->theta, mm->norm, y);
+                       (long)M, mm->wsw, y);
     MLP_HIP(mm, hipGetLastError());
     return SP_OK;
 }
@@ -635,7 +635,7 @@ sp_status sp_mlp_create(void* stream, sp_mlp** out)
         st = SP_EDEVICE;
     if (!st) st = malloc_m(mm, &mm->theta, kNParams);
     if (!st) st = malloc_m(mm, &mm->theta_h, kNParams);
-    if (!st) st = malloc_m(mm, &mm->wsw, (size_t)kFwdTiles * 64);
+    if (!st) st = malloc_m(mm, &mm->wsw, kFwdLds);
     if (!st) st = malloc_m(mm, &mm->m, kNParams);
     if (!st) st = malloc_m(mm, &mm->v, kNParams);
     if (!st) st = malloc_m(mm, &mm->grad, kNParams);
@@ -716,6 +716,7 @@ sp_status sp_mlp_set_norm(sp_mlp* mm, const float* x_mean, const float* x_std, c
     }
     MLP_HIP(mm, hipMemcpyAsync(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice, mm->stream));
     MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    mm->wsw_stale = true;
     return SP_OK;
 }
 
@@ -752,6 +753,7 @@ sp_status sp_mlp_fit_norm(sp_mlp* mm, const float* X, const float* T, int64_t n)
     for (int i = 0; i < kOut; ++i)
         if (nrm[2 * kIn + kOut + i] == 0.0f) nrm[2 * kIn + kOut + i] = 1.0f;
     MLP_HIP(mm, hipMemcpy(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice));
+    mm->wsw_stale = true;
     return SP_OK;
 }
 

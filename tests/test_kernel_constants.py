@@ -7,11 +7,16 @@ when the host selects the direct path, where sin d and cos d come from two
 fixed polynomials.  Their coefficients are read from the kernel source and
 the polynomials evaluated like the kernel does (FP32 fused multiply-adds),
 then compared with numpy's sin and cos in FP64.
+
+The closure MLP's GELU takes the normal tail erfc(|z| / sqrt 2) as a base-2
+exponential of a fitted polynomial; its constants are read the same way and
+the GELU evaluated like the kernel, against scipy's erf.
 """
 import os
 import re
 
 import numpy as np
+import pytest
 
 SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2303_07819_amd", "csrc", "dem_kernels.h")
 
@@ -73,3 +78,68 @@ def test_direct_sincos_approximation_error_in_fp64():
     # the sin error equioscillates (a minimax polynomial): extrema of both signs
     e = s - np.sin(x)
     assert e.max() > 3e-8 and e.min() < -3e-8
+
+
+# ------------------------------------------------------------ GELU of the MLP
+MLP_SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2303_07819_amd", "csrc", "mlp_kernels.h")
+
+
+def _erfc_tail_constants():
+    """(scale, coefficients of R from the highest degree down to degree 1)."""
+    text = open(MLP_SRC).read()
+    body = text[text.index("float erfc_tail("):]
+    body = body[:body.index("\n}\n")]
+    lits = [float(x) for x in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
+    return np.float32(lits[0]), np.float32(lits[1:])
+
+
+def _twice_gelu32(z):
+    """twice_gelu evaluated like the kernel: FP32 multiplies and fused
+    multiply-adds, the base-2 exponential correctly rounded."""
+    a, c = _erfc_tail_constants()
+    z = z.astype(np.float32)
+    az = np.abs(z)
+    s = np.float32(az * a)
+    q = np.full_like(s, c[0])
+    for cc in c[1:]:
+        q = _fma32(q, s, np.full_like(s, cc))
+    e = np.float32(s * np.float32(q - s))
+    E = np.float32(np.exp2(e.astype(np.float64)))
+    return _fma32(-az, E, np.float32(z + az)), E
+
+
+def test_erfc_tail_scale_and_degree():
+    from scipy.special import erfc
+    a, c = _erfc_tail_constants()
+    assert a == np.float32(np.sqrt(0.5 / np.log(2.0)))
+    assert len(c) == 7 and c[0] < 0.0                   # degree 7, falling past the fit range
+    # R'(0) = log2(e) P'(0) / sqrt(log2 e), P'(0) = d/dx log erfc(x) at 0 = -2 / sqrt(pi)
+    assert c[-1] == pytest.approx(-2.0 / np.sqrt(np.pi) * np.sqrt(1.0 / np.log(2.0)), rel=2e-3)
+    # the polynomial in FP64: erfc(x) = exp(-x^2 + P(x)) within 4e-6 relative on [0, 4]
+    x = np.linspace(0.0, 4.0, 200001)
+    s = x * np.sqrt(1.0 / np.log(2.0))
+    q = np.zeros_like(s)
+    for cc in c:
+        q = q * s + float(cc)
+    E = np.exp2(s * (q - s))
+    assert np.max(np.abs(E / erfc(x) - 1.0)) < 4e-6
+
+
+def test_gelu_in_fp32_is_within_7e_7_for_every_z():
+    from scipy.special import erf
+    z = np.concatenate([np.linspace(-12.0, 12.0, 800001), -np.geomspace(12.0, 1e30, 2001),
+                        np.geomspace(12.0, 1e30, 2001)]).astype(np.float32)
+    with np.errstate(over="ignore"):                  # s^7 overflows to -inf far out, as on the GPU
+        g2, E = _twice_gelu32(z)
+    zz = z.astype(np.float64)
+    exact = 0.5 * zz * (1.0 + erf(zz / np.sqrt(2.0)))
+    g = 0.5 * g2.astype(np.float64)
+    assert not np.isnan(g).any()
+    inner = np.abs(zz) <= 12.0
+    assert np.max(np.abs(g - exact)[inner]) < 7e-7
+    # relative on the positive side, and the tail vanishes (not NaN or growing) far out
+    pos = zz > 0.05
+    m = pos & inner
+    assert np.max(np.abs(g[m] - exact[m]) / exact[m]) < 4e-6
+    assert np.all(E[np.abs(zz) > 6.0] < 1e-8)
+    assert g2[zz == 0.0].max() == 0.0
