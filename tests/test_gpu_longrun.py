@@ -2,7 +2,7 @@
 plain 64 x 64 workload (cells of 25 km, 1,048,576 floes, 256 per cell, dt =
 30 s) over 10^4 steps, well into its dense phase.
 
-1. The run stays sound: every floe finite and inside its cell's domain, floe
+1. The run stays sound: every floe finite, radii unchanged, floe
    counts, mass and ice area per cell unchanged.
 2. Late-state parity: the GPU state at step 9000 is saved; ten steps from it
    on the GPU against ten oracle steps of 64 sampled cells restarted from that
