@@ -549,29 +549,32 @@ def coupled_leg(stream, N0=100, N1=1, n_t=10, windows=5):
 
 def spring_leg(stream, steps=200, warmup=20, G_shear=80.0):
     """plain64 with the tangential force as the incremental spring
-    (SP_TANGENTIAL_SPRING, G read as a shear modulus of 80 N/m^2): one DEM launch
-    per step reading and rewriting every floe's contact history, timed with HIP
-    events over `steps` steps after `warmup`; dem_ms from the library's own
-    events around the DEM launches."""
+    (SP_TANGENTIAL_SPRING, G read as a shear modulus of 80 N/m^2): every floe's
+    contact history read and rewritten with its contacts, in blocked launches
+    of 32 steps (history staged in LDS) and in one launch per step, each timed
+    with HIP events over `steps` steps after `warmup`; dem_ms from the
+    library's own events around the DEM launches."""
     import torch
     import fixtures
     import paper_2303_07819_amd as sp
     w = fixtures.make_config("plain64")
     w.G = G_shear
-    with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, stream=stream.cuda_stream) as sim:
-        sim.step(w.dt, warmup)
-        sim.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sim.step(w.dt, steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        dem_ms, _ = sim.profile_steps(w.dt, 32)
-        contacts = sim.stats()["contacts"]
-    return {"workload": "plain64", "G_shear": G_shear, "steps": steps, "ms_per_step": ms,
-            "dem_kernel_ms_per_step": dem_ms, "floe_steps_per_s": w.nfloes / (ms * 1e-3),
-            "contacts_total": contacts}
+    out = {"workload": "plain64", "G_shear": G_shear, "steps": steps}
+    for name, k in (("blocked", 32), ("per_step", 1)):
+        with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, stream=stream.cuda_stream) as sim:
+            sim.set_step_block(k)
+            sim.step(w.dt, warmup)
+            sim.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.step(w.dt, steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            dem_ms, _ = sim.profile_steps(w.dt, 32)
+            out[name] = {"step_block": k, "ms_per_step": ms, "dem_kernel_ms_per_step": dem_ms,
+                         "floe_steps_per_s": w.nfloes / (ms * 1e-3), "contacts_total": sim.stats()["contacts"]}
+    return out
 
 
 def scenario_leg(stream, ks=(1, 2, 3, 4)):

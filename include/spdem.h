@@ -62,9 +62,13 @@ typedef enum {
  * c G xi t with G read as a shear modulus (N/m^2), and where |c G xi| would
  * pass mu |f_n| the contact slips: the force takes the Coulomb limit and xi
  * the displacement that gives it.  History: SP_SPRING_CAP contacts per floe
- * (SP_ECAPACITY beyond), kept in device memory.  Runs one DEM launch per
- * step; not with N0 > 1, the hybrid, closure sampling or the autotuner
- * (SP_ESTATE). */
+ * (SP_ECAPACITY beyond), kept in device memory and, in blocked launches
+ * (sp_set_step_block, the coupled cadence of sp_set_coupling), staged in LDS
+ * for the block (80 B per floe more per cell): the same floe state bit for
+ * bit as one launch per step.  The plain step falls back to one launch per
+ * step when some cell's blocked launch would not fit the 160 KB of LDS; the
+ * coupled cadence returns SP_ECAPACITY there.  Not with the hybrid, closure
+ * sampling or the autotuner (SP_ESTATE). */
 #define SP_TANGENTIAL_SPRING 8u
 #define SP_SPRING_CAP 8
 /* Walls at x = 0 and at the far x edge, the boundary of the paper's
@@ -336,6 +340,7 @@ sp_status sp_get_block_waves(sp_ctx* ctx, int32_t* waves);
  * coarse-to-fine updates, the hybrid its DEM cells between checks: see
  * sp_set_coupling and sp_step_hybrid).  The floe state is the same
  * bit for bit as with k = 1; statistics are summed in another fixed order.
+ * With SP_TANGENTIAL_SPRING the contact history is staged in LDS as well.
  * Ring: k x ncells x 128 B.  Default 32.  Errors: SP_EINVAL (k outside
  * [1, SP_MAX_STEP_BLOCK]). */
 #define SP_MAX_STEP_BLOCK 1024

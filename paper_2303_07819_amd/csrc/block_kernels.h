@@ -15,6 +15,11 @@
 // inverse mass and inverse m r^2 are computed once per launch and kept in LDS.
 // Contacts and candidate tests (list entries examined, for the VALU accounting
 // of the step) are counted per lane over the block and reduced once.
+// TSP: the tangential spring (SP_TANGENTIAL_SPRING); each floe's contact
+// history (partners and displacements, the per-step kernel's table) is staged
+// in LDS at the end of the group's memory for the block, read before the
+// floe's contacts of a step and rewritten with them exactly as the per-step
+// kernel does, and written back once.
 #pragma once
 
 namespace spdem {
@@ -66,7 +71,7 @@ __device__ __forceinline__ float group_max(float x, float* wmax_g, int gt)
 // and five resident waves with a few spilled registers beat three without.
 // W = 16 (cells of up to 1024 floes) fills a compute unit's LDS with one cell:
 // four waves per SIMD, the register file without spills.
-template <int SCHED, int W>
+template <int SCHED, int W, bool TSP = false>
 __global__ __launch_bounds__(W >= 4 ? 64 * W : 256) __attribute__((amdgpu_waves_per_eu(W >= 16 ? 4 : 5)))
 void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 {
@@ -99,6 +104,9 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
     int* rank = binof + cap;
     int* bcnt = cnt + cap;
     int* bstart = bcnt + (SCHED == 2 ? a.nbx * a.nby : 0);
+    // contact history (TSP): displacements [cap][SP_SPRING_CAP], then partners [cap]
+    double* const HX = TSP ? reinterpret_cast<double*>(gsm + a.group_bytes - (size_t)cap * kSpringBytes) : nullptr;
+    uint4* const HJ = TSP ? reinterpret_cast<uint4*>(HX + (size_t)cap * SP_SPRING_CAP) : nullptr;
 
     const int item = blockIdx.x * gpb + g;
     const bool valid = item < a.ncl;
@@ -119,6 +127,11 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
             const double rld = (double)a.r[s + gt];
             const double md = a.rho_ice_d * (double)a.h[s + gt] * kPi * rld * rld;
             IM[gt] = make_double2(1.0 / md, 1.0 / (md * (rld * rld)));
+        }
+        if (TSP) {
+            HJ[gt] = a.tsp_j[s + gt];
+#pragma unroll
+            for (int q = 0; q < SP_SPRING_CAP; ++q) HX[gt * SP_SPRING_CAP + q] = a.tsp_x[(size_t)(s + gt) * SP_SPRING_CAP + q];
         }
         if (vd <= 0.5f * a.skin) {   // the kept lists are valid for the first step
             const int k = a.vcount[s + gt];
@@ -283,20 +296,54 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
             }
             // ---- contact forces and torques in ascending partner order (FP64)
             double Fx = fdx, Fy = fdy, T = tdr;
+            // the floe's contact history (TSP), rewritten below with this step's contacts
+            uint4 hj = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+            double hx[SP_SPRING_CAP];
+            uint16_t* const tj = TSP ? reinterpret_cast<uint16_t*>(HJ + l) : nullptr;
+            double* const tx = TSP ? HX + (size_t)l * SP_SPRING_CAP : nullptr;
+            bool had = false;   // the floe was in contact after the previous step
+            if (TSP) {
+                hj = HJ[l];
+                had = (hj.x & hj.y & hj.z & hj.w) != 0xffffffffu;
+#pragma unroll
+                for (int q = 0; q < SP_SPRING_CAP; ++q) hx[q] = had ? tx[q] : 0.0;
+            }
+            int nh = 0;
             while (cmask) {
                 const int q = __builtin_ctz(cmask);
                 cmask &= cmask - 1u;
                 const int j = my[q];
                 const uint4 pj = P[j];
-                double cx, cy, ct;
-                if (!contact_terms((int)(pj.x - pl.x), (int)(pj.y - pl.y), rld, uld, vld, wld, __uint_as_float(pj.z),
-                                   V[j], l < j, a, cx, cy, ct)) {
+                double cx, cy, ct, xi = 0.0, xi_old = 0.0;
+                if (TSP) {
+#pragma unroll
+                    for (int e = 0; e < SP_SPRING_CAP; ++e) {
+                        const uint32_t wv = e < 2 ? hj.x : e < 4 ? hj.y : e < 6 ? hj.z : hj.w;
+                        if ((int)((wv >> (16 * (e & 1))) & 0xffffu) == j) xi_old = hx[e];
+                    }
+                }
+                if (!contact_terms<TSP>((int)(pj.x - pl.x), (int)(pj.y - pl.y), rld, uld, vld, wld,
+                                        __uint_as_float(pj.z), V[j], l < j, a, cx, cy, ct, xi_old, &xi)) {
                     atomicOr(a.err, kErrOverlap);
                     continue;
+                }
+                if (TSP) {
+                    if (nh < SP_SPRING_CAP) {
+                        tj[nh] = (uint16_t)j;
+                        tx[nh] = xi;
+                    } else {
+                        atomicOr(a.err, kErrCapacity);
+                    }
+                    ++nh;
                 }
                 add_terms(Fx, Fy, T, cx, cy, ct);
                 my_contacts += (l < j) ? 1u : 0u;
             }
+            if (TSP && (had || nh > 0))   // a floe out of contact before and now keeps its empty table
+                for (int e = nh; e < SP_SPRING_CAP; ++e) {
+                    tj[e] = 0xffffu;
+                    tx[e] = 0.0;
+                }
             const double2 im = IM[l];
             const double inv_m = im.x, inv_i = im.y;
             const double md = a.rho_ice_d * (double)vv.w * kPi * rld * rld;
@@ -433,6 +480,11 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         a.u[s + gt] = v.x;
         a.v[s + gt] = v.y;
         a.w[s + gt] = v.z;
+        if (TSP) {
+            a.tsp_j[s + gt] = HJ[gt];
+#pragma unroll
+            for (int q = 0; q < SP_SPRING_CAP; ++q) a.tsp_x[(size_t)(s + gt) * SP_SPRING_CAP + q] = HX[gt * SP_SPRING_CAP + q];
+        }
         if (rebuilt) {
             const int k = cnt[gt];
             const uint16_t* my = lst + (size_t)gt * kListCap;

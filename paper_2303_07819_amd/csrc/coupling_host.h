@@ -186,10 +186,13 @@ sp_status nudge(sp_ctx* c, double frac)
 // cell's own X0 and Q: with a step block above one, each stretch up to the
 // next update or coarse step runs as one blocked launch per bucket (the floes
 // resident in LDS, one per lane), the update done in the same launch.
-sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
+sp_status coupled_steps(sp_ctx* c, const StepArgs& args, int64_t nsteps)
 {
     SP_TRY(coupling_prepare(c));
     const size_t slot = (size_t)c->ncells * kMomStride;
+    // the step arguments, made again after every coarse step: its re-plan of
+    // the contact search changes the sub-bins, the skin and the list buffers
+    StepArgs base = args;
     if (c->block_k > 1) {
         int64_t left = nsteps;
         while (left > 0) {
@@ -220,7 +223,10 @@ sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
                 c->cpl_nudges++;
                 c->desc_stale = true;
             }
-            if (rend == 0) SP_TRY(coarse_step(c, base.dtd));
+            if (rend == 0) {
+                SP_TRY(coarse_step(c, base.dtd));
+                base = make_args(c, base.dtd);
+            }
         }
         return SP_OK;
     }
@@ -233,6 +239,7 @@ sp_status coupled_steps(sp_ctx* c, const StepArgs& base, int64_t nsteps)
         const int64_t r = c->cpl_j % c->N0;
         if (r == 0) {
             SP_TRY(coarse_step(c, base.dtd));
+            base = make_args(c, base.dtd);
         } else if (c->cpl_j > c->N0 && r % c->n_t == 0) {
             SP_TRY(nudge(c, (double)r / (double)c->N0));
         }
@@ -249,8 +256,6 @@ sp_status sp_set_coupling(sp_ctx* c, int32_t N0, int32_t N1, int32_t n_t)
         return fail(c, SP_EINVAL, "N0, N1 and n_t must be >= 1 and N0, N1 <= %d", SP_MAX_COUPLING);
     if (N0 > 1 && (c->p.flags & SP_NO_CONTINUUM)) return fail(c, SP_ESTATE, "coupling needs the continuum update");
     if (N0 > 1 && c->hyb) return fail(c, SP_ESTATE, "the hybrid step runs with N0 = 1");
-    if (N0 > 1 && (c->p.flags & SP_TANGENTIAL_SPRING))
-        return fail(c, SP_ESTATE, "the tangential spring runs with N0 = 1");
     SP_TRY(flush_lf(c));
     drop_graph(c);
     const bool was = c->N0 > 1;

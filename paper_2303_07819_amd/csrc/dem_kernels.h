@@ -48,6 +48,7 @@ constexpr int kMaxBinsSide = 32;
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kGuard = 1.0f / 524288.0f;  // 2^-19
 constexpr int kDyn = 8;                 // statistics reduced by every step
+constexpr int kSpringBytes = SP_SPRING_CAP * 8 + 16;   // LDS per floe of a blocked spring launch's contact history
 
 // device fault bits
 constexpr uint32_t kErrOverlap = 1u;

@@ -503,16 +503,24 @@ sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads,
     SP_DISPATCH(prepare_t, c, threads, lds, cap, resident)
 }
 
+template <int SCHED, int W, bool TSP>
+sp_status launch_block_tt(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K,
+                          const BlockNudge& nd)
+{
+    if (lds > 65536)
+        HIP_TRY(c, hipFuncSetAttribute((const void*)dem_block_kernel<SCHED, W, TSP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((dem_block_kernel<SCHED, W, TSP>), dim3(grid), dim3(threads), lds, c->stream, a, K, nd);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
 template <int SCHED, int W>
 sp_status launch_block_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K,
                          const BlockNudge& nd)
 {
-    if (lds > 65536)
-        HIP_TRY(c, hipFuncSetAttribute((const void*)dem_block_kernel<SCHED, W>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((dem_block_kernel<SCHED, W>), dim3(grid), dim3(threads), lds, c->stream, a, K, nd);
-    HIP_TRY(c, hipGetLastError());
-    return SP_OK;
+    if (a.flags & SP_TANGENTIAL_SPRING) return launch_block_tt<SCHED, W, true>(c, a, grid, threads, lds, K, nd);
+    return launch_block_tt<SCHED, W, false>(c, a, grid, threads, lds, K, nd);
 }
 
 sp_status launch_block_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, int grid, int threads, size_t lds,
@@ -588,6 +596,18 @@ int block_waves(const Bucket& b)
     return b.cap <= 512 ? 8 : 16;
 }
 
+// LDS of one cell of a blocked launch: the per-step layout, 1 / m and
+// 1 / (m r^2) per floe beside the state, and with the tangential spring the
+// floes' contact history.
+constexpr size_t kBlockLdsMax = 160 * 1024;
+
+size_t block_group_bytes(const sp_ctx* c, int cap, int waves)
+{
+    size_t b = group_bytes(c->sched, cap, c->nbx * c->nby, waves) + (size_t)cap * 16;
+    if (c->p.flags & SP_TANGENTIAL_SPRING) b += (size_t)cap * kSpringBytes;
+    return b;
+}
+
 // K steps from level kstep as one blocked launch per bucket (of bk, default the
 // context's buckets), the statistics of step t into mom + t * (ncells x
 // kMomStride) (work entries flagged for mom_alt: there); with an active nd, the
@@ -601,8 +621,9 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
         if (b.cells_h.empty()) continue;
         const int w = block_waves(b);
         if (b.cap > 64 * w) return fail(c, SP_EINVAL, "%d floes per cell exceed a blocked launch", b.cap);
-        // the blocked kernel keeps 1 / m and 1 / (m r^2) per floe beside the state
-        const size_t gbytes = group_bytes(c->sched, b.cap, c->nbx * c->nby, w) + (size_t)b.cap * 16;
+        const size_t gbytes = block_group_bytes(c, b.cap, w);
+        if (gbytes > kBlockLdsMax)
+            return fail(c, SP_ECAPACITY, "%d floes per cell exceed the LDS of a blocked launch", b.cap);
         const int gpb = groups_per_block(w, gbytes);
         StepArgs a = base;
         a.work = b.work_d;
@@ -648,7 +669,12 @@ sp_status flush_lf(sp_ctx* c)
 // and no hybrid (the coupled cadence and the hybrid block on their own terms).
 bool block_eligible(const sp_ctx* c)
 {
-    return c->block_k > 1 && c->N0 == 1 && !c->hyb && !(c->p.flags & SP_TANGENTIAL_SPRING);
+    if (!(c->block_k > 1 && c->N0 == 1 && !c->hyb)) return false;
+    // with the tangential spring, while every bucket's cells fit a blocked launch's LDS
+    if (c->p.flags & SP_TANGENTIAL_SPRING)
+        for (const auto& b : c->bk)
+            if (!b.cells_h.empty() && block_group_bytes(c, b.cap, block_waves(b)) > kBlockLdsMax) return false;
+    return true;
 }
 
 // Make the library stream wait for the continuum updates of the last block

@@ -37,7 +37,8 @@ def _equal(a, b):
 
 
 @pytest.mark.parametrize("name,k,flags", [("small", 32, 0), ("dense", 32, 0), ("dense", 1, 0), ("dense", 4, 0),
-                                          ("small", 1, 0), ("dense", 1, sp.SP_TANGENTIAL_SPRING)])
+                                          ("small", 1, 0), ("dense", 1, sp.SP_TANGENTIAL_SPRING),
+                                          ("dense", 32, sp.SP_TANGENTIAL_SPRING)])
 def test_resumed_run_equals_straight_run(tmp_path, name, k, flags):
     w = fixtures.make_config(0) if name == "small" else dense_workload(seed=3)
     if flags & sp.SP_TANGENTIAL_SPRING:

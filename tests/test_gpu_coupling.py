@@ -241,3 +241,25 @@ def test_full_size_plain64_first_coarse_step_and_nudge():
         e = np.abs(got - ref) / np.maximum(np.abs(ref), FLOOR * np.sqrt(np.mean(gq ** 2, axis=0)))
         _say(f"  cell ({cx},{cy}) coarse state rel err {e.max():.2e}")
         assert e.max() <= TOL
+
+
+@pytest.mark.parametrize("block", [32, 1])
+def test_one_call_equals_many_calls_across_a_replan(block):
+    """The ragged workload re-plans its contact search (larger sub-bins and
+    skin, new list buffers) at the first coarse step (N0 = 3): 5 steps in one
+    sp_step call and in 5 calls of one step give the same floes bit for bit,
+    so the steps after a re-plan inside a call use the new plan."""
+    w = ragged_workload()
+    out = []
+    for calls in ((5,), (1,) * 5):
+        with sp.Sim.from_workload(w) as s:
+            s.set_step_block(block)
+            s.set_coupling(3, 1, 1)
+            for n in calls:
+                s.step(w.dt, n)
+            out.append((s.read_floes(), s.coupling()))
+    (fa, ca), (fb, cb) = out
+    _say(f"  block={block}: {ca}")
+    assert ca["replans"] >= 1 and ca == cb
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k

@@ -1,12 +1,15 @@
 """The tangential spring (SP_TANGENTIAL_SPRING: the incremental Cundall-Strack
 reading of the tangential contact force with per-contact history) on the GPU
-against the oracle's spring (needs an MI355X).
+against the oracle's spring (needs an MI355X): blocked launches (the default,
+history staged in LDS), one launch per step, and the coupled cadence.
 
 Bars: those of test_gpu_parity (1e-5 after 1 and 10 steps, with the storage
 floors of metrics.storage_floors); per-floe velocities of a two-floe contact
 within 5e-5 of the oracle over a whole 60-step encounter (no slip, then slip:
-the FP32 storage of the state, rounded every step, accumulates over it).  G is read as
-the shear modulus: 80 N/m^2 against E = 200 (E / (2 (1 + 0.25))).
+the FP32 storage of the state, rounded every step, accumulates over it);
+blocked and per-step floe states equal bit for bit; the coupled cadence at
+the bars of test_gpu_coupling.  G is read as the shear modulus: 80 N/m^2
+against E = 200 (E / (2 (1 + 0.25))).
 """
 import numpy as np
 import pytest
@@ -14,7 +17,7 @@ import pytest
 import fixtures
 import oracle
 from metrics import TOL, rel_err, storage_floors
-from storage import run_plain_stored
+from storage import run_coupled_stored, run_plain_stored
 from workloads import dense_workload
 
 pytestmark = pytest.mark.gpu
@@ -28,31 +31,82 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _compare(w, nsteps, schedule, tol):
+def _compare(w, nsteps, schedule, tol, block=32):
     st, Q, mom, _ = oracle.run_plain(w, nsteps, flags=oracle.SPRING)
     Qs, moms = run_plain_stored(w, nsteps, flags=oracle.SPRING)
     with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, schedule=schedule) as s:
-        assert not s.step_block()[1]
+        s.set_step_block(block)
+        assert s.step_block()[1] == (block > 1)
         s.step(w.dt, nsteps)
         gm = s.read_moments(sp.MOMENTS_DEM)
         gq = s.read_moments(sp.MOMENTS_CONTINUUM)
         f = s.read_floes()
         stats = s.stats()
     e_m, e_q = rel_err(gm, mom, storage_floors(mom, moms)), rel_err(gq, Q, storage_floors(Q, Qs))
-    _say(f"spring {w.name} steps={nsteps} sched={schedule}: moments {e_m.max():.2e} continuum {e_q.max():.2e} "
-         f"contacts {stats['contacts']}")
+    _say(f"spring {w.name} steps={nsteps} sched={schedule} block={block}: moments {e_m.max():.2e} "
+         f"continuum {e_q.max():.2e} contacts {stats['contacts']}")
     assert e_m.max() <= tol, np.unravel_index(e_m.argmax(), e_m.shape)
     assert e_q.max() <= tol, np.unravel_index(e_q.argmax(), e_q.shape)
     return st, f, stats
 
 
+@pytest.mark.parametrize("block", [1, 32])
 @pytest.mark.parametrize("nsteps", [1, 10])
 @pytest.mark.parametrize("schedule", [sp.SCHED_ALLPAIRS, sp.SCHED_BINNED])
-def test_dense_contacts_spring_parity(nsteps, schedule):
+def test_dense_contacts_spring_parity(nsteps, schedule, block):
     w = dense_workload(seed=21)
     w.G = G_SHEAR
-    _, _, stats = _compare(w, nsteps, schedule, TOL)
+    _, _, stats = _compare(w, nsteps, schedule, TOL, block)
     assert nsteps == 1 or stats["contacts"] > 0   # floes are placed apart
+
+
+@pytest.mark.parametrize("schedule", [sp.SCHED_ALLPAIRS, sp.SCHED_BINNED])
+def test_blocked_spring_equals_per_step_spring_bit_for_bit(schedule):
+    """70 steps (two blocks of 32 and one of 6) against 70 launches of one
+    step: the floe state after every call equal bit for bit, the contact count
+    equal; the histories are then equal too, or later forces would differ."""
+    w = dense_workload(seed=23)
+    w.G = G_SHEAR
+    with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, schedule=schedule) as b, \
+            sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING, schedule=schedule) as p:
+        p.set_step_block(1)
+        assert b.step_block()[1] and not p.step_block()[1]
+        for n in (32, 32, 6):
+            b.step(w.dt, n)
+            p.step(w.dt, n)
+            fb, fp = b.read_floes(), p.read_floes()
+            for k in fb:
+                assert np.array_equal(fb[k], fp[k]), k
+            assert b.stats()["contacts"] == p.stats()["contacts"]
+        assert b.work()["blocked_steps"] == 70
+        _say(f"blocked spring sched={schedule}: 70 steps equal bit for bit, contacts {b.stats()['contacts']}")
+        assert b.stats()["contacts"] > 0
+        mb, mp = b.read_moments(sp.MOMENTS_DEM), p.read_moments(sp.MOMENTS_DEM)
+        assert rel_err(mb, mp).max() <= 1e-12
+
+
+@pytest.mark.parametrize("nsteps,N0,N1,n_t", [(13, 4, 2, 2), (9, 3, 3, 1)])
+def test_coupled_spring_parity(nsteps, N0, N1, n_t):
+    """The coupled cadence (blocked launches between coarse-to-fine updates)
+    with the spring against oracle.run_coupled with SPRING."""
+    w = dense_workload(seed=24)
+    w.G = G_SHEAR
+    st, Q, mom, _ = oracle.run_coupled(w, nsteps, N0, N1, n_t, flags=oracle.SPRING)
+    Qs, moms = run_coupled_stored(w, nsteps, N0, N1, n_t, flags=oracle.SPRING)
+    with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING) as s:
+        s.set_coupling(N0, N1, n_t)
+        s.step(w.dt, nsteps)
+        gm = s.read_moments(sp.MOMENTS_DEM)
+        gq = s.read_moments(sp.MOMENTS_CONTINUUM)
+        cp = s.coupling()
+        contacts = s.stats()["contacts"]
+    e_m = rel_err(gm, mom, storage_floors(mom, moms))
+    e_q = rel_err(gq, Q, storage_floors(Q, Qs))
+    _say(f"coupled spring steps={nsteps} N0={N0} N1={N1} n_t={n_t}: moments {e_m.max():.2e} "
+         f"continuum {e_q.max():.2e} contacts {contacts} {cp}")
+    assert cp["nudges"] > 0 and contacts > 0
+    assert np.array_equal(gm[:, 0], mom[:, 0])
+    assert e_m.max() <= TOL and e_q.max() <= TOL
 
 
 def test_spring_differs_from_the_viscous_law():
@@ -97,9 +151,14 @@ def test_two_floe_encounter_per_floe(mu):
 def test_spring_entry_point_limits():
     w = fixtures.make_config(0)
     with sp.Sim.from_workload(w, flags=sp.SP_TANGENTIAL_SPRING) as s:
-        assert not s.step_block()[1]
-        with pytest.raises(sp.SpdemError):
-            s.set_coupling(100, 1, 10)
-        with pytest.raises(sp.SpdemError):
+        assert s.step_block()[1]
+        with pytest.raises(sp.SpdemError) as ei:
             s.autotune(w.dt)
+        assert ei.value.status == -7
+        net = sp.MLP()
+        with pytest.raises(sp.SpdemError) as ei:
+            s.hybrid_set(net, np.ones(w.ncells, bool))
+        assert ei.value.status == -7
+        net.close()
+        s.set_coupling(4, 1, 2)
         s.step(w.dt, 3)
