@@ -507,9 +507,11 @@ sp_status sp_get_schedule(sp_ctx* ctx, int32_t* schedule, int32_t* bins_x, int32
  * every pair a potential contact.  Positions are unsigned 32-bit fractions of
  * the domain: X = lx * xi / 2^32; the ocean is evaluated at X as for sp_ctx.
  * Contacts are searched in sub-bins of side >= 2 r_max (3 x 3 sweep, one
- * sub-bin along an axis with fewer than 3), re-binned every step by a stable
- * radix sort; decisions and forces match the cell DEM's.  Statistics for any
- * coarse grid are read with sp_gdem_coarse_moments. */
+ * sub-bin along an axis with fewer than 3), re-binned before every step by a
+ * stable counting sort (the order a stable sort by sub-bin of the current
+ * order gives; one launch, the counts made by the previous step's launch);
+ * decisions and forces match the cell DEM's.  Statistics for any coarse grid
+ * are read with sp_gdem_coarse_moments. */
 typedef struct sp_gdem sp_gdem;
 
 typedef struct {
@@ -551,6 +553,13 @@ sp_status sp_gdem_coarse_moments(sp_gdem* g, int32_t nxc, int32_t nyc, double* o
  * sub-bins per side.  Synchronises. */
 sp_status sp_gdem_get_stats(sp_gdem* g, int64_t* contacts, int64_t* steps, int32_t* bins_x,
                             int32_t* bins_y);
+/* Debug/test call: the floe indices (those of sp_gdem_set_floes) in the
+ * context's current order, grouped by the sub-bins of the positions at the
+ * last re-binning; the starts of those sub-bins in that order
+ * [bins_x * bins_y + 1]; and how many sub-bins and coarse cells gathered their
+ * floes by scanning every floe (a floe that moved more than one sub-bin since
+ * the previous grouping).  Any output may be NULL.  Synchronises. */
+sp_status sp_gdem_read_order(sp_gdem* g, int32_t* ids, int32_t* starts, int64_t* fallbacks);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,8 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
-            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size", "sp_read_moments_noalloc", "sp_get_block_waves"]
+            "sp_gdem_get_stats", "sp_set_step_block", "sp_get_step_block", "sp_get_work", "sp_save", "sp_load", "sp_get_size", "sp_read_moments_noalloc", "sp_get_block_waves",
+            "sp_gdem_read_order"]
 NUM_BUCKETS = 5
 MLP_NPARAMS, MLP_IN, MLP_OUT = 39428, 45, 4
 
@@ -143,6 +144,7 @@ def load_library(path: str = LIB_PATH):
     lib.sp_gdem_coarse_moments.argtypes = [P, I32, I32, P]
     lib.sp_gdem_get_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32),
                                       ctypes.POINTER(I32)]
+    lib.sp_gdem_read_order.argtypes = [P, P, P, ctypes.POINTER(I64)]
     for name in EXPORTED:
         fn = getattr(lib, name)
         if name not in ("sp_destroy", "sp_last_error", "sp_mlp_destroy", "sp_mlp_last_error", "sp_gdem_destroy",
@@ -550,3 +552,13 @@ class GlobalDEM:
         self._check(self._lib.sp_gdem_get_stats(self._h, ctypes.byref(c), ctypes.byref(s), ctypes.byref(bx),
                                                 ctypes.byref(by)))
         return dict(contacts=int(c.value), steps=int(s.value), bins=(int(bx.value), int(by.value)))
+
+    def read_order(self):
+        """(floe indices in the current order, sub-bin starts of that order,
+        sub-bins and coarse cells gathered by a full scan so far)."""
+        bx, by = self.stats()["bins"]
+        ids = np.zeros(self.n, np.int32)
+        starts = np.zeros(bx * by + 1, np.int32)
+        fb = ctypes.c_int64()
+        self._check(self._lib.sp_gdem_read_order(self._h, _p(ids), _p(starts), ctypes.byref(fb)))
+        return ids, starts, int(fb.value)

@@ -4,14 +4,20 @@
 // compared with; its coarse-grid statistics are read for that comparison.
 // Included at the end of spdem.hip.
 //
-// Per fine step: every floe's sub-bin (side >= 2 r_max, so contacts only join
-// neighbouring sub-bins) from its fixed-point position; a stable radix sort of
-// (sub-bin, slot) pairs; the state gathered into sub-bin order; sub-bin starts
-// by binary search; then one thread per floe sweeps the 3 x 3 neighbouring
-// sub-bins, decides contacts exactly as the cell kernel does (FP32 screen, FP64
-// in the guard band), sums drag and contact forces in FP64 and writes the
-// updated floe in the same order.  The state stays in sub-bin order between
-// steps, so the next sort moves few floes.
+// Per fine step, two launches.  The re-binning (gpull_kernel) is a stable
+// counting sort of the floes by sub-bin (side >= 2 r_max, so contacts only
+// join neighbouring sub-bins): the counts per sub-bin and per sub-bin row come
+// from the previous step's atomics, every row's workgroup takes its row start
+// from the row counts and its sub-bin starts by a scan, and every sub-bin
+// gathers its floes in their current order from the 3 x 3 sub-bins around it
+// (the state is grouped by the previous sub-bins and a floe moves far less
+// than a sub-bin per step; a sub-bin that finds fewer floes than its count
+// scans all floes instead).  The result is the order a stable sort by sub-bin
+// gives.  Then one thread per floe (gstep_kernel) sweeps the 3 x 3
+// neighbouring sub-bins, decides contacts exactly as the cell kernel does
+// (FP32 screen, FP64 in the guard band), sums drag and contact forces in FP64,
+// writes the updated floe in the same order, and counts the sub-bin of its
+// new position for the next re-binning.
 #pragma once
 
 struct sp_gdem {
@@ -40,12 +46,21 @@ struct sp_gdem {
     float* h[2] = {nullptr, nullptr};
     int32_t* id[2] = {nullptr, nullptr};
     int cur = 0;
-    // sort
-    uint32_t* keys[2] = {nullptr, nullptr};
-    int32_t* vals[2] = {nullptr, nullptr};
-    void* sort_tmp = nullptr;
-    size_t sort_bytes = 0;
-    int32_t* bstart = nullptr;         // sub-bin starts [nbins + 1]
+    // re-binning: the sub-bin of every floe's position (order of buffer cur),
+    // floes per sub-bin and per sub-bin row of those, sub-bin starts
+    int32_t* key = nullptr;            // [n]
+    int32_t* bcount[2] = {nullptr, nullptr};   // [nb], alternating per step
+    int32_t* rcount[2] = {nullptr, nullptr};   // [nby], alternating per step
+    int32_t* starts[2] = {nullptr, nullptr};   // [nb + 1]
+    int sb = 0;                        // starts[sb] groups buffer cur
+    int rb = 0;                        // bcount[rb] and rcount[rb] count sub-bins and rows of key
+    unsigned long long* fallbacks_d = nullptr;  // sub-bins (and coarse cells) gathered by a full scan
+    // coarse read-out: coarse cell of every floe, counts, starts, floes in cell order
+    int32_t* ckey = nullptr;           // [n]
+    int32_t* perm = nullptr;           // [n]
+    int32_t* ccount = nullptr;         // [ncoarse]
+    int32_t* crow = nullptr;           // [nyc]
+    size_t ccount_cap = 0, crow_cap = 0;
     int32_t* cstart = nullptr;         // coarse-cell starts (read-out)
     size_t cstart_cap = 0;
     double* cmom = nullptr;            // coarse statistics (read-out)
@@ -91,7 +106,13 @@ struct GArgs {
     Modes modes;                       // kxL, kyL per sub-bin side
     uint32_t* err;
     unsigned long long* contacts;
+    // the sub-bin of every updated position, counted per sub-bin and per row
+    int32_t* key_out;
+    int32_t* count;
+    int32_t* rows;
 };
+
+constexpr uint32_t kErrRebin = 32u;    // a re-binning gathered another number of floes than it counted
 
 __device__ __forceinline__ uint32_t gbin_axis(uint32_t x, int nb)
 {
@@ -105,48 +126,186 @@ __device__ __forceinline__ float gbin_offset(uint32_t x, int nb)
     return (float)(int)(lo - 0x80000000u) * 2.3283064365386963e-10f;
 }
 
-__global__ __launch_bounds__(256) void gkey_kernel(const uint32_t* xi, const uint32_t* yi, int n, int nbx, int nby,
-                                                   uint32_t* keys, int32_t* vals)
+// The axis indices lo - 1 .. hi + 1 modulo n as at most two ascending,
+// disjoint segments [a0, a1] and [b0, b1] (b0 > b1: none), the first below
+// the second; all of 0 .. n - 1 when they cover the axis.
+struct Segs {
+    int a0, a1, b0, b1;
+};
+
+__device__ __forceinline__ Segs wrap_segments(int lo, int hi, int n)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    keys[k] = gbin_axis(yi[k], nby) * (uint32_t)nbx + gbin_axis(xi[k], nbx);
-    vals[k] = k;
+    if (hi - lo + 3 >= n) return Segs{0, n - 1, 1, 0};
+    const int s = lo - 1, e = hi + 1;
+    if (s < 0) return Segs{0, e, s + n, n - 1};
+    if (e >= n) return Segs{0, e - n, s, n - 1};
+    return Segs{s, e, 1, 0};
 }
 
-__global__ __launch_bounds__(256) void ggather_kernel(const int32_t* perm, int n, const uint32_t* xi,
-                                                      const uint32_t* yi, const float* u, const float* v,
-                                                      const float* w, const float* th, const float* r,
-                                                      const float* h, const int32_t* id, uint32_t* xo,
-                                                      uint32_t* yo, float* uo, float* vo, float* wo, float* tho,
-                                                      float* ro, float* ho, int32_t* ido)
+// Every position p of the grouped order whose sub-bin lies in rows ry and
+// columns rx (segments of wrap_segments), in ascending p: sub-bins are visited
+// in ascending index (rows, then columns, ascending), and the grouping puts a
+// lower sub-bin's floes first.
+template <class F>
+__device__ __forceinline__ void for_sources(const int32_t* ostart, int nbx, Segs ry, Segs rx, F f)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int p = perm[k];
-    xo[k] = xi[p];
-    yo[k] = yi[p];
-    uo[k] = u[p];
-    vo[k] = v[p];
-    wo[k] = w[p];
-    tho[k] = th[p];
-    ro[k] = r[p];
-    ho[k] = h[p];
-    ido[k] = id[p];
+    const int ys[4] = {ry.a0, ry.a1, ry.b0, ry.b1};
+    const int xs[4] = {rx.a0, rx.a1, rx.b0, rx.b1};
+    for (int sy = 0; sy < 2; ++sy)
+        for (int yy = ys[2 * sy]; yy <= ys[2 * sy + 1]; ++yy)
+            for (int sx = 0; sx < 2; ++sx) {
+                if (xs[2 * sx] > xs[2 * sx + 1]) continue;
+                const int p1 = ostart[yy * nbx + xs[2 * sx + 1] + 1];
+                for (int p = ostart[yy * nbx + xs[2 * sx]]; p < p1; ++p) f(p);
+            }
 }
 
-// start[b] = first position of key b in the sorted keys (b = 0 .. nb).
-__global__ __launch_bounds__(256) void gstart_kernel(const uint32_t* keys, int n, int nb, int32_t* start)
+// Exclusive prefix over a 256-thread workgroup (LDS s[256]); total of all in tot.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s, int& tot)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > nb) return;
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (keys[mid] < (uint32_t)b) lo = mid + 1;
-        else hi = mid;
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int x = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += x;
+        __syncthreads();
     }
-    start[b] = lo;
+    const int incl = s[t];
+    tot = s[255];
+    __syncthreads();
+    return incl - v;
+}
+
+// Sum over the rows before `row` of per-row counts (every thread gets it).
+__device__ __forceinline__ int rows_before(const int32_t* rows, int row, int* s)
+{
+    int part = 0;
+    for (int i = threadIdx.x; i < row; i += 256) part += rows[i];
+    int tot;
+    (void)block_exclusive_scan(part, s, tot);
+    return tot;
+}
+
+// Sum over the wavefront (every lane gets it) and exclusive prefix over its lanes.
+__device__ __forceinline__ int wave_sum_i32(int x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ int wave_exclusive_i32(int x)
+{
+    const int lane = threadIdx.x & 63;
+    int incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    return incl - x;
+}
+
+struct GPull {
+    // buffer cur, grouped by ostart -> buffer out, grouped by nstart
+    const uint32_t* xi;
+    const uint32_t* yi;
+    const float *u, *v, *w, *th, *r, *h;
+    const int32_t* id;
+    uint32_t* xo;
+    uint32_t* yo;
+    float *uo, *vo, *wo, *tho, *ro, *ho;
+    int32_t* ido;
+    const int32_t* key;        // [n] sub-bin of every floe of buffer cur
+    const int32_t* ostart;     // [nb + 1]
+    int32_t* nstart;           // [nb + 1]
+    const int32_t* count;      // [nb] floes per sub-bin of key
+    int32_t* count_next;       // [nb] zeroed here for the next step's counts
+    const int32_t* rows;       // [nby] floes per sub-bin row of key
+    int32_t* rows_next;        // [nby] zeroed here
+    int n, nbx, nby;
+    uint32_t* err;
+    unsigned long long* fallbacks;
+};
+
+// Re-binning: one wavefront per run of 64 sub-bins of a row, one lane per
+// sub-bin.  A run starts after the floes of the rows before it and of its
+// row's earlier sub-bins.
+__global__ __launch_bounds__(256) void gpull_kernel(GPull g)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int runs = (g.nbx + 63) >> 6;
+    if (wid >= g.nby * runs) return;          // whole wavefronts
+    const int by = wid / runs, c0 = (wid % runs) * 64;
+    int part = 0;
+    for (int i = lane; i < by; i += 64) part += g.rows[i];
+    for (int i = lane; i < c0; i += 64) part += g.count[by * g.nbx + i];
+    const int base = wave_sum_i32(part);
+    const int bx = c0 + lane;
+    const bool in = bx < g.nbx;
+    const int b = by * g.nbx + bx;
+    const int cnt = in ? g.count[b] : 0;
+    const int q0 = base + wave_exclusive_i32(cnt);
+    if (c0 == 0 && lane == 0) g.rows_next[by] = 0;
+    if (wid == g.nby * runs - 1 && lane == 63) g.nstart[g.nbx * g.nby] = g.n;
+    if (!in) return;
+    g.count_next[b] = 0;
+    g.nstart[b] = q0;
+    int i = 0;
+    auto take = [&](int p) {
+        if (g.key[p] != b) return;
+        if (i < cnt) {
+            const int q = q0 + i;
+            g.xo[q] = g.xi[p];
+            g.yo[q] = g.yi[p];
+            g.uo[q] = g.u[p];
+            g.vo[q] = g.v[p];
+            g.wo[q] = g.w[p];
+            g.tho[q] = g.th[p];
+            g.ro[q] = g.r[p];
+            g.ho[q] = g.h[p];
+            g.ido[q] = g.id[p];
+        }
+        ++i;
+    };
+    // the (at most 3 x 2) position ranges of the neighbouring sub-bins in
+    // ascending order, their bounds read together, then 4 keys at a time
+    {
+        const Segs ry = wrap_segments(by, by, g.nby), rx = wrap_segments(bx, bx, g.nbx);
+        int row[3], nrow = 0;
+        for (int y = ry.a0; y <= ry.a1 && nrow < 3; ++y) row[nrow++] = y;
+        for (int y = ry.b0; y <= ry.b1 && nrow < 3; ++y) row[nrow++] = y;
+        const bool two = rx.b0 <= rx.b1;
+        int lo[6], hi[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int rr = k >> 1, sg = k & 1;
+            const bool use = rr < nrow && (sg == 0 || two);
+            const int b0 = use ? row[rr] * g.nbx + (sg ? rx.b0 : rx.a0) : 0;
+            const int b1 = use ? row[rr] * g.nbx + (sg ? rx.b1 : rx.a1) + 1 : 0;
+            lo[k] = use ? g.ostart[b0] : 0;
+            hi[k] = use ? g.ostart[b1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            for (int p = lo[k]; p < hi[k]; p += 4) {
+                int kk[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) kk[e] = p + e < hi[k] ? g.key[p + e] : -1;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (kk[e] == b) take(p + e);
+            }
+    }
+    if (i != cnt) {   // a floe came from further away: every floe, in order
+        atomicAdd(g.fallbacks, 1ull);
+        i = 0;
+        for (int p = 0; p < g.n; ++p) take(p);
+        if (i != cnt) atomicOr(g.err, kErrRebin);
+    }
 }
 
 // Ocean current and curl at a floe from the phase table of its sub-bin: the
@@ -201,6 +360,7 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ncontact = 0;
+    int row = -1;   // sub-bin row of the updated position
     if (k < a.n) {
         const uint32_t xl = a.xi[k], yl = a.yi[k];
         const float rl = a.r[k];
@@ -303,8 +463,15 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
             const long long xn = (long long)xl + sx;
             if (xn < 0 || xn >= 0x100000000ll) atomicOr(a.err, kErrWall);
         }
-        a.xo[k] = xl + (uint32_t)sx;
-        a.yo[k] = yl + (uint32_t)sy;
+        const uint32_t xn = xl + (uint32_t)sx, yn = yl + (uint32_t)sy;
+        a.xo[k] = xn;
+        a.yo[k] = yn;
+        {
+            row = (int)gbin_axis(yn, a.nby);
+            const int b = row * a.nbx + (int)gbin_axis(xn, a.nbx);
+            a.key_out[k] = b;
+            atomicAdd(&a.count[b], 1);
+        }
         a.uo[k] = un;
         a.vo[k] = vn;
         a.wo[k] = wn;
@@ -316,16 +483,89 @@ __global__ __launch_bounds__(256) void gstep_kernel(GArgs a)
     }
     const unsigned long long cs = wave_sum_u64(ncontact);
     if ((threadIdx.x & 63) == 0 && cs) atomicAdd(a.contacts, cs);
+    // floes per row: one atomic per wavefront when its floes share a row (the
+    // order is by sub-bin, so they mostly do)
+    const int row0 = __shfl(row, 0);
+    const unsigned long long valid = __ballot(row >= 0), same = __ballot(row >= 0 && row == row0);
+    if (same == valid) {
+        if ((threadIdx.x & 63) == 0 && valid) atomicAdd(&a.rows[row0], (int)__popcll(valid));
+    } else if (row >= 0) {
+        atomicAdd(&a.rows[row], 1);
+    }
 }
 
-// Coarse cell of every floe (read-out).
+// Coarse cell of every floe of buffer cur (read-out), counted per cell and per row.
 __global__ __launch_bounds__(256) void ckey_kernel(const uint32_t* xi, const uint32_t* yi, int n, int nxc, int nyc,
-                                                   uint32_t* keys, int32_t* vals)
+                                                   int32_t* ckey, int32_t* ccount, int32_t* crow)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    keys[k] = gbin_axis(yi[k], nyc) * (uint32_t)nxc + gbin_axis(xi[k], nxc);
-    vals[k] = k;
+    const int cy = (int)gbin_axis(yi[k], nyc);
+    const int c = cy * nxc + (int)gbin_axis(xi[k], nxc);
+    ckey[k] = c;
+    atomicAdd(&ccount[c], 1);
+    atomicAdd(&crow[cy], 1);
+}
+
+// The floes of every coarse cell in the current order (perm, from cstart): a
+// stable counting sort as the re-binning, one workgroup per coarse row, the
+// row's cells scanned for their starts, then one wavefront per cell gathering
+// in order (ballot and prefix count) from the sub-bins its cell overlaps, one
+// more on every side (the grouping is that of the last re-binning, the
+// positions a step later); a cell that finds fewer floes than its count scans
+// all floes instead.
+__global__ __launch_bounds__(256) void cpull_kernel(const int32_t* ckey, const int32_t* ccount, const int32_t* crow,
+                                                    const int32_t* ostart, int n, int nbx, int nby, int nxc,
+                                                    int nyc, int32_t* cstart, int32_t* perm, uint32_t* err,
+                                                    unsigned long long* fallbacks)
+{
+    __shared__ int s[256];
+    const int cy = blockIdx.x;
+    const int row0 = rows_before(crow, cy, s);
+    if (threadIdx.x == 0 && cy == nyc - 1) cstart[nxc * nyc] = n;
+    int carry = 0;
+    for (int c0 = 0; c0 < nxc; c0 += 256) {
+        const int cx = c0 + (int)threadIdx.x;
+        const int cnt = cx < nxc ? ccount[cy * nxc + cx] : 0;
+        int tot;
+        const int q0 = row0 + carry + block_exclusive_scan(cnt, s, tot);
+        carry += tot;
+        if (cx < nxc) cstart[cy * nxc + cx] = q0;
+    }
+    __syncthreads();
+    // sub-bin rows and columns a coarse cell overlaps
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ylo = (int)(((long long)cy * nby) / nyc), yhi = (int)(((long long)(cy + 1) * nby - 1) / nyc);
+    for (int cx = wave; cx < nxc; cx += 4) {
+        const int c = cy * nxc + cx;
+        const int q0 = cstart[c], cnt = ccount[c];
+        const int xlo = (int)(((long long)cx * nbx) / nxc), xhi = (int)(((long long)(cx + 1) * nbx - 1) / nxc);
+        int i = 0;   // floes of c gathered so far (the same in every lane)
+        auto chunk = [&](int p0, int p1) {   // positions [p0, p1), 64 at a time, in order
+            for (int b = p0; b < p1; b += 64) {
+                const int p = b + lane;
+                const bool hit = p < p1 && ckey[p] == c;
+                const unsigned long long m = __ballot(hit);
+                const int before = __popcll(m & ((1ull << lane) - 1ull));
+                if (hit && i + before < cnt) perm[q0 + i + before] = p;
+                i += __popcll(m);
+            }
+        };
+        const Segs ry = wrap_segments(ylo, yhi, nby), rx = wrap_segments(xlo, xhi, nbx);
+        const int ys[4] = {ry.a0, ry.a1, ry.b0, ry.b1};
+        const int xs[4] = {rx.a0, rx.a1, rx.b0, rx.b1};
+        for (int sy = 0; sy < 2; ++sy)
+            for (int yy = ys[2 * sy]; yy <= ys[2 * sy + 1]; ++yy)
+                for (int sx = 0; sx < 2; ++sx)
+                    if (xs[2 * sx] <= xs[2 * sx + 1])
+                        chunk(ostart[yy * nbx + xs[2 * sx]], ostart[yy * nbx + xs[2 * sx + 1] + 1]);
+        if (i != cnt) {
+            if (lane == 0) atomicAdd(fallbacks, 1ull);
+            i = 0;
+            chunk(0, n);
+            if (i != cnt && lane == 0) atomicOr(err, kErrRebin);
+        }
+    }
 }
 
 // The 11 statistics of every coarse cell, one wavefront per cell over its
@@ -426,53 +666,25 @@ void gdem_free(sp_gdem* g)
 {
     for (int b = 0; b < 2; ++b) {
         void* ps[] = {g->xi[b], g->yi[b], g->u[b], g->v[b], g->w[b], g->th[b], g->r[b], g->h[b], g->id[b],
-                      g->keys[b], g->vals[b]};
+                      g->rcount[b], g->starts[b], g->bcount[b]};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         g->xi[b] = g->yi[b] = nullptr;
         g->u[b] = g->v[b] = g->w[b] = g->th[b] = g->r[b] = g->h[b] = nullptr;
         g->id[b] = nullptr;
-        g->keys[b] = nullptr;
-        g->vals[b] = nullptr;
+        g->rcount[b] = g->starts[b] = g->bcount[b] = nullptr;
     }
-    void* ps[] = {g->sort_tmp, g->bstart, g->cstart, g->cmom, g->phase, g->err_d, g->contacts_d};
+    void* ps[] = {g->key, g->ckey, g->perm, g->ccount, g->crow, g->cstart, g->cmom, g->phase, g->err_d,
+                  g->contacts_d, g->fallbacks_d};
     for (void* p : ps)
         if (p) (void)hipFree(p);
-    g->sort_tmp = nullptr;
-    g->bstart = g->cstart = nullptr;
+    g->key = g->ckey = g->perm = g->ccount = g->crow = g->cstart = nullptr;
     g->cmom = nullptr;
     g->phase = nullptr;
     g->err_d = nullptr;
     g->contacts_d = nullptr;
-    g->sort_bytes = g->cstart_cap = g->cmom_cap = 0;
-}
-
-int key_bits(uint32_t nkeys)
-{
-    int b = 1;
-    while (b < 32 && (1u << b) < nkeys) ++b;
-    return b;
-}
-
-// Sort (key, slot) pairs of the n floes; the sorted slots in vals[1].
-sp_status gsort(sp_gdem* g, int nkeys)
-{
-    size_t bytes = 0;
-    GD_TRY(g, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, g->keys[0], g->keys[1], g->vals[0], g->vals[1],
-                                                  (int)g->n, 0, key_bits((uint32_t)nkeys), g->stream));
-    if (bytes > g->sort_bytes) {
-        if (g->sort_tmp) (void)hipFree(g->sort_tmp);
-        g->sort_tmp = nullptr;
-        if (hipMalloc(&g->sort_tmp, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            g->sort_bytes = 0;
-            return gfail(g, SP_ENOMEM, "sort workspace of %zu bytes", bytes);
-        }
-        g->sort_bytes = bytes;
-    }
-    GD_TRY(g, hipcub::DeviceRadixSort::SortPairs(g->sort_tmp, bytes, g->keys[0], g->keys[1], g->vals[0], g->vals[1],
-                                                  (int)g->n, 0, key_bits((uint32_t)nkeys), g->stream));
-    return SP_OK;
+    g->fallbacks_d = nullptr;
+    g->ccount_cap = g->crow_cap = g->cstart_cap = g->cmom_cap = 0;
 }
 
 GArgs gargs(const sp_gdem* g, double dt, int from, int to)
@@ -497,7 +709,10 @@ GArgs gargs(const sp_gdem* g, double dt, int from, int to)
     a.ro = g->r[to];
     a.ho = g->h[to];
     a.ido = g->id[to];
-    a.bstart = g->bstart;
+    a.bstart = g->starts[g->sb ^ 1];   // the starts the re-binning before the step makes
+    a.key_out = g->key;
+    a.count = g->bcount[g->rb ^ 1];
+    a.rows = g->rcount[g->rb ^ 1];
     a.phase = g->phase;
     a.n = (int)g->n;
     a.nbx = g->nbx;
@@ -564,6 +779,7 @@ sp_status gcheck(sp_gdem* g)
     if (e & kErrOverlap) return gfail(g, SP_EOVERLAP, "two floe centres coincide");
     if (e & kErrNaN) return gfail(g, SP_ENAN, "non-finite floe state");
     if (e & kErrWall) return gfail(g, SP_EWALL, "a floe crossed a wall");
+    if (e & kErrRebin) return gfail(g, SP_EDEVICE, "re-binning gathered another number of floes than it counted");
     return SP_OK;
 }
 
@@ -663,6 +879,7 @@ sp_status sp_gdem_set_floes(sp_gdem* g, int64_t n, const uint32_t* xi, const uin
     g->rmax = rmax;
     g->n = n;
     const size_t N = (size_t)n;
+    const size_t nb = (size_t)bx * by;
     for (int b = 0; b < 2; ++b) {
         SP_TRY(galloc(g, &g->xi[b], N));
         SP_TRY(galloc(g, &g->yi[b], N));
@@ -673,26 +890,53 @@ sp_status sp_gdem_set_floes(sp_gdem* g, int64_t n, const uint32_t* xi, const uin
         SP_TRY(galloc(g, &g->r[b], N));
         SP_TRY(galloc(g, &g->h[b], N));
         SP_TRY(galloc(g, &g->id[b], N));
-        SP_TRY(galloc(g, &g->keys[b], N));
-        SP_TRY(galloc(g, &g->vals[b], N));
+        SP_TRY(galloc(g, &g->rcount[b], (size_t)by));
+        SP_TRY(galloc(g, &g->starts[b], nb + 1));
+        SP_TRY(galloc(g, &g->bcount[b], nb));
     }
-    SP_TRY(galloc(g, &g->bstart, (size_t)bx * by + 1));
-    g->cur = 0;
-    std::vector<int32_t> ids(N);
-    for (size_t i = 0; i < N; ++i) ids[i] = (int32_t)i;
+    SP_TRY(galloc(g, &g->key, N));
+    SP_TRY(galloc(g, &g->ckey, N));
+    SP_TRY(galloc(g, &g->perm, N));
+    if (!g->fallbacks_d) SP_TRY(galloc(g, &g->fallbacks_d, 1));
+    // the first grouping: a stable counting sort by sub-bin on the host, the
+    // counts and starts the first re-binning reads
+    std::vector<int32_t> key(N), count(nb, 0), rows((size_t)by, 0), start(nb + 1, 0), order(N);
+    for (size_t i = 0; i < N; ++i) {
+        const uint32_t ky = (uint32_t)(((uint64_t)yi[i] * (uint64_t)by) >> 32);
+        const uint32_t kx = (uint32_t)(((uint64_t)xi[i] * (uint64_t)bx) >> 32);
+        key[i] = (int32_t)(ky * (uint32_t)bx + kx);
+        ++count[key[i]];
+        ++rows[ky];
+    }
+    for (size_t b = 0; b < nb; ++b) start[b + 1] = start[b] + count[b];
+    {
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (size_t i = 0; i < N; ++i) order[fill[key[i]]++] = (int32_t)i;
+    }
+    std::vector<int32_t> skey(N);
+    for (size_t q = 0; q < N; ++q) skey[q] = key[order[q]];
+    std::vector<uint32_t> bits(N);
     const void* src[8] = {xi, yi, u, v, omega, theta, r, h};
     void* dst[8] = {g->xi[0], g->yi[0], g->u[0], g->v[0], g->w[0], g->th[0], g->r[0], g->h[0]};
     for (int k = 0; k < 8; ++k) {
-        if (src[k]) {
-            GD_TRY(g, hipMemcpyAsync(dst[k], src[k], N * 4, hipMemcpyHostToDevice, g->stream));
-        } else {
-            GD_TRY(g, hipMemsetAsync(dst[k], 0, N * 4, g->stream));
-        }
+        const uint32_t* sk = static_cast<const uint32_t*>(src[k]);
+        for (size_t q = 0; q < N; ++q) bits[q] = sk ? sk[order[q]] : 0u;
+        GD_TRY(g, hipMemcpy(dst[k], bits.data(), N * 4, hipMemcpyHostToDevice));
     }
-    GD_TRY(g, hipMemcpyAsync(g->id[0], ids.data(), N * 4, hipMemcpyHostToDevice, g->stream));
+    GD_TRY(g, hipMemcpy(g->id[0], order.data(), N * 4, hipMemcpyHostToDevice));
+    GD_TRY(g, hipMemcpy(g->key, skey.data(), N * 4, hipMemcpyHostToDevice));
+    GD_TRY(g, hipMemcpy(g->bcount[0], count.data(), nb * 4, hipMemcpyHostToDevice));
+    GD_TRY(g, hipMemsetAsync(g->bcount[1], 0, nb * 4, g->stream));
+    GD_TRY(g, hipMemcpy(g->rcount[0], rows.data(), (size_t)by * 4, hipMemcpyHostToDevice));
+    GD_TRY(g, hipMemcpy(g->starts[0], start.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+    GD_TRY(g, hipMemsetAsync(g->rcount[1], 0, (size_t)by * 4, g->stream));
     GD_TRY(g, hipMemsetAsync(g->err_d, 0, 4, g->stream));
     GD_TRY(g, hipMemsetAsync(g->contacts_d, 0, 8, g->stream));
-    GD_TRY(g, hipStreamSynchronize(g->stream));   // ids is a host temporary
+    GD_TRY(g, hipMemsetAsync(g->fallbacks_d, 0, 8, g->stream));
+    GD_TRY(g, hipStreamSynchronize(g->stream));
+    g->cur = 0;
+    g->sb = 0;
+    g->rb = 0;
     g->steps = 0;
     g->phase_dirty = true;
     g->have_floes = true;
@@ -706,23 +950,47 @@ sp_status sp_gdem_step(sp_gdem* g, double dt, int64_t nsteps)
     if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return gfail(g, SP_EINVAL, "dt must be positive");
     SP_TRY(gupload_phase(g));
     const int n = (int)g->n;
-    const int nb = g->nbx * g->nby;
     const dim3 grid((n + 255) / 256), blk(256);
     for (int64_t it = 0; it < nsteps; ++it) {
         const int c = g->cur, o = c ^ 1;
-        hipLaunchKernelGGL(gkey_kernel, grid, blk, 0, g->stream, g->xi[c], g->yi[c], n, g->nbx, g->nby, g->keys[0],
-                           g->vals[0]);
-        GD_TRY(g, hipGetLastError());
-        SP_TRY(gsort(g, nb));
-        hipLaunchKernelGGL(ggather_kernel, grid, blk, 0, g->stream, g->vals[1], n, g->xi[c], g->yi[c], g->u[c],
-                           g->v[c], g->w[c], g->th[c], g->r[c], g->h[c], g->id[c], g->xi[o], g->yi[o], g->u[o],
-                           g->v[o], g->w[o], g->th[o], g->r[o], g->h[o], g->id[o]);
-        GD_TRY(g, hipGetLastError());
-        hipLaunchKernelGGL(gstart_kernel, dim3((nb + 1 + 255) / 256), blk, 0, g->stream, g->keys[1], n, nb,
-                           g->bstart);
+        GPull pl;
+        pl.xi = g->xi[c];
+        pl.yi = g->yi[c];
+        pl.u = g->u[c];
+        pl.v = g->v[c];
+        pl.w = g->w[c];
+        pl.th = g->th[c];
+        pl.r = g->r[c];
+        pl.h = g->h[c];
+        pl.id = g->id[c];
+        pl.xo = g->xi[o];
+        pl.yo = g->yi[o];
+        pl.uo = g->u[o];
+        pl.vo = g->v[o];
+        pl.wo = g->w[o];
+        pl.tho = g->th[o];
+        pl.ro = g->r[o];
+        pl.ho = g->h[o];
+        pl.ido = g->id[o];
+        pl.key = g->key;
+        pl.ostart = g->starts[g->sb];
+        pl.nstart = g->starts[g->sb ^ 1];
+        pl.count = g->bcount[g->rb];
+        pl.count_next = g->bcount[g->rb ^ 1];
+        pl.rows = g->rcount[g->rb];
+        pl.rows_next = g->rcount[g->rb ^ 1];
+        pl.n = n;
+        pl.nbx = g->nbx;
+        pl.nby = g->nby;
+        pl.err = g->err_d;
+        pl.fallbacks = g->fallbacks_d;
+        const int64_t waves = (int64_t)g->nby * ((g->nbx + 63) / 64);
+        hipLaunchKernelGGL(gpull_kernel, dim3((unsigned)((waves + 3) / 4)), blk, 0, g->stream, pl);
         GD_TRY(g, hipGetLastError());
         hipLaunchKernelGGL(gstep_kernel, grid, blk, 0, g->stream, gargs(g, dt, o, c));
         GD_TRY(g, hipGetLastError());
+        g->sb ^= 1;
+        g->rb ^= 1;
         g->steps++;
     }
     return SP_OK;
@@ -763,18 +1031,42 @@ sp_status sp_gdem_coarse_moments(sp_gdem* g, int32_t nxc, int32_t nyc, double* o
         SP_TRY(galloc(g, &g->cmom, (size_t)ncoarse * SP_NMOM));
         g->cmom_cap = (size_t)ncoarse * SP_NMOM;
     }
+    if ((size_t)ncoarse > g->ccount_cap) {
+        SP_TRY(galloc(g, &g->ccount, (size_t)ncoarse));
+        g->ccount_cap = (size_t)ncoarse;
+    }
+    if ((size_t)nyc > g->crow_cap) {
+        SP_TRY(galloc(g, &g->crow, (size_t)nyc));
+        g->crow_cap = (size_t)nyc;
+    }
+    GD_TRY(g, hipMemsetAsync(g->ccount, 0, (size_t)ncoarse * 4, g->stream));
+    GD_TRY(g, hipMemsetAsync(g->crow, 0, (size_t)nyc * 4, g->stream));
     hipLaunchKernelGGL(ckey_kernel, dim3((n + 255) / 256), dim3(256), 0, g->stream, g->xi[c], g->yi[c], n, nxc, nyc,
-                       g->keys[0], g->vals[0]);
+                       g->ckey, g->ccount, g->crow);
     GD_TRY(g, hipGetLastError());
-    SP_TRY(gsort(g, ncoarse));
-    hipLaunchKernelGGL(gstart_kernel, dim3((ncoarse + 1 + 255) / 256), dim3(256), 0, g->stream, g->keys[1], n, ncoarse,
-                       g->cstart);
+    hipLaunchKernelGGL(cpull_kernel, dim3(nyc), dim3(256), 0, g->stream, g->ckey, g->ccount, g->crow,
+                       g->starts[g->sb], n, g->nbx, g->nby, nxc, nyc, g->cstart, g->perm, g->err_d,
+                       g->fallbacks_d);
     GD_TRY(g, hipGetLastError());
-    hipLaunchKernelGGL(cmom_kernel, dim3(ncoarse), dim3(64), 0, g->stream, gargs(g, 0.0, c, c ^ 1), g->vals[1],
+    hipLaunchKernelGGL(cmom_kernel, dim3(ncoarse), dim3(64), 0, g->stream, gargs(g, 0.0, c, c ^ 1), g->perm,
                        g->cstart, ncoarse, g->cmom);
     GD_TRY(g, hipGetLastError());
     GD_TRY(g, hipMemcpyAsync(out, g->cmom, (size_t)ncoarse * SP_NMOM * 8, hipMemcpyDeviceToHost, g->stream));
     GD_TRY(g, hipStreamSynchronize(g->stream));
+    return gcheck(g);
+}
+
+sp_status sp_gdem_read_order(sp_gdem* g, int32_t* ids, int32_t* starts, int64_t* fallbacks)
+{
+    if (!g) return SP_EINVAL;
+    if (!g->have_floes) return gfail(g, SP_ESTATE, "no floes");
+    const size_t N = (size_t)g->n, nb = (size_t)g->nbx * g->nby;
+    if (ids) GD_TRY(g, hipMemcpyAsync(ids, g->id[g->cur], N * 4, hipMemcpyDeviceToHost, g->stream));
+    if (starts) GD_TRY(g, hipMemcpyAsync(starts, g->starts[g->sb], (nb + 1) * 4, hipMemcpyDeviceToHost, g->stream));
+    unsigned long long fb = 0;
+    GD_TRY(g, hipMemcpyAsync(&fb, g->fallbacks_d, 8, hipMemcpyDeviceToHost, g->stream));
+    GD_TRY(g, hipStreamSynchronize(g->stream));
+    if (fallbacks) *fallbacks = (int64_t)fb;
     return gcheck(g);
 }
 

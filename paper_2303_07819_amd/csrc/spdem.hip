@@ -16,7 +16,6 @@
 // step k runs inside the DEM launch of step k + 1, and chunks of steady-state
 // steps are replayed as one captured HIP graph.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <math.h>
 #include <stdarg.h>

@@ -153,3 +153,79 @@ def test_error_paths():
     big = fixtures.from_arrays(1, 1, 10e3, [1], [0], [0], [3000.0], [1.0])
     with pytest.raises(sp.SpdemError):
         sp.GlobalDEM.from_workload(big)
+
+
+def _stable_order(prev, xi, yi, bins):
+    """The previous order stably sorted by the sub-bin of every floe's
+    position (xi, yi indexed by floe), and the sub-bin starts."""
+    bx, by = bins
+    kx = (xi.astype(np.uint64) * np.uint64(bx)) >> np.uint64(32)
+    ky = (yi.astype(np.uint64) * np.uint64(by)) >> np.uint64(32)
+    key = (ky * np.uint64(bx) + kx).astype(np.int64)
+    order = prev[np.argsort(key[prev], kind="stable")]
+    starts = np.concatenate([[0], np.cumsum(np.bincount(key, minlength=bx * by))]).astype(np.int32)
+    return order, starts
+
+
+def test_rebinning_is_a_stable_sort_by_sub_bin():
+    """The first grouping (input order sorted by sub-bin) and every re-binning
+    over 25 steps of the dense domain: the order a stable sort of the previous
+    order by the sub-bins of the positions before the step gives, and its
+    sub-bin starts; no floe moves more than one sub-bin per step, so no
+    sub-bin falls back to a full scan."""
+    w = dense_global(seed=25)
+    with sp.GlobalDEM.from_workload(w) as g:
+        bins = g.stats()["bins"]
+        ids, starts, fb = g.read_order()
+        exp, est = _stable_order(np.arange(w.nfloes), w.xi, w.yi, bins)
+        assert np.array_equal(ids, exp) and np.array_equal(starts, est)
+        for _ in range(25):
+            f = g.read_floes()
+            exp, est = _stable_order(ids, f["xi"], f["yi"], bins)
+            g.step(w.dt, 1)
+            ids, starts, fb = g.read_order()
+            assert np.array_equal(ids, exp)
+            assert np.array_equal(starts, est)
+        moved = np.any(ids != np.arange(w.nfloes))
+        _say(f"  bins {bins}, 25 re-binnings equal to the stable sort, full scans {fb}")
+        assert fb == 0 and moved
+
+
+def test_rebinning_of_a_floe_that_jumps_sub_bins():
+    """One floe of a sparse domain crosses 3.5 sub-bins per step (no ocean):
+    the re-binning after each of its steps finds it outside the 3 x 3 sub-bins
+    of its target, gathers that sub-bin by a full scan, and still gives the
+    stable sort; the coarse read-out falls back the same way; the run matches
+    the oracle."""
+    L, n = 100e3, 400
+    w = fixtures.custom(1, 1, L, n, seed=26, r_scale=fixtures.radius_scale(n, L * L, phi=0.05))
+    w.dt = 30.0
+    w.u[:] = 0.0
+    w.v[:] = 0.0
+    with sp.GlobalDEM.from_workload(w) as g:
+        bins = g.stats()["bins"]
+    side = L / bins[0]
+    w.u[0] = np.float32(3.5 * side / w.dt)
+    _say(f"  bins {bins}, sub-bin side {side:.0f} m, fast floe {w.u[0]:.1f} m/s")
+    with sp.GlobalDEM.from_workload(w, flags=sp.SP_OCEAN_OFF) as g:
+        ids = g.read_order()[0]
+        for _ in range(3):
+            f = g.read_floes()
+            exp, est = _stable_order(ids, f["xi"], f["yi"], bins)
+            g.step(w.dt, 1)
+            ids, starts, fb = g.read_order()
+            assert np.array_equal(ids, exp) and np.array_equal(starts, est)
+        fb_steps = g.read_order()[2]
+        assert fb_steps >= 2                  # two target sub-bins after the first step
+        got = g.coarse_moments(10, 10)
+        fb_all = g.read_order()[2]
+        f = g.read_floes()
+    st, stats = oracle.run_global(w, 3, flags=oracle.OCEAN_OFF)
+    ref = oracle.coarse_moments(w, st, 10, 10, oracle.OCEAN_OFF)
+    dx = (f["xi"] / TWO32 - st.xs + 0.5) % 1.0 - 0.5
+    _say(f"  full scans: re-binning {fb_steps}, coarse read-out {fb_all - fb_steps}; "
+         f"position err {np.abs(dx).max() * L / w.r.min():.2e} r_min")
+    assert fb_all > fb_steps
+    assert np.array_equal(got[:, 0], ref[:, 0])
+    assert np.abs(dx).max() * L / w.r.min() <= 1e-4
+    assert rel_err(got, ref).max() <= TOL
