@@ -5,6 +5,7 @@
 #pragma once
 
 #include "mlp_kernels.h"
+#include "train_kernels.h"
 
 namespace spdem {
 
@@ -354,19 +355,19 @@ struct sp_mlp {
     int64_t adam_t = 0;
     // normalisation: x_n = (x - x_mean) x_inv_std; y = y_n y_std + y_mean
     float* norm = nullptr;       // [x_mean 45 | x_inv_std 45 | y_mean 4 | y_inv_std 4 | y_std 4]
-    // workspace for `rows` samples
-    int64_t rows = 0;
-    uint16_t* a0 = nullptr;
-    float* z[3] = {nullptr, nullptr, nullptr};
-    uint16_t* a[3] = {nullptr, nullptr, nullptr};
-    float* y = nullptr;
-    float* dF = nullptr;
-    uint16_t* dH = nullptr;
-    float* dzF[2] = {nullptr, nullptr};
-    uint16_t* dzH[2] = {nullptr, nullptr};
-    float* sq = nullptr;
     float* loss_d = nullptr;
-    float* part = nullptr;       // split-K partial products [kSplitMax][kHid * kHid]
+    // fused training step: two LDS images (current weights, the next step's), per-batch scratch
+    unsigned char* timg[2] = {nullptr, nullptr};
+    int tcur = 0;
+    bool timg_stale = true;      // parameters or normalisation changed outside the fused step
+    int64_t tr_rows = 0;         // padded batch the scratch holds
+    float* tr_gp = nullptr;
+    uint16_t* tr_aT = nullptr;
+    uint16_t* tr_dT = nullptr;
+    float* tr_bpart = nullptr;
+    double* tr_lpart = nullptr;
+    float* epoch_loss = nullptr; // per-batch losses of sp_mlp_train_epoch
+    int64_t epoch_cap = 0;
 };
 
 namespace {
@@ -407,129 +408,6 @@ sp_status malloc_m(sp_mlp* mm, T** p, size_t count)
     return SP_OK;
 }
 
-sp_status ensure_rows(sp_mlp* mm, int64_t rows)
-{
-    if (rows <= mm->rows) return SP_OK;
-    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
-    const size_t R = (size_t)rows;
-    sp_status st = SP_OK;
-    if (!st) st = malloc_m(mm, &mm->a0, R * kIn);
-    for (int l = 0; l < 3 && !st; ++l) {
-        st = malloc_m(mm, &mm->z[l], R * kHid);
-        if (!st) st = malloc_m(mm, &mm->a[l], R * kHid);
-    }
-    if (!st) st = malloc_m(mm, &mm->y, R * kOut);
-    if (!st) st = malloc_m(mm, &mm->dF, R * kOut);
-    if (!st) st = malloc_m(mm, &mm->dH, R * kOut);
-    for (int q = 0; q < 2 && !st; ++q) {
-        st = malloc_m(mm, &mm->dzF[q], R * kHid);
-        if (!st) st = malloc_m(mm, &mm->dzH[q], R * kHid);
-    }
-    if (!st) st = malloc_m(mm, &mm->sq, R * kOut);
-    if (st) return st;
-    mm->rows = rows;
-    return SP_OK;
-}
-
-// Largest number of K slices of a split product, and the K per slice below
-// which it does not split.
-constexpr int kSplitMax = 64;
-constexpr int kSplitMinK = 64;
-
-sp_status gemm(sp_mlp* mm, GemmArgs g)
-{
-    if (g.M <= 0 || g.N <= 0) return SP_OK;
-    const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
-    int slices = 1;
-    if (g.mode == EPI_STORE && g.outF && !g.outH && (long)g.M * g.N <= (long)kHid * kHid && tiles < 256) {
-        // enough workgroups for the chip, at least kSplitMinK per slice
-        slices = std::min(kSplitMax, std::max(1, std::min(256 / tiles, g.K / kSplitMinK)));
-    }
-    if (slices > 1 && g.ldf != g.N) slices = 1;   // partial tiles are dense [M][N]
-    if (slices > 1) {
-        if (!mm->part) SP_TRY(malloc_m(mm, &mm->part, (size_t)kSplitMax * kHid * kHid));
-        const int kc = ((g.K + slices - 1) / slices + 15) / 16 * 16;
-        slices = (g.K + kc - 1) / kc;
-        float* out = g.outF;
-        g.outF = mm->part;
-        g.ldf = g.N;
-        g.kchunk = kc;
-        g.part_stride = (long)g.M * g.N;
-        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, slices);
-        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, mm->stream, g);
-        MLP_HIP(mm, hipGetLastError());
-        const long n = (long)g.M * g.N;
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, mm->stream,
-                           (const float*)mm->part, slices, n, n, out);
-        MLP_HIP(mm, hipGetLastError());
-        return SP_OK;
-    }
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, mm->stream, g);
-    MLP_HIP(mm, hipGetLastError());
-    return SP_OK;
-}
-
-GemmArgs gemm_args(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn, int M, int N,
-                   int K, int mode)
-{
-    GemmArgs g;
-    memset(&g, 0, sizeof g);
-    g.A = A;
-    g.sam = sam;
-    g.sak = sak;
-    g.B = B;
-    g.sbk = sbk;
-    g.sbn = sbn;
-    g.M = M;
-    g.N = N;
-    g.K = K;
-    g.mode = mode;
-    return g;
-}
-
-// Forward pass of `B` rows (gathered by `rows` if not null).  keep: store the
-// pre-activations for the backward pass; out_raw: de-normalised output there
-// instead of the normalised output in mm->y.
-sp_status mlp_forward(sp_mlp* mm, const float* X, const int32_t* rows, int B, bool keep, float* out_raw)
-{
-    const float* xm = mm->norm;
-    const float* xis = mm->norm + kIn;
-    const float* ym = mm->norm + 2 * kIn;
-    const float* ys = mm->norm + 2 * kIn + 2 * kOut;
-    const long tot = (long)B * kIn;
-    hipLaunchKernelGGL(normalize_input_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, mm->stream, X,
-                       rows, (long)B, xm, xis, mm->a0);
-    MLP_HIP(mm, hipGetLastError());
-    const uint16_t* Wh[4] = {mm->theta_h + kOffW1, mm->theta_h + kOffW2, mm->theta_h + kOffW3,
-                             mm->theta_h + kOffW4};
-    const float* bias[4] = {mm->theta + kOffB1, mm->theta + kOffB2, mm->theta + kOffB3, mm->theta + kOffB4};
-    const uint16_t* in = mm->a0;
-    int K = kIn;
-    for (int l = 0; l < 3; ++l) {
-        GemmArgs g = gemm_args(in, K, 1, Wh[l], 1, K, B, kHid, K, EPI_HIDDEN);
-        g.bias = bias[l];
-        g.outF = keep ? mm->z[l] : nullptr;
-        g.ldf = kHid;
-        g.outH = mm->a[l];
-        g.ldh = kHid;
-        SP_TRY(gemm(mm, g));
-        in = mm->a[l];
-        K = kHid;
-    }
-    GemmArgs g = gemm_args(in, kHid, 1, Wh[3], 1, kHid, B, kOut, kHid, EPI_AFFINE);
-    g.bias = bias[3];
-    if (out_raw) {
-        g.scale = ys;
-        g.shift = ym;
-        g.outF = out_raw;
-    } else {
-        g.outF = mm->y;
-    }
-    g.ldf = kOut;
-    return gemm(mm, g);
-}
-
 // Inference forward pass of M rows in one fused launch (no scratch, nothing
 // kept), on `stream`.
 sp_status mlp_infer(sp_mlp* mm, const float* x, int64_t M, float* y, hipStream_t stream)
@@ -549,61 +427,94 @@ sp_status mlp_infer(sp_mlp* mm, const float* x, int64_t M, float* y, hipStream_t
     return SP_OK;
 }
 
-// Backward pass of the mean squared error on normalised targets into mm->grad;
-// the loss into mm->loss_d.
-sp_status mlp_backward(sp_mlp* mm, const float* T, const int32_t* rows, int B)
+// Scratch of the fused training step for a batch of B rows (padded to a
+// multiple of kTrRowAlign); the deltas start zeroed (the output deltas use 4
+// of their 16 rows, the rest stay zero).
+sp_status ensure_train(sp_mlp* mm, int B, int* Bp_out)
 {
-    const float* tm = mm->norm + 2 * kIn;
-    const float* tis = mm->norm + 2 * kIn + kOut;
-    hipLaunchKernelGGL(mse_grad_kernel, dim3((B * kOut + 255) / 256), dim3(256), 0, mm->stream, mm->y, T, rows, B,
-                       tm, tis, mm->dF, mm->dH, mm->sq);
-    MLP_HIP(mm, hipGetLastError());
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, mm->stream, mm->sq, B * kOut, mm->loss_d);
-    MLP_HIP(mm, hipGetLastError());
-    const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
-    const int offB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
-    const int nin[4] = {kIn, kHid, kHid, kHid};
-    const int nout[4] = {kHid, kHid, kHid, kOut};
-    const uint16_t* acts[4] = {mm->a0, mm->a[0], mm->a[1], mm->a[2]};
-    const float* dF = mm->dF;
-    const uint16_t* dH = mm->dH;
-    for (int l = 3; l >= 0; --l) {
-        // dW_l = d^T a_{l-1}   [nout x nin], reduction over the batch
-        GemmArgs gw = gemm_args(dH, 1, nout[l], acts[l], nin[l], 1, nout[l], nin[l], B, EPI_STORE);
-        gw.outF = mm->grad + offW[l];
-        gw.ldf = nin[l];
-        SP_TRY(gemm(mm, gw));
-        hipLaunchKernelGGL(colsum_kernel, dim3(nout[l]), dim3(256), 0, mm->stream, dF, B, nout[l],
-                           mm->grad + offB[l]);
-        MLP_HIP(mm, hipGetLastError());
-        if (l == 0) break;
-        // d_{l-1} = (d W_l) * gelu'(z_{l-1})
-        const int q = l & 1;
-        GemmArgs gd = gemm_args(dH, nout[l], 1, mm->theta_h + offW[l], nin[l], 1, B, nin[l], nout[l],
-                                EPI_GELU_BACK);
-        gd.zsaved = mm->z[l - 1];
-        gd.ldz = kHid;
-        gd.outF = mm->dzF[q];
-        gd.ldf = kHid;
-        gd.outH = mm->dzH[q];
-        gd.ldh = kHid;
-        SP_TRY(gemm(mm, gd));
-        dF = mm->dzF[q];
-        dH = mm->dzH[q];
+    const int Bp = (B + kTrRowAlign - 1) / kTrRowAlign * kTrRowAlign;
+    *Bp_out = Bp;
+    if (Bp <= mm->tr_rows) return SP_OK;
+    MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+    const size_t P = (size_t)Bp;
+    sp_status st = malloc_m(mm, &mm->tr_gp, P * 384);
+    if (!st) st = malloc_m(mm, &mm->tr_aT, P * kTrARows);
+    if (!st) st = malloc_m(mm, &mm->tr_dT, P * kTrDRows);
+    if (!st) st = malloc_m(mm, &mm->tr_bpart, P / 16 * kTrBias);
+    if (!st) st = malloc_m(mm, &mm->tr_lpart, P / 16);
+    if (st) {
+        mm->tr_rows = 0;
+        return st;
     }
+    MLP_HIP(mm, hipMemsetAsync(mm->tr_dT, 0, P * kTrDRows * 2, mm->stream));
+    mm->tr_rows = Bp;
     return SP_OK;
 }
 
-sp_status mlp_adam(sp_mlp* mm, float lr)
+// One fused step on B rows (gathered by `rows` if not null): the gradient into
+// mm->grad (adam false), or an Adam step at rate lr; the summed squared error
+// into *loss_d (device).
+sp_status fused_step(sp_mlp* mm, const float* X, const float* T, const int32_t* rows, int B, bool adam, float lr,
+                     float* loss_d)
 {
-    mm->adam_t++;
-    const double b1 = 0.9, b2 = 0.999;
-    const float c1 = (float)(1.0 - pow(b1, (double)mm->adam_t));
-    const float c2 = (float)(1.0 - pow(b2, (double)mm->adam_t));
-    hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, mm->m, mm->v,
-                       mm->grad, kNParams, lr, (float)b1, (float)b2, 1e-8f, c1, c2, mm->theta_h);
-    mm->wsw_stale = true;
+    int Bp = 0;
+    SP_TRY(ensure_train(mm, B, &Bp));
+    if (mm->timg_stale) {
+        for (int b = 0; b < 2; ++b) {
+            hipLaunchKernelGGL(tr_stage_kernel, dim3((kTrStageThreads + 255) / 256), dim3(256), 0, mm->stream,
+                               mm->theta_h, mm->theta, mm->norm, mm->timg[b]);
+            MLP_HIP(mm, hipGetLastError());
+        }
+        mm->tcur = 0;
+        mm->timg_stale = false;
+    }
+    TrainArgs ta;
+    ta.X = X;
+    ta.T = T;
+    ta.rows = rows;
+    ta.B = B;
+    ta.Bp = Bp;
+    ta.img = mm->timg[mm->tcur];
+    ta.gp = mm->tr_gp;
+    ta.aT = mm->tr_aT;
+    ta.dT = mm->tr_dT;
+    ta.bpart = mm->tr_bpart;
+    ta.lpart = mm->tr_lpart;
+    hipLaunchKernelGGL(tr_rows_kernel, dim3((unsigned)(Bp / 16 / kTrWaves)), dim3(64 * kTrWaves), kTrLds, mm->stream,
+                       ta);
     MLP_HIP(mm, hipGetLastError());
+    GradArgs ga;
+    memset(&ga, 0, sizeof ga);
+    ga.aT = mm->tr_aT;
+    ga.dT = mm->tr_dT;
+    ga.bpart = mm->tr_bpart;
+    ga.lpart = mm->tr_lpart;
+    ga.ntile = Bp / 16;
+    ga.Bp = Bp;
+    ga.loss = loss_d;
+    if (adam) {
+        mm->adam_t++;
+        const double b1 = 0.9, b2 = 0.999;
+        ga.theta = mm->theta;
+        ga.m = mm->m;
+        ga.v = mm->v;
+        ga.theta_h = mm->theta_h;
+        ga.img_next = mm->timg[mm->tcur ^ 1];
+        ga.lr = lr;
+        ga.b1 = (float)b1;
+        ga.b2 = (float)b2;
+        ga.eps = 1e-8f;
+        ga.c1 = (float)(1.0 - pow(b1, (double)mm->adam_t));
+        ga.c2 = (float)(1.0 - pow(b2, (double)mm->adam_t));
+    } else {
+        ga.grad = mm->grad;
+    }
+    hipLaunchKernelGGL(tr_grad_kernel, dim3(kTrGradTiles), dim3(64 * kTrGradWaves), 0, mm->stream, ga);
+    MLP_HIP(mm, hipGetLastError());
+    if (adam) {
+        mm->tcur ^= 1;
+        mm->wsw_stale = true;   // the inference image follows the new weights when next used
+    }
     return SP_OK;
 }
 
@@ -631,11 +542,15 @@ sp_status sp_mlp_create(void* stream, sp_mlp** out)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         mm->num_cus = cus;
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_forward_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds) != hipSuccess)
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(tr_rows_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kTrLds) != hipSuccess)
         st = SP_EDEVICE;
     if (!st) st = malloc_m(mm, &mm->theta, kNParams);
     if (!st) st = malloc_m(mm, &mm->theta_h, kNParams);
     if (!st) st = malloc_m(mm, &mm->wsw, kFwdLds);
+    if (!st) st = malloc_m(mm, &mm->timg[0], kTrLds);
+    if (!st) st = malloc_m(mm, &mm->timg[1], kTrLds);
     if (!st) st = malloc_m(mm, &mm->m, kNParams);
     if (!st) st = malloc_m(mm, &mm->v, kNParams);
     if (!st) st = malloc_m(mm, &mm->grad, kNParams);
@@ -663,9 +578,8 @@ void sp_mlp_destroy(sp_mlp* mm)
 {
     if (!mm) return;
     if (mm->stream) (void)hipStreamSynchronize(mm->stream);
-    void* ps[] = {mm->theta, mm->theta_h, mm->wsw, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->a0, mm->z[0], mm->z[1],
-                  mm->z[2], mm->a[0], mm->a[1], mm->a[2], mm->y, mm->dF, mm->dH, mm->dzF[0], mm->dzF[1],
-                  mm->dzH[0], mm->dzH[1], mm->sq, mm->part};
+    void* ps[] = {mm->theta, mm->theta_h, mm->wsw, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->timg[0],
+                  mm->timg[1], mm->tr_gp, mm->tr_aT, mm->tr_dT, mm->tr_bpart, mm->tr_lpart, mm->epoch_loss};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (mm->own_stream && mm->stream) (void)hipStreamDestroy(mm->stream);
@@ -683,6 +597,7 @@ sp_status sp_mlp_set_params(sp_mlp* mm, const float* params)
     hipLaunchKernelGGL(to_bf16_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, mm->stream, mm->theta, kNParams,
                        mm->theta_h);
     mm->wsw_stale = true;
+    mm->timg_stale = true;
     MLP_HIP(mm, hipGetLastError());
     MLP_HIP(mm, hipMemsetAsync(mm->m, 0, kNParams * 4, mm->stream));
     MLP_HIP(mm, hipMemsetAsync(mm->v, 0, kNParams * 4, mm->stream));
@@ -717,6 +632,7 @@ sp_status sp_mlp_set_norm(sp_mlp* mm, const float* x_mean, const float* x_std, c
     MLP_HIP(mm, hipMemcpyAsync(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice, mm->stream));
     MLP_HIP(mm, hipStreamSynchronize(mm->stream));
     mm->wsw_stale = true;
+    mm->timg_stale = true;
     return SP_OK;
 }
 
@@ -754,6 +670,7 @@ sp_status sp_mlp_fit_norm(sp_mlp* mm, const float* X, const float* T, int64_t n)
         if (nrm[2 * kIn + kOut + i] == 0.0f) nrm[2 * kIn + kOut + i] = 1.0f;
     MLP_HIP(mm, hipMemcpy(mm->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice));
     mm->wsw_stale = true;
+    mm->timg_stale = true;
     return SP_OK;
 }
 
@@ -768,9 +685,7 @@ sp_status sp_mlp_forward(sp_mlp* mm, const float* x, int64_t M, float* y)
 sp_status sp_mlp_gradient(sp_mlp* mm, const float* X, const float* T, int32_t B, float* grad_host, float* loss)
 {
     if (!mm || !X || !T || B < 1 || !grad_host) return mm ? mfail(mm, SP_EINVAL, "bad gradient arguments") : SP_EINVAL;
-    SP_TRY(ensure_rows(mm, B));
-    SP_TRY(mlp_forward(mm, X, nullptr, B, true, nullptr));
-    SP_TRY(mlp_backward(mm, T, nullptr, B));
+    SP_TRY(fused_step(mm, X, T, nullptr, B, false, 0.0f, mm->loss_d));
     MLP_HIP(mm, hipMemcpyAsync(grad_host, mm->grad, kNParams * 4, hipMemcpyDeviceToHost, mm->stream));
     float ls = 0.0f;
     MLP_HIP(mm, hipMemcpyAsync(&ls, mm->loss_d, 4, hipMemcpyDeviceToHost, mm->stream));
@@ -783,10 +698,7 @@ sp_status sp_mlp_train_step(sp_mlp* mm, const float* X, const float* T, const in
                             float* loss)
 {
     if (!mm || !X || !T || B < 1 || !(lr > 0)) return mm ? mfail(mm, SP_EINVAL, "bad training arguments") : SP_EINVAL;
-    SP_TRY(ensure_rows(mm, B));
-    SP_TRY(mlp_forward(mm, X, rows, B, true, nullptr));
-    SP_TRY(mlp_backward(mm, T, rows, B));
-    SP_TRY(mlp_adam(mm, lr));
+    SP_TRY(fused_step(mm, X, T, rows, B, true, lr, mm->loss_d));
     if (loss) {
         float ls = 0.0f;
         MLP_HIP(mm, hipMemcpyAsync(&ls, mm->loss_d, 4, hipMemcpyDeviceToHost, mm->stream));
@@ -801,19 +713,16 @@ sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const i
 {
     if (!mm || !X || !T || !perm || n < 1 || batch < 1 || !(lr > 0))
         return mm ? mfail(mm, SP_EINVAL, "bad epoch arguments") : SP_EINVAL;
-    SP_TRY(ensure_rows(mm, batch));
     const int64_t nb = n / batch;   // full batches only
     std::vector<float> losses;
-    float* lbuf = nullptr;
-    SP_TRY(malloc_m(mm, &lbuf, (size_t)std::max<int64_t>(nb, 1)));
-    sp_status st = SP_OK;
-    for (int64_t b = 0; b < nb && !st; ++b) {
-        st = mlp_forward(mm, X, perm + b * batch, batch, true, nullptr);
-        if (!st) st = mlp_backward(mm, T, perm + b * batch, batch);
-        if (!st) st = mlp_adam(mm, lr);
-        if (!st && hipMemcpyAsync(lbuf + b, mm->loss_d, 4, hipMemcpyDeviceToDevice, mm->stream) != hipSuccess)
-            st = SP_EDEVICE;
+    if (nb > mm->epoch_cap) {
+        MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+        SP_TRY(malloc_m(mm, &mm->epoch_loss, (size_t)nb));
+        mm->epoch_cap = nb;
     }
+    float* const lbuf = mm->epoch_loss;
+    sp_status st = SP_OK;
+    for (int64_t b = 0; b < nb && !st; ++b) st = fused_step(mm, X, T, perm + b * batch, batch, true, lr, lbuf + b);
     if (!st && mean_loss) {
         losses.resize((size_t)std::max<int64_t>(nb, 1));
         if (hipMemcpyAsync(losses.data(), lbuf, losses.size() * 4, hipMemcpyDeviceToHost, mm->stream) != hipSuccess ||
@@ -824,7 +733,6 @@ sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const i
         *mean_loss = nb > 0 ? (float)(s / (double)nb / (double)(batch * kOut)) : 0.0f;
     }
     (void)hipStreamSynchronize(mm->stream);
-    (void)hipFree(lbuf);
     if (st == SP_EDEVICE) return mfail(mm, st, "epoch copy failed");
     return st;
 }

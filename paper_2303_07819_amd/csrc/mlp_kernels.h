@@ -1,17 +1,9 @@
-// Device code of the learned closure: a 45 -> 128 -> 128 -> 128 -> 4 GELU
-// network run with bfloat16 MFMA (v_mfma_f32_16x16x16_bf16) and FP32
-// accumulation, its backward pass, Adam, and the per-cell feature gather.
-//
-// Every matrix product goes through one tiled kernel: C = A B with A(m, k) and
-// B(k, n) addressed through strides, so the transposed products of the
-// backward pass need no copies.  A 256-thread workgroup computes a 64 x 64
-// output tile; each wavefront owns a 32 x 32 quarter as 2 x 2 MFMA tiles and
-// the K loop stages 64 x 16 and 16 x 64 bfloat16 tiles in LDS.  Products with
-// few output tiles and a long K (the weight gradients, K = batch) split K over
-// the grid's z dimension into partial tiles that a second kernel sums in a
-// fixed order.  The epilogue
-// adds the bias and applies GELU (forward), the GELU derivative (backward) or
-// an affine output map, and writes FP32 and/or bfloat16 results.
+// Device code of the learned closure's inference: a 45 -> 128 -> 128 -> 128
+// -> 4 GELU network run with bfloat16 MFMA (v_mfma_f32_16x16x32_bf16 and
+// 16x16x16 steps) and FP32 accumulation, in one fused launch per batch of
+// rows; the GELU used by inference and training; the per-cell feature gather
+// helpers.  The training step (forward, backward, Adam) is in
+// train_kernels.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -79,124 +71,16 @@ __device__ __forceinline__ float erfc_tail(float z)
 // Twice GELU in its erf form: 2 z Phi(z) = z + |z| - |z| E(z).
 __device__ __forceinline__ float twice_gelu(float z) { return fmaf(-fabsf(z), erfc_tail(z), z + fabsf(z)); }
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * twice_gelu(z); }
-
-// Phi(z): half the tail, or one minus it.
-__device__ __forceinline__ float phi_cdf(float z)
+// GELU = z Phi(z) (half of twice_gelu) and its derivative Phi(z) + z phi(z),
+// phi(z) = exp(-z^2 / 2) / sqrt(2 pi), from one evaluation of the tail.
+__device__ __forceinline__ void gelu_and_grad(float z, float& g, float& dg)
 {
-    const float h = 0.5f * erfc_tail(z);
-    return z >= 0.0f ? 1.0f - h : h;
-}
-
-// d GELU / dz = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi).
-__device__ __forceinline__ float gelu_grad_f(float z)
-{
+    const float e = erfc_tail(z);
+    g = 0.5f * fmaf(-fabsf(z), e, z + fabsf(z));
+    const float h = 0.5f * e;
+    const float phi = z >= 0.0f ? 1.0f - h : h;
     const float dens = 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
-    return fmaf(z, dens, phi_cdf(z));
-}
-
-enum { EPI_STORE = 0, EPI_HIDDEN = 1, EPI_AFFINE = 2, EPI_GELU_BACK = 3 };
-
-struct GemmArgs {
-    const uint16_t* A;
-    long sam, sak;          // A(m, k) = A[m sam + k sak]
-    const uint16_t* B;
-    long sbk, sbn;          // B(k, n) = B[k sbk + n sbn]
-    int M, N, K;
-    int mode;
-    const float* bias;      // [N] (EPI_HIDDEN, EPI_AFFINE)
-    const float* scale;     // [N] (EPI_AFFINE): out = (C + bias) scale + shift
-    const float* shift;
-    float* outF;            // FP32 result (may be null)
-    long ldf;
-    uint16_t* outH;         // bfloat16 result (may be null)
-    long ldh;
-    const float* zsaved;    // EPI_GELU_BACK: pre-activations [M][ldz]
-    long ldz;
-    int kchunk;             // split K: workgroup z covers k in [z kchunk, (z + 1) kchunk) (EPI_STORE into
-    long part_stride;       // outF + z part_stride; 0: one slice)
-};
-
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
-{
-    __shared__ uint16_t As[64][16];
-    __shared__ uint16_t Bs[16][64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int kbeg = g.kchunk > 0 ? (int)blockIdx.z * g.kchunk : 0;
-    const int kend = g.kchunk > 0 ? min(g.K, kbeg + g.kchunk) : g.K;
-    if (g.kchunk > 0) g.outF += (long)blockIdx.z * g.part_stride;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
-        {
-            const int r = tid >> 2, kk = (tid & 3) * 4;
-            const int m = m0 + r;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = k0 + kk + q;
-                As[r][kk + q] = (m < g.M && k < kend) ? g.A[(long)m * g.sam + (long)k * g.sak] : (uint16_t)0;
-            }
-        }
-        {
-            const int kk = tid >> 4, cc = (tid & 15) * 4;
-            const int k = k0 + kk;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int n = n0 + cc + q;
-                Bs[kk][cc + q] = (k < kend && n < g.N) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (uint16_t)0;
-            }
-        }
-        __syncthreads();
-        const int kq = 4 * (lane >> 4), li = lane & 15;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            bf16x4 a;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = (short)As[wm + i * 16 + li][kq + q];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                bf16x4 b;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) b[q] = (short)Bs[kq + q][wn + j * 16 + li];
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-
-    // output element (row, col) of lane / register: row = 4 (lane / 16) + r, col = lane % 16
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-                const int col = n0 + wn + j * 16 + (lane & 15);
-                if (row >= g.M || col >= g.N) continue;
-                float v = acc[i][j][r];
-                if (g.mode == EPI_HIDDEN) {
-                    const float z = v + g.bias[col];
-                    if (g.outF) g.outF[(long)row * g.ldf + col] = z;
-                    g.outH[(long)row * g.ldh + col] = f2bf(gelu_f(z));
-                } else if (g.mode == EPI_AFFINE) {
-                    const float y = v + g.bias[col];
-                    g.outF[(long)row * g.ldf + col] = g.scale ? y * g.scale[col] + g.shift[col] : y;
-                } else if (g.mode == EPI_GELU_BACK) {
-                    const float d = v * gelu_grad_f(g.zsaved[(long)row * g.ldz + col]);
-                    if (g.outF) g.outF[(long)row * g.ldf + col] = d;
-                    if (g.outH) g.outH[(long)row * g.ldh + col] = f2bf(d);
-                } else {
-                    if (g.outF) g.outF[(long)row * g.ldf + col] = v;
-                    if (g.outH) g.outH[(long)row * g.ldh + col] = f2bf(v);
-                }
-            }
+    dg = fmaf(z, dens, phi);
 }
 
 // ------------------------------------------------ fused forward (inference)
@@ -475,96 +359,6 @@ __global__ __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(
         }
         if (r0 + step < M) load_inputs(r0 + step);
     }
-}
-
-// Sum of the `slices` partial products of a split-K product, in slice order:
-// out[i] = sum_z part[z stride + i], i < n.
-__global__ void splitk_reduce_kernel(const float* part, int slices, long stride, long n, float* out)
-{
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int z = 0; z < slices; ++z) s += part[(long)z * stride + i];
-    out[i] = s;
-}
-
-// x [M][kIn] FP32 -> bfloat16 of (x - mean) / std; optional row gather.
-__global__ void normalize_input_kernel(const float* x, const int32_t* rows, long M, const float* mean,
-                                       const float* inv_std, uint16_t* out)
-{
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M * kIn) return;
-    const long m = i / kIn;
-    const int f = (int)(i % kIn);
-    const long src = rows ? (long)rows[m] : m;
-    out[i] = f2bf((x[src * kIn + f] - mean[f]) * inv_std[f]);
-}
-
-// Mean-squared-error gradient on normalised targets: d = 2 (y - (t - mean) / std) / (B kOut),
-// written in FP32 and bfloat16; per-element squared errors for the loss.
-__global__ void mse_grad_kernel(const float* y, const float* t, const int32_t* rows, int B, const float* tmean,
-                                const float* tinv_std, float* dF, uint16_t* dH, float* sq)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B * kOut) return;
-    const int m = i / kOut, o = i % kOut;
-    const long src = rows ? (long)rows[m] : m;
-    const float tn = (t[src * kOut + o] - tmean[o]) * tinv_std[o];
-    const float e = y[i] - tn;
-    const float d = 2.0f * e / (float)(B * kOut);
-    dF[i] = d;
-    dH[i] = f2bf(d);
-    sq[i] = e * e;
-}
-
-// Column sums of d [rows][cols] (bias gradients), one workgroup per column,
-// fixed reduction order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* d, int rows, int cols, float* out)
-{
-    __shared__ float part[256];
-    const int col = blockIdx.x;
-    float s = 0.0f;
-    for (int r = threadIdx.x; r < rows; r += 256) s += d[(long)r * cols + col];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[col] = part[0];
-}
-
-// Sum of n floats in a fixed order (one workgroup).
-__global__ __launch_bounds__(256) void sum_kernel(const float* x, int n, float* out)
-{
-    __shared__ double part[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += (double)x[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = (float)part[0];
-}
-
-// Adam (bias-corrected) on the FP32 master parameters; refreshes the
-// bfloat16 copy the matrix products read.
-__global__ void adam_kernel(float* theta, float* m, float* v, const float* grad, int n, float lr, float b1,
-                            float b2, float eps, float c1, float c2, uint16_t* theta_h)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = grad[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float mh = mi / c1, vh = vi / c2;
-    const float th = theta[i] - lr * mh / (sqrtf(vh) + eps);
-    theta[i] = th;
-    theta_h[i] = f2bf(th);
 }
 
 __global__ void to_bf16_kernel(const float* x, int n, uint16_t* out)
