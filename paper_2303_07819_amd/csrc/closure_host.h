@@ -104,6 +104,17 @@ __device__ __forceinline__ CellOcean ocean_centre(int C, const double2* phase, i
     return o;
 }
 
+// Ocean current and curl at every cell centre, kept for the closure kernels
+// (the ocean is steady: computed once per ocean or grid change).
+__global__ void ocean_centre_kernel(int ncells, const double2* phase, int nmodes, Modes modes, double u0, double v0,
+                                    double* oc)
+{
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= ncells) return;
+    const CellOcean o = ocean_centre(C, phase, nmodes, modes, u0, v0);
+    reinterpret_cast<double4*>(oc)[C] = make_double4(o.u, o.v, o.zeta, 0.0);
+}
+
 // Relative velocity and spin of cell C's reduced DEM at time t.
 __device__ __forceinline__ void reduced_rel(int C, const double* red, const double* mf, double t, double& dux,
                                             double& duy, double& dw)
@@ -120,11 +131,16 @@ __device__ __forceinline__ void reduced_rel(int C, const double* red, const doub
 
 // Statistics of cell C's reduced DEM at time t: coefficient (u, v), sources
 // per unit area (s_x, s_y, s_w).
-__device__ __forceinline__ void reduced_stats(int C, const double* red, const double* mf, const double2* phase,
-                                              int nmodes, const Modes& modes, double u0, double v0, double t,
+__device__ __forceinline__ CellOcean centre_of(int C, const double* oc)
+{
+    const double4 q = reinterpret_cast<const double4*>(oc)[C];
+    return CellOcean{q.x, q.y, q.z};
+}
+
+__device__ __forceinline__ void reduced_stats(int C, const double* red, const double* mf, const double* oc, double t,
                                               double out[5])
 {
-    const CellOcean o = ocean_centre(C, phase, nmodes, modes, u0, v0);
+    const CellOcean o = centre_of(C, oc);
     double dux, duy, dw;
     reduced_rel(C, red, mf, t, dux, duy, dw);
     const double* k = mf + (size_t)C * 4;
@@ -139,10 +155,7 @@ __device__ __forceinline__ void reduced_stats(int C, const double* red, const do
 struct ClosureArgs {
     const double* red;
     const double* mf;
-    const double2* phase;
-    int nmodes;
-    Modes modes;
-    double u0, v0;
+    const double* oc;   // [ncells][4]: ocean u, v, curl at each cell centre (ocean_centre_kernel)
     int nx, ny;
     double dX, dY;
     double t;       // time of the pre-step state
@@ -156,7 +169,7 @@ __device__ __forceinline__ void cell_rstats(int C, const ClosureArgs& a, double 
 #pragma unroll
         for (int k = 0; k < 5; ++k) out[k] = a.rs[(size_t)C * 5 + k];
     } else {
-        reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, out);
+        reduced_stats(C, a.red, a.mf, a.oc, a.t, out);
     }
 }
 
@@ -199,7 +212,7 @@ __global__ void reduced_stats_kernel(ClosureArgs a, double* rs, const int32_t* r
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     if (C >= a.nx * a.ny) return;
     double o[5];
-    reduced_stats(C, a.red, a.mf, a.phase, a.nmodes, a.modes, a.u0, a.v0, a.t, o);
+    reduced_stats(C, a.red, a.mf, a.oc, a.t, o);
 #pragma unroll
     for (int k = 0; k < 5; ++k) rs[(size_t)C * 5 + k] = o[k];
     if (mom && row[C] >= 0) {
@@ -234,7 +247,7 @@ __global__ void reduced_init_kernel(const int32_t* cells, int ncl, const int32_t
     const double n = s[M_N], M = s[M_MASS], r2m = a.mf[(size_t)C * 4 + 2];
     const double U = n > 0.0 ? s[M_UX] / n : 0.0, V = n > 0.0 ? s[M_UY] / n : 0.0;
     const double Om = (M > 0.0 && r2m > 0.0) ? s[M_L] / (M * r2m) : 0.0;
-    const CellOcean o = ocean_centre(C, a.phase, a.nmodes, a.modes, a.u0, a.v0);
+    const CellOcean o = centre_of(C, a.oc);
     double* q = red + (size_t)C * 4;
     q[0] = o.u - U;
     q[1] = o.v - V;
@@ -260,7 +273,7 @@ __device__ __forceinline__ void cell_features(int c, const double* Q, const Clos
             for (int f = 0; f < 4; ++f) o[k++] = (float)Q[(size_t)f * nc + nb];
         }
     }
-    const CellOcean oc = ocean_centre(c, a.phase, a.nmodes, a.modes, a.u0, a.v0);
+    const CellOcean oc = centre_of(c, a.oc);
     o[36] = (float)oc.u;
     o[37] = (float)oc.v;
     o[38] = (float)oc.zeta;
@@ -757,18 +770,23 @@ sp_status ensure_cell_data(sp_ctx* c)
     return SP_OK;
 }
 
+sp_status upload_ocean_centres(sp_ctx* c)
+{
+    SP_TRY(dalloc(c, &c->ocen, (size_t)c->ncells * 4));
+    const StepArgs s = make_args(c, 0.0);
+    hipLaunchKernelGGL(ocean_centre_kernel, dim3((c->ncells + 255) / 256), dim3(256), 0, c->stream, c->ncells,
+                       c->phase, c->nmodes, s.modes, s.u0, s.v0, c->ocen);
+    HIP_TRY(c, hipGetLastError());
+    return SP_OK;
+}
+
 ClosureArgs closure_args(const sp_ctx* c, double t)
 {
-    const StepArgs s = make_args(c, 0.0);
     ClosureArgs a;
     memset(&a, 0, sizeof a);
     a.red = c->red;
     a.mf = c->mf;
-    a.phase = c->phase;
-    a.nmodes = c->nmodes;
-    a.modes = s.modes;
-    a.u0 = s.u0;
-    a.v0 = s.v0;
+    a.oc = c->ocen;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.dX = c->p.cell_lx;

@@ -96,6 +96,7 @@ struct sp_ctx {
     float *u = nullptr, *v = nullptr, *w = nullptr, *th = nullptr, *r = nullptr, *h = nullptr;
     int32_t* cell_start = nullptr;
     double2* phase = nullptr;
+    double* ocen = nullptr;                 // [ncells][4]: ocean u, v and curl at each cell centre, 0
     double* momb[2] = {nullptr, nullptr};   // statistics of time level k in momb[k & 1]
     double* mom2 = nullptr;                 // statistics of the current state (read_moments)
     double* Q[2] = {nullptr, nullptr};      // continuum of time level k in Q[k & 1]
@@ -268,7 +269,7 @@ void free_all(sp_ctx* c)
     drop_graph(c);
     hybrid_free(c);
     coupling_free(c);
-    void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase,
+    void* ps[] = {c->xi, c->yi, c->u, c->v, c->w, c->th, c->r, c->h, c->cell_start, c->phase, c->ocen,
                   c->momb[0], c->momb[1], c->mom2, c->Q[0], c->Q[1], c->err_d, c->contacts_d,
                   c->cfl_bits_d, c->desc, c->mf, c->red, c->qprev, c->vlist, c->vcount, c->vdisp, c->empty_d,
                   c->blk_ring, c->cands_d, c->tsp_j, c->tsp_x};
@@ -282,6 +283,7 @@ void free_all(sp_ctx* c)
     c->u = c->v = c->w = c->th = c->r = c->h = nullptr;
     c->cell_start = nullptr;
     c->phase = nullptr;
+    c->ocen = nullptr;
     c->momb[0] = c->momb[1] = c->mom2 = nullptr;
     c->Q[0] = c->Q[1] = nullptr;
     c->err_d = nullptr;
@@ -386,6 +388,8 @@ StepArgs make_args(const sp_ctx* c, double dt)
     return a;
 }
 
+sp_status upload_ocean_centres(sp_ctx* c);
+
 sp_status upload_phase(sp_ctx* c)
 {
     if (!c->phase_dirty || c->ncells == 0) return SP_OK;
@@ -402,6 +406,7 @@ sp_status upload_phase(sp_ctx* c)
     SP_TRY(dalloc(c, &c->phase, tab.size()));
     HIP_TRY(c, hipMemcpyAsync(c->phase, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice,
                               c->stream));
+    SP_TRY(upload_ocean_centres(c));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->phase_dirty = false;
     drop_graph(c);
