@@ -282,17 +282,28 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
                 }
             }
             my_tests += (uint32_t)k;
-            for (int q0 = 0; q0 < k; q0 += 8) {
-                const uint4 ix = *reinterpret_cast<const uint4*>(my + q0);
-                const int qe = min(8, k - q0);
-                for (int t = 0; t < qe; ++t) {
-                    const uint32_t wv = t < 2 ? ix.x : t < 4 ? ix.y : t < 6 ? ix.z : ix.w;
-                    const int j = (int)((wv >> (16 * (t & 1))) & 0xffffu);
-                    if (j == l) continue;
-                    const uint4 pj = P[j];
-                    if (decide((int)(pj.x - pl.x), (int)(pj.y - pl.y), __uint_as_float(pl.z), __uint_as_float(pj.z), a))
-                        cmask |= 1u << (q0 + t);
+            // four candidates at a time: their partners' positions loaded
+            // together (an index past the list reads the floe itself and is
+            // skipped), then decided
+            for (int q0 = 0; q0 < k; q0 += 4) {
+                const uint2 ix = *reinterpret_cast<const uint2*>(my + q0);
+                int jv[4];
+                jv[0] = (int)(ix.x & 0xffffu);
+                jv[1] = (int)(ix.x >> 16);
+                jv[2] = (int)(ix.y & 0xffffu);
+                jv[3] = (int)(ix.y >> 16);
+                uint4 pj[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    jv[t] = q0 + t < k ? jv[t] : l;
+                    pj[t] = P[jv[t]];
                 }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (jv[t] != l &&
+                        decide((int)(pj[t].x - pl.x), (int)(pj[t].y - pl.y), __uint_as_float(pl.z),
+                               __uint_as_float(pj[t].z), a))
+                        cmask |= 1u << (q0 + t);
             }
             // ---- contact forces and torques in ascending partner order (FP64)
             double Fx = fdx, Fy = fdy, T = tdr;

@@ -148,6 +148,9 @@ __device__ __forceinline__ float wave_max_f32(float x)
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_f32(float x)
 {
+    // a row shift with every row enabled writes every lane (zero where the
+    // source lies outside the row): no old value to keep
+    if (CTRL < 0x140 && ROWS == 0xf) return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, CTRL < 0x140));
 }
 
@@ -177,6 +180,24 @@ __device__ __forceinline__ double sqrt_nonneg(double x)
     const double d = fma(-g, g, x);
     g = fma(d, h, g);
     return x > 0.0 ? g : 0.0;
+}
+
+// Square root d of a finite x > 0 and its reciprocal: the iteration of
+// sqrt_nonneg, then one Newton step for h ~ 1 / (2 d) against the refined d
+// (h += 2 h (1/2 - d h), quadratic in the error of h), and 1 / d = 2 h; within
+// a few ulp of 1 / d.
+__device__ __forceinline__ void root_and_reciprocal(double x, double& d, double& inv_d)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double e = fma(-g, g, x);
+    g = fma(e, h, g);
+    h = fma(2.0 * h, fma(-g, h, 0.5), h);
+    d = g;
+    inv_d = 2.0 * h;
 }
 
 // FP64 contact predicate: (dx*dx + dy*dy) < R*R without contraction.
@@ -341,8 +362,8 @@ __device__ __forceinline__ bool contact_terms(int dxi, int dyi, double rld, doub
     const double d2 = dx * dx + dy * dy;
     if (!(d2 > 0.0)) return false;
     const double rjd = (double)rj;
-    const double d = sqrt_nonneg(d2);
-    const double inv_d = 1.0 / d;
+    double d, inv_d;
+    root_and_reciprocal(d2, d, inv_d);
     const double nx = dx * inv_d, ny = dy * inv_d;
     const double tx = -ny, ty = nx;
     const double R = rld + rjd;
@@ -395,8 +416,8 @@ __device__ __forceinline__ void add_terms(double& Fx, double& Fy, double& T, dou
 template <int CTRL>
 __device__ __forceinline__ double dpp_shr(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -409,11 +430,13 @@ __device__ __forceinline__ double row_sum(double x)
     return x;
 }
 
+// A lane permutation within rows (row_ror, row_half_mirror, quad_perm); every
+// lane of the wavefront must be active, since no old value is kept.
 template <int CTRL>
 __device__ __forceinline__ double dpp_perm(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 
