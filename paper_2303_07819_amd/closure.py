@@ -251,7 +251,8 @@ def hybrid_experiment(w, net, nsteps: int, stream, marks=(10, 100, 400), window_
     nsteps-step runs, relative L2 errors against full DEM per component at
     nsteps and at the marks (short horizons), 95th-percentile per-cell errors.
     Also the speed / error curve of wider DEM bands (DEM iff MIZ_LO <= c <= hi
-    for each hi of curve_hi, with and without the network), and the distance
+    for each hi of curve_hi, with and without the network) and of a fallback
+    policy that keeps every cell whose check fails in DEM mode, and the distance
     between two full-DEM runs whose floes differ by one position unit (2^-32
     of the cell): how far the DEM's own continuum is determined by its
     initial state over the run."""
@@ -296,10 +297,23 @@ def hybrid_experiment(w, net, nsteps: int, stream, marks=(10, 100, 400), window_
         band = (c >= MIZ_LO) & (c <= hi)
         for name, nt in (("network", net), ("no_network", zero)):
             h = _evolve(w, stream, nsteps, (), nt, band, window, check, timed=True)
-            curve.append({"dem_band": [MIZ_LO, hi], "closure": name,
+            curve.append({"dem_band": [MIZ_LO, hi], "closure": name, "check_cells": check[1],
+                          "fallback_steps": check[3],
                           "floes_in_dem_cells": float(w.counts[band].sum()) / w.nfloes,
                           "ms_per_step": 1e3 * h["seconds"] / nsteps, "speedup": full["seconds"] / h["seconds"],
                           "rel_l2": errs(h[nsteps], Qf)[0]})
+    # fallback policy: a cell whose check fails stays in DEM mode for the rest
+    # of the run, with the default number of checked cells and with sixteen
+    # times as many (a check pool of four times that many cells)
+    for ccells in (check[1], 16 * check[1]):
+        pol = (check[0], ccells, check[2], nsteps)
+        h = _evolve(w, stream, nsteps, (), net, dem, window, pol, timed=True)
+        curve.append({"dem_band": [MIZ_LO, MIZ_HI], "closure": "network", "check_cells": ccells,
+                      "fallback_steps": nsteps, "fallbacks": h["stats"]["fallbacks"],
+                      "dem_cells_at_end": h["stats"]["dem_cells"],
+                      "floes_in_dem_cells": float(w.counts[dem].sum()) / w.nfloes,
+                      "ms_per_step": 1e3 * h["seconds"] / nsteps, "speedup": full["seconds"] / h["seconds"],
+                      "rel_l2": errs(h[nsteps], Qf)[0]})
     res["curve"] = curve
     import copy
     w2 = copy.copy(w)

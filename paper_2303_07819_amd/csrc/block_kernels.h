@@ -110,11 +110,14 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
 
     const int item = blockIdx.x * gpb + g;
     const bool valid = item < a.ncl;
-    const int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
+    int4 wk = valid ? a.work[item] : make_int4(0, 0, 0, 0);
+    // a wavefront lies within one group: its work entry is uniform (scalar registers)
+    wk.x = __builtin_amdgcn_readfirstlane(wk.x);
+    wk.y = __builtin_amdgcn_readfirstlane(wk.y);
+    wk.z = __builtin_amdgcn_readfirstlane(wk.z);
+    wk.w = __builtin_amdgcn_readfirstlane(wk.w);
     const int c = wk.x, s = wk.y, n = wk.z;
     const bool has = valid && gt < n;          // this lane's floe
-    const unsigned long long ccell = (valid && gt == 0) ? a.contacts[c] : 0ull;
-    const unsigned long long tcell = (valid && gt == 0) ? a.cands[c] : 0ull;
     const size_t slot_len = (size_t)a.ncells * kMomStride;
     uint16_t* const vlst = a.vlist + (size_t)s * kListCap;
 
@@ -481,32 +484,37 @@ void dem_block_kernel(StepArgs a, int K, BlockNudge nd)
         __syncthreads();
     }
 
-    // ---- state, lists, bound and contact count back to HBM
+    // ---- state, lists, bound and contact count back to HBM (the floe index
+    // formed afresh from the scalar cell start: nothing per lane is kept
+    // across the step loop for it)
+    int s_end = s;
+    asm volatile("" : "+s"(s_end));
+    const int fi = s_end + gt;
     if (has) {
         const uint4 p = P[gt];
         const float4 v = V[gt];
-        a.xi[s + gt] = p.x;
-        a.yi[s + gt] = p.y;
-        a.th[s + gt] = __uint_as_float(p.w);
-        a.u[s + gt] = v.x;
-        a.v[s + gt] = v.y;
-        a.w[s + gt] = v.z;
+        a.xi[fi] = p.x;
+        a.yi[fi] = p.y;
+        a.th[fi] = __uint_as_float(p.w);
+        a.u[fi] = v.x;
+        a.v[fi] = v.y;
+        a.w[fi] = v.z;
         if (TSP) {
-            a.tsp_j[s + gt] = HJ[gt];
+            a.tsp_j[fi] = HJ[gt];
 #pragma unroll
-            for (int q = 0; q < SP_SPRING_CAP; ++q) a.tsp_x[(size_t)(s + gt) * SP_SPRING_CAP + q] = HX[gt * SP_SPRING_CAP + q];
+            for (int q = 0; q < SP_SPRING_CAP; ++q) a.tsp_x[(size_t)fi * SP_SPRING_CAP + q] = HX[gt * SP_SPRING_CAP + q];
         }
         if (rebuilt) {
             const int k = cnt[gt];
             const uint16_t* my = lst + (size_t)gt * kListCap;
             for (int q = 0; q < k; ++q) vlst[(size_t)(q & ~7) * n + (size_t)gt * 8 + (q & 7)] = my[q];
-            a.vcount[s + gt] = (uint8_t)k;
+            a.vcount[fi] = (uint8_t)k;
         }
     }
     if (valid && gt == 0) {
         a.vdisp[c] = vd;
-        a.contacts[c] = ccell + ctot;
-        a.cands[c] = tcell + ttot;
+        a.contacts[c] += ctot;   // read here, not at the start: nothing long-lived
+        a.cands[c] += ttot;
     }
 }
 
