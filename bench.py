@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--config", default="plain64")
     ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--step-block", type=int, default=0,
+                    help="steps per DEM launch of the headline run (0: the library's default of 32; "
+                         "1: one launch per step, replayed as captured graphs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=64)
     ap.add_argument("--no-hybrid", action="store_true",
@@ -298,6 +301,8 @@ def main():
     stream = torch.cuda.Stream()          # default priority; handed to the library
     torch.cuda.set_stream(stream)
     sim = sp.Sim.from_workload(w, schedule=args.schedule, stream=stream.cuda_stream)
+    if args.step_block > 0:
+        sim.set_step_block(args.step_block)
     sched = sim.schedule()
     print(f"bench: {w.nfloes} floes in {w.ncells} cells, schedule {sched}", file=sys.stderr, flush=True)
 
