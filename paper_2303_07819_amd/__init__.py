@@ -41,7 +41,7 @@ EXPORTED = ["sp_create", "sp_destroy", "sp_last_error", "sp_set_ocean", "sp_set_
             "sp_get_batching", "sp_set_batching", "sp_autotune", "sp_set_graph_chunk",
             "sp_mlp_create", "sp_mlp_destroy", "sp_mlp_last_error", "sp_mlp_set_params", "sp_mlp_get_params",
             "sp_mlp_set_norm", "sp_mlp_get_norm", "sp_mlp_fit_norm", "sp_mlp_forward", "sp_mlp_gradient",
-            "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_closure_features", "sp_closure_sample",
+            "sp_mlp_train_step", "sp_mlp_train_epoch", "sp_mlp_set_input_noise", "sp_closure_features", "sp_closure_sample",
             "sp_resync_cells", "sp_hybrid_set", "sp_step_hybrid", "sp_hybrid_stats", "sp_set_coupling",
             "sp_get_coupling", "sp_gdem_create", "sp_gdem_destroy", "sp_gdem_last_error", "sp_gdem_set_ocean",
             "sp_gdem_set_floes", "sp_gdem_step", "sp_gdem_read_floes", "sp_gdem_coarse_moments",
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     lib.sp_mlp_gradient.argtypes = [P, P, P, I32, P, F]
     lib.sp_mlp_train_step.argtypes = [P, P, P, P, I32, ctypes.c_float, F]
     lib.sp_mlp_train_epoch.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, F]
+    lib.sp_mlp_set_input_noise.argtypes = [P, I32, F, ctypes.c_uint64]
     lib.sp_closure_features.argtypes = [P, P]
     lib.sp_closure_sample.argtypes = [P, D, I32, P, P]
     lib.sp_get_schedule.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -476,6 +477,14 @@ class MLP:
         self._check(self._lib.sp_mlp_train_epoch(self._h, _p(X), _p(T), _p(perm), int(perm.shape[0]), int(batch),
                                                  float(lr), ctypes.byref(loss)))
         return float(loss.value)
+
+    def set_input_noise(self, sd=None, seed: int = 0):
+        """Gaussian noise of scale sd[f] (raw input units) on inputs f < len(sd)
+        of every training row (None or empty: off)."""
+        a = np.zeros(0, np.float32) if sd is None else np.ascontiguousarray(sd, np.float32)
+        self._check(self._lib.sp_mlp_set_input_noise(self._h, int(a.size),
+                                                     a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a.size else None,
+                                                     ctypes.c_uint64(int(seed) & (2**64 - 1))))
 
 
 class GlobalDEM:

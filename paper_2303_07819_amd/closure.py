@@ -122,8 +122,8 @@ def _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, t
     import torch
     import fixtures
     n = X.shape[0]
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    order = torch.randperm(n, generator=g)
+    rng = np.random.default_rng(seed)
+    order = torch.as_tensor(rng.permutation(n))
     nval = int(n * holdout)
     val = order[:nval].to("cuda", torch.int32)
     tr = order[nval:]
@@ -138,33 +138,34 @@ def _train(X, T, epochs, batch, lr, seed, holdout, stencil_noise, use_stencil, t
         xs[:36] = 0.0
         net.set_norm(xm, xs, ym, ys)
     hist = {"train": [], "val": [], "seconds": 0.0, "step_seconds": 0.0, "batch": batch}
-    sd = Xtr[:, :36].std(dim=0, keepdim=True)
-    gd = torch.Generator(device="cuda").manual_seed(seed + 1)
+    if stencil_noise > 0:
+        # the training kernel adds the noise (stencil_noise times each stencil
+        # column's spread over the training rows, from the fitted normalisation)
+        _, xinv, _, _ = net.get_norm()
+        spread = np.where(xinv[:36] > 0, 1.0 / np.where(xinv[:36] > 0, xinv[:36], 1.0), 0.0)
+        net.set_input_noise((stencil_noise * spread).astype(np.float32), seed + 1)
     t0 = time.perf_counter()
     for ep in range(epochs):
-        perm = torch.randperm(Xtr.shape[0], generator=g).to("cuda", torch.int32)
-        Xe = Xtr
-        if stencil_noise > 0:
-            Xe = Xtr.clone()
-            Xe[:, :36] += stencil_noise * sd * torch.randn(Xe.shape[0], 36, device="cuda", generator=gd)
+        perm = torch.as_tensor(rng.permutation(Xtr.shape[0]).astype(np.int32), device="cuda")
         ts.synchronize()
         t_ep = time.perf_counter()
-        hist["train"].append(net.train_epoch(Xe, Ttr, perm, batch, lr))   # returns synchronised
+        hist["train"].append(net.train_epoch(Xtr, Ttr, perm, batch, lr))   # returns synchronised
         hist["step_seconds"] += time.perf_counter() - t_ep
-        del Xe
         hist["val"].append(validation_loss(net, X, T, val))
         if log:
             log(f"epoch {ep + 1}: train {hist['train'][-1]:.4f} held-out {hist['val'][-1]:.4f}")
     torch.cuda.synchronize()
     hist["seconds"] = time.perf_counter() - t0
+    net.set_input_noise(None)
     hist["samples"] = int(Xtr.shape[0])
     hist["steps"] = epochs * (int(Xtr.shape[0]) // batch)
     return net, hist
 
 
 def validation_loss(net, X, T, rows, chunk: int = 1 << 17) -> float:
-    """Mean squared error on normalised targets over the listed rows (torch's
-    work runs on the network's stream)."""
+    """Mean squared error on normalised targets over the listed rows: the
+    network's outputs (its forward kernel) compared with the targets on the
+    host (rows gathered on the network's stream)."""
     import torch
     with torch.cuda.stream(_torch_stream(net.stream)):
         return _validation_loss(net, X, T, rows, chunk)
@@ -172,18 +173,19 @@ def validation_loss(net, X, T, rows, chunk: int = 1 << 17) -> float:
 
 def _validation_loss(net, X, T, rows, chunk):
     import torch
-    x_mean, x_inv, y_mean, y_std = net.get_norm()
-    ym = torch.as_tensor(y_mean, device="cuda")
-    ys = torch.as_tensor(y_std, device="cuda")
+    _, _, _, y_std = net.get_norm()
+    ys = np.asarray(y_std, np.float64)
     tot, cnt = 0.0, 0
     for a in range(0, rows.numel(), chunk):
         idx = rows[a:a + chunk].long()
         x = X[idx].contiguous()
         y = torch.empty((idx.numel(), 4), device="cuda")
         net.forward(x, y)
-        e = (y - T[idx]) / ys
+        t = T[idx]
+        torch.cuda.current_stream().synchronize()
+        e = (y.cpu().numpy().astype(np.float64) - t.cpu().numpy().astype(np.float64)) / ys
         tot += float((e * e).sum())
-        cnt += e.numel()
+        cnt += e.size
     return tot / max(cnt, 1)
 
 

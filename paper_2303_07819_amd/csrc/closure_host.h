@@ -381,6 +381,10 @@ struct sp_mlp {
     double* tr_lpart = nullptr;
     float* epoch_loss = nullptr; // per-batch losses of sp_mlp_train_epoch
     int64_t epoch_cap = 0;
+    // input noise of training steps (sp_mlp_set_input_noise)
+    int noise_n = 0;
+    uint64_t noise_seed = 0;
+    float noise_sd[spmlp::kIn] = {};
 };
 
 namespace {
@@ -493,6 +497,10 @@ sp_status fused_step(sp_mlp* mm, const float* X, const float* T, const int32_t* 
     ta.dT = mm->tr_dT;
     ta.bpart = mm->tr_bpart;
     ta.lpart = mm->tr_lpart;
+    ta.noise_n = adam ? mm->noise_n : 0;   // training steps only, never the plain gradient
+    ta.noise_seed = mm->noise_seed;
+    ta.noise_step = mm->adam_t;
+    for (int f = 0; f < 48; ++f) ta.noise_sd[f] = f < mm->noise_n ? mm->noise_sd[f] : 0.0f;
     hipLaunchKernelGGL(tr_rows_kernel, dim3((unsigned)(Bp / 16 / kTrWaves)), dim3(64 * kTrWaves), kTrLds, mm->stream,
                        ta);
     MLP_HIP(mm, hipGetLastError());
@@ -718,6 +726,18 @@ sp_status sp_mlp_train_step(sp_mlp* mm, const float* X, const float* T, const in
         MLP_HIP(mm, hipStreamSynchronize(mm->stream));
         *loss = ls / (float)(B * kOut);
     }
+    return SP_OK;
+}
+
+sp_status sp_mlp_set_input_noise(sp_mlp* mm, int32_t nfeat, const float* sd, uint64_t seed)
+{
+    if (!mm) return SP_EINVAL;
+    if (nfeat < 0 || nfeat > kIn || (nfeat > 0 && !sd)) return mfail(mm, SP_EINVAL, "bad input noise arguments");
+    for (int f = 0; f < nfeat; ++f)
+        if (!(sd[f] >= 0.0f) || !std::isfinite(sd[f])) return mfail(mm, SP_EINVAL, "noise scale of input %d", f);
+    mm->noise_n = nfeat;
+    mm->noise_seed = seed;
+    for (int f = 0; f < kIn; ++f) mm->noise_sd[f] = f < nfeat ? sd[f] : 0.0f;
     return SP_OK;
 }
 

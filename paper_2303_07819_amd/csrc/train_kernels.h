@@ -168,7 +168,36 @@ struct TrainArgs {
     uint16_t* dT;             // kTrDRows x Bp deltas (tr_at)
     float* bpart;             // [Bp / 16][kTrBias] column sums of the FP32 deltas
     double* lpart;            // [Bp / 16] squared errors
+    // input noise of training steps: feature f < noise_n of X row i gets
+    // noise_sd[f] times a standard normal of (noise_seed, noise_step, i, f)
+    int noise_n;
+    unsigned long long noise_seed;
+    long long noise_step;
+    float noise_sd[48];
 };
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the output function of one step.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x)
+{
+    unsigned long long z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Two standard normals from 64 random bits by the Box-Muller transform
+// (two 24-bit uniforms, the first in (0, 1]).
+__device__ __forceinline__ void box_muller(unsigned long long h, float& z0, float& z1)
+{
+    const float u1 = (float)((h >> 40) + 1) * 5.9604644775390625e-8f;
+    const float u2 = (float)(h & 0xffffffull) * 5.9604644775390625e-8f;
+    const float r = sqrtf(-2.0f * __logf(u1));
+    float sn, cs;
+    __sincosf(6.283185307179586f * u2, &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
+}
 
 // FP32 sum over each row of 16 lanes by DPP row shifts (fixed order); the
 // total lands in the row's last lane.
@@ -214,6 +243,21 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
     float xr[12], tr[4];
 #pragma unroll
     for (int i = 0; i < 12; ++i) xr[i] = ta.X[src * kIn + min((i >> 2) * 16 + g4 + (i & 3), kIn - 1)];
+    if (ta.noise_n > 0) {
+        // features f and f + 1 (f even) take the two normals of pair f / 2
+        const unsigned long long base = splitmix64(splitmix64(ta.noise_seed ^ (unsigned long long)ta.noise_step) ^
+                                                   (unsigned long long)src);
+#pragma unroll
+        for (int i = 0; i < 12; i += 2) {
+            const int f = (i >> 2) * 16 + g4 + (i & 3);
+            if (f < ta.noise_n) {
+                float z0, z1;
+                box_muller(splitmix64(base ^ (unsigned long long)(f >> 1)), z0, z1);
+                xr[i] += ta.noise_sd[f] * z0;
+                if (f + 1 < ta.noise_n) xr[i + 1] += ta.noise_sd[f + 1] * z1;
+            }
+        }
+    }
 #pragma unroll
     for (int o = 0; o < 4; ++o) tr[o] = ta.T[src * kOut + o];
     {

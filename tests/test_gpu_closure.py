@@ -196,3 +196,74 @@ def test_residual_tendencies_match_oracle():
     e = np.abs(ts - ref) / np.maximum(np.abs(ref), 1e-2 * np.sqrt(np.mean(ref ** 2, axis=0)))
     _say(f"residual tendency max rel err {e.max():.2e}")
     assert e.max() <= 1e-3
+
+
+# ------------------------------------------------------- training input noise
+def _probe_net(f):
+    """A network whose first output reproduces input f (weights 2^-10 into the
+    first hidden unit, which GELU halves at such small arguments in each of
+    the three layers, then 2^13 out) and whose other outputs are zero."""
+    p = {n: np.zeros(s) for n, s in omlp.SHAPES}
+    p["W1"][0, f] = 2.0 ** -10
+    p["W2"][0, 0] = 1.0
+    p["W3"][0, 0] = 1.0
+    p["W4"][0, 0] = 2.0 ** 13
+    net = sp.MLP()
+    net.set_params(omlp.pack(p).astype(np.float32))
+    net.set_norm(np.zeros(45), np.ones(45), np.zeros(4), np.ones(4))
+    return net
+
+
+def test_training_input_noise_scale_and_repeatability():
+    """sp_mlp_set_input_noise: with noise of scale s on input f only, the
+    probe network's first output is the input plus that noise, so the loss a
+    training step reports (before its update; lr far too small to move the
+    weights) is s^2 / 4 of the four outputs, within the sampling spread of
+    4096 rows (2.2 % for a mean of squared normals; bar 10 %).  Every step
+    draws new noise, a second network with the same seed draws the same, and
+    the plain gradient never sees noise."""
+    f, B = 5, 4096
+    rng = np.random.default_rng(7)
+    x = rng.normal(0, 1, (B, 45)).astype(np.float32)
+    t = np.zeros((B, 4), np.float32)
+    t[:, 0] = x[:, f]
+    X, T = dev(x), dev(t)
+    losses = {}
+    for s in (0.0, 1.0, 2.0):
+        net = _probe_net(f)
+        sd = np.zeros(36, np.float32)
+        sd[f] = s
+        net.set_input_noise(sd if s > 0 else None, seed=11)
+        losses[s] = [net.train_step(X, T, None, B, 1e-30) for _ in range(4)]
+        if s > 0:
+            _, g_loss = net.gradient(X, T)
+            assert g_loss < 1e-4                     # the gradient's inputs are clean
+        net.close()
+    _say(f"reported losses: {losses}")
+    assert max(losses[0.0]) < 1e-4                   # the probe reproduces its input up to rounding
+    for s in (1.0, 2.0):
+        for ls in losses[s]:
+            assert abs(ls / (s * s / 4.0) - 1.0) < 0.1
+    assert len(set(losses[1.0])) == 4                # new noise in every Adam step
+    net = _probe_net(f)
+    sd = np.zeros(36, np.float32)
+    sd[f] = 1.0
+    net.set_input_noise(sd, seed=11)
+    again = [net.train_step(X, T, None, B, 1e-30) for _ in range(4)]
+    net.set_input_noise(sd, seed=12)
+    other = net.train_step(X, T, None, B, 1e-30)
+    net.close()
+    assert again == losses[1.0]                      # the same seed repeats the same draws
+    assert other != losses[1.0][0]
+
+
+def test_training_input_noise_limits():
+    net = sp.MLP()
+    with pytest.raises(sp.SpdemError):
+        net.set_input_noise(np.ones(46, np.float32))
+    with pytest.raises(sp.SpdemError):
+        net.set_input_noise(np.array([1.0, -1.0], np.float32))
+    with pytest.raises(sp.SpdemError):
+        net.set_input_noise(np.array([np.nan], np.float32))
+    net.set_input_noise(None)
+    net.close()
