@@ -101,7 +101,7 @@ def generate_samples(workloads, schedule=None, stream=None, log=None):
 
 
 def train(X, T, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0, holdout: float = 0.05,
-          stencil_noise: float = 0.5, use_stencil: bool = True, stream=None, log=None):
+          stencil_noise: float = 1.0, use_stencil: bool = True, stream=None, log=None):
     """Adam on the bfloat16 network from Kaiming-uniform initial weights;
     normalisation from the training rows.  Every epoch sees the continuum
     stencil inputs (the first 36 features) with Gaussian noise of
