@@ -419,13 +419,16 @@ sp_status sp_mlp_train_epoch(sp_mlp* net, const float* X, const float* T, const 
                              int32_t batch, float lr, float* mean_loss);
 /* Input noise of the training steps (sp_mlp_train_step, sp_mlp_train_epoch;
  * never sp_mlp_gradient or sp_mlp_forward), the data augmentation of the
- * closure's training: in Adam step s (counted since the network was created)
- * input f < nfeat of row i of X gets sd[f] (host, raw input units) times a
- * standard normal from the counter-based generator SplitMix64 of (seed, s, i,
- * f / 2) through the Box-Muller transform (features f and f + 1 of an even f
- * share one pair), so that a run repeats bit for bit.  nfeat = 0 turns it off.
+ * closure's training: in Adam step s (the number of steps the network took
+ * before it) input f < nfeat of row i of X gets sd[f] (host, raw input units)
+ * times a standard normal from the counter-based generator SplitMix64 of
+ * (seed, s, i, f / 2) through the Box-Muller transform (features f and f + 1
+ * of an even f share one pair), so that a run repeats bit for bit.  With noise
+ * on, a training call first writes a noisy copy of its rows (all of an
+ * epoch's, in the order its steps read them) into a buffer the network owns
+ * (grown as needed, 196 B per row).  nfeat = 0 turns it off.
  * Errors: SP_EINVAL (nfeat outside [0, SP_MLP_IN], sd null for nfeat > 0, a
- * negative or non-finite sd). */
+ * negative or non-finite sd); the training calls also SP_ENOMEM. */
 sp_status sp_mlp_set_input_noise(sp_mlp* net, int32_t nfeat, const float* sd, uint64_t seed);
 /* closure inputs of every cell of the current state Q into x [ncells][45] (device) */
 sp_status sp_closure_features(sp_ctx* ctx, float* x);

@@ -381,10 +381,14 @@ struct sp_mlp {
     double* tr_lpart = nullptr;
     float* epoch_loss = nullptr; // per-batch losses of sp_mlp_train_epoch
     int64_t epoch_cap = 0;
-    // input noise of training steps (sp_mlp_set_input_noise)
+    // input noise of training steps (sp_mlp_set_input_noise) and the noisy
+    // copy of the rows a call's steps read
     int noise_n = 0;
     uint64_t noise_seed = 0;
     float noise_sd[spmlp::kIn] = {};
+    float* aug_x = nullptr;
+    float* aug_t = nullptr;
+    int64_t aug_cap = 0;
 };
 
 namespace {
@@ -468,6 +472,30 @@ sp_status ensure_train(sp_mlp* mm, int B, int* Bp_out)
     return SP_OK;
 }
 
+// The noisy copy of n training rows (gathered by `rows` if not null) for the
+// next Adam steps (step s = the number of steps taken before it), `batch`
+// rows per step; *X, *T then point at the copy.
+sp_status augment_rows(sp_mlp* mm, const float** X, const float** T, const int32_t* rows, int64_t n, int batch)
+{
+    if (n > mm->aug_cap) {
+        MLP_HIP(mm, hipStreamSynchronize(mm->stream));
+        SP_TRY(malloc_m(mm, &mm->aug_x, (size_t)n * kIn));
+        SP_TRY(malloc_m(mm, &mm->aug_t, (size_t)n * kOut));
+        mm->aug_cap = n;
+    }
+    NoiseArgs na;
+    memset(&na, 0, sizeof na);
+    na.n = mm->noise_n;
+    na.seed = mm->noise_seed;
+    for (int f = 0; f < mm->noise_n; ++f) na.sd[f] = mm->noise_sd[f];
+    hipLaunchKernelGGL(tr_augment_kernel, dim3((unsigned)((n * 24 + 255) / 256)), dim3(256), 0, mm->stream, *X, *T, rows,
+                       (long)n, (long long)mm->adam_t, batch, na, mm->aug_x, mm->aug_t);
+    MLP_HIP(mm, hipGetLastError());
+    *X = mm->aug_x;
+    *T = mm->aug_t;
+    return SP_OK;
+}
+
 // One fused step on B rows (gathered by `rows` if not null): the gradient into
 // mm->grad (adam false), or an Adam step at rate lr; the summed squared error
 // into *loss_d (device).
@@ -497,10 +525,6 @@ sp_status fused_step(sp_mlp* mm, const float* X, const float* T, const int32_t* 
     ta.dT = mm->tr_dT;
     ta.bpart = mm->tr_bpart;
     ta.lpart = mm->tr_lpart;
-    ta.noise_n = adam ? mm->noise_n : 0;   // training steps only, never the plain gradient
-    ta.noise_seed = mm->noise_seed;
-    ta.noise_step = mm->adam_t;
-    for (int f = 0; f < 48; ++f) ta.noise_sd[f] = f < mm->noise_n ? mm->noise_sd[f] : 0.0f;
     hipLaunchKernelGGL(tr_rows_kernel, dim3((unsigned)(Bp / 16 / kTrWaves)), dim3(64 * kTrWaves), kTrLds, mm->stream,
                        ta);
     MLP_HIP(mm, hipGetLastError());
@@ -600,7 +624,8 @@ void sp_mlp_destroy(sp_mlp* mm)
     if (!mm) return;
     if (mm->stream) (void)hipStreamSynchronize(mm->stream);
     void* ps[] = {mm->theta, mm->theta_h, mm->wsw, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->timg[0],
-                  mm->timg[1], mm->tr_gp, mm->tr_aT, mm->tr_dT, mm->tr_bpart, mm->tr_lpart, mm->epoch_loss};
+                  mm->timg[1], mm->tr_gp, mm->tr_aT, mm->tr_dT, mm->tr_bpart, mm->tr_lpart, mm->epoch_loss,
+                  mm->aug_x, mm->aug_t};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (mm->own_stream && mm->stream) (void)hipStreamDestroy(mm->stream);
@@ -719,6 +744,10 @@ sp_status sp_mlp_train_step(sp_mlp* mm, const float* X, const float* T, const in
                             float* loss)
 {
     if (!mm || !X || !T || B < 1 || !(lr > 0)) return mm ? mfail(mm, SP_EINVAL, "bad training arguments") : SP_EINVAL;
+    if (mm->noise_n > 0) {
+        SP_TRY(augment_rows(mm, &X, &T, rows, B, B));
+        rows = nullptr;
+    }
     SP_TRY(fused_step(mm, X, T, rows, B, true, lr, mm->loss_d));
     if (loss) {
         float ls = 0.0f;
@@ -755,7 +784,14 @@ sp_status sp_mlp_train_epoch(sp_mlp* mm, const float* X, const float* T, const i
     }
     float* const lbuf = mm->epoch_loss;
     sp_status st = SP_OK;
-    for (int64_t b = 0; b < nb && !st; ++b) st = fused_step(mm, X, T, perm + b * batch, batch, true, lr, lbuf + b);
+    if (mm->noise_n > 0 && nb > 0) {
+        // the epoch's rows with their noise, in the order the steps read them
+        SP_TRY(augment_rows(mm, &X, &T, perm, nb * batch, batch));
+        for (int64_t b = 0; b < nb && !st; ++b)
+            st = fused_step(mm, X + b * batch * kIn, T + b * batch * kOut, nullptr, batch, true, lr, lbuf + b);
+    } else {
+        for (int64_t b = 0; b < nb && !st; ++b) st = fused_step(mm, X, T, perm + b * batch, batch, true, lr, lbuf + b);
+    }
     if (!st && mean_loss) {
         losses.resize((size_t)std::max<int64_t>(nb, 1));
         if (hipMemcpyAsync(losses.data(), lbuf, losses.size() * 4, hipMemcpyDeviceToHost, mm->stream) != hipSuccess ||

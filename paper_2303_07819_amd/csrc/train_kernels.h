@@ -168,12 +168,15 @@ struct TrainArgs {
     uint16_t* dT;             // kTrDRows x Bp deltas (tr_at)
     float* bpart;             // [Bp / 16][kTrBias] column sums of the FP32 deltas
     double* lpart;            // [Bp / 16] squared errors
-    // input noise of training steps: feature f < noise_n of X row i gets
-    // noise_sd[f] times a standard normal of (noise_seed, noise_step, i, f)
-    int noise_n;
-    unsigned long long noise_seed;
-    long long noise_step;
-    float noise_sd[48];
+};
+
+// Input noise of training steps: feature f < n of row i (of the caller's X)
+// consumed by Adam step s gets sd[f] times a standard normal of (seed, s, i,
+// f / 2).
+struct NoiseArgs {
+    int n;
+    unsigned long long seed;
+    float sd[48];
 };
 
 // SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
@@ -197,6 +200,40 @@ __device__ __forceinline__ void box_muller(unsigned long long h, float& z0, floa
     __sincosf(6.283185307179586f * u2, &sn, &cs);
     z0 = r * cs;
     z1 = r * sn;
+}
+
+// Training rows with their input noise, in the order the steps read them:
+// row k of the output is row rows[k] of X (k if rows is null) plus its noise
+// for Adam step step0 + k / batch; targets copied alongside.  24 threads per
+// row, neighbouring threads on neighbouring words: thread p < 23 takes
+// features 2p and 2p + 1 (the two normals of pair p), thread 23 the targets.
+__global__ __launch_bounds__(256) void tr_augment_kernel(const float* X, const float* T, const int32_t* rows,
+                                                         long n, long long step0, int batch, NoiseArgs na,
+                                                         float* Xo, float* To)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long k = t / 24;
+    const int p = (int)(t - k * 24);
+    if (k >= n) return;
+    const long i = rows ? (long)rows[k] : k;
+    if (p == 23) {
+#pragma unroll
+        for (int o = 0; o < kOut; ++o) To[k * kOut + o] = T[i * kOut + o];
+        return;
+    }
+    const int f = 2 * p;
+    float a = X[i * kIn + f];
+    float b = f + 1 < kIn ? X[i * kIn + f + 1] : 0.0f;
+    if (f < na.n) {
+        const unsigned long long base =
+            splitmix64(splitmix64(na.seed ^ (unsigned long long)(step0 + k / batch)) ^ (unsigned long long)i);
+        float z0, z1;
+        box_muller(splitmix64(base ^ (unsigned long long)p), z0, z1);
+        a += na.sd[f] * z0;
+        if (f + 1 < na.n) b += na.sd[f + 1] * z1;
+    }
+    Xo[k * kIn + f] = a;
+    if (f + 1 < kIn) Xo[k * kIn + f + 1] = b;
 }
 
 // FP32 sum over each row of 16 lanes by DPP row shifts (fixed order); the
@@ -243,21 +280,7 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
     float xr[12], tr[4];
 #pragma unroll
     for (int i = 0; i < 12; ++i) xr[i] = ta.X[src * kIn + min((i >> 2) * 16 + g4 + (i & 3), kIn - 1)];
-    if (ta.noise_n > 0) {
-        // features f and f + 1 (f even) take the two normals of pair f / 2
-        const unsigned long long base = splitmix64(splitmix64(ta.noise_seed ^ (unsigned long long)ta.noise_step) ^
-                                                   (unsigned long long)src);
-#pragma unroll
-        for (int i = 0; i < 12; i += 2) {
-            const int f = (i >> 2) * 16 + g4 + (i & 3);
-            if (f < ta.noise_n) {
-                float z0, z1;
-                box_muller(splitmix64(base ^ (unsigned long long)(f >> 1)), z0, z1);
-                xr[i] += ta.noise_sd[f] * z0;
-                if (f + 1 < ta.noise_n) xr[i + 1] += ta.noise_sd[f + 1] * z1;
-            }
-        }
-    }
+
 #pragma unroll
     for (int o = 0; o < 4; ++o) tr[o] = ta.T[src * kOut + o];
     {
