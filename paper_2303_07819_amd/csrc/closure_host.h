@@ -374,7 +374,6 @@ struct sp_mlp {
     int tcur = 0;
     bool timg_stale = true;      // parameters or normalisation changed outside the fused step
     int64_t tr_rows = 0;         // padded batch the scratch holds
-    float* tr_gp = nullptr;
     uint16_t* tr_aT = nullptr;
     uint16_t* tr_dT = nullptr;
     float* tr_bpart = nullptr;
@@ -458,8 +457,7 @@ sp_status ensure_train(sp_mlp* mm, int B, int* Bp_out)
     if (Bp <= mm->tr_rows) return SP_OK;
     MLP_HIP(mm, hipStreamSynchronize(mm->stream));
     const size_t P = (size_t)Bp;
-    sp_status st = malloc_m(mm, &mm->tr_gp, P * 384);
-    if (!st) st = malloc_m(mm, &mm->tr_aT, P * kTrARows);
+    sp_status st = malloc_m(mm, &mm->tr_aT, P * kTrARows);
     if (!st) st = malloc_m(mm, &mm->tr_dT, P * kTrDRows);
     if (!st) st = malloc_m(mm, &mm->tr_bpart, P / 16 * kTrBias);
     if (!st) st = malloc_m(mm, &mm->tr_lpart, P / 16);
@@ -520,12 +518,11 @@ sp_status fused_step(sp_mlp* mm, const float* X, const float* T, const int32_t* 
     ta.B = B;
     ta.Bp = Bp;
     ta.img = mm->timg[mm->tcur];
-    ta.gp = mm->tr_gp;
     ta.aT = mm->tr_aT;
     ta.dT = mm->tr_dT;
     ta.bpart = mm->tr_bpart;
     ta.lpart = mm->tr_lpart;
-    hipLaunchKernelGGL(tr_rows_kernel, dim3((unsigned)(Bp / 16 / kTrWaves)), dim3(64 * kTrWaves), kTrLds, mm->stream,
+    hipLaunchKernelGGL(tr_rows_kernel, dim3((unsigned)(Bp / 16)), dim3(64 * kTrSplit), kTrLdsAll, mm->stream,
                        ta);
     MLP_HIP(mm, hipGetLastError());
     GradArgs ga;
@@ -589,7 +586,7 @@ sp_status sp_mlp_create(void* stream, sp_mlp** out)
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_forward_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void*>(tr_rows_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kTrLds) != hipSuccess)
+                            (int)kTrLdsAll) != hipSuccess)
         st = SP_EDEVICE;
     if (!st) st = malloc_m(mm, &mm->theta, kNParams);
     if (!st) st = malloc_m(mm, &mm->theta_h, kNParams);
@@ -624,7 +621,7 @@ void sp_mlp_destroy(sp_mlp* mm)
     if (!mm) return;
     if (mm->stream) (void)hipStreamSynchronize(mm->stream);
     void* ps[] = {mm->theta, mm->theta_h, mm->wsw, mm->m, mm->v, mm->grad, mm->norm, mm->loss_d, mm->timg[0],
-                  mm->timg[1], mm->tr_gp, mm->tr_aT, mm->tr_dT, mm->tr_bpart, mm->tr_lpart, mm->epoch_loss,
+                  mm->timg[1], mm->tr_aT, mm->tr_dT, mm->tr_bpart, mm->tr_lpart, mm->epoch_loss,
                   mm->aug_x, mm->aug_t};
     for (void* p : ps)
         if (p) (void)hipFree(p);

@@ -1,18 +1,20 @@
 // Fused training step of the closure network: two launches per Adam step.
 //
-// tr_rows_kernel: one wavefront per 16 rows of the batch, the network's
+// tr_rows_kernel: one workgroup per 16 rows of the batch, the network's
 // weights staged in LDS as MFMA operand tiles (forward tiles as in the
 // inference forward, unhalved, and the transposed tiles of W2, W3 and W4 for
-// the backward products).  Forward through the four layers with the
-// activations chained in registers; the GELU derivatives kept in a scratch
-// buffer in the lane layout that reads them back; the loss gradient of the
-// mean squared error on normalised targets; then backward through W4^T, W3^T
-// and W2^T, chained the same way (the transposed products dH^T = W^T dZ^T
-// take W^T as the A operand, so the output tile of one is the B operand of the
-// next).  Written out for the weight gradients: every layer's input
-// activations and deltas in bfloat16 (blocks of 16 features x 8 rows), and per
-// 16-row tile the FP32 column sums of the deltas (bias gradients) and the
-// squared error (loss).
+// the backward products).  Each of its eight wavefronts takes one 16-unit
+// tile of every hidden layer: forward through the four layers, each layer's
+// output tiles exchanged through LDS to form the next product's B operand;
+// the GELU derivatives of the wavefront's own tiles kept in registers; the
+// loss gradient of the mean squared error on normalised targets (every
+// wavefront forms it); then backward through W4^T, W3^T and W2^T, exchanged
+// the same way (the transposed products dH^T = W^T dZ^T take W^T as the A
+// operand, so the output tile of one is the B operand of the next).  Written
+// out for the weight gradients: every layer's input activations and deltas in
+// bfloat16 (blocks of 16 features x 8 rows), and per 16-row tile the FP32
+// column sums of the deltas (bias gradients) and the squared error (loss).
+// Every value is computed as by one wavefront carrying the whole tile.
 //
 // tr_grad_kernel: one workgroup per 16 x 16 tile of a weight gradient
 // (160 tiles), dW = sum over rows of d^T a as 16x16x32 MFMA steps over the
@@ -30,8 +32,10 @@
 
 namespace spmlp {
 
-constexpr int kTrWaves = 4;            // wavefronts (16-row tiles) per workgroup of tr_rows_kernel
-constexpr int kTrRowAlign = 256;       // padded batch: whole workgroups and 32-row steps per gradient wavefront
+constexpr int kTrSplit = 8;            // wavefronts sharing one 16-row tile in tr_rows_kernel
+constexpr int kTrTiles = 8 / kTrSplit; // 16-unit tiles of each hidden layer per wavefront
+static_assert(kTrTiles * kTrSplit == 8, "the eight tiles of a hidden layer split evenly");
+constexpr int kTrRowAlign = 256;       // padded batch: 32-row steps for each wavefront of tr_grad_kernel
 constexpr int kTrGradWaves = 8;        // wavefronts splitting the rows of one weight-gradient tile
 // LDS image of tr_rows_kernel (bytes)
 constexpr size_t kTrOffF1 = 0;                                   // W1: 8 x 3 tiles of 16 x 16 (bf16x4 per lane)
@@ -44,7 +48,9 @@ constexpr size_t kTrOffB2 = kTrOffB3 + (size_t)32 * 64 * 16;     // W2^T
 constexpr size_t kTrOffBias = kTrOffB2 + (size_t)32 * 64 * 16;  // b1, b2, b3 [128], b4 [4] (FP32)
 constexpr size_t kTrOffNorm = kTrOffBias + (size_t)(3 * kHid + kOut) * 4;   // x mean, x inv std [48 each], t mean, t inv std [4 each]
 constexpr size_t kTrLds = kTrOffNorm + (size_t)104 * 4;
-static_assert(kTrLds <= 160 * 1024, "one training image per compute unit");
+constexpr size_t kTrOffX = kTrLds;                               // layer exchange: 2 x 8 tiles x 64 lanes x bf16x4
+constexpr size_t kTrLdsAll = kTrOffX + (size_t)2 * 8 * 64 * 8;
+static_assert(kTrLdsAll <= 160 * 1024, "one training workgroup per compute unit");
 static_assert(kTrOffBias % 16 == 0 && kTrOffNorm % 16 == 0, "aligned LDS reads");
 constexpr int kTrBias = 3 * kHid + kOut;   // bias partials per tile: d1, d2, d3 [128], d4 [4]
 // activation and delta regions (offsets in features; a region of F features holds F x Bp values)
@@ -163,7 +169,6 @@ struct TrainArgs {
     const int32_t* rows;      // batch row r is X row rows[r] (identity if null)
     int B, Bp;                // batch, padded batch (multiple of kTrRowAlign)
     const unsigned char* img; // training image (kTrLds bytes)
-    float* gp;                // [Bp / 16][3][8][64] f32x4: GELU derivatives in lane layout
     uint16_t* aT;             // kTrARows x Bp activations (tr_at)
     uint16_t* dT;             // kTrDRows x Bp deltas (tr_at)
     float* bpart;             // [Bp / 16][kTrBias] column sums of the FP32 deltas
@@ -267,16 +272,16 @@ __device__ __forceinline__ bf16x4 tr_delta(const f32x4 dh, const f32x4 gpz, bool
     return h;
 }
 
-__global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
+__global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
 {
     extern __shared__ __align__(16) unsigned char tr_smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = blockIdx.x * kTrWaves + wave;
+    const int tile = blockIdx.x;
     const int g4 = 4 * (lane >> 4);
     const long rr = (long)tile * 16 + (lane & 15);
     const bool ok = rr < ta.B;
     const long src = ta.rows ? (long)ta.rows[ok ? rr : ta.B - 1] : (ok ? rr : ta.B - 1);
-    // the row's raw inputs and targets, in flight with the staging
+    // the row's raw inputs and targets (every wavefront of the tile), in flight with the staging
     float xr[12], tr[4];
 #pragma unroll
     for (int i = 0; i < 12; ++i) xr[i] = ta.X[src * kIn + min((i >> 2) * 16 + g4 + (i & 3), kIn - 1)];
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
     for (int o = 0; o < 4; ++o) tr[o] = ta.T[src * kOut + o];
     {
         // eight reads in flight before their writes, the image in rounds of eight
-        constexpr int kVec = (int)(kTrLds / 16), kStride = 64 * kTrWaves;
+        constexpr int kVec = (int)(kTrLds / 16), kStride = 64 * kTrSplit;
         const uint4* srcv = reinterpret_cast<const uint4*>(ta.img);
         uint4* dst = reinterpret_cast<uint4*>(tr_smem);
         for (int base = 0; base < kVec; base += 8 * kStride) {
@@ -309,8 +314,17 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
     const bf16x8* B2 = reinterpret_cast<const bf16x8*>(tr_smem + kTrOffB2);
     const float* bias = reinterpret_cast<const float*>(tr_smem + kTrOffBias);
     const float* nrm = reinterpret_cast<const float*>(tr_smem + kTrOffNorm);
+    // exchange of a layer's output tiles: buffer q holds tile t of lane l as
+    // the (t % 2) half of bf16x8 slot (q 4 + t / 2) 64 + l, so that one read
+    // gives the next product's B operand of K block t / 2
+    bf16x4* xw = reinterpret_cast<bf16x4*>(tr_smem + kTrOffX);
+    const bf16x8* xr8 = reinterpret_cast<const bf16x8*>(tr_smem + kTrOffX);
+    auto put = [&](int q, int t, const bf16x4 h) { xw[2 * ((q * 4 + (t >> 1)) * 64 + lane) + (t & 1)] = h; };
+    auto get = [&](int q, bf16x8* b) {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) b[kb] = xr8[(q * 4 + kb) * 64 + lane];
+    };
     const int Bp = ta.Bp;
-    f32x4* gp = reinterpret_cast<f32x4*>(ta.gp) + (size_t)tile * 3 * 8 * 64;
     float* bp = ta.bpart + (size_t)tile * kTrBias;
 
     // ---- inputs: features 4 (lane / 16) + q of each 16-feature block, normalised
@@ -324,12 +338,15 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
             v[q] = ok ? (xr[kb * 4 + q] - nrm[f0 + q]) * nrm[48 + f0 + q] : 0.0f;
         }
         xb[kb] = to_bf16x4(v[0], v[1], v[2], v[3]);
+        if (kb % kTrSplit == wave) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ta.aT[tr_at(kTrA0 + f0 + q, rr, Bp)] = (uint16_t)xb[kb][q];
+            for (int q = 0; q < 4; ++q) ta.aT[tr_at(kTrA0 + f0 + q, rr, Bp)] = (uint16_t)xb[kb][q];
+        }
     }
-    // ---- forward: z = bias + W a, a' = GELU(z) in bfloat16, GELU'(z) kept
-    bf16x4 h1[8], h2[8], h3[8];
-    auto hidden = [&](const f32x4 z, int layer, int ob, bf16x4& out) {
+    // ---- forward: z = bias + W a, a' = GELU(z) in bfloat16, GELU'(z) kept in
+    // registers; this wavefront takes output tiles wave kTrTiles .. + kTrTiles - 1
+    f32x4 gz[3][kTrTiles];
+    auto hidden = [&](const f32x4 z, int layer, int ob, bf16x4& out, f32x4& gd) {
         float a[4], d[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -338,46 +355,57 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
             a[r] = ok ? gl : 0.0f;
         }
         out = to_bf16x4(a[0], a[1], a[2], a[3]);
-        gp[(layer * 8 + ob) * 64 + lane] = f32x4{d[0], d[1], d[2], d[3]};
+        gd = f32x4{d[0], d[1], d[2], d[3]};
         const int arow = (layer == 0 ? kTrA1 : layer == 1 ? kTrA2 : kTrA3) + ob * 16 + g4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) ta.aT[tr_at(arow + r, rr, Bp)] = (uint16_t)out[r];
     };
+    bf16x8 b[4];
 #pragma unroll
-    for (int ob = 0; ob < 8; ++ob) {
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ob = wave * kTrTiles + j;
         f32x4 acc = *reinterpret_cast<const f32x4*>(bias + ob * 16 + g4);
 #pragma unroll
         for (int kb = 0; kb < 3; ++kb) acc = mfma_step(F1[(ob * 3 + kb) * 64 + lane], xb[kb], acc);
-        hidden(acc, 0, ob, h1[ob]);
+        bf16x4 h;
+        hidden(acc, 0, ob, h, gz[0][j]);
+        put(0, ob, h);
     }
-    {
-        bf16x8 b[4];
+    __syncthreads();
+    get(0, b);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) b[kb] = join(h1[2 * kb], h1[2 * kb + 1]);
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ob = wave * kTrTiles + j;
+        f32x4 acc = *reinterpret_cast<const f32x4*>(bias + kHid + ob * 16 + g4);
 #pragma unroll
-        for (int ob = 0; ob < 8; ++ob) {
-            f32x4 acc = *reinterpret_cast<const f32x4*>(bias + kHid + ob * 16 + g4);
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F2[(ob * 4 + kb) * 64 + lane], b[kb], acc);
-            hidden(acc, 1, ob, h2[ob]);
-        }
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) b[kb] = join(h2[2 * kb], h2[2 * kb + 1]);
-#pragma unroll
-        for (int ob = 0; ob < 8; ++ob) {
-            f32x4 acc = *reinterpret_cast<const f32x4*>(bias + 2 * kHid + ob * 16 + g4);
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F3[(ob * 4 + kb) * 64 + lane], b[kb], acc);
-            hidden(acc, 2, ob, h3[ob]);
-        }
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F2[(ob * 4 + kb) * 64 + lane], b[kb], acc);
+        bf16x4 h;
+        hidden(acc, 1, ob, h, gz[1][j]);
+        put(1, ob, h);
     }
-    // ---- output, loss and its gradient (lanes 0-15 hold the 4 outputs of row lane)
+    __syncthreads();
+    get(1, b);
+#pragma unroll
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ob = wave * kTrTiles + j;
+        f32x4 acc = *reinterpret_cast<const f32x4*>(bias + 2 * kHid + ob * 16 + g4);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F3[(ob * 4 + kb) * 64 + lane], b[kb], acc);
+        bf16x4 h;
+        hidden(acc, 2, ob, h, gz[2][j]);
+        put(0, ob, h);
+    }
+    __syncthreads();
+    get(0, b);
+    // ---- output, loss and its gradient (lanes 0-15 hold the 4 outputs of row
+    // lane); every wavefront forms the output gradient, the first stores it
+    // with the loss and the output bias partials
     bf16x4 dy = bf16x4{0, 0, 0, 0};
     {
         f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         const int ai = g4 + (lane & 3);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F4[kb * 16 + ai], join(h3[2 * kb], h3[2 * kb + 1]), acc);
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(F4[kb * 16 + ai], b[kb], acc);
         const bool out_lane = lane < 16 && ok;
         float d[4];
         double sq = 0.0;
@@ -389,57 +417,51 @@ __global__ __launch_bounds__(64 * kTrWaves) void tr_rows_kernel(TrainArgs ta)
             d[o] = out_lane ? 2.0f * e / (float)(ta.B * kOut) : 0.0f;
             sq += out_lane ? (double)(e * e) : 0.0;
         }
+        if (lane < 16) dy = to_bf16x4(d[0], d[1], d[2], d[3]);
+        if (wave == 0) {
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
-        if (lane == 0) ta.lpart[tile] = sq;
+            for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+            if (lane == 0) ta.lpart[tile] = sq;
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            float s = d[o];
+            for (int o = 0; o < 4; ++o) {
+                float s = d[o];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (lane == 0) bp[3 * kHid + o] = s;
-        }
-        if (lane < 16) {
-            dy = to_bf16x4(d[0], d[1], d[2], d[3]);
+                for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+                if (lane == 0) bp[3 * kHid + o] = s;
+            }
+            if (lane < 16) {
 #pragma unroll
-            for (int o = 0; o < 4; ++o) ta.dT[tr_at(kTrD4 + o, rr, Bp)] = (uint16_t)dy[o];
+                for (int o = 0; o < 4; ++o) ta.dT[tr_at(kTrD4 + o, rr, Bp)] = (uint16_t)dy[o];
+            }
         }
     }
-    // ---- backward: dh3 = W4^T dy, then W3^T d3 and W2^T d2; each layer's
-    // GELU derivatives read together before its products
-    bf16x4 d3[8], d2[8];
-    f32x4 gz[8];
+    // ---- backward: dh3 = W4^T dy, then W3^T d3 and W2^T d2, this wavefront's
+    // tiles of each, exchanged like the forward's
 #pragma unroll
-    for (int ib = 0; ib < 8; ++ib) gz[ib] = gp[(2 * 8 + ib) * 64 + lane];
-#pragma unroll
-    for (int ib = 0; ib < 8; ++ib) {
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ib = wave * kTrTiles + j;
         const f32x4 dh = mfma_step(B4[ib * 64 + lane], dy, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-        d3[ib] = tr_delta(dh, gz[ib], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD3 * Bp, bp + 2 * kHid);
+        put(1, ib, tr_delta(dh, gz[2][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD3 * Bp, bp + 2 * kHid));
     }
-    {
-        bf16x8 b[4];
+    __syncthreads();
+    get(1, b);
 #pragma unroll
-        for (int ib = 0; ib < 8; ++ib) gz[ib] = gp[(1 * 8 + ib) * 64 + lane];
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ib = wave * kTrTiles + j;
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) b[kb] = join(d3[2 * kb], d3[2 * kb + 1]);
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B3[(ib * 4 + kb) * 64 + lane], b[kb], acc);
+        put(0, ib, tr_delta(acc, gz[1][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD2 * Bp, bp + kHid));
+    }
+    __syncthreads();
+    get(0, b);
 #pragma unroll
-        for (int ib = 0; ib < 8; ++ib) {
-            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < kTrTiles; ++j) {
+        const int ib = wave * kTrTiles + j;
+        f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B3[(ib * 4 + kb) * 64 + lane], b[kb], acc);
-            d2[ib] = tr_delta(acc, gz[ib], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD2 * Bp, bp + kHid);
-        }
-#pragma unroll
-        for (int ib = 0; ib < 8; ++ib) gz[ib] = gp[(0 * 8 + ib) * 64 + lane];
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) b[kb] = join(d2[2 * kb], d2[2 * kb + 1]);
-#pragma unroll
-        for (int ib = 0; ib < 8; ++ib) {
-            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B2[(ib * 4 + kb) * 64 + lane], b[kb], acc);
-            (void)tr_delta(acc, gz[ib], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD1 * Bp, bp);
-        }
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B2[(ib * 4 + kb) * 64 + lane], b[kb], acc);
+        (void)tr_delta(acc, gz[0][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD1 * Bp, bp);
     }
 }
 
