@@ -17,9 +17,10 @@
 // Every value is computed as by one wavefront carrying the whole tile.
 //
 // tr_grad_kernel: one workgroup per 16 x 16 tile of a weight gradient
-// (160 tiles), dW = sum over rows of d^T a as 16x16x32 MFMA steps over the
-// batch, split over eight wavefronts and added in a fixed order; the bias
-// gradients from the tile partials in tile order; then either the gradient
+// (160 tiles, those of one output block of a layer on one XCD), dW = sum over
+// rows of d^T a as 16x16x32 MFMA steps over the batch, split over eight
+// wavefronts and added in a fixed order; the bias gradients from the tile
+// partials (stored column by column) in tile order; then either the gradient
 // written out, or the Adam update of the tile's parameters with the new
 // bfloat16 weights written into the other of two LDS images for the next step.
 //
@@ -171,7 +172,7 @@ struct TrainArgs {
     const unsigned char* img; // training image (kTrLds bytes)
     uint16_t* aT;             // kTrARows x Bp activations (tr_at)
     uint16_t* dT;             // kTrDRows x Bp deltas (tr_at)
-    float* bpart;             // [Bp / 16][kTrBias] column sums of the FP32 deltas
+    float* bpart;             // [kTrBias][Bp / 16] column sums of the FP32 deltas, by column then tile
     double* lpart;            // [Bp / 16] squared errors
 };
 
@@ -256,7 +257,7 @@ __device__ __forceinline__ float row16_sum(float x)
 // batch), its column sums over the 16 rows into the bias partials, and the
 // bfloat16 copy stored (tr_at) and returned as the next B operand.
 __device__ __forceinline__ bf16x4 tr_delta(const f32x4 dh, const f32x4 gpz, bool ok, int lane, int f0, long rr, int Bp,
-                                          uint16_t* dT, float* bp)
+                                          uint16_t* dT, float* bp, int bstride)
 {
     float d[4];
 #pragma unroll
@@ -264,7 +265,7 @@ __device__ __forceinline__ bf16x4 tr_delta(const f32x4 dh, const f32x4 gpz, bool
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const float s = row16_sum(d[r]);
-        if ((lane & 15) == 15) bp[f0 + r] = s;
+        if ((lane & 15) == 15) bp[(size_t)(f0 + r) * bstride] = s;
     }
     const bf16x4 h = to_bf16x4(d[0], d[1], d[2], d[3]);
 #pragma unroll
@@ -325,7 +326,8 @@ __global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
         for (int kb = 0; kb < 4; ++kb) b[kb] = xr8[(q * 4 + kb) * 64 + lane];
     };
     const int Bp = ta.Bp;
-    float* bp = ta.bpart + (size_t)tile * kTrBias;
+    const int ntile = Bp >> 4;
+    float* bp = ta.bpart + tile;   // bias partial of column c at bp[c ntile]
 
     // ---- inputs: features 4 (lane / 16) + q of each 16-feature block, normalised
     bf16x4 xb[3];
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
                 float s = d[o];
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-                if (lane == 0) bp[3 * kHid + o] = s;
+                if (lane == 0) bp[(size_t)(3 * kHid + o) * ntile] = s;
             }
             if (lane < 16) {
 #pragma unroll
@@ -441,7 +443,8 @@ __global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
     for (int j = 0; j < kTrTiles; ++j) {
         const int ib = wave * kTrTiles + j;
         const f32x4 dh = mfma_step(B4[ib * 64 + lane], dy, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-        put(1, ib, tr_delta(dh, gz[2][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD3 * Bp, bp + 2 * kHid));
+        put(1, ib, tr_delta(dh, gz[2][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD3 * Bp,
+                                     bp + (size_t)2 * kHid * ntile, ntile));
     }
     __syncthreads();
     get(1, b);
@@ -451,7 +454,8 @@ __global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
         f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B3[(ib * 4 + kb) * 64 + lane], b[kb], acc);
-        put(0, ib, tr_delta(acc, gz[1][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD2 * Bp, bp + kHid));
+        put(0, ib, tr_delta(acc, gz[1][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD2 * Bp,
+                                     bp + (size_t)kHid * ntile, ntile));
     }
     __syncthreads();
     get(0, b);
@@ -461,14 +465,14 @@ __global__ __launch_bounds__(64 * kTrSplit) void tr_rows_kernel(TrainArgs ta)
         f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) acc = mfma_step(B2[(ib * 4 + kb) * 64 + lane], b[kb], acc);
-        (void)tr_delta(acc, gz[0][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD1 * Bp, bp);
+        (void)tr_delta(acc, gz[0][j], ok, lane, ib * 16 + g4, rr, Bp, ta.dT + (long)kTrD1 * Bp, bp, ntile);
     }
 }
 
 struct GradArgs {
     const uint16_t* aT;       // [kTrARows][Bp]
     const uint16_t* dT;       // [kTrDRows][Bp]
-    const float* bpart;       // [ntile][kTrBias]
+    const float* bpart;       // [kTrBias][ntile]
     const double* lpart;      // [ntile]
     int ntile, Bp;
     float* grad;              // gradient mode: [kNParams] out
@@ -503,16 +507,21 @@ __global__ __launch_bounds__(64 * kTrGradWaves) void tr_grad_kernel(GradArgs g)
     __shared__ f32x4 red[kTrGradWaves][64];
     __shared__ uint16_t Wn[16][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int t = blockIdx.x;
+    // XCD-aware tiles: workgroups are dealt to the eight XCDs in turn, so the
+    // workgroups of XCD x = blockIdx % 8 take the tiles of output block ot = x
+    // of W1, W2 and W3 (their deltas read once into that XCD's L2) and input
+    // block it = x of W4
+    const int t = blockIdx.x;
+    const int x = t & 7, jt = t >> 3;
     int layer, ot, it;
-    if (t < 24) {
-        layer = 0; ot = t / 3; it = t % 3;
-    } else if (t < 88) {
-        layer = 1; ot = (t - 24) >> 3; it = (t - 24) & 7;
-    } else if (t < 152) {
-        layer = 2; ot = (t - 88) >> 3; it = (t - 88) & 7;
+    if (jt < 3) {
+        layer = 0; ot = x; it = jt;
+    } else if (jt < 11) {
+        layer = 1; ot = x; it = jt - 3;
+    } else if (jt < 19) {
+        layer = 2; ot = x; it = jt - 11;
     } else {
-        layer = 3; ot = 0; it = t - 152;
+        layer = 3; ot = 0; it = x;
     }
     const int nin = layer == 0 ? kIn : kHid, nout = layer == 3 ? kOut : kHid;
     const int offW = layer == 0 ? kOffW1 : layer == 1 ? kOffW2 : layer == 2 ? kOffW3 : kOffW4;
@@ -549,7 +558,7 @@ __global__ __launch_bounds__(64 * kTrGradWaves) void tr_grad_kernel(GradArgs g)
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int q = q0 + 32 * u;
-                    pv[u] = q < g.ntile ? g.bpart[(size_t)q * kTrBias + boff] : 0.0f;
+                    pv[u] = q < g.ntile ? g.bpart[(size_t)boff * g.ntile + q] : 0.0f;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) sb += pv[u];
