@@ -309,6 +309,7 @@ def main():
     sim.step(w.dt, args.warmup)
     sim.synchronize()
     torch.cuda.synchronize()
+    work_before = sim.work()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -343,7 +344,7 @@ def main():
                    "floes": w.nfloes, "floes_per_cell": float(w.nfloes) / w.ncells, "dt_s": w.dt,
                    "schedule": ["auto", "allpairs", "binned"][sched[0]], "sub_bins": [sched[1], sched[2]],
                    "continuum": "lax-friedrichs every step", "step_block": roofline.get("steps_per_launch", 1),
-                   "blocked_steps_timed": work_timed["blocked_steps"]},
+                   "blocked_steps_timed": work_timed["blocked_steps"] - work_before["blocked_steps"]},
         "roofline": roofline,
         "moment_error": None,
         "contacts_per_floe_step": contacts_per_floe_step,
