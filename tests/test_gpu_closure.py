@@ -80,10 +80,11 @@ def test_normalisation_is_applied():
     net.close()
 
 
-def test_gradient_matches_reference():
+@pytest.mark.parametrize("B", [512, 300, 7])
+def test_gradient_matches_reference(B):
+    # whole 256-row blocks, a ragged tail of 16-row tiles, and a batch below one tile
     net, th = make_net(3)
     rng = np.random.default_rng(1)
-    B = 512
     x = rng.normal(0, 1, (B, 45)).astype(np.float32)
     t = rng.normal(0, 1, (B, 4)).astype(np.float32)
     g, loss = net.gradient(dev(x), dev(t))
