@@ -34,7 +34,10 @@ def _run(w, k, nsteps, flags=0):
                     q=s.read_moments(sp.MOMENTS_CONTINUUM), stats=s.stats(), work=s.work(), active=active)
 
 
-@pytest.mark.parametrize("name,k,nsteps", [("small", 4, 12), ("small", 5, 13), ("dense", 4, 12), ("dense", 8, 16)])
+# the last two cases end their call in a short block of two steps (a last block
+# of 12 or more steps on a small grid splits)
+@pytest.mark.parametrize("name,k,nsteps", [("small", 4, 12), ("small", 5, 13), ("dense", 4, 12), ("dense", 8, 16),
+                                           ("small", 32, 20), ("dense", 16, 32)])
 def test_blocked_equals_per_step(name, k, nsteps):
     w = fixtures.make_config(0) if name == "small" else dense_workload()
     a = _run(w, 1, nsteps)
@@ -122,6 +125,32 @@ def test_uneven_workload_blocked_parity():
     _say("  continuum " + report(b["q"], Q, storage_floors(Q, Qs), oracle.Q_NAMES))
     assert b["active"]
     assert e_m <= TOL and e_q <= TOL
+
+
+def test_plain64_call_ending_in_a_short_block():
+    """The benchmark's call shape (20 steps after 5, blocks of 32, 1,048,576
+    floes): the call ends in a short block so that the continuum updates of
+    its first steps run beside it; the state equals that of per-step launches
+    (floes, contacts and DEM statistics bit for bit, the continuum within
+    1e-12)."""
+    w = fixtures.make_config(1)
+    out = []
+    for k in (1, 32):
+        with sp.Sim.from_workload(w) as s:
+            s.set_step_block(k)
+            s.step(w.dt, 5)
+            s.step(w.dt, 20)
+            out.append(dict(floes=s.read_floes(), mom=s.read_moments(sp.MOMENTS_DEM),
+                            q=s.read_moments(sp.MOMENTS_CONTINUUM), stats=s.stats(), work=s.work()))
+    a, b = out
+    for key in a["floes"]:
+        assert np.array_equal(a["floes"][key], b["floes"][key]), key
+    assert a["stats"]["contacts"] == b["stats"]["contacts"]
+    assert np.array_equal(a["mom"], b["mom"])
+    e = rel_err(b["q"], a["q"], floor=1e-6)
+    _say(f"plain64 5 + 20 steps, blocked against per-step: continuum max rel err {e.max():.2e}")
+    assert e.max() <= 1e-12, e.max()
+    assert b["work"]["blocked_steps"] == 25
 
 
 def test_full_size_plain64_blocks():
