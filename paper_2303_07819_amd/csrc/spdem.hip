@@ -1272,19 +1272,20 @@ sp_status sp_set_floes_device(sp_ctx* c, int64_t n, const int32_t* counts, const
 // launch of kTailSteps steps lets the updates of the steps before it run
 // beside that launch, and leaves only its own after it; the extra launch costs
 // its staging and write-back.  Measured on MI355X: a continuum launch on a grid
-// of up to kTailMaxCells cells takes about kLfLaunchNs (launch and memory
-// latency, not bandwidth), one more blocked launch about kStageNsPerFloe per
-// floe (plain64, 1,048,576 floes in 4096 cells: a 20-step call 3-4 % faster;
-// uneven128, 4.17 M floes in 16,384 cells: slower, so not split).
+// of up to kTailMaxCells cells takes about kLfLaunchPs (launch and memory
+// latency, not bandwidth), one more blocked launch about kStagePsPerFloe
+// picoseconds per floe (plain64, 1,048,576 floes in 4096 cells: 27 us, and a
+// 20-step call 3-4 % faster; uneven128, 4.17 M floes in 16,384 cells: 108 us
+// against 30 updates of 2.8 us, slower split, so not split).
 constexpr int kTailSteps = 2;
 constexpr int kTailMaxCells = 16384;
-constexpr double kLfLaunchNs = 2800.0;
-constexpr double kStageNsPerFloe = 26.0;
+constexpr double kLfLaunchPs = 2.8e6;
+constexpr double kStagePsPerFloe = 26.0;
 
 static bool tail_split_pays(const sp_ctx* c, int K)
 {
     if (K < 6 * kTailSteps || c->ncells > kTailMaxCells) return false;
-    return (double)(K - kTailSteps) * kLfLaunchNs > kStageNsPerFloe * (double)c->n;
+    return (double)(K - kTailSteps) * kLfLaunchPs > kStagePsPerFloe * (double)c->n;
 }
 
 sp_status sp_step(sp_ctx* c, double dt, int64_t nsteps)
