@@ -143,6 +143,8 @@ struct sp_ctx {
     int32_t blk_ring_slots = 0;
     int blk_parity = 0;                     // ring half of the next block
     hipStream_t lf_stream = nullptr;        // continuum updates of blocks (default priority)
+    hipStream_t bk_stream = nullptr;        // blocked launches of the smaller buckets (default priority)
+    hipEvent_t bk_fork = nullptr, bk_join = nullptr;
     hipEvent_t dem_done[2] = {nullptr, nullptr};
     hipEvent_t lf_done[2] = {nullptr, nullptr};
     bool lf_used[2] = {false, false};       // lf_done[i] was recorded
@@ -508,35 +510,35 @@ sp_status prepare_sel(sp_ctx* c, int sched, int waves, int persist, int threads,
 }
 
 template <int SCHED, int W, bool TSP>
-sp_status launch_block_tt(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K,
+sp_status launch_block_tt(sp_ctx* c, hipStream_t st, const StepArgs& a, int grid, int threads, size_t lds, int K,
                           const BlockNudge& nd)
 {
     if (lds > 65536)
         HIP_TRY(c, hipFuncSetAttribute((const void*)dem_block_kernel<SCHED, W, TSP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((dem_block_kernel<SCHED, W, TSP>), dim3(grid), dim3(threads), lds, c->stream, a, K, nd);
+    hipLaunchKernelGGL((dem_block_kernel<SCHED, W, TSP>), dim3(grid), dim3(threads), lds, st, a, K, nd);
     HIP_TRY(c, hipGetLastError());
     return SP_OK;
 }
 
 template <int SCHED, int W>
-sp_status launch_block_t(sp_ctx* c, const StepArgs& a, int grid, int threads, size_t lds, int K,
+sp_status launch_block_t(sp_ctx* c, hipStream_t st, const StepArgs& a, int grid, int threads, size_t lds, int K,
                          const BlockNudge& nd)
 {
-    if (a.flags & SP_TANGENTIAL_SPRING) return launch_block_tt<SCHED, W, true>(c, a, grid, threads, lds, K, nd);
-    return launch_block_tt<SCHED, W, false>(c, a, grid, threads, lds, K, nd);
+    if (a.flags & SP_TANGENTIAL_SPRING) return launch_block_tt<SCHED, W, true>(c, st, a, grid, threads, lds, K, nd);
+    return launch_block_tt<SCHED, W, false>(c, st, a, grid, threads, lds, K, nd);
 }
 
-sp_status launch_block_sel(sp_ctx* c, int sched, int waves, const StepArgs& a, int grid, int threads, size_t lds,
-                           int K, const BlockNudge& nd)
+sp_status launch_block_sel(sp_ctx* c, hipStream_t st, int sched, int waves, const StepArgs& a, int grid,
+                           int threads, size_t lds, int K, const BlockNudge& nd)
 {
     const bool binned = sched == SP_SCHED_BINNED;
     switch (waves) {
-    case 1: return binned ? launch_block_t<2, 1>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 1>(c, a, grid, threads, lds, K, nd);
-    case 2: return binned ? launch_block_t<2, 2>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 2>(c, a, grid, threads, lds, K, nd);
-    case 4: return binned ? launch_block_t<2, 4>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 4>(c, a, grid, threads, lds, K, nd);
-    case 8: return binned ? launch_block_t<2, 8>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 8>(c, a, grid, threads, lds, K, nd);
-    case 16: return binned ? launch_block_t<2, 16>(c, a, grid, threads, lds, K, nd) : launch_block_t<1, 16>(c, a, grid, threads, lds, K, nd);
+    case 1: return binned ? launch_block_t<2, 1>(c, st, a, grid, threads, lds, K, nd) : launch_block_t<1, 1>(c, st, a, grid, threads, lds, K, nd);
+    case 2: return binned ? launch_block_t<2, 2>(c, st, a, grid, threads, lds, K, nd) : launch_block_t<1, 2>(c, st, a, grid, threads, lds, K, nd);
+    case 4: return binned ? launch_block_t<2, 4>(c, st, a, grid, threads, lds, K, nd) : launch_block_t<1, 4>(c, st, a, grid, threads, lds, K, nd);
+    case 8: return binned ? launch_block_t<2, 8>(c, st, a, grid, threads, lds, K, nd) : launch_block_t<1, 8>(c, st, a, grid, threads, lds, K, nd);
+    case 16: return binned ? launch_block_t<2, 16>(c, st, a, grid, threads, lds, K, nd) : launch_block_t<1, 16>(c, st, a, grid, threads, lds, K, nd);
     default: return fail(c, SP_EINVAL, "no blocked kernel for waves=%d", waves);
     }
 }
@@ -620,14 +622,40 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
                         const Bucket* bk = nullptr)
 {
     if (!bk) bk = c->bk;
-    for (int q = 0; q < kNumBuckets; ++q) {
+    // with several buckets, the one of most floes on the library stream and
+    // the others beside it on a second stream (their cells are disjoint; the
+    // library stream waits for both)
+    int main_q = -1, nb = 0;
+    int64_t most = -1;
+    for (int q = 0; q < kNumBuckets; ++q) {   // every bucket checked before any launch
         const Bucket& b = bk[q];
         if (b.cells_h.empty()) continue;
         const int w = block_waves(b);
         if (b.cap > 64 * w) return fail(c, SP_EINVAL, "%d floes per cell exceed a blocked launch", b.cap);
-        const size_t gbytes = block_group_bytes(c, b.cap, w);
-        if (gbytes > kBlockLdsMax)
+        if (block_group_bytes(c, b.cap, w) > kBlockLdsMax)
             return fail(c, SP_ECAPACITY, "%d floes per cell exceed the LDS of a blocked launch", b.cap);
+        ++nb;
+        const int64_t f = (int64_t)bk[q].cells_h.size() * bk[q].cap;
+        if (f > most) {
+            most = f;
+            main_q = q;
+        }
+    }
+    if (nb > 1) {
+        if (!c->bk_stream) {
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->bk_stream, hipStreamNonBlocking));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->bk_fork, hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->bk_join, hipEventDisableTiming));
+        }
+        HIP_TRY(c, hipEventRecord(c->bk_fork, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->bk_stream, c->bk_fork, 0));
+    }
+    for (int q = 0; q < kNumBuckets; ++q) {
+        const Bucket& b = bk[q];
+        if (b.cells_h.empty()) continue;
+        const hipStream_t st = (nb > 1 && q != main_q) ? c->bk_stream : c->stream;
+        const int w = block_waves(b);
+        const size_t gbytes = block_group_bytes(c, b.cap, w);
         const int gpb = groups_per_block(w, gbytes);
         StepArgs a = base;
         a.work = b.work_d;
@@ -637,7 +665,11 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
         a.mom = mom;
         a.lf = 0;
         const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, c->sched, w, a, grid, gpb * 64 * w, (size_t)gpb * gbytes, K, nd));
+        SP_TRY(launch_block_sel(c, st, c->sched, w, a, grid, gpb * 64 * w, (size_t)gpb * gbytes, K, nd));
+    }
+    if (nb > 1) {
+        HIP_TRY(c, hipEventRecord(c->bk_join, c->bk_stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->bk_join, 0));
     }
     return SP_OK;
 }
@@ -1058,6 +1090,10 @@ void sp_destroy(sp_ctx* c)
         if (c->lf_done[i]) (void)hipEventDestroy(c->lf_done[i]);
     }
     if (c->lf_stream) (void)hipStreamDestroy(c->lf_stream);
+    if (c->bk_stream) (void)hipStreamSynchronize(c->bk_stream);
+    if (c->bk_fork) (void)hipEventDestroy(c->bk_fork);
+    if (c->bk_join) (void)hipEventDestroy(c->bk_join);
+    if (c->bk_stream) (void)hipStreamDestroy(c->bk_stream);
     free_all(c);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
