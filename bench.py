@@ -495,15 +495,17 @@ def inference_leg(stream, reps=20):
 
 def uneven_leg(stream, steps=500, warmup=20):
     """The uneven 128 x 128 workload (Poisson counts, 0 to about 700 floes per
-    cell): default batching, then the autotuner's choice, each over graph-replayed
-    steps timed with HIP events."""
+    cell): default batching, then the autotuner's choice, each timed with HIP
+    events over the same `steps` steps from the same state (saved after
+    `warmup` steps and restored for the tuned run)."""
+    import tempfile
     import torch
     import fixtures
     import paper_2303_07819_amd as sp
     w = fixtures.make_config("uneven128")
+    path = os.path.join(tempfile.mkdtemp(prefix="spdem_"), "uneven128.spdem")
 
     def timed(sim):
-        sim.step(w.dt, warmup)
         sim.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -513,12 +515,16 @@ def uneven_leg(stream, steps=500, warmup=20):
         return e0.elapsed_time(e1) / steps
 
     with sp.Sim.from_workload(w, stream=stream.cuda_stream) as sim:
+        sim.step(w.dt, warmup)
+        sim.save(path)
         ms_default = timed(sim)
         cells, _, _ = sim.batching()
         bw0, k0 = sim.block_waves(), sim.step_block()[0]
+        sim.load(path)
         best = sim.autotune(w.dt, 5)
         ms_tuned = timed(sim)
         bw, k = sim.block_waves(), sim.step_block()[0]
+    os.remove(path)
     return {"workload": "uneven128", "cells": [w.nx, w.ny], "floes": w.nfloes, "steps": steps,
             "bucket_cells": cells.tolist(), "tuned": "blocked kernel: wavefronts per cell per bucket, block length",
             "default_block_waves": bw0.tolist(), "default_step_block": k0, "default_ms_per_step": ms_default,
