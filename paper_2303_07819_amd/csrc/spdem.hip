@@ -650,6 +650,7 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
         HIP_TRY(c, hipEventRecord(c->bk_fork, c->stream));
         HIP_TRY(c, hipStreamWaitEvent(c->bk_stream, c->bk_fork, 0));
     }
+    sp_status status = SP_OK;
     for (int q = 0; q < kNumBuckets; ++q) {
         const Bucket& b = bk[q];
         if (b.cells_h.empty()) continue;
@@ -665,13 +666,14 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
         a.mom = mom;
         a.lf = 0;
         const int grid = (int)((b.cells_h.size() + gpb - 1) / gpb);
-        SP_TRY(launch_block_sel(c, st, c->sched, w, a, grid, gpb * 64 * w, (size_t)gpb * gbytes, K, nd));
+        status = launch_block_sel(c, st, c->sched, w, a, grid, gpb * 64 * w, (size_t)gpb * gbytes, K, nd);
+        if (status) break;
     }
-    if (nb > 1) {
+    if (nb > 1) {   // joined also after a failed launch: nothing stays behind on the second stream
         HIP_TRY(c, hipEventRecord(c->bk_join, c->bk_stream));
         HIP_TRY(c, hipStreamWaitEvent(c->stream, c->bk_join, 0));
     }
-    return SP_OK;
+    return status;
 }
 
 sp_status launch_empty_lf(sp_ctx* c, const StepArgs& base, int64_t k);
