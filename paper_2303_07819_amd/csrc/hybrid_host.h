@@ -234,6 +234,11 @@ struct HybridState {
     double* rs = nullptr;                 // reduced DEM statistics of every cell at the step's time [ncells][5]
     int32_t* back_d = nullptr;            // cells whose fallback window ended [ncells]
     int ndem = 0;
+    // the next block's DEM launch beside this block's closure work: its stream,
+    // a block's DEM launch done (per ring half), closure work done with a half
+    hipStream_t dem_stream = nullptr;
+    hipEvent_t fork = nullptr, dem_done[2] = {nullptr, nullptr}, clos_done[2] = {nullptr, nullptr};
+    bool clos_used[2] = {false, false};
 };
 
 namespace {
@@ -415,7 +420,12 @@ sp_status hybrid_check(sp_ctx* c, double dt)
 void hybrid_free(sp_ctx* c)
 {
     if (!c || !c->hyb) return;
+    HybridState* h = c->hyb;
+    if (h->dem_stream) (void)hipStreamSynchronize(h->dem_stream);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : {h->fork, h->dem_done[0], h->dem_done[1], h->clos_done[0], h->clos_done[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (h->dem_stream) (void)hipStreamDestroy(h->dem_stream);
     hybrid_free_buffers(c->hyb);
     delete c->hyb;
     c->hyb = nullptr;
@@ -564,23 +574,64 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
     // of a fallback window run as blocked launches (statistics of step t into
     // slot t of the block ring), followed by the closure and continuum work of
     // each step in order, on the library stream.
+    // When nothing at a block's end changes the DEM cells (no check, no
+    // fallback window ending), the next block's DEM launch is issued at once on
+    // a second stream, into the other half of the ring, and runs beside this
+    // block's closure work (it waits for this block's DEM launch and for the
+    // closure work that last read its half).
     const bool can_block = c->block_k > 1;
-    if (can_block) SP_TRY(block_prepare(c));
-    for (int64_t it = 0; it < nsteps;) {
-        int64_t K = 1;
-        if (can_block) {
-            K = std::min<int64_t>(c->block_k, nsteps - it);
-            K = std::min<int64_t>(K, h->check_every - h->hsteps % h->check_every);
-            for (int32_t cell : h->fallback_cells) K = std::min<int64_t>(K, h->fallback_left[cell]);
+    if (can_block) {
+        SP_TRY(block_prepare(c));
+        if (!h->dem_stream) {
+            HIP_TRY(c, hipStreamCreateWithFlags(&h->dem_stream, hipStreamNonBlocking));
+            HIP_TRY(c, hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+            for (int i = 0; i < 2; ++i) {
+                HIP_TRY(c, hipEventCreateWithFlags(&h->dem_done[i], hipEventDisableTiming));
+                HIP_TRY(c, hipEventCreateWithFlags(&h->clos_done[i], hipEventDisableTiming));
+            }
         }
+    }
+    // steps of the block from loop step i0, with h->hsteps = hs and every
+    // fallback window `done` steps shorter
+    auto block_len = [&](int64_t i0, int64_t hs, int64_t done) -> int64_t {
+        if (!can_block) return 1;
+        int64_t L = std::min<int64_t>(c->block_k, nsteps - i0);
+        L = std::min<int64_t>(L, h->check_every - hs % h->check_every);
+        for (int32_t cell : h->fallback_cells) L = std::min<int64_t>(L, h->fallback_left[cell] - done);
+        return L;
+    };
+    BlockNudge none;
+    memset(&none, 0, sizeof none);
+    const size_t half = (size_t)c->blk_ring_slots * slot;
+    int hp = 0;                 // ring half of the current block
+    int64_t early_K = 0;        // steps of the block already launched on the DEM stream (0: none)
+    for (int64_t it = 0; it < nsteps;) {
+        const int64_t K = block_len(it, h->hsteps, 0);
         double* ring = nullptr;
         if (K > 1) {
-            SP_TRY(join_block_lf(c));
-            BlockNudge none;
-            memset(&none, 0, sizeof none);
-            ring = c->blk_ring;
-            SP_TRY(launch_blocks(c, base, ring, (int)K, none, h->bk));
+            ring = c->blk_ring + (size_t)hp * half;
+            if (early_K > 0) {
+                if (early_K != K) return fail(c, SP_EDEVICE, "hybrid block of %lld steps launched as %lld",
+                                              (long long)K, (long long)early_K);
+                HIP_TRY(c, hipStreamWaitEvent(c->stream, h->dem_done[hp], 0));
+            } else {
+                SP_TRY(join_block_lf(c));
+                SP_TRY(launch_blocks(c, base, ring, (int)K, none, h->bk));
+            }
+            early_K = 0;
             c->blk_steps += K;
+            bool quiet = (h->hsteps + K) % h->check_every != 0 && it + K < nsteps;
+            for (int32_t cell : h->fallback_cells) quiet = quiet && h->fallback_left[cell] > K;
+            const int64_t K2 = quiet ? block_len(it + K, h->hsteps + K, K) : 0;
+            if (K2 > 1) {
+                const int q = hp ^ 1;
+                HIP_TRY(c, hipEventRecord(h->fork, c->stream));   // after this block's DEM launch
+                HIP_TRY(c, hipStreamWaitEvent(h->dem_stream, h->fork, 0));
+                if (h->clos_used[q]) HIP_TRY(c, hipStreamWaitEvent(h->dem_stream, h->clos_done[q], 0));
+                SP_TRY(launch_blocks(c, base, c->blk_ring + (size_t)q * half, (int)K2, none, h->bk, h->dem_stream));
+                HIP_TRY(c, hipEventRecord(h->dem_done[q], h->dem_stream));
+                early_K = K2;
+            }
         }
         for (int64_t t = 0; t < K; ++t, ++it) {
             const int64_t k = c->kstep;
@@ -638,6 +689,11 @@ sp_status sp_step_hybrid(sp_ctx* c, double dt, int64_t nsteps)
                 SP_TRY(hybrid_rebuild(c));   // synchronises: `back` may go
             }
             if (h->hsteps % h->check_every == 0) SP_TRY(hybrid_check(c, dt));
+        }
+        if (ring) {   // this block's closure work is done with its half of the ring
+            HIP_TRY(c, hipEventRecord(h->clos_done[hp], c->stream));
+            h->clos_used[hp] = true;
+            hp ^= 1;
         }
     }
     return SP_OK;

@@ -619,9 +619,10 @@ size_t block_group_bytes(const sp_ctx* c, int cap, int waves)
 // kMomStride) (work entries flagged for mom_alt: there); with an active nd, the
 // coarse-to-fine update of every launched cell at the end.
 sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, const BlockNudge& nd,
-                        const Bucket* bk = nullptr)
+                        const Bucket* bk = nullptr, hipStream_t on = nullptr)
 {
     if (!bk) bk = c->bk;
+    const hipStream_t s0 = on ? on : c->stream;   // the stream the launches follow and that waits for them
     // with several buckets, the one of most floes on the library stream and
     // the others beside it on a second stream (their cells are disjoint; the
     // library stream waits for both)
@@ -647,14 +648,14 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
             HIP_TRY(c, hipEventCreateWithFlags(&c->bk_fork, hipEventDisableTiming));
             HIP_TRY(c, hipEventCreateWithFlags(&c->bk_join, hipEventDisableTiming));
         }
-        HIP_TRY(c, hipEventRecord(c->bk_fork, c->stream));
+        HIP_TRY(c, hipEventRecord(c->bk_fork, s0));
         HIP_TRY(c, hipStreamWaitEvent(c->bk_stream, c->bk_fork, 0));
     }
     sp_status status = SP_OK;
     for (int q = 0; q < kNumBuckets; ++q) {
         const Bucket& b = bk[q];
         if (b.cells_h.empty()) continue;
-        const hipStream_t st = (nb > 1 && q != main_q) ? c->bk_stream : c->stream;
+        const hipStream_t st = (nb > 1 && q != main_q) ? c->bk_stream : s0;
         const int w = block_waves(b);
         const size_t gbytes = block_group_bytes(c, b.cap, w);
         const int gpb = groups_per_block(w, gbytes);
@@ -671,7 +672,7 @@ sp_status launch_blocks(sp_ctx* c, const StepArgs& base, double* mom, int K, con
     }
     if (nb > 1) {   // joined also after a failed launch: nothing stays behind on the second stream
         HIP_TRY(c, hipEventRecord(c->bk_join, c->bk_stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->bk_join, 0));
+        HIP_TRY(c, hipStreamWaitEvent(s0, c->bk_join, 0));
     }
     return status;
 }
